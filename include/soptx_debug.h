@@ -1,0 +1,44 @@
+/*
+ * soptx_debug.h -- host-only introspection of the once-per-mesh build of
+ * libsoptx (CSR pattern, element geometry and assembly plan), for tests and
+ * tools.  None of these functions touches a device.
+ *
+ * The build is the one soptx_build_pattern performs before its uploads
+ * (paper, Sec. 2.2: sparse K = sum_e E(rho_e) K_e^0; Sec. 3.2.2: invariant
+ * components built once and reused).
+ */
+#ifndef SOPTX_DEBUG_H
+#define SOPTX_DEBUG_H
+
+#include <stdint.h>
+
+#include "soptx.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct soptx_host_plan_s *soptx_host_plan;
+
+/* Build pattern, geometry and plan on the host.  Same validation and error
+ * codes as soptx_build_pattern.  *out is released with
+ * soptx_debug_host_plan_free. */
+int soptx_debug_host_plan(const soptx_mesh *mesh, soptx_host_plan *out);
+
+/* Borrow one array of the plan by name: "row_ptr", "col_idx" (int32 CSR),
+ * "geo" (double, [(dim*dim+1)][n_cells]: J^-1 row-major then det J),
+ * "sig_info", "sig_pos_ptr", "sig_contrib", "sig_wave", "grp_info",
+ * "grp_nodes", "grp_elems" (int32), "grp_n2l", "pos" (uint16).
+ * The pointer stays valid until soptx_debug_host_plan_free. */
+int soptx_debug_host_plan_array(soptx_host_plan p, const char *name, const void **data, int64_t *count,
+                                int32_t *elem_bytes);
+
+/* out8 = {ndof, nnz, n_groups, n_signatures, emax, kmax, dim, nen}. */
+int soptx_debug_host_plan_scalars(soptx_host_plan p, int64_t *out8);
+
+void soptx_debug_host_plan_free(soptx_host_plan p);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SOPTX_DEBUG_H */

@@ -1,0 +1,230 @@
+"""Python binding of libsoptx (argument marshalling only).
+
+Torch tensors serve as device buffers and torch streams as HIP streams; every
+step of assembly, sensitivity, compliance and backward runs in the library's
+HIP kernels.  The names mirror the C ABI in include/soptx.h.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import Optional
+
+import numpy as np
+
+from . import _lib
+from ._lib import BF16_FP32ACC, FP32, FP64, REF_QUADRATURE, REF_SYMBOLIC, check, lib
+
+__all__ = ["Material", "Pattern", "FP64", "FP32", "BF16_FP32ACC", "REF_SYMBOLIC", "REF_QUADRATURE",
+           "reference_tensor", "validate_mesh", "host_plan"]
+
+_DIM = {1: 2, 2: 2, 3: 3, 4: 3}
+_NEN = {1: 4, 2: 3, 3: 8, 4: 10}
+
+
+@dataclasses.dataclass
+class Material:
+    """Linear elastic SIMP material (Sec. 2.1, Sec. 3.2.1): E0, Emin, nu, p."""
+    E0: float = 1.0
+    Emin: float = 1e-9
+    nu: float = 0.3
+    p: float = 3.0
+    plane_strain: int = 0
+
+    def _c(self) -> _lib.Material:
+        return _lib.Material(self.E0, self.Emin, self.nu, self.p, self.plane_strain)
+
+
+def _mesh_struct(elem: int, coords: np.ndarray, cells: np.ndarray):
+    coords = np.ascontiguousarray(coords, dtype=np.float64)
+    cells = np.ascontiguousarray(cells, dtype=np.int32)
+    m = _lib.Mesh(elem, _DIM.get(elem, 0), coords.shape[0], coords.ctypes.data, cells.shape[0], cells.ctypes.data)
+    return m, (coords, cells)
+
+
+def reference_tensor(elem: int, method: int = REF_SYMBOLIC) -> np.ndarray:
+    """M[i, j, m, n] = int_ref d_m phi_i d_n phi_j (host only)."""
+    d, n = _DIM[elem], _NEN[elem]
+    M = np.zeros((n, n, d, d))
+    check(lib().soptx_reference_tensor(elem, method, M.ctypes.data), "soptx_reference_tensor")
+    return M
+
+
+def validate_mesh(elem: int, coords, cells) -> int:
+    """Status code of the library's mesh validation (host only)."""
+    m, keep = _mesh_struct(elem, coords, cells)
+    return lib().soptx_validate_mesh(ctypes.byref(m))
+
+
+def host_plan(elem: int, coords, cells) -> dict:
+    """Host-side pattern, geometry and assembly plan as numpy arrays (copies)."""
+    m, keep = _mesh_struct(elem, coords, cells)
+    L = lib()
+    h = ctypes.c_void_p()
+    check(L.soptx_debug_host_plan(ctypes.byref(m), ctypes.byref(h)), "soptx_debug_host_plan")
+    try:
+        out = {}
+        dt = {4: np.int32, 2: np.uint16, 8: np.float64}
+        for name in ("row_ptr", "col_idx", "geo", "sig_info", "sig_pos_ptr", "sig_contrib", "sig_wave",
+                     "grp_info", "grp_nodes", "grp_elems", "grp_n2l", "pos"):
+            ptr, cnt, eb = ctypes.c_void_p(), ctypes.c_int64(), ctypes.c_int32()
+            check(L.soptx_debug_host_plan_array(h, name.encode(), ctypes.byref(ptr), ctypes.byref(cnt),
+                                                ctypes.byref(eb)), name)
+            dtype = np.float64 if name == "geo" else dt[eb.value]
+            if cnt.value == 0:
+                out[name] = np.zeros(0, dtype=dtype)
+            else:
+                buf = (ctypes.c_char * (cnt.value * eb.value)).from_address(ptr.value)
+                out[name] = np.frombuffer(buf, dtype=dtype).copy()
+        sc = np.zeros(8, dtype=np.int64)
+        check(L.soptx_debug_host_plan_scalars(h, sc.ctypes.data), "scalars")
+        out.update(dict(zip(["ndof", "nnz", "n_groups", "n_signatures", "emax", "kmax", "dim", "nen"],
+                            [int(x) for x in sc])))
+        return out
+    finally:
+        L.soptx_debug_host_plan_free(h)
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _dptr(t, name, dtype=None, numel=None):
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    return t.data_ptr()
+
+
+class Pattern:
+    """A mesh's CSR pattern, geometry and assembly plan, resident on the device.
+
+    Built once per mesh (Sec. 3.2.2: invariant components are cached);
+    assemble / sensitivity / compliance / backward run per call.
+    """
+
+    def __init__(self, elem: int, coords, cells, ref_method: int = REF_SYMBOLIC, stream=None):
+        m, keep = _mesh_struct(elem, coords, cells)
+        h = ctypes.c_void_p()
+        check(lib().soptx_build_pattern_ex(ctypes.byref(m), ref_method, ctypes.byref(h), _stream_ptr(stream)),
+              "soptx_build_pattern")
+        self._h = h
+        self.elem = elem
+        self.dim = _DIM[elem]
+        self.nen = _NEN[elem]
+        self.n_nodes = int(keep[0].shape[0])
+        self.n_cells = int(keep[1].shape[0])
+        ndof, nnz = ctypes.c_int64(), ctypes.c_int64()
+        check(lib().soptx_pattern_info(h, ctypes.byref(ndof), ctypes.byref(nnz), None, None), "pattern_info")
+        self.ndof, self.nnz = ndof.value, nnz.value
+
+    @classmethod
+    def from_mesh(cls, mesh, **kw) -> "Pattern":
+        return cls(mesh.elem, mesh.coords, mesh.cells, **kw)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().soptx_destroy_pattern(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def stats(self) -> dict:
+        s = _lib.PatternStats()
+        check(lib().soptx_pattern_stats_get(self._h, ctypes.byref(s)), "stats")
+        return {f: getattr(s, f) for f, _ in s._fields_}
+
+    def pattern(self):
+        """(row_ptr, col_idx) copied to host numpy int32 arrays."""
+        rp = np.zeros(self.ndof + 1, dtype=np.int32)
+        ci = np.zeros(max(self.nnz, 1), dtype=np.int32)
+        check(lib().soptx_pattern_copy(self._h, rp.ctypes.data, ci.ctypes.data), "soptx_pattern_copy")
+        return rp, ci[: self.nnz]
+
+    # ------------------------------------------------------------- per call
+    def _rho_dtype(self, prec):
+        import torch
+        return torch.float64 if prec == FP64 else torch.float32
+
+    def assemble(self, material: Material, rho, mask=None, out=None, prec: int = FP64, stream=None):
+        """K values (FP64, [nnz]) = sum_e E(rho_e) K_e^0 (Eq. cmpd), Dirichlet rows/cols if mask."""
+        import torch
+        if out is None:
+            out = torch.empty(self.nnz, dtype=torch.float64, device=rho.device)
+        mc = material._c()
+        check(lib().soptx_assemble(self._h, ctypes.byref(mc), _dptr(rho, "rho", self._rho_dtype(prec), self.n_cells),
+                                   _dptr(mask, "mask", torch.uint8, self.ndof),
+                                   _dptr(out, "out", torch.float64, self.nnz), prec, _stream_ptr(stream)),
+              "soptx_assemble")
+        return out
+
+    def sensitivity(self, material: Material, rho, u, out=None, prec: int = FP64, stream=None):
+        """dc_e = -E'(rho_e) u_e^T K_e^0 u_e (Appendix D)."""
+        import torch
+        if out is None:
+            out = torch.empty(self.n_cells, dtype=self._rho_dtype(prec), device=rho.device)
+        mc = material._c()
+        check(lib().soptx_sensitivity(self._h, ctypes.byref(mc),
+                                      _dptr(rho, "rho", self._rho_dtype(prec), self.n_cells),
+                                      _dptr(u, "u", torch.float64, self.ndof),
+                                      _dptr(out, "dc", self._rho_dtype(prec), self.n_cells), prec,
+                                      _stream_ptr(stream)), "soptx_sensitivity")
+        return out
+
+    def compliance(self, material: Material, rho, u, f=None, out=None, prec: int = FP64, stream=None):
+        """[u^T K u, f^T u] as a device FP64 tensor of 2 (Eq. cmpd)."""
+        import torch
+        if out is None:
+            out = torch.zeros(2, dtype=torch.float64, device=rho.device)
+        mc = material._c()
+        check(lib().soptx_compliance(self._h, ctypes.byref(mc),
+                                     _dptr(rho, "rho", self._rho_dtype(prec), self.n_cells),
+                                     _dptr(u, "u", torch.float64, self.ndof),
+                                     _dptr(f, "f", torch.float64, self.ndof),
+                                     _dptr(out, "c", torch.float64, 2), prec, _stream_ptr(stream)),
+              "soptx_compliance")
+        return out
+
+    def evaluate(self, material: Material, rho, u, f=None, dc=None, c=None, prec: int = FP64, stream=None):
+        """Fused sensitivity + compliance; returns (dc, c)."""
+        import torch
+        if dc is None:
+            dc = torch.empty(self.n_cells, dtype=self._rho_dtype(prec), device=rho.device)
+        if c is None:
+            c = torch.zeros(2, dtype=torch.float64, device=rho.device)
+        mc = material._c()
+        check(lib().soptx_evaluate(self._h, ctypes.byref(mc),
+                                   _dptr(rho, "rho", self._rho_dtype(prec), self.n_cells),
+                                   _dptr(u, "u", torch.float64, self.ndof), _dptr(f, "f", torch.float64, self.ndof),
+                                   _dptr(dc, "dc", self._rho_dtype(prec), self.n_cells),
+                                   _dptr(c, "c", torch.float64, 2), prec, _stream_ptr(stream)), "soptx_evaluate")
+        return dc, c
+
+    def backward(self, material: Material, rho, Kbar, mask=None, out=None, prec: int = FP64, stream=None):
+        """drho_e = E'(rho_e) <Kbar, K_e^0> over the element's slots (reverse of assemble)."""
+        import torch
+        if out is None:
+            out = torch.empty(self.n_cells, dtype=self._rho_dtype(prec), device=rho.device)
+        mc = material._c()
+        check(lib().soptx_assemble_backward(self._h, ctypes.byref(mc),
+                                            _dptr(rho, "rho", self._rho_dtype(prec), self.n_cells),
+                                            _dptr(mask, "mask", torch.uint8, self.ndof),
+                                            _dptr(Kbar, "Kbar", torch.float64, self.nnz),
+                                            _dptr(out, "drho", self._rho_dtype(prec), self.n_cells), prec,
+                                            _stream_ptr(stream)), "soptx_assemble_backward")
+        return out

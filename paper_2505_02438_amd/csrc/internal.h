@@ -1,0 +1,75 @@
+// Internal declarations shared by the host plan builder, the reference data,
+// the HIP kernels and the C ABI of libsoptx.
+#pragma once
+
+#include <array>
+#include <cstdint>
+#include <vector>
+
+#include "../../include/soptx.h"
+
+namespace soptx {
+
+constexpr int kGroupNodes = 64;   // nodes per assembly group = lanes of one wavefront
+constexpr int kWaves = 4;         // wavefronts per assembly workgroup
+constexpr int kMaxNen = 10;
+
+inline int elem_dim(int elem) {
+    switch (elem) {
+    case SOPTX_QUAD4: case SOPTX_TRI3: return 2;
+    case SOPTX_HEX8: case SOPTX_TET10: return 3;
+    default: return -1;
+    }
+}
+inline int elem_nen(int elem) {
+    switch (elem) {
+    case SOPTX_QUAD4: return 4;
+    case SOPTX_TRI3: return 3;
+    case SOPTX_HEX8: return 8;
+    case SOPTX_TET10: return 10;
+    default: return -1;
+    }
+}
+
+int corner_bit(int elem, int i, int a);
+void quadrature_rule(int elem, std::vector<double> &pts, std::vector<double> &wts);
+int reference_tensor(int elem, int method, double *M);
+int reference_qp_grads(int elem, std::vector<double> &wts, std::vector<double> &grads);
+
+// Host-side result of the once-per-mesh build (pattern, geometry, plan).
+//
+// Assembly plan.  Nodes whose local connectivity is identical ("signature":
+// number of adjacent elements K, number of neighbour nodes deg, and for each
+// neighbour position p the ordered list of (k, i, j) = (index of the element
+// in the node's ascending element list, local index of the node, local index
+// of the neighbour)) are packed into groups of up to 64.  One workgroup
+// assembles one group: lane = node, and every lane walks the same positions
+// and contributions, so the reference-tensor index (i, j) is wave-uniform.
+struct HostPlan {
+    int elem = 0, dim = 0, nen = 0;
+    int64_t n_nodes = 0, n_cells = 0, ndof = 0, nnz = 0;
+    std::vector<int32_t> row_ptr;  // [ndof+1]
+    std::vector<int32_t> col_idx;  // [nnz]
+    std::vector<double> geo;       // [(dim*dim+1)][n_cells]: G[m][a] = d xi_m / d x_a, then det J
+
+    // signatures
+    std::vector<int32_t> sig_info;     // [nsig][4]: K, deg, pos_off, wave_off
+    std::vector<int32_t> sig_pos_ptr;  // per signature deg+1 offsets into sig_contrib
+    std::vector<int32_t> sig_contrib;  // (k << 16) | (i << 8) | j
+    std::vector<int32_t> sig_wave;     // [nsig][kWaves+1] position split among waves
+    // groups
+    std::vector<int32_t> grp_info;   // [ngroups][5]: sig, n_nodes, elem_off, n_elem, n2l_off
+    std::vector<int32_t> grp_nodes;  // [ngroups][64], -1 padded
+    std::vector<int32_t> grp_elems;  // concatenated element ids, grp_info elem_off .. next
+    std::vector<uint16_t> grp_n2l;   // per group K*64 (k-major): slot of element k of lane's node
+    // backward: position of cells[e][j] in the neighbour list of cells[e][i]
+    std::vector<uint16_t> pos;       // [n_cells][nen][nen]
+    int kmax = 0, emax = 0;
+    int64_t n_groups() const { return (int64_t)grp_info.size() / 5; }
+    int64_t n_sigs() const { return (int64_t)sig_info.size() / 4; }
+};
+
+int validate_mesh(const soptx_mesh *mesh);
+int build_host_plan(const soptx_mesh *mesh, HostPlan &hp);
+
+}  // namespace soptx

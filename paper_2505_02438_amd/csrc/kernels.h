@@ -1,0 +1,81 @@
+// Kernel parameter blocks and launchers (device side in kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace soptx {
+
+constexpr int kF64 = SOPTX_FP64;
+constexpr int kF32 = SOPTX_FP32;
+constexpr int kBF16 = SOPTX_BF16_FP32ACC;
+
+struct AsmParams {
+    const int32_t *grp_info;    // [G][5]: sig, n_nodes, elem_off, n_elem, n2l_off
+    const int32_t *grp_nodes;   // [G][64]
+    const int32_t *grp_elems;
+    const uint16_t *grp_n2l;
+    const int32_t *sig_info;    // [S][4]
+    const int32_t *sig_pos_ptr;
+    const int32_t *sig_contrib;
+    const int32_t *sig_wave;
+    const int32_t *row_ptr;
+    const int32_t *cells;
+    const double *geo;
+    const void *rho;
+    const uint8_t *mask;
+    const double *M;
+    const float *M32;
+    const float *Mbf;
+    double *K;
+    int64_t n_cells;
+    double E0, Emin, p;
+    int ip;          // integer exponent, or -1
+    double lam, mu;  // Lame constants at unit modulus (plane-stress lambda* in 2D)
+    int emax, kmax;
+};
+
+struct EnergyParams {
+    const int32_t *cells;
+    const double *geo;
+    const void *rho;
+    const double *u;
+    const double *qw;      // [NQ]
+    const double *qgrad;   // [NQ][nen][dim]
+    const float *qgrad32;  // [NQ][nen][dim]
+    const double *cgrad;   // [nen][dim] reference gradients at the centroid
+    const double *xref;    // [nen][dim] reference node coordinates
+    void *dc;              // or null
+    double *partials;      // [ceil(NC/256)] or null
+    int64_t n_cells;
+    double E0, Emin, p;
+    int ip;
+    double lam, mu;
+};
+
+struct BwdParams {
+    const int32_t *cells;
+    const int32_t *row_ptr;
+    const uint16_t *pos;
+    const double *geo;
+    const void *rho;
+    const double *Kbar;
+    const uint8_t *mask;
+    const double *M;
+    const float *M32;
+    void *drho;
+    int64_t n_cells;
+    double E0, Emin, p;
+    int ip;
+    double lam, mu;
+};
+
+hipError_t launch_assemble(int elem, int prec, const AsmParams &P, int64_t ngroups, hipStream_t st);
+hipError_t launch_energy(int elem, int prec, const EnergyParams &P, hipStream_t st);
+hipError_t launch_dot_partials(const double *f, const double *u, int64_t n, double *partials, int nblocks,
+                               hipStream_t st);
+hipError_t launch_finalize(const double *p0, int n0, const double *p1, int n1, double *c, hipStream_t st);
+hipError_t launch_backward(int elem, int prec, const BwdParams &P, hipStream_t st);
+
+}  // namespace soptx

@@ -1,0 +1,367 @@
+// Once-per-mesh host work: mesh validation, per-element geometry, the CSR
+// pattern and the assembly plan (Sec. 3.2.2: invariant components are built
+// once and reused across optimisation iterations).
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <thread>
+#include <unordered_map>
+
+#include "internal.h"
+
+namespace soptx {
+
+namespace {
+
+int hw_threads() {
+    unsigned n = std::thread::hardware_concurrency();
+    if (n == 0) n = 4;
+    if (n > 16) n = 16;
+    return (int)n;
+}
+
+template <class F>
+void parallel_for(int64_t n, F &&f) {
+    int T = hw_threads();
+    if (n < 4096 || T <= 1) { f(0, n); return; }
+    std::vector<std::thread> th;
+    int64_t chunk = (n + T - 1) / T;
+    for (int t = 0; t < T; t++) {
+        int64_t a = t * chunk, b = std::min(n, a + chunk);
+        if (a >= b) break;
+        th.emplace_back([&f, a, b] { f(a, b); });
+    }
+    for (auto &x : th) x.join();
+}
+
+// det and inverse of a dim x dim row-major matrix J[a][m] = d x_a / d xi_m;
+// G[m][a] = (J^-1)[m][a].
+double inv_small(int dim, const double *J, double *G) {
+    if (dim == 2) {
+        double d = J[0] * J[3] - J[1] * J[2];
+        G[0] = J[3] / d; G[1] = -J[1] / d; G[2] = -J[2] / d; G[3] = J[0] / d;
+        return d;
+    }
+    double c00 = J[4] * J[8] - J[5] * J[7], c01 = J[5] * J[6] - J[3] * J[8], c02 = J[3] * J[7] - J[4] * J[6];
+    double d = J[0] * c00 + J[1] * c01 + J[2] * c02;
+    G[0] = c00 / d; G[1] = (J[2] * J[7] - J[1] * J[8]) / d; G[2] = (J[1] * J[5] - J[2] * J[4]) / d;
+    G[3] = c01 / d; G[4] = (J[0] * J[8] - J[2] * J[6]) / d; G[5] = (J[2] * J[3] - J[0] * J[5]) / d;
+    G[6] = c02 / d; G[7] = (J[1] * J[6] - J[0] * J[7]) / d; G[8] = (J[0] * J[4] - J[1] * J[3]) / d;
+    return d;
+}
+
+}  // namespace
+
+int validate_mesh(const soptx_mesh *mesh) {
+    if (!mesh) return SOPTX_E_INVALID_ARG;
+    const int dim = elem_dim(mesh->elem), nen = elem_nen(mesh->elem);
+    if (dim < 0) return SOPTX_E_UNSUPPORTED_ELEM;
+    if (mesh->dim != dim || mesh->n_nodes < 0 || mesh->n_cells < 0) return SOPTX_E_INVALID_ARG;
+    if ((mesh->n_nodes > 0 && !mesh->coords) || (mesh->n_cells > 0 && !mesh->cells))
+        return SOPTX_E_INVALID_ARG;
+    if ((int64_t)dim * mesh->n_nodes >= INT32_MAX) return SOPTX_E_OVERFLOW;
+    if (mesh->n_cells >= INT32_MAX / kMaxNen) return SOPTX_E_OVERFLOW;
+    for (int64_t e = 0; e < mesh->n_cells; e++) {
+        const int32_t *c = mesh->cells + e * nen;
+        for (int i = 0; i < nen; i++) {
+            if (c[i] < 0 || c[i] >= mesh->n_nodes) return SOPTX_E_BAD_MESH;
+            for (int j = 0; j < i; j++)
+                if (c[j] == c[i]) return SOPTX_E_BAD_MESH;
+        }
+    }
+    // geometry: affine map, positive orientation
+    for (int64_t e = 0; e < mesh->n_cells; e++) {
+        const int32_t *c = mesh->cells + e * nen;
+        auto X = [&](int i, int a) { return mesh->coords[(int64_t)c[i] * dim + a]; };
+        // map-defining nodes: Q1 quad 0,1,3; Q1 hex 0,1,3,4; simplices 0..dim
+        int def[3];
+        if (mesh->elem == SOPTX_QUAD4) { def[0] = 1; def[1] = 3; }
+        else if (mesh->elem == SOPTX_HEX8) { def[0] = 1; def[1] = 3; def[2] = 4; }
+        else { for (int m = 0; m < dim; m++) def[m] = m + 1; }
+        double J[9], G[9], scale = 0.0;
+        for (int a = 0; a < dim; a++)
+            for (int m = 0; m < dim; m++) {
+                J[a * dim + m] = X(def[m], a) - X(0, a);
+                scale = std::max(scale, std::fabs(J[a * dim + m]));
+            }
+        double det = inv_small(dim, J, G);
+        if (!(det > 0.0) || !std::isfinite(det)) return SOPTX_E_JACOBIAN;
+        // every node must sit at the affine image of its reference position
+        const double tol = 1e-10 * scale;
+        for (int i = 0; i < nen; i++) {
+            double xi[3] = {0, 0, 0};
+            if (mesh->elem == SOPTX_QUAD4 || mesh->elem == SOPTX_HEX8) {
+                for (int m = 0; m < dim; m++) xi[m] = corner_bit(mesh->elem, i, m);
+            } else if (mesh->elem == SOPTX_TRI3) {
+                if (i > 0) xi[i - 1] = 1.0;
+            } else {  // TET10: vertices then edge midpoints
+                static const int E[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+                auto vref = [](int v, double *o) { o[0] = o[1] = o[2] = 0.0; if (v > 0) o[v - 1] = 1.0; };
+                if (i < 4) vref(i, xi);
+                else {
+                    double p[3], q[3];
+                    vref(E[i - 4][0], p); vref(E[i - 4][1], q);
+                    for (int m = 0; m < 3; m++) xi[m] = 0.5 * (p[m] + q[m]);
+                }
+            }
+            for (int a = 0; a < dim; a++) {
+                double x = X(0, a);
+                for (int m = 0; m < dim; m++) x += J[a * dim + m] * xi[m];
+                if (std::fabs(x - X(i, a)) > tol) return SOPTX_E_NONAFFINE;
+            }
+        }
+    }
+    return SOPTX_OK;
+}
+
+int build_host_plan(const soptx_mesh *mesh, HostPlan &hp) {
+    int rc = validate_mesh(mesh);
+    if (rc) return rc;
+    const int dim = elem_dim(mesh->elem), nen = elem_nen(mesh->elem);
+    const int64_t NN = mesh->n_nodes, NC = mesh->n_cells;
+    hp.elem = mesh->elem; hp.dim = dim; hp.nen = nen;
+    hp.n_nodes = NN; hp.n_cells = NC; hp.ndof = dim * NN;
+    const int32_t *cells = mesh->cells;
+
+    // ---- geometry (a1): G = J^-1 and det J per element, SoA
+    hp.geo.assign((size_t)(dim * dim + 1) * NC, 0.0);
+    parallel_for(NC, [&](int64_t a0, int64_t a1) {
+        for (int64_t e = a0; e < a1; e++) {
+            const int32_t *c = cells + e * nen;
+            int def[3];
+            if (mesh->elem == SOPTX_QUAD4) { def[0] = 1; def[1] = 3; }
+            else if (mesh->elem == SOPTX_HEX8) { def[0] = 1; def[1] = 3; def[2] = 4; }
+            else { for (int m = 0; m < dim; m++) def[m] = m + 1; }
+            double J[9], G[9];
+            for (int a = 0; a < dim; a++)
+                for (int m = 0; m < dim; m++)
+                    J[a * dim + m] = mesh->coords[(int64_t)c[def[m]] * dim + a] - mesh->coords[(int64_t)c[0] * dim + a];
+            double det = inv_small(dim, J, G);
+            for (int k = 0; k < dim * dim; k++) hp.geo[(size_t)k * NC + e] = G[k];
+            hp.geo[(size_t)dim * dim * NC + e] = det;
+        }
+    });
+
+    // ---- node -> (element, local index), elements ascending (counting sort)
+    std::vector<int64_t> n2e_ptr(NN + 1, 0);
+    for (int64_t e = 0; e < NC; e++)
+        for (int i = 0; i < nen; i++) n2e_ptr[cells[e * nen + i] + 1]++;
+    for (int64_t n = 0; n < NN; n++) n2e_ptr[n + 1] += n2e_ptr[n];
+    std::vector<int32_t> n2e_e(n2e_ptr[NN]);
+    std::vector<uint8_t> n2e_i(n2e_ptr[NN]);
+    {
+        std::vector<int64_t> fill(n2e_ptr.begin(), n2e_ptr.end() - 1);
+        for (int64_t e = 0; e < NC; e++)
+            for (int i = 0; i < nen; i++) {
+                int64_t s = fill[cells[e * nen + i]]++;
+                n2e_e[s] = (int32_t)e;
+                n2e_i[s] = (uint8_t)i;
+            }
+    }
+
+    // ---- neighbour lists (a2): sorted unique nodes of the adjacent elements
+    std::vector<int64_t> deg(NN, 0);
+    std::vector<int64_t> nb_ptr(NN + 1, 0);
+    // first pass: degrees
+    parallel_for(NN, [&](int64_t a0, int64_t a1) {
+        std::vector<int32_t> buf;
+        for (int64_t n = a0; n < a1; n++) {
+            buf.clear();
+            for (int64_t s = n2e_ptr[n]; s < n2e_ptr[n + 1]; s++)
+                for (int j = 0; j < nen; j++) buf.push_back(cells[(int64_t)n2e_e[s] * nen + j]);
+            std::sort(buf.begin(), buf.end());
+            deg[n] = std::unique(buf.begin(), buf.end()) - buf.begin();
+        }
+    });
+    for (int64_t n = 0; n < NN; n++) nb_ptr[n + 1] = nb_ptr[n] + deg[n];
+    const int64_t nnz = nb_ptr[NN] * dim * dim;
+    if (nnz >= INT32_MAX) return SOPTX_E_OVERFLOW;
+    for (int64_t n = 0; n < NN; n++)
+        if (deg[n] > 65535) return SOPTX_E_OVERFLOW;
+    hp.nnz = nnz;
+    std::vector<int32_t> nb(nb_ptr[NN]);
+    parallel_for(NN, [&](int64_t a0, int64_t a1) {
+        std::vector<int32_t> buf;
+        for (int64_t n = a0; n < a1; n++) {
+            buf.clear();
+            for (int64_t s = n2e_ptr[n]; s < n2e_ptr[n + 1]; s++)
+                for (int j = 0; j < nen; j++) buf.push_back(cells[(int64_t)n2e_e[s] * nen + j]);
+            std::sort(buf.begin(), buf.end());
+            buf.erase(std::unique(buf.begin(), buf.end()), buf.end());
+            std::copy(buf.begin(), buf.end(), nb.begin() + nb_ptr[n]);
+        }
+    });
+
+    // ---- CSR: rows dim*n+a hold dim*J+b for J in nb(n) ascending, b ascending
+    hp.row_ptr.assign(hp.ndof + 1, 0);
+    for (int64_t n = 0; n < NN; n++)
+        for (int a = 0; a < dim; a++)
+            hp.row_ptr[dim * n + a + 1] = (int32_t)(dim * dim * nb_ptr[n] + (a + 1) * dim * deg[n]);
+    hp.col_idx.resize(nnz);
+    parallel_for(NN, [&](int64_t a0, int64_t a1) {
+        for (int64_t n = a0; n < a1; n++)
+            for (int a = 0; a < dim; a++) {
+                int64_t o = hp.row_ptr[dim * n + a];
+                for (int64_t k = nb_ptr[n]; k < nb_ptr[n + 1]; k++)
+                    for (int b = 0; b < dim; b++) hp.col_idx[o++] = (int32_t)(dim * nb[k] + b);
+            }
+    });
+
+    // ---- signatures and the backward position table
+    hp.pos.assign((size_t)NC * nen * nen, 0);
+    std::vector<int32_t> node_sig(NN, -1);
+    std::unordered_map<uint64_t, std::vector<int32_t>> sig_by_hash;
+    std::vector<std::vector<int32_t>> sigs;  // canonical vectors
+    const int64_t CH = 1 << 16;
+    for (int64_t c0 = 0; c0 < NN; c0 += CH) {
+        int64_t c1 = std::min(NN, c0 + CH);
+        std::vector<std::vector<int32_t>> sv(c1 - c0);
+        std::vector<uint64_t> hv(c1 - c0);
+        parallel_for(c1 - c0, [&](int64_t a0, int64_t a1) {
+            std::vector<std::array<int32_t, 4>> t;  // p, k, i, j
+            for (int64_t x = a0; x < a1; x++) {
+                int64_t n = c0 + x;
+                const int32_t *nbn = nb.data() + nb_ptr[n];
+                const int64_t dg = deg[n];
+                const int K = (int)(n2e_ptr[n + 1] - n2e_ptr[n]);
+                t.clear();
+                for (int k = 0; k < K; k++) {
+                    int64_t e = n2e_e[n2e_ptr[n] + k];
+                    int i = n2e_i[n2e_ptr[n] + k];
+                    for (int j = 0; j < nen; j++) {
+                        int32_t J = cells[e * nen + j];
+                        int p = (int)(std::lower_bound(nbn, nbn + dg, J) - nbn);
+                        t.push_back({p, k, i, j});
+                        hp.pos[((size_t)e * nen + i) * nen + j] = (uint16_t)p;
+                    }
+                }
+                std::sort(t.begin(), t.end());
+                std::vector<int32_t> &s = sv[x];
+                s.clear();
+                s.push_back(K);
+                s.push_back((int32_t)dg);
+                size_t q = 0;
+                for (int p = 0; p < dg; p++) {
+                    size_t q0 = q;
+                    while (q < t.size() && t[q][0] == p) q++;
+                    s.push_back((int32_t)(q - q0));
+                    for (size_t r = q0; r < q; r++) s.push_back((t[r][1] << 16) | (t[r][2] << 8) | t[r][3]);
+                }
+                uint64_t h = 1469598103934665603ull;
+                for (int32_t v : s) { h ^= (uint32_t)v; h *= 1099511628211ull; }
+                hv[x] = h;
+            }
+        });
+        for (int64_t x = 0; x < c1 - c0; x++) {
+            auto &cand = sig_by_hash[hv[x]];
+            int32_t id = -1;
+            for (int32_t c : cand)
+                if (sigs[c] == sv[x]) { id = c; break; }
+            if (id < 0) {
+                id = (int32_t)sigs.size();
+                sigs.push_back(sv[x]);
+                cand.push_back(id);
+            }
+            node_sig[c0 + x] = id;
+        }
+    }
+
+    // ---- signature tables
+    const int64_t nsig = (int64_t)sigs.size();
+    hp.sig_info.assign(nsig * 4, 0);
+    hp.sig_wave.assign(nsig * (kWaves + 1), 0);
+    hp.sig_pos_ptr.clear();
+    hp.sig_contrib.clear();
+    hp.kmax = 0;
+    for (int64_t s = 0; s < nsig; s++) {
+        const auto &v = sigs[s];
+        int K = v[0], dg = v[1];
+        hp.kmax = std::max(hp.kmax, K);
+        hp.sig_info[s * 4 + 0] = K;
+        hp.sig_info[s * 4 + 1] = dg;
+        hp.sig_info[s * 4 + 2] = (int32_t)hp.sig_pos_ptr.size();
+        hp.sig_info[s * 4 + 3] = (int32_t)(s * (kWaves + 1));
+        size_t q = 2;
+        std::vector<int> cnt(dg);
+        for (int p = 0; p < dg; p++) {
+            hp.sig_pos_ptr.push_back((int32_t)hp.sig_contrib.size());
+            int c = v[q++];
+            cnt[p] = c;
+            for (int r = 0; r < c; r++) hp.sig_contrib.push_back(v[q++]);
+        }
+        hp.sig_pos_ptr.push_back((int32_t)hp.sig_contrib.size());
+        // split positions among waves, balancing contribution work (a position
+        // costs about one contribution of overhead for its transform and stores)
+        double total = 0.0;
+        for (int p = 0; p < dg; p++) total += cnt[p] + 1.0;
+        double acc = 0.0;
+        int w = 1;
+        hp.sig_wave[s * (kWaves + 1) + 0] = 0;
+        for (int p = 0; p < dg && w < kWaves; p++) {
+            acc += cnt[p] + 1.0;
+            while (w < kWaves && acc >= total * w / kWaves) hp.sig_wave[s * (kWaves + 1) + w++] = p + 1;
+        }
+        while (w <= kWaves) hp.sig_wave[s * (kWaves + 1) + w++] = dg;
+    }
+    if (hp.sig_contrib.size() >= (size_t)INT32_MAX) return SOPTX_E_OVERFLOW;
+
+    // ---- groups: same-signature nodes in ascending order, up to 64 nodes and
+    // at most emax distinct elements each
+    hp.emax = std::max(384, hp.kmax);
+    if (hp.emax > 2048) return SOPTX_E_OVERFLOW;
+    struct Open { int32_t gid; std::vector<int32_t> nodes; std::vector<int32_t> elems; };
+    std::vector<Open> open(nsig);
+    for (auto &o : open) o.gid = -1;
+    std::vector<int32_t> mark(NC, -1);
+    int32_t next_gid = 0;
+    hp.grp_info.clear(); hp.grp_nodes.clear(); hp.grp_elems.clear(); hp.grp_n2l.clear();
+    auto flush = [&](int64_t s) {
+        Open &o = open[s];
+        if (o.nodes.empty()) return;
+        const int K = hp.sig_info[s * 4 + 0];
+        hp.grp_info.push_back((int32_t)s);
+        hp.grp_info.push_back((int32_t)o.nodes.size());
+        hp.grp_info.push_back((int32_t)hp.grp_elems.size());
+        hp.grp_info.push_back((int32_t)o.elems.size());
+        hp.grp_info.push_back((int32_t)hp.grp_n2l.size());
+        for (int l = 0; l < kGroupNodes; l++) hp.grp_nodes.push_back(l < (int)o.nodes.size() ? o.nodes[l] : -1);
+        // element slot lookup: elements were appended in order of first use
+        std::unordered_map<int32_t, uint16_t> slot;
+        for (size_t t = 0; t < o.elems.size(); t++) slot[o.elems[t]] = (uint16_t)t;
+        for (int32_t e : o.elems) hp.grp_elems.push_back(e);
+        for (int k = 0; k < K; k++)
+            for (int l = 0; l < kGroupNodes; l++) {
+                uint16_t v = 0;
+                if (l < (int)o.nodes.size()) v = slot[n2e_e[n2e_ptr[o.nodes[l]] + k]];
+                hp.grp_n2l.push_back(v);
+            }
+        o.nodes.clear();
+        o.elems.clear();
+        o.gid = -1;
+    };
+    for (int64_t n = 0; n < NN; n++) {
+        const int32_t s = node_sig[n];
+        if (hp.sig_info[s * 4 + 1] == 0) continue;  // isolated node: empty rows
+        Open &o = open[s];
+        if (o.gid < 0) o.gid = next_gid++;
+        // count new elements this node would add
+        int add = 0;
+        for (int64_t q = n2e_ptr[n]; q < n2e_ptr[n + 1]; q++) add += (mark[n2e_e[q]] != o.gid);
+        if ((int)o.elems.size() + add > hp.emax || (int)o.nodes.size() == kGroupNodes) {
+            flush(s);
+            o.gid = next_gid++;
+        }
+        o.nodes.push_back((int32_t)n);
+        for (int64_t q = n2e_ptr[n]; q < n2e_ptr[n + 1]; q++) {
+            int32_t e = n2e_e[q];
+            if (mark[e] != o.gid) { mark[e] = o.gid; o.elems.push_back(e); }
+        }
+    }
+    for (int64_t s = 0; s < nsig; s++) flush(s);
+    if (hp.grp_elems.size() >= (size_t)INT32_MAX || hp.grp_n2l.size() >= (size_t)INT32_MAX)
+        return SOPTX_E_OVERFLOW;
+    return SOPTX_OK;
+}
+
+}  // namespace soptx

@@ -1,0 +1,422 @@
+// C ABI of libsoptx: handle lifetime, argument validation, device uploads and
+// kernel dispatch.  Every numeric step runs in the HIP kernels of kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "../../include/soptx.h"
+#include "../../include/soptx_debug.h"
+#include "internal.h"
+#include "kernels.h"
+
+using namespace soptx;
+
+struct soptx_pattern_s {
+    int elem = 0, dim = 0, nen = 0, ref_method = 0, device = 0, nq = 0;
+    int64_t n_nodes = 0, n_cells = 0, ndof = 0, nnz = 0, ngroups = 0, nsig = 0;
+    int emax = 0, kmax = 0;
+    int32_t *row_ptr = nullptr, *col_idx = nullptr, *cells = nullptr;
+    double *geo = nullptr;
+    int32_t *grp_info = nullptr, *grp_nodes = nullptr, *grp_elems = nullptr;
+    uint16_t *grp_n2l = nullptr;
+    int32_t *sig_info = nullptr, *sig_pos_ptr = nullptr, *sig_contrib = nullptr, *sig_wave = nullptr;
+    uint16_t *pos = nullptr;
+    double *M = nullptr;
+    float *M32 = nullptr, *Mbf = nullptr;
+    double *qw = nullptr, *qgrad = nullptr, *cgrad = nullptr, *xref = nullptr;
+    float *qgrad32 = nullptr;
+    soptx_pattern_stats stats{};
+    std::vector<void *> allocs;
+};
+
+struct soptx_host_plan_s {
+    HostPlan hp;
+};
+
+namespace {
+
+// Per-(device, stream) scratch for the fixed-order reduction partials.  Work
+// on one stream is ordered, so one buffer per stream is race-free.
+struct Workspace {
+    double *buf = nullptr;
+    size_t n = 0;
+};
+std::mutex g_ws_mu;
+std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
+
+int get_workspace(int device, hipStream_t st, size_t n, double **out) {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    Workspace &w = g_ws[{device, st}];
+    if (w.n < n) {
+        if (w.buf) {
+            if (hipStreamSynchronize(st) != hipSuccess) return SOPTX_E_DEVICE;
+            (void)hipFree(w.buf);
+            w.buf = nullptr;
+            w.n = 0;
+        }
+        size_t cap = n < 4096 ? 4096 : n;
+        if (hipMalloc(&w.buf, cap * sizeof(double)) != hipSuccess) return SOPTX_E_OOM;
+        w.n = cap;
+    }
+    *out = w.buf;
+    return SOPTX_OK;
+}
+
+template <class T>
+int upload(soptx_pattern_s *h, const std::vector<T> &v, T **dst, hipStream_t st) {
+    *dst = nullptr;
+    if (v.empty()) return SOPTX_OK;
+    void *p = nullptr;
+    if (hipMalloc(&p, v.size() * sizeof(T)) != hipSuccess) return SOPTX_E_OOM;
+    h->allocs.push_back(p);
+    if (hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st) != hipSuccess)
+        return SOPTX_E_DEVICE;
+    *dst = static_cast<T *>(p);
+    h->stats.device_bytes += (int64_t)(v.size() * sizeof(T));
+    return SOPTX_OK;
+}
+
+void free_handle(soptx_pattern_s *h) {
+    if (!h) return;
+    for (void *p : h->allocs) (void)hipFree(p);
+    delete h;
+}
+
+int check_material(const soptx_material *m) {
+    if (!m) return SOPTX_E_INVALID_ARG;
+    if (!(m->E0 > m->Emin) || !(m->Emin >= 0.0) || !(m->nu > -1.0 && m->nu < 0.5) || !(m->p >= 1.0) ||
+        !std::isfinite(m->E0) || !std::isfinite(m->p))
+        return SOPTX_E_INVALID_ARG;
+    return SOPTX_OK;
+}
+
+// Lame constants at unit modulus; 2D plane stress uses lambda* = nu/(1-nu^2)
+void lame(const soptx_pattern_s *h, const soptx_material *m, double *lam, double *mu) {
+    const double nu = m->nu;
+    *mu = 1.0 / (2.0 * (1.0 + nu));
+    if (h->dim == 2 && !m->plane_strain) *lam = nu / (1.0 - nu * nu);
+    else *lam = nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+}
+
+int int_exponent(double p) {
+    if (p == std::floor(p) && p >= 0.0 && p <= 16.0) return (int)p;
+    return -1;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
+        if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+bool valid_prec(int32_t prec) { return prec == SOPTX_FP64 || prec == SOPTX_FP32 || prec == SOPTX_BF16_FP32ACC; }
+
+}  // namespace
+
+extern "C" {
+
+const char *soptx_status_string(int s) {
+    switch (s) {
+    case SOPTX_OK: return "ok";
+    case SOPTX_E_INVALID_ARG: return "invalid argument";
+    case SOPTX_E_UNSUPPORTED_ELEM: return "unsupported element type";
+    case SOPTX_E_BAD_MESH: return "bad mesh (node index out of range or repeated in a cell)";
+    case SOPTX_E_JACOBIAN: return "element with non-positive Jacobian determinant";
+    case SOPTX_E_NONAFFINE: return "element map is not affine";
+    case SOPTX_E_OVERFLOW: return "size exceeds the int32 index range";
+    case SOPTX_E_OOM: return "out of memory";
+    case SOPTX_E_DEVICE: return "HIP device or launch error";
+    default: return "unknown status";
+    }
+}
+
+int soptx_validate_mesh(const soptx_mesh *mesh) { return validate_mesh(mesh); }
+
+int soptx_reference_tensor(int32_t elem, int32_t ref_method, double *M_out) {
+    if (!M_out) return SOPTX_E_INVALID_ARG;
+    if (elem_dim(elem) < 0) return SOPTX_E_UNSUPPORTED_ELEM;
+    return reference_tensor(elem, ref_method, M_out);
+}
+
+int soptx_build_pattern_ex(const soptx_mesh *mesh, int32_t ref_method, soptx_pattern *out, void *stream) {
+    if (!out) return SOPTX_E_INVALID_ARG;
+    *out = nullptr;
+    if (ref_method != SOPTX_REF_SYMBOLIC && ref_method != SOPTX_REF_QUADRATURE) return SOPTX_E_INVALID_ARG;
+    HostPlan hp;
+    int rc;
+    try {
+        rc = build_host_plan(mesh, hp);
+    } catch (const std::bad_alloc &) {
+        return SOPTX_E_OOM;
+    } catch (...) {
+        return SOPTX_E_INVALID_ARG;
+    }
+    if (rc) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    soptx_pattern_s *h = new (std::nothrow) soptx_pattern_s();
+    if (!h) return SOPTX_E_OOM;
+    try {
+        h->elem = hp.elem; h->dim = hp.dim; h->nen = hp.nen; h->ref_method = ref_method;
+        h->n_nodes = hp.n_nodes; h->n_cells = hp.n_cells; h->ndof = hp.ndof; h->nnz = hp.nnz;
+        h->ngroups = hp.n_groups(); h->nsig = hp.n_sigs(); h->emax = hp.emax; h->kmax = hp.kmax;
+        if (hipGetDevice(&h->device) != hipSuccess) { free_handle(h); return SOPTX_E_DEVICE; }
+        // reference data
+        const int nen = hp.nen, dim = hp.dim;
+        std::vector<double> M((size_t)nen * nen * dim * dim);
+        rc = reference_tensor(hp.elem, ref_method, M.data());
+        if (rc) { free_handle(h); return rc; }
+        std::vector<float> M32(M.size()), Mbf(M.size());
+        for (size_t k = 0; k < M.size(); k++) {
+            M32[k] = (float)M[k];
+            uint32_t u;
+            std::memcpy(&u, &M32[k], 4);
+            u = (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u;  // round to nearest even bf16
+            std::memcpy(&Mbf[k], &u, 4);
+        }
+        std::vector<double> qw, qg;
+        rc = reference_qp_grads(hp.elem, qw, qg);
+        if (rc) { free_handle(h); return rc; }
+        h->nq = (int)qw.size();
+        std::vector<float> qg32(qg.begin(), qg.end());
+        // centroid gradients and reference node coordinates (rigid-motion removal)
+        std::vector<double> xref((size_t)nen * dim, 0.0), cg((size_t)nen * dim, 0.0);
+        {
+            static const int E[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+            for (int i = 0; i < nen; i++) {
+                if (hp.elem == SOPTX_QUAD4 || hp.elem == SOPTX_HEX8) {
+                    for (int m = 0; m < dim; m++) xref[i * dim + m] = corner_bit(hp.elem, i, m);
+                } else if (hp.elem == SOPTX_TRI3) {
+                    if (i > 0) xref[i * dim + i - 1] = 1.0;
+                } else {
+                    auto v = [&](int vv, int m) { return (vv > 0 && vv - 1 == m) ? 1.0 : 0.0; };
+                    for (int m = 0; m < 3; m++)
+                        xref[i * dim + m] = i < 4 ? v(i, m) : 0.5 * (v(E[i - 4][0], m) + v(E[i - 4][1], m));
+                }
+            }
+            // weighted mean of the quadrature-point gradients: the reference
+            // gradient at the centroid (the rules are symmetric and the
+            // gradients multilinear / affine)
+            double wsum = 0.0;
+            for (size_t q = 0; q < qw.size(); q++) wsum += qw[q];
+            for (size_t q = 0; q < qw.size(); q++)
+                for (int k = 0; k < nen * dim; k++) cg[k] += qw[q] / wsum * qg[q * nen * dim + k];
+        }
+        // pattern / plan uploads
+        std::vector<int32_t> cells(mesh->cells, mesh->cells + (size_t)mesh->n_cells * nen);
+        if ((rc = upload(h, hp.row_ptr, &h->row_ptr, st)) || (rc = upload(h, hp.col_idx, &h->col_idx, st)) ||
+            (rc = upload(h, cells, &h->cells, st)) || (rc = upload(h, hp.geo, &h->geo, st))) {
+            free_handle(h); return rc;
+        }
+        const int64_t base_bytes = h->stats.device_bytes;
+        if ((rc = upload(h, hp.grp_info, &h->grp_info, st)) || (rc = upload(h, hp.grp_nodes, &h->grp_nodes, st)) ||
+            (rc = upload(h, hp.grp_elems, &h->grp_elems, st)) || (rc = upload(h, hp.grp_n2l, &h->grp_n2l, st)) ||
+            (rc = upload(h, hp.sig_info, &h->sig_info, st)) || (rc = upload(h, hp.sig_pos_ptr, &h->sig_pos_ptr, st)) ||
+            (rc = upload(h, hp.sig_contrib, &h->sig_contrib, st)) || (rc = upload(h, hp.sig_wave, &h->sig_wave, st))) {
+            free_handle(h); return rc;
+        }
+        h->stats.plan_bytes = h->stats.device_bytes - base_bytes;
+        if ((rc = upload(h, hp.pos, &h->pos, st)) || (rc = upload(h, M, &h->M, st)) ||
+            (rc = upload(h, M32, &h->M32, st)) || (rc = upload(h, Mbf, &h->Mbf, st)) ||
+            (rc = upload(h, qw, &h->qw, st)) || (rc = upload(h, qg, &h->qgrad, st)) ||
+            (rc = upload(h, qg32, &h->qgrad32, st)) || (rc = upload(h, cg, &h->cgrad, st)) ||
+            (rc = upload(h, xref, &h->xref, st))) {
+            free_handle(h); return rc;
+        }
+        if (hipStreamSynchronize(st) != hipSuccess) { free_handle(h); return SOPTX_E_DEVICE; }
+        const int64_t ncontrib = hp.n_cells * (int64_t)nen * nen;
+        h->stats.ndof = hp.ndof; h->stats.nnz = hp.nnz; h->stats.n_cells = hp.n_cells; h->stats.n_nodes = hp.n_nodes;
+        h->stats.n_groups = h->ngroups; h->stats.n_signatures = h->nsig; h->stats.n_contributions = ncontrib;
+    } catch (const std::bad_alloc &) {
+        free_handle(h);
+        return SOPTX_E_OOM;
+    }
+    *out = h;
+    return SOPTX_OK;
+}
+
+int soptx_build_pattern(const soptx_mesh *mesh, soptx_pattern *out, void *stream) {
+    return soptx_build_pattern_ex(mesh, SOPTX_REF_SYMBOLIC, out, stream);
+}
+
+int soptx_pattern_info(soptx_pattern h, int64_t *ndof, int64_t *nnz, const int32_t **d_row_ptr,
+                       const int32_t **d_col_idx) {
+    if (!h) return SOPTX_E_INVALID_ARG;
+    if (ndof) *ndof = h->ndof;
+    if (nnz) *nnz = h->nnz;
+    if (d_row_ptr) *d_row_ptr = h->row_ptr;
+    if (d_col_idx) *d_col_idx = h->col_idx;
+    return SOPTX_OK;
+}
+
+int soptx_pattern_copy(soptx_pattern h, int32_t *h_row_ptr, int32_t *h_col_idx) {
+    if (!h) return SOPTX_E_INVALID_ARG;
+    DeviceGuard dg(h->device);
+    if (!dg.ok) return SOPTX_E_DEVICE;
+    if (h_row_ptr && hipMemcpy(h_row_ptr, h->row_ptr, sizeof(int32_t) * (h->ndof + 1), hipMemcpyDeviceToHost) != hipSuccess)
+        return SOPTX_E_DEVICE;
+    if (h_col_idx && h->nnz > 0 &&
+        hipMemcpy(h_col_idx, h->col_idx, sizeof(int32_t) * h->nnz, hipMemcpyDeviceToHost) != hipSuccess)
+        return SOPTX_E_DEVICE;
+    return SOPTX_OK;
+}
+
+int soptx_pattern_stats_get(soptx_pattern h, soptx_pattern_stats *out) {
+    if (!h || !out) return SOPTX_E_INVALID_ARG;
+    *out = h->stats;
+    return SOPTX_OK;
+}
+
+int soptx_assemble(soptx_pattern h, const soptx_material *m, const void *d_rho, const uint8_t *d_dirichlet,
+                   double *d_K_vals, int32_t prec, void *stream) {
+    if (!h || !valid_prec(prec)) return SOPTX_E_INVALID_ARG;
+    int rc = check_material(m);
+    if (rc) return rc;
+    if ((h->n_cells > 0 && !d_rho) || (h->nnz > 0 && !d_K_vals)) return SOPTX_E_INVALID_ARG;
+    if (h->nnz == 0) return SOPTX_OK;
+    DeviceGuard dg(h->device);
+    if (!dg.ok) return SOPTX_E_DEVICE;
+    AsmParams P{};
+    P.grp_info = h->grp_info; P.grp_nodes = h->grp_nodes; P.grp_elems = h->grp_elems; P.grp_n2l = h->grp_n2l;
+    P.sig_info = h->sig_info; P.sig_pos_ptr = h->sig_pos_ptr; P.sig_contrib = h->sig_contrib; P.sig_wave = h->sig_wave;
+    P.row_ptr = h->row_ptr; P.cells = h->cells; P.geo = h->geo; P.rho = d_rho; P.mask = d_dirichlet;
+    P.M = h->M; P.M32 = h->M32; P.Mbf = h->Mbf; P.K = d_K_vals;
+    P.n_cells = h->n_cells; P.E0 = m->E0; P.Emin = m->Emin; P.p = m->p; P.ip = int_exponent(m->p);
+    lame(h, m, &P.lam, &P.mu);
+    P.emax = h->emax; P.kmax = h->kmax;
+    if (launch_assemble(h->elem, prec, P, h->ngroups, static_cast<hipStream_t>(stream)) != hipSuccess)
+        return SOPTX_E_DEVICE;
+    return SOPTX_OK;
+}
+
+int soptx_evaluate(soptx_pattern h, const soptx_material *m, const void *d_rho, const double *d_u,
+                   const double *d_f, void *d_dc, double *d_c, int32_t prec, void *stream) {
+    if (!h || !valid_prec(prec)) return SOPTX_E_INVALID_ARG;
+    int rc = check_material(m);
+    if (rc) return rc;
+    if (h->n_cells > 0 && (!d_rho || !d_u)) return SOPTX_E_INVALID_ARG;
+    if (!d_dc && !d_c) return SOPTX_E_INVALID_ARG;
+    DeviceGuard dg(h->device);
+    if (!dg.ok) return SOPTX_E_DEVICE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int nblk = (int)((h->n_cells + 255) / 256);
+    const int ndot = 512;
+    double *ws = nullptr;
+    if (d_c) {
+        rc = get_workspace(h->device, st, (size_t)nblk + ndot + 1, &ws);
+        if (rc) return rc;
+    }
+    EnergyParams P{};
+    P.cells = h->cells; P.geo = h->geo; P.rho = d_rho; P.u = d_u;
+    P.qw = h->qw; P.qgrad = h->qgrad; P.qgrad32 = h->qgrad32; P.cgrad = h->cgrad; P.xref = h->xref;
+    P.dc = d_dc; P.partials = d_c ? ws : nullptr;
+    P.n_cells = h->n_cells; P.E0 = m->E0; P.Emin = m->Emin; P.p = m->p; P.ip = int_exponent(m->p);
+    lame(h, m, &P.lam, &P.mu);
+    if (launch_energy(h->elem, prec, P, st) != hipSuccess) return SOPTX_E_DEVICE;
+    if (d_c) {
+        double *p1 = nullptr;
+        if (d_f) {
+            p1 = ws + nblk;
+            if (launch_dot_partials(d_f, d_u, h->ndof, p1, ndot, st) != hipSuccess) return SOPTX_E_DEVICE;
+        }
+        if (launch_finalize(ws, nblk, p1, ndot, d_c, st) != hipSuccess) return SOPTX_E_DEVICE;
+    }
+    return SOPTX_OK;
+}
+
+int soptx_sensitivity(soptx_pattern h, const soptx_material *m, const void *d_rho, const double *d_u,
+                      void *d_dc, int32_t prec, void *stream) {
+    if (h && h->n_cells > 0 && !d_dc) return SOPTX_E_INVALID_ARG;
+    if (h && h->n_cells == 0) return (h && valid_prec(prec) && check_material(m) == 0) ? SOPTX_OK : SOPTX_E_INVALID_ARG;
+    return soptx_evaluate(h, m, d_rho, d_u, nullptr, d_dc, nullptr, prec, stream);
+}
+
+int soptx_compliance(soptx_pattern h, const soptx_material *m, const void *d_rho, const double *d_u,
+                     const double *d_f, double *d_c, int32_t prec, void *stream) {
+    if (!d_c) return SOPTX_E_INVALID_ARG;
+    return soptx_evaluate(h, m, d_rho, d_u, d_f, nullptr, d_c, prec, stream);
+}
+
+int soptx_assemble_backward(soptx_pattern h, const soptx_material *m, const void *d_rho,
+                            const uint8_t *d_dirichlet, const double *d_Kbar, void *d_drho, int32_t prec,
+                            void *stream) {
+    if (!h || !valid_prec(prec)) return SOPTX_E_INVALID_ARG;
+    int rc = check_material(m);
+    if (rc) return rc;
+    if (h->n_cells > 0 && (!d_rho || !d_Kbar || !d_drho)) return SOPTX_E_INVALID_ARG;
+    if (h->n_cells == 0) return SOPTX_OK;
+    DeviceGuard dg(h->device);
+    if (!dg.ok) return SOPTX_E_DEVICE;
+    BwdParams P{};
+    P.cells = h->cells; P.row_ptr = h->row_ptr; P.pos = h->pos; P.geo = h->geo; P.rho = d_rho;
+    P.Kbar = d_Kbar; P.M = h->M; P.M32 = h->M32; P.drho = d_drho; P.mask = d_dirichlet;
+    P.n_cells = h->n_cells; P.E0 = m->E0; P.Emin = m->Emin; P.p = m->p; P.ip = int_exponent(m->p);
+    lame(h, m, &P.lam, &P.mu);
+    if (launch_backward(h->elem, prec, P, static_cast<hipStream_t>(stream)) != hipSuccess) return SOPTX_E_DEVICE;
+    return SOPTX_OK;
+}
+
+void soptx_destroy_pattern(soptx_pattern h) {
+    if (!h) return;
+    DeviceGuard dg(h->device);
+    free_handle(h);
+}
+
+// ----------------------------------------------------------- host-only debug
+
+int soptx_debug_host_plan(const soptx_mesh *mesh, soptx_host_plan *out) {
+    if (!out) return SOPTX_E_INVALID_ARG;
+    *out = nullptr;
+    soptx_host_plan_s *p = new (std::nothrow) soptx_host_plan_s();
+    if (!p) return SOPTX_E_OOM;
+    int rc;
+    try {
+        rc = build_host_plan(mesh, p->hp);
+    } catch (...) {
+        rc = SOPTX_E_OOM;
+    }
+    if (rc) { delete p; return rc; }
+    *out = p;
+    return SOPTX_OK;
+}
+
+int soptx_debug_host_plan_array(soptx_host_plan p, const char *name, const void **data, int64_t *count,
+                                int32_t *elem_bytes) {
+    if (!p || !name || !data || !count || !elem_bytes) return SOPTX_E_INVALID_ARG;
+    const HostPlan &hp = p->hp;
+#define SOPTX_ARR(N)                                            \
+    if (std::strcmp(name, #N) == 0) {                           \
+        *data = hp.N.data();                                    \
+        *count = (int64_t)hp.N.size();                         \
+        *elem_bytes = (int32_t)sizeof(hp.N[0]);                 \
+        return SOPTX_OK;                                        \
+    }
+    SOPTX_ARR(row_ptr) SOPTX_ARR(col_idx) SOPTX_ARR(geo) SOPTX_ARR(sig_info) SOPTX_ARR(sig_pos_ptr)
+    SOPTX_ARR(sig_contrib) SOPTX_ARR(sig_wave) SOPTX_ARR(grp_info) SOPTX_ARR(grp_nodes) SOPTX_ARR(grp_elems)
+    SOPTX_ARR(grp_n2l) SOPTX_ARR(pos)
+#undef SOPTX_ARR
+    return SOPTX_E_INVALID_ARG;
+}
+
+int soptx_debug_host_plan_scalars(soptx_host_plan p, int64_t *out8) {
+    if (!p || !out8) return SOPTX_E_INVALID_ARG;
+    const HostPlan &hp = p->hp;
+    out8[0] = hp.ndof; out8[1] = hp.nnz; out8[2] = hp.n_groups(); out8[3] = hp.n_sigs();
+    out8[4] = hp.emax; out8[5] = hp.kmax; out8[6] = hp.dim; out8[7] = hp.nen;
+    return SOPTX_OK;
+}
+
+void soptx_debug_host_plan_free(soptx_host_plan p) { delete p; }
+
+}  // extern "C"

@@ -1,0 +1,245 @@
+"""CPU tests of the HIP library's host side (no device work).
+
+* the shared library loads and exports every function include/*.h declares;
+* mesh validation error paths;
+* the reference tensor against exact rational integrals (tests/exact_fe.py);
+* the host pattern is bit-identical to the oracle's set-based pattern;
+* the assembly plan is complete and consistent (every element-local pair
+  (e, i, j) lands exactly once, in the right row, column and order), and a
+  numpy model that walks the plan with the separated element formula matches
+  the oracle's standard-quadrature assembly.
+"""
+import ctypes
+import glob
+import os
+import re
+
+import numpy as np
+import pytest
+
+import exact_fe
+from oracle import oracle as O
+from paper_2505_02438_amd import _lib, api
+from paper_2505_02438_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ELEMS = [I.QUAD4, I.TRI3, I.HEX8, I.TET10]
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.lib()
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        txt = open(h).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        for m in re.finditer(r"\b(soptx_\w+)\s*\(", txt):
+            names.add(m.group(1))
+    assert len(names) >= 15
+    for n in sorted(names):
+        assert hasattr(L, n), n
+
+
+def test_status_strings():
+    L = _lib.lib()
+    for code in range(0, -9, -1):
+        assert L.soptx_status_string(code)
+    assert L.soptx_status_string(-99) == b"unknown status"
+
+
+def _bad(elem, coords, cells):
+    return api.validate_mesh(elem, coords, cells)
+
+
+def test_validation_error_codes():
+    m = I.quad_grid(3, 2)
+    assert _bad(m.elem, m.coords, m.cells) == 0
+    c = m.cells.copy()
+    c[1, 2] = m.n_nodes  # out of range
+    assert _bad(m.elem, m.coords, c) == -3
+    c = m.cells.copy()
+    c[1, 2] = c[1, 0]  # repeated node
+    assert _bad(m.elem, m.coords, c) == -3
+    c = m.cells[:, ::-1].copy()  # clockwise: inverted
+    assert _bad(m.elem, m.coords, c) == -4
+    x = m.coords.copy()
+    x[5] += [0.1, 0.05]  # interior node moved: quads no longer parallelograms
+    assert _bad(m.elem, x, m.cells) == -5
+    assert _bad(9, m.coords, m.cells) == -2
+    # hexes and P2 tets
+    h = I.hex_grid(2, 2, 2)
+    xh = h.coords.copy()
+    xh[13] += 0.1
+    assert _bad(h.elem, xh, h.cells) == -5
+    t = I.kuhn_p2_tets(2, 1, 1)
+    xt = t.coords.copy()
+    edge_node = t.cells[0, 5]
+    xt[edge_node] += 0.05  # curved edge
+    assert _bad(t.elem, xt, t.cells) == -5
+    # null pointers / wrong dim through the raw ABI
+    L = _lib.lib()
+    mesh = _lib.Mesh(I.QUAD4, 2, m.n_nodes, None, m.n_cells, None)
+    assert L.soptx_validate_mesh(ctypes.byref(mesh)) == -1
+    mesh = _lib.Mesh(I.QUAD4, 3, m.n_nodes, m.coords.ctypes.data, m.n_cells, m.cells.ctypes.data)
+    assert L.soptx_validate_mesh(ctypes.byref(mesh)) == -1
+    assert L.soptx_validate_mesh(None) == -1
+
+
+def test_per_call_argument_errors_without_device():
+    """Calls with a NULL handle or bad arguments fail before any device work."""
+    L = _lib.lib()
+    mat = _lib.Material(1.0, 1e-9, 0.3, 3.0, 0)
+    assert L.soptx_assemble(None, ctypes.byref(mat), None, None, None, 0, None) == -1
+    assert L.soptx_sensitivity(None, ctypes.byref(mat), None, None, None, 0, None) == -1
+    assert L.soptx_compliance(None, ctypes.byref(mat), None, None, None, None, 0, None) == -1
+    assert L.soptx_evaluate(None, ctypes.byref(mat), None, None, None, None, None, 0, None) == -1
+    assert L.soptx_assemble_backward(None, ctypes.byref(mat), None, None, None, None, 0, None) == -1
+    assert L.soptx_pattern_info(None, None, None, None, None) == -1
+    assert L.soptx_pattern_copy(None, None, None) == -1
+    L.soptx_destroy_pattern(None)
+    out = ctypes.c_void_p(1)
+    assert L.soptx_build_pattern_ex(None, 0, ctypes.byref(out), None) == -1
+    assert out.value is None
+    assert L.soptx_build_pattern_ex(None, 7, ctypes.byref(out), None) == -1
+
+
+@pytest.mark.parametrize("elem", ELEMS)
+def test_reference_tensor_symbolic_exact(elem):
+    ex = exact_fe.exact_ref_moments(elem)
+    exf = np.array([[[[float(ex[i][j][m][n]) for n in range(len(ex[0][0][0]))]
+                      for m in range(len(ex[0][0]))] for j in range(len(ex[0]))] for i in range(len(ex))])
+    M = api.reference_tensor(elem, api.REF_SYMBOLIC)
+    assert np.array_equal(M, exf)
+    Mq = api.reference_tensor(elem, api.REF_QUADRATURE)
+    assert np.max(np.abs(Mq - exf)) <= 8 * np.finfo(float).eps * np.max(np.abs(exf))
+
+
+@pytest.mark.parametrize("elem", ELEMS)
+@pytest.mark.parametrize("seed", [3, 4])
+def test_host_pattern_matches_oracle(elem, seed):
+    pr = I.small_problem(elem, seed=seed)
+    hp = api.host_plan(elem, pr.mesh.coords, pr.mesh.cells)
+    rp, ci = O.pattern(elem, pr.mesh.n_nodes, pr.mesh.cells)
+    assert np.array_equal(hp["row_ptr"], rp) and np.array_equal(hp["col_idx"], ci)
+
+
+def test_host_pattern_matches_oracle_configs():
+    for mesh in [I.quad_grid(60, 20), I.tri_grid(60, 20, jitter=0.2, rng=np.random.default_rng(1)),
+                 I.hex_grid(12, 4, 4), I.kuhn_p2_tets(4, 3, 3, jitter=0.15, rng=np.random.default_rng(2))]:
+        hp = api.host_plan(mesh.elem, mesh.coords, mesh.cells)
+        rp, ci = O.pattern(mesh.elem, mesh.n_nodes, mesh.cells)
+        assert np.array_equal(hp["row_ptr"], rp) and np.array_equal(hp["col_idx"], ci)
+
+
+def test_host_pattern_shuffled_mesh():
+    rng = np.random.default_rng(5)
+    m = I.kuhn_p2_tets(2, 2, 2, jitter=0.1, rng=rng)
+    perm = rng.permutation(m.n_nodes)
+    cells = perm[m.cells][rng.permutation(m.n_cells)].astype(np.int32)
+    coords = np.empty_like(m.coords)
+    coords[perm] = m.coords
+    hp = api.host_plan(m.elem, coords, cells)
+    rp, ci = O.pattern(m.elem, m.n_nodes, cells)
+    assert np.array_equal(hp["row_ptr"], rp) and np.array_equal(hp["col_idx"], ci)
+
+
+def _lame(dim, nu, plane_strain=0):
+    mu = 1.0 / (2.0 * (1.0 + nu))
+    lam = nu / (1.0 - nu * nu) if (dim == 2 and not plane_strain) else nu / ((1 + nu) * (1 - 2 * nu))
+    return lam, mu
+
+
+def walk_plan(hp, mesh, rho, M, E0=1.0, Emin=1e-9, p=3.0, nu=0.3, mask=None):
+    """Model of the assembly kernel's walk over the plan (numpy, FP64)."""
+    D, nen, NC = mesh.dim, mesh.nen, mesh.n_cells
+    cells = mesh.cells
+    geo = hp["geo"].reshape(D * D + 1, NC)
+    G = geo[: D * D].T.reshape(NC, D, D)
+    det = geo[D * D]
+    E = Emin + rho ** p * (E0 - Emin)
+    Gp = np.sqrt(E * det)[:, None, None] * G
+    lam, mu = _lame(D, nu)
+    rp, ci = hp["row_ptr"], hp["col_idx"]
+    K = np.full(hp["nnz"], np.nan)
+    seen = np.zeros((NC, nen, nen), dtype=np.int32)
+    gi = hp["grp_info"].reshape(-1, 5)
+    si = hp["sig_info"].reshape(-1, 4)
+    sw = hp["sig_wave"].reshape(-1, 5)
+    for g in range(gi.shape[0]):
+        sig, nn, eoff, ne, n2loff = gi[g]
+        Kk, deg, posoff, woff = si[sig]
+        assert sw[sig, 0] == 0 and sw[sig, -1] == deg and np.all(np.diff(sw[sig]) >= 0)
+        elems = hp["grp_elems"][eoff:eoff + ne]
+        assert ne <= hp["emax"]
+        n2l = hp["grp_n2l"][n2loff:n2loff + Kk * 64].reshape(Kk, 64)
+        for lane in range(nn):
+            Inode = hp["grp_nodes"][64 * g + lane]
+            base = rp[D * Inode]
+            rowlen = rp[D * Inode + 1] - base
+            assert rowlen == D * deg
+            prev_e = None
+            for pp in range(deg):
+                c0, c1 = hp["sig_pos_ptr"][posoff + pp], hp["sig_pos_ptr"][posoff + pp + 1]
+                acc = np.zeros((D, D))
+                last = -1
+                Jcol = ci[base + D * pp] // D
+                for t in range(c0, c1):
+                    pk = int(hp["sig_contrib"][t])
+                    k, i, j = pk >> 16, (pk >> 8) & 255, pk & 255
+                    e = elems[n2l[k, lane]]
+                    assert cells[e, i] == Inode and cells[e, j] == Jcol
+                    assert e > last  # ascending elements within a stored block
+                    last = e
+                    seen[e, i, j] += 1
+                    acc += Gp[e].T @ M[i, j] @ Gp[e]
+                out = lam * acc + mu * acc.T + mu * np.trace(acc) * np.eye(D)
+                if mask is not None:
+                    for a in range(D):
+                        for b in range(D):
+                            r, c = D * Inode + a, D * Jcol + b
+                            if mask[r] or mask[c]:
+                                out[a, b] = 1.0 if r == c else 0.0
+                for a in range(D):
+                    K[base + a * rowlen + D * pp: base + a * rowlen + D * pp + D] = out[a]
+    assert np.all(seen == 1), "every element-local pair must be assembled exactly once"
+    return K
+
+
+def row_scaled_err(rp, Kx, Kref):
+    """max over rows of max|dK| / max|Kref| in the row (structural cancellations kept)."""
+    n = rp.shape[0] - 1
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    den = np.zeros(n)
+    np.maximum.at(den, rows, np.abs(Kref))
+    num = np.zeros(n)
+    np.maximum.at(num, rows, np.abs(Kx - Kref))
+    ok = den > 0
+    return float(np.max(num[ok] / den[ok])) if ok.any() else 0.0
+
+
+@pytest.mark.parametrize("elem", ELEMS)
+@pytest.mark.parametrize("use_mask", [False, True])
+def test_plan_walk_model_matches_oracle(elem, use_mask):
+    pr = I.small_problem(elem, seed=6)
+    m = pr.mesh
+    hp = api.host_plan(elem, m.coords, m.cells)
+    M = api.reference_tensor(elem)
+    mask = pr.mask if use_mask else None
+    K = walk_plan(hp, m, pr.rho, M, mask=mask)
+    rp, ci = O.pattern(elem, m.n_nodes, m.cells)
+    Kref = O.assemble(elem, m.coords, m.cells, pr.rho, rp, ci, mask=mask)
+    assert not np.isnan(K).any()
+    assert row_scaled_err(rp, K, Kref) <= 1e-13
+
+
+def test_backward_position_table():
+    pr = I.small_problem(I.TET10, seed=2)
+    m = pr.mesh
+    hp = api.host_plan(m.elem, m.coords, m.cells)
+    pos = hp["pos"].reshape(m.n_cells, m.nen, m.nen)
+    rp, ci = hp["row_ptr"], hp["col_idx"]
+    D = m.dim
+    for e in range(m.n_cells):
+        for i in range(m.nen):
+            for j in range(m.nen):
+                Inode, Jnode = m.cells[e, i], m.cells[e, j]
+                assert ci[rp[D * Inode] + D * pos[e, i, j]] == D * Jnode
