@@ -10,8 +10,11 @@
 
 namespace soptx {
 
-constexpr int kGroupNodes = 64;   // nodes per assembly group = lanes of one wavefront
-constexpr int kWaves = 4;         // wavefronts per assembly workgroup
+constexpr int kGroupNodes = 64;    // nodes per assembly group = lanes of one wavefront
+constexpr int kWaves = 8;          // wavefronts per assembly workgroup
+constexpr int kGroupElems = 256;   // distinct elements per group (staged in LDS)
+constexpr int kMaxAdjacent = 32;   // elements around one node (the slot table is prefetched in registers)
+constexpr int kStageBytes = 124416;  // LDS for a group's row blocks (64 Q1-hex nodes x 243 values)
 constexpr int kMaxNen = 10;
 
 inline int elem_dim(int elem) {
@@ -53,18 +56,21 @@ struct HostPlan {
     std::vector<double> geo;       // [(dim*dim+1)][n_cells]: G[m][a] = d xi_m / d x_a, then det J
 
     // signatures
-    std::vector<int32_t> sig_info;     // [nsig][4]: K, deg, pos_off, wave_off
+    std::vector<int32_t> sig_info;     // [nsig][4]: K, deg, pos_off, blk (row-block doubles, odd)
     std::vector<int32_t> sig_pos_ptr;  // per signature deg+1 offsets into sig_contrib
     std::vector<int32_t> sig_contrib;  // (k << 16) | (i << 8) | j
-    std::vector<int32_t> sig_wave;     // [nsig][kWaves+1] position split among waves
+    std::vector<int32_t> sig_order;    // per signature deg positions, most contributions first, then -1
     // groups
     std::vector<int32_t> grp_info;   // [ngroups][5]: sig, n_nodes, elem_off, n_elem, n2l_off
     std::vector<int32_t> grp_nodes;  // [ngroups][64], -1 padded
     std::vector<int32_t> grp_elems;  // concatenated element ids, grp_info elem_off .. next
     std::vector<uint16_t> grp_n2l;   // per group K*64 (k-major): slot of element k of lane's node
+    std::vector<int32_t> grp_rows;   // [ngroups][64][2]: first CSR slot of the node's rows, row length
     // backward: position of cells[e][j] in the neighbour list of cells[e][i]
     std::vector<uint16_t> pos;       // [n_cells][nen][nen]
-    int kmax = 0, emax = 0;
+    int kmax = 0, emax = 0, ne_max = 0;  // emax: grouping limit; ne_max: largest group
+    int blk_max = 0;                     // largest padded row block (doubles)
+    int64_t stage_max = 0;               // largest group stage (doubles)
     int64_t n_groups() const { return (int64_t)grp_info.size() / 5; }
     int64_t n_sigs() const { return (int64_t)sig_info.size() / 4; }
 };

@@ -14,26 +14,28 @@ constexpr int kBF16 = SOPTX_BF16_FP32ACC;
 struct AsmParams {
     const int32_t *grp_info;    // [G][5]: sig, n_nodes, elem_off, n_elem, n2l_off
     const int32_t *grp_nodes;   // [G][64]
-    const int32_t *grp_elems;
-    const uint16_t *grp_n2l;
-    const int32_t *sig_info;    // [S][4]
+    const int32_t *grp_elems;   // per group, sorted element ids
+    const uint16_t *grp_n2l;    // per group [K][64]: slot of the lane's k-th element
+    const int32_t *grp_rows;    // [G][64][2]: first CSR slot of the node's rows, row length
+    const int32_t *sig_info;    // [S][4]: K, deg, pos_off, padded row-block size
     const int32_t *sig_pos_ptr;
     const int32_t *sig_contrib;
-    const int32_t *sig_wave;
-    const int32_t *row_ptr;
-    const int32_t *cells;
+    const int32_t *sig_order;   // per signature: positions in pick order
     const double *geo;
     const void *rho;
-    const uint8_t *mask;
     const double *M;
     const float *M32;
     const float *Mbf;
     double *K;
     int64_t n_cells;
+    int64_t n_groups;
+    int n_cu;
     double E0, Emin, p;
     int ip;          // integer exponent, or -1
     double lam, mu;  // Lame constants at unit modulus (plane-stress lambda* in 2D)
-    int emax, kmax;
+    int kmax;
+    int64_t stage;   // doubles of LDS stage needed by the largest group
+    int desync;      // start delay of odd workgroups, in units of s_sleep(127)
 };
 
 struct EnergyParams {
@@ -72,6 +74,8 @@ struct BwdParams {
 };
 
 hipError_t launch_assemble(int elem, int prec, const AsmParams &P, int64_t ngroups, hipStream_t st);
+hipError_t launch_dirichlet(int dim, const int32_t *row_ptr, const int32_t *col_idx, const uint8_t *mask,
+                            double *K, int64_t n_nodes, hipStream_t st);
 hipError_t launch_energy(int elem, int prec, const EnergyParams &P, hipStream_t st);
 hipError_t launch_dot_partials(const double *f, const double *u, int64_t n, double *partials, int nblocks,
                                hipStream_t st);

@@ -14,6 +14,7 @@
 // G' = sqrt(E |det J|) G) and L is applied once per stored block.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "internal.h"
@@ -56,159 +57,278 @@ template <> struct CT<kF64> { using T = double; };
 
 __device__ __forceinline__ int wave_uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// Reads of tables that no kernel writes (plan, reference tensor) through the
+// constant address space: at wave-uniform indices they become scalar loads
+// through the scalar cache, unaffected by the wave-level LDS fences.
+template <class T>
+__device__ __forceinline__ T ldc(const T *base, int64_t idx) {
+    return ((const __attribute__((address_space(4))) T *)(base))[idx];
+}
+__device__ __forceinline__ double ref_f64(const double *base, int idx) { return ldc(base, idx); }
+__device__ __forceinline__ float ref_f32(const float *base, int idx) { return ldc(base, idx); }
+
 }  // namespace
 
 // ------------------------------------------------------------------ assembly
 //
-// One workgroup = one group of up to 64 nodes sharing a connectivity
-// signature; lane l of every wave is node grp_nodes[g][l]; wave w stores the
-// neighbour positions [sig_wave[w], sig_wave[w+1]) of the row block of its
-// node.  Element data of the group (G' per element) is staged once in LDS.
-// Summation order of a stored block: the signature's contribution order
-// (elements ascending within the block), fixed by the mesh.
-template <int DIM, int NEN, int PREC>
-__global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
-    using T = typename CT<PREC>::T;
-    constexpr int D2 = DIM * DIM;
-    extern __shared__ __align__(16) unsigned char smem[];
-    T *sG = reinterpret_cast<T *>(smem);                          // [D2][emax]
-    int32_t *sgid = reinterpret_cast<int32_t *>(sG + D2 * P.emax);  // [emax]
-    uint16_t *sn2l = reinterpret_cast<uint16_t *>(sgid + P.emax);    // [kmax][64]
-
-    const int g = blockIdx.x;
-    const int sig = P.grp_info[5 * g + 0];
-    const int nn = P.grp_info[5 * g + 1];
-    const int eoff = P.grp_info[5 * g + 2];
-    const int ne = P.grp_info[5 * g + 3];
-    const int n2loff = P.grp_info[5 * g + 4];
-    const int K = P.sig_info[4 * sig + 0];
-    const int posoff = P.sig_info[4 * sig + 2];
-    const int woff = P.sig_info[4 * sig + 3];
-    const int tid = threadIdx.x;
-    const int64_t NC = P.n_cells;
-
-    for (int t = tid; t < ne; t += 256) {
-        const int e = P.grp_elems[eoff + t];
-        const double r = load_rho<PREC>(P.rho, e);
-        const double E = P.Emin + simp_pow(r, P.p, P.ip) * (P.E0 - P.Emin);
-        const double q = sqrt(E * P.geo[(int64_t)D2 * NC + e]);
-#pragma unroll
-        for (int c = 0; c < D2; c++) {
-            sG[c * P.emax + t] = (T)(q * P.geo[(int64_t)c * NC + e]);
-        }
-        sgid[t] = e;
-    }
-    for (int t = tid; t < K * 64; t += 256) sn2l[t] = P.grp_n2l[n2loff + t];
-    __syncthreads();
-
-    const int lane = tid & 63;
-    const int w = wave_uniform(tid >> 6);
-    if (lane >= nn) return;
-    const int I = P.grp_nodes[64 * g + lane];
-    const int base = P.row_ptr[DIM * I];
-    const int rowlen = P.row_ptr[DIM * I + 1] - base;
-    const int p0 = P.sig_wave[woff + w], p1 = P.sig_wave[woff + w + 1];
-
-    for (int p = p0; p < p1; p++) {
-        double acc[DIM][DIM];
+// acc += G'^T M_ij G' in the precision of the form (FP64 accumulation)
+template <int DIM, int PREC, typename T>
+__device__ __forceinline__ void accumulate(const T (&G)[DIM][DIM], const T (&M)[DIM * DIM], double (&acc)[DIM][DIM]) {
+    if (PREC == kBF16) {
+        // bf16 inputs, fp32 accumulation: A[a][b] = sum_mn M[m][n] W[m,a][n,b]
+        // with both GEMM operands rounded to bf16, W = G'[m][a] G'[n][b]
 #pragma unroll
         for (int a = 0; a < DIM; a++)
 #pragma unroll
-            for (int b = 0; b < DIM; b++) acc[a][b] = 0.0;
-        const int c0 = P.sig_pos_ptr[posoff + p], c1 = P.sig_pos_ptr[posoff + p + 1];
-        for (int t = c0; t < c1; t++) {
-            const int pk = P.sig_contrib[t];
-            const int k = pk >> 16, i = (pk >> 8) & 255, j = pk & 255;
-            const int le = sn2l[k * 64 + lane];
-            T G[DIM][DIM];
-#pragma unroll
-            for (int m = 0; m < DIM; m++)
-#pragma unroll
-                for (int a = 0; a < DIM; a++) G[m][a] = sG[(m * DIM + a) * P.emax + le];
-            const int mij = (i * NEN + j) * D2;
-            T Tm[DIM][DIM];
-            if (PREC == kF64) {
-                const double *Mij = P.M + mij;
+            for (int b = 0; b < DIM; b++) {
+                float s = 0.0f;
 #pragma unroll
                 for (int m = 0; m < DIM; m++)
 #pragma unroll
-                    for (int b = 0; b < DIM; b++) {
-                        double s = 0.0;
-#pragma unroll
-                        for (int n = 0; n < DIM; n++) s += Mij[m * DIM + n] * (double)G[n][b];
-                        Tm[m][b] = (T)s;
-                    }
-#pragma unroll
-                for (int a = 0; a < DIM; a++)
-#pragma unroll
-                    for (int b = 0; b < DIM; b++)
-#pragma unroll
-                        for (int m = 0; m < DIM; m++) acc[a][b] += (double)G[m][a] * (double)Tm[m][b];
-            } else if (PREC == kF32) {
-                const float *Mij = P.M32 + mij;
-#pragma unroll
-                for (int m = 0; m < DIM; m++)
-#pragma unroll
-                    for (int b = 0; b < DIM; b++) {
-                        float s = 0.0f;
-#pragma unroll
-                        for (int n = 0; n < DIM; n++) s += Mij[m * DIM + n] * (float)G[n][b];
-                        Tm[m][b] = s;
-                    }
-#pragma unroll
-                for (int a = 0; a < DIM; a++)
-#pragma unroll
-                    for (int b = 0; b < DIM; b++) {
-                        float s = 0.0f;
-#pragma unroll
-                        for (int m = 0; m < DIM; m++) s += (float)G[m][a] * (float)Tm[m][b];
-                        acc[a][b] += (double)s;
-                    }
-            } else {
-                // bf16 inputs, fp32 accumulation: A[a][b] = sum_mn M[m][n] W[m,a][n,b]
-                // with both GEMM operands rounded to bf16, W = G'[m][a] G'[n][b]
-                const float *Mij = P.Mbf + mij;
-#pragma unroll
-                for (int a = 0; a < DIM; a++)
-#pragma unroll
-                    for (int b = 0; b < DIM; b++) {
-                        float s = 0.0f;
-#pragma unroll
-                        for (int m = 0; m < DIM; m++)
-#pragma unroll
-                            for (int n = 0; n < DIM; n++)
-                                s += Mij[m * DIM + n] * bf16_round((float)G[m][a] * (float)G[n][b]);
-                        acc[a][b] += (double)s;
-                    }
+                    for (int n = 0; n < DIM; n++)
+                        s += (float)M[m * DIM + n] * bf16_round((float)G[m][a] * (float)G[n][b]);
+                acc[a][b] += (double)s;
             }
-        }
-        double tr = 0.0;
+        return;
+    }
+    T Tm[DIM][DIM];
 #pragma unroll
-        for (int a = 0; a < DIM; a++) tr += acc[a][a];
-        double out[DIM][DIM];
+    for (int m = 0; m < DIM; m++)
+#pragma unroll
+        for (int b = 0; b < DIM; b++) {
+            T s = 0;
+#pragma unroll
+            for (int n = 0; n < DIM; n++) s += M[m * DIM + n] * G[n][b];
+            Tm[m][b] = s;
+        }
+    if (PREC == kF64) {
 #pragma unroll
         for (int a = 0; a < DIM; a++)
 #pragma unroll
             for (int b = 0; b < DIM; b++)
-                out[a][b] = P.lam * acc[a][b] + P.mu * acc[b][a] + (a == b ? P.mu * tr : 0.0);
-        if (P.mask) {
-            // column node of this position: node j of the first contributing element
-            const int pk = P.sig_contrib[c0];
-            const int k = pk >> 16, j = pk & 255;
-            const int e = sgid[sn2l[k * 64 + lane]];
-            const int Jn = P.cells[(int64_t)e * NEN + j];
 #pragma unroll
-            for (int a = 0; a < DIM; a++)
-#pragma unroll
-                for (int b = 0; b < DIM; b++) {
-                    const int r = DIM * I + a, c = DIM * Jn + b;
-                    if (P.mask[r] | P.mask[c]) out[a][b] = (r == c) ? 1.0 : 0.0;
-                }
-        }
+                for (int m = 0; m < DIM; m++) acc[a][b] += (double)G[m][a] * (double)Tm[m][b];
+    } else {
 #pragma unroll
         for (int a = 0; a < DIM; a++)
 #pragma unroll
-            for (int b = 0; b < DIM; b++) P.K[base + a * rowlen + DIM * p + b] = out[a][b];
+            for (int b = 0; b < DIM; b++) {
+                T s = 0;
+#pragma unroll
+                for (int m = 0; m < DIM; m++) s += G[m][a] * Tm[m][b];
+                acc[a][b] += (double)s;
+            }
+    }
+}
+
+// G' of the element in LDS slot `slot` and the reference block M_ij
+template <int DIM, int NEN, int PREC, typename T>
+__device__ __forceinline__ void fetch_contrib(const AsmParams &P, const T *sG, int slot, int pk, T (&G)[DIM][DIM],
+                                              T (&M)[DIM * DIM]) {
+    constexpr int D2 = DIM * DIM;
+    const int i = (pk >> 8) & 255, j = pk & 255;
+#pragma unroll
+    for (int m = 0; m < DIM; m++)
+#pragma unroll
+        for (int a = 0; a < DIM; a++) G[m][a] = sG[(m * DIM + a) * kGroupElems + slot];
+    const int mij = (i * NEN + j) * D2;
+#pragma unroll
+    for (int x = 0; x < D2; x++) {
+        if (PREC == kF64) M[x] = (T)ref_f64(P.M, mij + x);
+        else if (PREC == kF32) M[x] = (T)ref_f32(P.M32, mij + x);
+        else M[x] = (T)ref_f32(P.Mbf, mij + x);
+    }
+}
+
+size_t assemble_lds_bytes(int dim, int prec, int64_t stage, int kmax) {
+    const size_t csz = prec == kF64 ? 8 : 4;
+    return 8 * (size_t)stage + csz * dim * dim * kGroupElems + 64 * 2 * 4 + 2 * (size_t)kmax * 64;
+}
+
+// Persistent assembly.  One workgroup of 8 waves per CU walks the node groups
+// blockIdx.x, blockIdx.x + gridDim.x, ...  For a group (up to 64 nodes with
+// one connectivity signature):
+//   1. its elements' G' = sqrt(E(rho) det J) J^-1 are staged in LDS (the data
+//      was loaded to registers while the previous group was assembled);
+//   2. waves take neighbour positions from a ticket; lane l = node l of the
+//      group walks the position's contributions (the same (k, i, j) on every
+//      lane, so M_ij comes through scalar loads) and writes its finished
+//      DIM x DIM block into the group's row blocks in LDS;
+//   3. every node's DIM rows (contiguous in CSR) are written out as one
+//      contiguous run; the stores drain while the next group is assembled.
+// Summation order of a stored block: the signature's contribution order
+// (ascending element within the block), then L(A) = lam A + mu A^T +
+// mu tr(A) I; fixed by the mesh, independent of waves and streams.
+constexpr int kAsmThreads = 1024;  // 16 waves share one group's LDS
+
+template <int DIM, int NEN, int PREC>
+__global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
+    using T = typename CT<PREC>::T;
+    constexpr int D2 = DIM * DIM;
+    constexpr int NT = kAsmThreads;
+    constexpr int NPF = (kMaxAdjacent * 64 + NT - 1) / NT;  // slot-table entries prefetched per thread
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *stage = reinterpret_cast<double *>(smem);                           // [P.stage]
+    T *sG = reinterpret_cast<T *>(stage + P.stage);                              // [D2][kGroupElems]
+    int32_t *srows = reinterpret_cast<int32_t *>(sG + D2 * kGroupElems);         // [64][2]
+    uint16_t *sn2l = reinterpret_cast<uint16_t *>(srows + 128);                  // [kmax][64]
+    __shared__ int ticket;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = wave_uniform(tid >> 6);
+    const int64_t NC = P.n_cells;
+
+    int g = blockIdx.x;
+    if (g >= P.n_groups) return;
+
+    // next group, prefetched to registers: one element per thread (geometry and
+    // density), the slot table and the row offsets
+    int pid;
+    double pd[D2 + 2];
+    int pn2l[NPF];
+    int prow;
+    auto load_ids = [&](int gg) {
+        const int eoff = ldc(P.grp_info, 5 * gg + 2);
+        const int ne = ldc(P.grp_info, 5 * gg + 3);
+        pid = tid < ne ? P.grp_elems[eoff + tid] : -1;
+        const int sg = ldc(P.grp_info, 5 * gg + 0);
+        const int off = ldc(P.grp_info, 5 * gg + 4);
+        const int nk = ldc(P.sig_info, 4 * sg + 0) * 64;
+#pragma unroll
+        for (int r = 0; r < NPF; r++) pn2l[r] = tid + r * NT < nk ? P.grp_n2l[off + tid + r * NT] : 0;
+        prow = tid < 128 ? P.grp_rows[(int64_t)gg * 128 + tid] : 0;
+    };
+    auto load_data = [&]() {
+        if (pid >= 0) {
+#pragma unroll
+            for (int c = 0; c <= D2; c++) pd[c] = P.geo[(int64_t)c * NC + pid];
+            pd[D2 + 1] = load_rho<PREC>(P.rho, pid);
+        }
+    };
+    auto write_group = [&](int gg) {
+        if (pid >= 0) {
+            const double E = P.Emin + simp_pow(pd[D2 + 1], P.p, P.ip) * (P.E0 - P.Emin);
+            const double q = sqrt(E * pd[D2]);
+#pragma unroll
+            for (int c = 0; c < D2; c++) sG[c * kGroupElems + tid] = (T)(q * pd[c]);
+        }
+        const int sg = ldc(P.grp_info, 5 * gg + 0);
+        const int nk = ldc(P.sig_info, 4 * sg + 0) * 64;
+#pragma unroll
+        for (int r = 0; r < NPF; r++)
+            if (tid + r * NT < nk) sn2l[tid + r * NT] = (uint16_t)pn2l[r];
+        if (tid < 128) srows[tid] = prow;
+        if (tid == 0) ticket = 0;
+    };
+
+    load_ids(g);
+    load_data();
+    write_group(g);
+    int gn = g + gridDim.x;
+    if (gn < P.n_groups) load_ids(gn);
+    // workgroups alternate between a compute phase and a store phase; odd
+    // ones start half a period late so that the device's stores are spread
+    // over time instead of arriving in waves
+    if (blockIdx.x & 1) {
+        for (int k = 0; k < P.desync; k++) __builtin_amdgcn_s_sleep(127);
+    }
+
+    for (;;) {
+        __syncthreads();  // LDS of group g complete; stage free
+        if (gn < P.n_groups) load_data();  // in flight while group g is assembled
+        const int sig = ldc(P.grp_info, 5 * g + 0);
+        const int nn = ldc(P.grp_info, 5 * g + 1);
+        const int deg = ldc(P.sig_info, 4 * sig + 1);
+        const int posoff = ldc(P.sig_info, 4 * sig + 2);
+        const int blk = ldc(P.sig_info, 4 * sig + 3);
+        const int rl = DIM * deg;  // row length
+        const bool active = lane < nn;
+        double *mystage = stage + lane * blk;
+
+        for (;;) {
+            int r = 0;
+            if (lane == 0) r = atomicAdd(&ticket, 1);
+            r = wave_uniform(r);
+            if (r >= deg) break;
+            const int p = ldc(P.sig_order, posoff + r);
+            const int c0 = ldc(P.sig_pos_ptr, posoff + p), c1 = ldc(P.sig_pos_ptr, posoff + p + 1);
+            double acc[DIM][DIM];
+#pragma unroll
+            for (int a = 0; a < DIM; a++)
+#pragma unroll
+                for (int b = 0; b < DIM; b++) acc[a][b] = 0.0;
+            for (int t = c0; t < c1; t += 2) {
+                // two contributions per round trip
+                const int pk0 = ldc(P.sig_contrib, t);
+                const bool two = t + 1 < c1;
+                const int pk1 = two ? ldc(P.sig_contrib, t + 1) : pk0;
+                const int s0 = sn2l[(pk0 >> 16) * 64 + lane];
+                const int s1 = sn2l[(pk1 >> 16) * 64 + lane];
+                T G0[DIM][DIM], G1[DIM][DIM], M0[D2], M1[D2];
+                fetch_contrib<DIM, NEN, PREC>(P, sG, s0, pk0, G0, M0);
+                fetch_contrib<DIM, NEN, PREC>(P, sG, s1, pk1, G1, M1);
+                accumulate<DIM, PREC>(G0, M0, acc);
+                if (two) accumulate<DIM, PREC>(G1, M1, acc);
+            }
+            double tr = 0.0;
+#pragma unroll
+            for (int a = 0; a < DIM; a++) tr += acc[a][a];
+            if (active) {
+#pragma unroll
+                for (int a = 0; a < DIM; a++)
+#pragma unroll
+                    for (int b = 0; b < DIM; b++) {
+                        double o = P.lam * acc[a][b] + P.mu * acc[b][a];
+                        if (a == b) o += P.mu * tr;
+                        mystage[a * rl + DIM * p + b] = o;
+                    }
+            }
+        }
+        __syncthreads();  // all row blocks of the group staged
+        // node n's DIM rows are contiguous in CSR: one run of DIM * rl values
+        const int bsz = DIM * rl;
+        for (int n = w; n < nn; n += NT / 64) {
+            const int base = srows[2 * n];
+            const double *src = stage + n * blk;
+            for (int o = lane; o < bsz; o += 64) P.K[base + o] = src[o];
+        }
+        __syncthreads();  // every stage value has been read
+        if (gn >= P.n_groups) break;
+        g = gn;
+        write_group(g);
+        gn = g + gridDim.x;
+        if (gn < P.n_groups) load_ids(gn);
+    }
+}
+
+// Dirichlet rows and columns (zero prescribed values): for every fixed dof r,
+// K[r,:] = 0, K[:,r] = 0, K[r,r] = 1, pattern unchanged.  Runs after the
+// assembly on the same stream.  16 lanes per node; entry (c, r) of a fixed
+// column is found by binary search in row c (the pattern is symmetric).
+template <int DIM>
+__global__ __launch_bounds__(256) void k_dirichlet(const int32_t *__restrict__ row_ptr,
+                                                   const int32_t *__restrict__ col_idx,
+                                                   const uint8_t *__restrict__ mask, double *K,
+                                                   int64_t n_nodes) {
+    const int64_t I = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+    const int l = threadIdx.x & 15;
+    if (I >= n_nodes) return;
+    for (int a = 0; a < DIM; a++) {
+        const int r = (int)(DIM * I + a);
+        if (!mask[r]) continue;
+        const int b0 = row_ptr[r], b1 = row_ptr[r + 1];
+        for (int k = b0 + l; k < b1; k += 16) {
+            const int c = col_idx[k];
+            K[k] = (c == r) ? 1.0 : 0.0;
+            // entry (c, r)
+            int lo = row_ptr[c], hi = row_ptr[c + 1] - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (col_idx[mid] < r) lo = mid + 1; else hi = mid;
+            }
+            K[lo] = (c == r) ? 1.0 : 0.0;
+        }
     }
 }
 
@@ -522,21 +642,30 @@ __global__ __launch_bounds__(256) void k_backward(BwdParams P) {
 // ---------------------------------------------------------------- launchers
 
 template <int DIM, int NEN, int PREC>
-static hipError_t launch_assemble_t(const AsmParams &P, int64_t ngroups, size_t lds, hipStream_t st) {
+static hipError_t launch_assemble_t(const AsmParams &P, int64_t ngroups, hipStream_t st) {
     if (ngroups <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_assemble<DIM, NEN, PREC>), dim3((unsigned)ngroups), dim3(256), lds, st, P);
+    const size_t lds = assemble_lds_bytes(DIM, PREC, P.stage, P.kmax);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    const void *fn = reinterpret_cast<const void *>(&k_assemble<DIM, NEN, PREC>);
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kAsmThreads, lds);
+    if (e != hipSuccess || per_cu < 1) per_cu = 1;
+    const int ncu = P.n_cu > 0 ? P.n_cu : 256;
+    const int64_t grid = std::min<int64_t>(ngroups, (int64_t)per_cu * ncu);
+    hipLaunchKernelGGL((k_assemble<DIM, NEN, PREC>), dim3((unsigned)grid), dim3(kAsmThreads), lds, st, P);
     return hipGetLastError();
 }
 
 hipError_t launch_assemble(int elem, int prec, const AsmParams &P, int64_t ngroups, hipStream_t st) {
-    const int dim = elem_dim(elem);
-    const size_t csz = prec == kF64 ? 8 : 4;
-    const size_t lds = csz * dim * dim * P.emax + 4 * (size_t)P.emax + 2 * (size_t)P.kmax * 64;
-#define SOPTX_ASM(E, D, N)                                                         \
-    case E:                                                                        \
-        if (prec == kF64) return launch_assemble_t<D, N, kF64>(P, ngroups, lds, st); \
-        if (prec == kF32) return launch_assemble_t<D, N, kF32>(P, ngroups, lds, st); \
-        return launch_assemble_t<D, N, kBF16>(P, ngroups, lds, st);
+#define SOPTX_ASM(E, D, N)                                                    \
+    case E:                                                                   \
+        if (prec == kF64) return launch_assemble_t<D, N, kF64>(P, ngroups, st); \
+        if (prec == kF32) return launch_assemble_t<D, N, kF32>(P, ngroups, st); \
+        return launch_assemble_t<D, N, kBF16>(P, ngroups, st);
     switch (elem) {
         SOPTX_ASM(SOPTX_QUAD4, 2, 4)
         SOPTX_ASM(SOPTX_TRI3, 2, 3)
@@ -571,6 +700,15 @@ hipError_t launch_energy(int elem, int prec, const EnergyParams &P, hipStream_t 
         return hipErrorInvalidValue;
     }
 #undef SOPTX_EN
+}
+
+hipError_t launch_dirichlet(int dim, const int32_t *row_ptr, const int32_t *col_idx, const uint8_t *mask,
+                            double *K, int64_t n_nodes, hipStream_t st) {
+    const unsigned nb = (unsigned)((n_nodes + 15) / 16);
+    if (nb == 0) return hipSuccess;
+    if (dim == 2) hipLaunchKernelGGL(k_dirichlet<2>, dim3(nb), dim3(256), 0, st, row_ptr, col_idx, mask, K, n_nodes);
+    else hipLaunchKernelGGL(k_dirichlet<3>, dim3(nb), dim3(256), 0, st, row_ptr, col_idx, mask, K, n_nodes);
+    return hipGetLastError();
 }
 
 hipError_t launch_dot_partials(const double *f, const double *u, int64_t n, double *partials, int nblocks,

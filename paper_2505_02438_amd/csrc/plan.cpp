@@ -7,6 +7,7 @@
 #include <cstring>
 #include <thread>
 #include <unordered_map>
+#include <unordered_set>
 
 #include "internal.h"
 
@@ -270,95 +271,109 @@ int build_host_plan(const soptx_mesh *mesh, HostPlan &hp) {
     // ---- signature tables
     const int64_t nsig = (int64_t)sigs.size();
     hp.sig_info.assign(nsig * 4, 0);
-    hp.sig_wave.assign(nsig * (kWaves + 1), 0);
     hp.sig_pos_ptr.clear();
     hp.sig_contrib.clear();
+    hp.sig_order.clear();
     hp.kmax = 0;
+    hp.blk_max = 0;
     for (int64_t s = 0; s < nsig; s++) {
         const auto &v = sigs[s];
-        int K = v[0], dg = v[1];
+        const int K = v[0], dg = v[1];
         hp.kmax = std::max(hp.kmax, K);
+        // a node's row block (dim rows of dim*deg values), padded to an odd
+        // number of doubles so that lanes (nodes) hit distinct LDS banks
+        int blk = dim * dim * dg;
+        if (blk % 2 == 0) blk += 1;
+        hp.blk_max = std::max(hp.blk_max, blk);
         hp.sig_info[s * 4 + 0] = K;
         hp.sig_info[s * 4 + 1] = dg;
         hp.sig_info[s * 4 + 2] = (int32_t)hp.sig_pos_ptr.size();
-        hp.sig_info[s * 4 + 3] = (int32_t)(s * (kWaves + 1));
+        hp.sig_info[s * 4 + 3] = blk;
         size_t q = 2;
-        std::vector<int> cnt(dg);
         for (int p = 0; p < dg; p++) {
             hp.sig_pos_ptr.push_back((int32_t)hp.sig_contrib.size());
-            int c = v[q++];
-            cnt[p] = c;
+            const int c = v[q++];
             for (int r = 0; r < c; r++) hp.sig_contrib.push_back(v[q++]);
         }
         hp.sig_pos_ptr.push_back((int32_t)hp.sig_contrib.size());
-        // split positions among waves, balancing contribution work (a position
-        // costs about one contribution of overhead for its transform and stores)
-        double total = 0.0;
-        for (int p = 0; p < dg; p++) total += cnt[p] + 1.0;
-        double acc = 0.0;
-        int w = 1;
-        hp.sig_wave[s * (kWaves + 1) + 0] = 0;
-        for (int p = 0; p < dg && w < kWaves; p++) {
-            acc += cnt[p] + 1.0;
-            while (w < kWaves && acc >= total * w / kWaves) hp.sig_wave[s * (kWaves + 1) + w++] = p + 1;
-        }
-        while (w <= kWaves) hp.sig_wave[s * (kWaves + 1) + w++] = dg;
+        // order in which the waves of a workgroup pick positions: costliest first
+        std::vector<int32_t> order(dg);
+        for (int p = 0; p < dg; p++) order[p] = p;
+        const int32_t *pp = hp.sig_pos_ptr.data() + hp.sig_info[s * 4 + 2];
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int32_t x, int32_t y) { return pp[x + 1] - pp[x] > pp[y + 1] - pp[y]; });
+        hp.sig_order.insert(hp.sig_order.end(), order.begin(), order.end());
+        hp.sig_order.push_back(-1);  // same stride as sig_pos_ptr (deg + 1 per signature)
     }
     if (hp.sig_contrib.size() >= (size_t)INT32_MAX) return SOPTX_E_OVERFLOW;
 
-    // ---- groups: same-signature nodes in ascending order, up to 64 nodes and
-    // at most emax distinct elements each
-    hp.emax = std::max(384, hp.kmax);
-    if (hp.emax > 2048) return SOPTX_E_OVERFLOW;
-    struct Open { int32_t gid; std::vector<int32_t> nodes; std::vector<int32_t> elems; };
+    // ---- groups: same-signature nodes in ascending order; at most 64 nodes,
+    // at most kGroupElems distinct elements, and the group's row blocks must
+    // fit the LDS stage of the assembly kernel
+    hp.emax = kGroupElems;
+    if (hp.kmax > kMaxAdjacent) return SOPTX_E_OVERFLOW;
+    if ((int64_t)hp.blk_max * 8 > kStageBytes) return SOPTX_E_OVERFLOW;
+    // one open group per signature; membership of its elements in a hash set
+    // (groups of different signatures share elements)
+    struct Open { std::vector<int32_t> nodes; std::vector<int32_t> elems; std::unordered_set<int32_t> in; };
     std::vector<Open> open(nsig);
-    for (auto &o : open) o.gid = -1;
-    std::vector<int32_t> mark(NC, -1);
-    int32_t next_gid = 0;
-    hp.grp_info.clear(); hp.grp_nodes.clear(); hp.grp_elems.clear(); hp.grp_n2l.clear();
+    hp.grp_info.clear(); hp.grp_nodes.clear(); hp.grp_elems.clear(); hp.grp_n2l.clear(); hp.grp_rows.clear();
+    hp.stage_max = 0;
     auto flush = [&](int64_t s) {
         Open &o = open[s];
         if (o.nodes.empty()) return;
         const int K = hp.sig_info[s * 4 + 0];
+        const int blk = hp.sig_info[s * 4 + 3];
+        hp.stage_max = std::max<int64_t>(hp.stage_max, (int64_t)o.nodes.size() * blk);
+        // elements sorted by id: for a fixed k, neighbouring lanes then read
+        // neighbouring LDS slots on structured meshes
+        std::sort(o.elems.begin(), o.elems.end());
         hp.grp_info.push_back((int32_t)s);
         hp.grp_info.push_back((int32_t)o.nodes.size());
         hp.grp_info.push_back((int32_t)hp.grp_elems.size());
         hp.grp_info.push_back((int32_t)o.elems.size());
         hp.grp_info.push_back((int32_t)hp.grp_n2l.size());
         for (int l = 0; l < kGroupNodes; l++) hp.grp_nodes.push_back(l < (int)o.nodes.size() ? o.nodes[l] : -1);
-        // element slot lookup: elements were appended in order of first use
-        std::unordered_map<int32_t, uint16_t> slot;
-        for (size_t t = 0; t < o.elems.size(); t++) slot[o.elems[t]] = (uint16_t)t;
         for (int32_t e : o.elems) hp.grp_elems.push_back(e);
         for (int k = 0; k < K; k++)
             for (int l = 0; l < kGroupNodes; l++) {
-                uint16_t v = 0;
-                if (l < (int)o.nodes.size()) v = slot[n2e_e[n2e_ptr[o.nodes[l]] + k]];
-                hp.grp_n2l.push_back(v);
+                const int ln = l < (int)o.nodes.size() ? l : 0;
+                const int32_t e = n2e_e[n2e_ptr[o.nodes[ln]] + k];
+                const int slot = (int)(std::lower_bound(o.elems.begin(), o.elems.end(), e) - o.elems.begin());
+                hp.grp_n2l.push_back((uint16_t)slot);
             }
+        for (int l = 0; l < kGroupNodes; l++) {
+            if (l < (int)o.nodes.size()) {
+                const int64_t n = o.nodes[l];
+                hp.grp_rows.push_back(hp.row_ptr[dim * n]);
+                hp.grp_rows.push_back(hp.row_ptr[dim * n + 1] - hp.row_ptr[dim * n]);
+            } else {
+                hp.grp_rows.push_back(0);
+                hp.grp_rows.push_back(0);
+            }
+        }
         o.nodes.clear();
         o.elems.clear();
-        o.gid = -1;
+        o.in.clear();
     };
     for (int64_t n = 0; n < NN; n++) {
         const int32_t s = node_sig[n];
         if (hp.sig_info[s * 4 + 1] == 0) continue;  // isolated node: empty rows
         Open &o = open[s];
-        if (o.gid < 0) o.gid = next_gid++;
+        const int ncap = (int)std::min<int64_t>(kGroupNodes, kStageBytes / (8 * (int64_t)hp.sig_info[s * 4 + 3]));
         // count new elements this node would add
         int add = 0;
-        for (int64_t q = n2e_ptr[n]; q < n2e_ptr[n + 1]; q++) add += (mark[n2e_e[q]] != o.gid);
-        if ((int)o.elems.size() + add > hp.emax || (int)o.nodes.size() == kGroupNodes) {
-            flush(s);
-            o.gid = next_gid++;
-        }
+        for (int64_t q = n2e_ptr[n]; q < n2e_ptr[n + 1]; q++) add += o.in.count(n2e_e[q]) ? 0 : 1;
+        if ((int)o.elems.size() + add > hp.emax || (int)o.nodes.size() >= ncap) flush(s);
         o.nodes.push_back((int32_t)n);
         for (int64_t q = n2e_ptr[n]; q < n2e_ptr[n + 1]; q++) {
-            int32_t e = n2e_e[q];
-            if (mark[e] != o.gid) { mark[e] = o.gid; o.elems.push_back(e); }
+            const int32_t e = n2e_e[q];
+            if (o.in.insert(e).second) o.elems.push_back(e);
         }
     }
     for (int64_t s = 0; s < nsig; s++) flush(s);
+    hp.ne_max = 0;
+    for (int64_t g = 0; g < hp.n_groups(); g++) hp.ne_max = std::max(hp.ne_max, hp.grp_info[5 * g + 3]);
     if (hp.grp_elems.size() >= (size_t)INT32_MAX || hp.grp_n2l.size() >= (size_t)INT32_MAX)
         return SOPTX_E_OVERFLOW;
     return SOPTX_OK;

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -20,11 +21,14 @@ struct soptx_pattern_s {
     int elem = 0, dim = 0, nen = 0, ref_method = 0, device = 0, nq = 0;
     int64_t n_nodes = 0, n_cells = 0, ndof = 0, nnz = 0, ngroups = 0, nsig = 0;
     int emax = 0, kmax = 0;
+    int64_t stage = 0;
     int32_t *row_ptr = nullptr, *col_idx = nullptr, *cells = nullptr;
     double *geo = nullptr;
     int32_t *grp_info = nullptr, *grp_nodes = nullptr, *grp_elems = nullptr;
     uint16_t *grp_n2l = nullptr;
-    int32_t *sig_info = nullptr, *sig_pos_ptr = nullptr, *sig_contrib = nullptr, *sig_wave = nullptr;
+    int32_t *grp_rows = nullptr;
+    int n_cu = 0;
+    int32_t *sig_info = nullptr, *sig_pos_ptr = nullptr, *sig_contrib = nullptr, *sig_order = nullptr;
     uint16_t *pos = nullptr;
     double *M = nullptr;
     float *M32 = nullptr, *Mbf = nullptr;
@@ -170,8 +174,10 @@ int soptx_build_pattern_ex(const soptx_mesh *mesh, int32_t ref_method, soptx_pat
     try {
         h->elem = hp.elem; h->dim = hp.dim; h->nen = hp.nen; h->ref_method = ref_method;
         h->n_nodes = hp.n_nodes; h->n_cells = hp.n_cells; h->ndof = hp.ndof; h->nnz = hp.nnz;
-        h->ngroups = hp.n_groups(); h->nsig = hp.n_sigs(); h->emax = hp.emax; h->kmax = hp.kmax;
+        h->ngroups = hp.n_groups(); h->nsig = hp.n_sigs(); h->emax = hp.ne_max; h->kmax = hp.kmax; h->stage = hp.stage_max;
         if (hipGetDevice(&h->device) != hipSuccess) { free_handle(h); return SOPTX_E_DEVICE; }
+        if (hipDeviceGetAttribute(&h->n_cu, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess)
+            h->n_cu = 0;
         // reference data
         const int nen = hp.nen, dim = hp.dim;
         std::vector<double> M((size_t)nen * nen * dim * dim);
@@ -222,8 +228,9 @@ int soptx_build_pattern_ex(const soptx_mesh *mesh, int32_t ref_method, soptx_pat
         const int64_t base_bytes = h->stats.device_bytes;
         if ((rc = upload(h, hp.grp_info, &h->grp_info, st)) || (rc = upload(h, hp.grp_nodes, &h->grp_nodes, st)) ||
             (rc = upload(h, hp.grp_elems, &h->grp_elems, st)) || (rc = upload(h, hp.grp_n2l, &h->grp_n2l, st)) ||
+            (rc = upload(h, hp.grp_rows, &h->grp_rows, st)) ||
             (rc = upload(h, hp.sig_info, &h->sig_info, st)) || (rc = upload(h, hp.sig_pos_ptr, &h->sig_pos_ptr, st)) ||
-            (rc = upload(h, hp.sig_contrib, &h->sig_contrib, st)) || (rc = upload(h, hp.sig_wave, &h->sig_wave, st))) {
+            (rc = upload(h, hp.sig_contrib, &h->sig_contrib, st)) || (rc = upload(h, hp.sig_order, &h->sig_order, st))) {
             free_handle(h); return rc;
         }
         h->stats.plan_bytes = h->stats.device_bytes - base_bytes;
@@ -289,13 +296,21 @@ int soptx_assemble(soptx_pattern h, const soptx_material *m, const void *d_rho, 
     if (!dg.ok) return SOPTX_E_DEVICE;
     AsmParams P{};
     P.grp_info = h->grp_info; P.grp_nodes = h->grp_nodes; P.grp_elems = h->grp_elems; P.grp_n2l = h->grp_n2l;
-    P.sig_info = h->sig_info; P.sig_pos_ptr = h->sig_pos_ptr; P.sig_contrib = h->sig_contrib; P.sig_wave = h->sig_wave;
-    P.row_ptr = h->row_ptr; P.cells = h->cells; P.geo = h->geo; P.rho = d_rho; P.mask = d_dirichlet;
+    P.grp_rows = h->grp_rows; P.n_groups = h->ngroups; P.n_cu = h->n_cu;
+    P.sig_info = h->sig_info; P.sig_pos_ptr = h->sig_pos_ptr; P.sig_contrib = h->sig_contrib;
+    P.sig_order = h->sig_order;
+    P.geo = h->geo; P.rho = d_rho;
     P.M = h->M; P.M32 = h->M32; P.Mbf = h->Mbf; P.K = d_K_vals;
     P.n_cells = h->n_cells; P.E0 = m->E0; P.Emin = m->Emin; P.p = m->p; P.ip = int_exponent(m->p);
     lame(h, m, &P.lam, &P.mu);
-    P.emax = h->emax; P.kmax = h->kmax;
-    if (launch_assemble(h->elem, prec, P, h->ngroups, static_cast<hipStream_t>(stream)) != hipSuccess)
+    P.kmax = h->kmax; P.stage = h->stage;
+    {
+        const char *ev = std::getenv("SOPTX_DESYNC");
+        P.desync = ev ? std::atoi(ev) : 0;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (launch_assemble(h->elem, prec, P, h->ngroups, st) != hipSuccess) return SOPTX_E_DEVICE;
+    if (d_dirichlet && launch_dirichlet(h->dim, h->row_ptr, h->col_idx, d_dirichlet, d_K_vals, h->n_nodes, st) != hipSuccess)
         return SOPTX_E_DEVICE;
     return SOPTX_OK;
 }
@@ -403,8 +418,8 @@ int soptx_debug_host_plan_array(soptx_host_plan p, const char *name, const void 
         return SOPTX_OK;                                        \
     }
     SOPTX_ARR(row_ptr) SOPTX_ARR(col_idx) SOPTX_ARR(geo) SOPTX_ARR(sig_info) SOPTX_ARR(sig_pos_ptr)
-    SOPTX_ARR(sig_contrib) SOPTX_ARR(sig_wave) SOPTX_ARR(grp_info) SOPTX_ARR(grp_nodes) SOPTX_ARR(grp_elems)
-    SOPTX_ARR(grp_n2l) SOPTX_ARR(pos)
+    SOPTX_ARR(sig_contrib) SOPTX_ARR(sig_order) SOPTX_ARR(grp_info) SOPTX_ARR(grp_nodes) SOPTX_ARR(grp_elems)
+    SOPTX_ARR(grp_n2l) SOPTX_ARR(grp_rows) SOPTX_ARR(pos)
 #undef SOPTX_ARR
     return SOPTX_E_INVALID_ARG;
 }

@@ -163,18 +163,22 @@ def walk_plan(hp, mesh, rho, M, E0=1.0, Emin=1e-9, p=3.0, nu=0.3, mask=None):
     seen = np.zeros((NC, nen, nen), dtype=np.int32)
     gi = hp["grp_info"].reshape(-1, 5)
     si = hp["sig_info"].reshape(-1, 4)
-    sw = hp["sig_wave"].reshape(-1, 5)
     for g in range(gi.shape[0]):
         sig, nn, eoff, ne, n2loff = gi[g]
-        Kk, deg, posoff, woff = si[sig]
-        assert sw[sig, 0] == 0 and sw[sig, -1] == deg and np.all(np.diff(sw[sig]) >= 0)
+        Kk, deg, posoff, blk = si[sig]
+        assert blk % 2 == 1 and blk >= D * D * deg
+        order = hp["sig_order"][posoff:posoff + deg + 1]
+        assert sorted(order[:deg]) == list(range(deg)) and order[deg] == -1
+        cnt = np.diff(hp["sig_pos_ptr"][posoff:posoff + deg + 1])
+        assert np.all(np.diff(cnt[order[:deg]]) <= 0)
         elems = hp["grp_elems"][eoff:eoff + ne]
-        assert ne <= hp["emax"]
+        assert ne <= hp["emax"] and np.all(np.diff(elems) > 0)
         n2l = hp["grp_n2l"][n2loff:n2loff + Kk * 64].reshape(Kk, 64)
         for lane in range(nn):
             Inode = hp["grp_nodes"][64 * g + lane]
             base = rp[D * Inode]
             rowlen = rp[D * Inode + 1] - base
+            assert hp["grp_rows"][128 * g + 2 * lane] == base and hp["grp_rows"][128 * g + 2 * lane + 1] == rowlen
             assert rowlen == D * deg
             prev_e = None
             for pp in range(deg):
