@@ -10,12 +10,15 @@
 
 namespace soptx {
 
-constexpr int kGroupNodes = 64;    // nodes per assembly group = lanes of one wavefront
-constexpr int kWaves = 8;          // wavefronts per assembly workgroup
-constexpr int kGroupElems = 256;   // distinct elements per group (staged in LDS)
-constexpr int kMaxAdjacent = 32;   // elements around one node (the slot table is prefetched in registers)
-constexpr int kStageBytes = 124416;  // LDS for a group's row blocks (64 Q1-hex nodes x 243 values)
+constexpr int kGroupNodes = 32;    // nodes per assembly group = lanes of half a wavefront
+constexpr int kGroupElems = 160;   // distinct elements per group (staged in LDS)
+constexpr int kMaxAdjacent = 32;   // elements around one node (slot table entries per node)
+constexpr int kStageBytes = 62208; // LDS for one group's row blocks (32 Q1-hex nodes x 243 values);
+                                   // the assembly kernel holds two
 constexpr int kMaxNen = 10;
+// fields per group in grp_info, and the flag bits of its last field
+constexpr int kGrpInfo = 6;
+constexpr int kGrpDiag = 1;  // every element of the group has a diagonal J^-1 (axis-aligned)
 
 inline int elem_dim(int elem) {
     switch (elem) {
@@ -45,9 +48,10 @@ int reference_qp_grads(int elem, std::vector<double> &wts, std::vector<double> &
 // number of adjacent elements K, number of neighbour nodes deg, and for each
 // neighbour position p the ordered list of (k, i, j) = (index of the element
 // in the node's ascending element list, local index of the node, local index
-// of the neighbour)) are packed into groups of up to 64.  One workgroup
-// assembles one group: lane = node, and every lane walks the same positions
-// and contributions, so the reference-tensor index (i, j) is wave-uniform.
+// of the neighbour)) are packed into groups of up to kGroupNodes.  The
+// assembly kernel gives each half of a wavefront one neighbour position of
+// the group's signature: lane = node within the half, and every lane of the
+// half walks the same contributions.
 struct HostPlan {
     int elem = 0, dim = 0, nen = 0;
     int64_t n_nodes = 0, n_cells = 0, ndof = 0, nnz = 0;
@@ -59,19 +63,19 @@ struct HostPlan {
     std::vector<int32_t> sig_info;     // [nsig][4]: K, deg, pos_off, blk (row-block doubles, odd)
     std::vector<int32_t> sig_pos_ptr;  // per signature deg+1 offsets into sig_contrib
     std::vector<int32_t> sig_contrib;  // (k << 16) | (i << 8) | j
-    std::vector<int32_t> sig_order;    // per signature deg positions, most contributions first, then -1
+    std::vector<int32_t> sig_pairs;    // per signature 2 (deg + 1) entries: work items (pa, pb), then -1
     // groups
-    std::vector<int32_t> grp_info;   // [ngroups][5]: sig, n_nodes, elem_off, n_elem, n2l_off
-    std::vector<int32_t> grp_nodes;  // [ngroups][64], -1 padded
+    std::vector<int32_t> grp_info;   // [ngroups][kGrpInfo]: sig, n_nodes, elem_off, n_elem, n2l_off, flags
+    std::vector<int32_t> grp_nodes;  // [ngroups][kGroupNodes], -1 padded
     std::vector<int32_t> grp_elems;  // concatenated element ids, grp_info elem_off .. next
-    std::vector<uint16_t> grp_n2l;   // per group K*64 (k-major): slot of element k of lane's node
-    std::vector<int32_t> grp_rows;   // [ngroups][64][2]: first CSR slot of the node's rows, row length
+    std::vector<uint16_t> grp_n2l;   // per group K*kGroupNodes (k-major): slot of element k of lane's node
+    std::vector<int32_t> grp_rows;   // [ngroups][kGroupNodes][2]: first CSR slot of the node's rows, row length
     // backward: position of cells[e][j] in the neighbour list of cells[e][i]
     std::vector<uint16_t> pos;       // [n_cells][nen][nen]
     int kmax = 0, emax = 0, ne_max = 0;  // emax: grouping limit; ne_max: largest group
     int blk_max = 0;                     // largest padded row block (doubles)
     int64_t stage_max = 0;               // largest group stage (doubles)
-    int64_t n_groups() const { return (int64_t)grp_info.size() / 5; }
+    int64_t n_groups() const { return (int64_t)grp_info.size() / kGrpInfo; }
     int64_t n_sigs() const { return (int64_t)sig_info.size() / 4; }
 };
 

@@ -12,7 +12,7 @@ constexpr int kF32 = SOPTX_FP32;
 constexpr int kBF16 = SOPTX_BF16_FP32ACC;
 
 struct AsmParams {
-    const int32_t *grp_info;    // [G][5]: sig, n_nodes, elem_off, n_elem, n2l_off
+    const int32_t *grp_info;    // [G][kGrpInfo]: sig, n_nodes, elem_off, n_elem, n2l_off, flags
     const int32_t *grp_nodes;   // [G][64]
     const int32_t *grp_elems;   // per group, sorted element ids
     const uint16_t *grp_n2l;    // per group [K][64]: slot of the lane's k-th element
@@ -20,7 +20,7 @@ struct AsmParams {
     const int32_t *sig_info;    // [S][4]: K, deg, pos_off, padded row-block size
     const int32_t *sig_pos_ptr;
     const int32_t *sig_contrib;
-    const int32_t *sig_order;   // per signature: positions in pick order
+    const int32_t *sig_pairs;   // per signature (offset 2 pos_off): work items (pa, pb), -1 terminated
     const double *geo;
     const void *rho;
     const double *M;
@@ -35,7 +35,6 @@ struct AsmParams {
     double lam, mu;  // Lame constants at unit modulus (plane-stress lambda* in 2D)
     int kmax;
     int64_t stage;   // doubles of LDS stage needed by the largest group
-    int desync;      // start delay of odd workgroups, in units of s_sleep(127)
 };
 
 struct EnergyParams {

@@ -14,8 +14,12 @@
 // G' = sqrt(E |det J|) G) and L is applied once per stored block.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <algorithm>
 #include <cstdint>
+#include <map>
+#include <mutex>
 
 #include "internal.h"
 #include "kernels.h"
@@ -24,13 +28,17 @@ namespace soptx {
 
 namespace {
 
+// kept out of line: inlined, its polynomial constants stay resident in VGPRs
+// across the callers' loops
+__device__ __noinline__ double pow_general(double x, double p) { return pow(x, p); }
+
 __device__ __forceinline__ double simp_pow(double x, double p, int ip) {
     if (ip >= 0) {
         double r = 1.0;
         for (int k = 0; k < ip; k++) r *= x;
         return r;
     }
-    return pow(x, p);
+    return pow_general(x, p);
 }
 
 template <int PREC>
@@ -121,184 +129,364 @@ __device__ __forceinline__ void accumulate(const T (&G)[DIM][DIM], const T (&M)[
     }
 }
 
-// G' of the element in LDS slot `slot` and the reference block M_ij
-template <int DIM, int NEN, int PREC, typename T>
-__device__ __forceinline__ void fetch_contrib(const AsmParams &P, const T *sG, int slot, int pk, T (&G)[DIM][DIM],
-                                              T (&M)[DIM * DIM]) {
-    constexpr int D2 = DIM * DIM;
-    const int i = (pk >> 8) & 255, j = pk & 255;
+// acc += G'^T M_ij G' for diagonal G': entry (a, b) is G'_aa G'_bb M_ij[a][b];
+// dd holds the products G'_aa G'_bb (bf16-rounded in the bf16 form)
+template <int DIM, int PREC, typename T>
+__device__ __forceinline__ void accumulate_diag(const T (&dd)[DIM][DIM], const T (&M)[DIM * DIM],
+                                                double (&acc)[DIM][DIM]) {
 #pragma unroll
-    for (int m = 0; m < DIM; m++)
+    for (int a = 0; a < DIM; a++)
 #pragma unroll
-        for (int a = 0; a < DIM; a++) G[m][a] = sG[(m * DIM + a) * kGroupElems + slot];
-    const int mij = (i * NEN + j) * D2;
-#pragma unroll
-    for (int x = 0; x < D2; x++) {
-        if (PREC == kF64) M[x] = (T)ref_f64(P.M, mij + x);
-        else if (PREC == kF32) M[x] = (T)ref_f32(P.M32, mij + x);
-        else M[x] = (T)ref_f32(P.Mbf, mij + x);
-    }
+        for (int b = 0; b < DIM; b++) {
+            if (PREC == kF64) acc[a][b] += (double)dd[a][b] * (double)M[a * DIM + b];
+            else acc[a][b] += (double)((float)dd[a][b] * (float)M[a * DIM + b]);
+        }
 }
 
-size_t assemble_lds_bytes(int dim, int prec, int64_t stage, int kmax) {
+static size_t assemble_lds_bytes(int dim, int nen, int prec, int64_t stage, int kmax) {
     const size_t csz = prec == kF64 ? 8 : 4;
-    return 8 * (size_t)stage + csz * dim * dim * kGroupElems + 64 * 2 * 4 + 2 * (size_t)kmax * 64;
+    return 2 * 8 * (size_t)stage + 2 * csz * dim * dim * kGroupElems + csz * nen * nen * dim * dim +
+           3 * kGroupNodes * 2 * 4 + 2 * 2 * (size_t)kmax * kGroupNodes;
 }
 
-// Persistent assembly.  One workgroup of 8 waves per CU walks the node groups
-// blockIdx.x, blockIdx.x + gridDim.x, ...  For a group (up to 64 nodes with
-// one connectivity signature):
-//   1. its elements' G' = sqrt(E(rho) det J) J^-1 are staged in LDS (the data
-//      was loaded to registers while the previous group was assembled);
-//   2. waves take neighbour positions from a ticket; lane l = node l of the
-//      group walks the position's contributions (the same (k, i, j) on every
-//      lane, so M_ij comes through scalar loads) and writes its finished
-//      DIM x DIM block into the group's row blocks in LDS;
-//   3. every node's DIM rows (contiguous in CSR) are written out as one
-//      contiguous run; the stores drain while the next group is assembled.
-// Summation order of a stored block: the signature's contribution order
-// (ascending element within the block), then L(A) = lam A + mu A^T +
-// mu tr(A) I; fixed by the mesh, independent of waves and streams.
-constexpr int kAsmThreads = 1024;  // 16 waves share one group's LDS
+// Persistent, warp-specialised assembly.  One workgroup of 16 waves per CU
+// walks the node groups g0 = blockIdx.x, g0 + gridDim.x, ...; in step s:
+//   - compute waves (0..7) assemble group s into LDS stage s&1: each takes a
+//     pair of neighbour positions of the group's signature from a ticket
+//     (costliest first); the low half of the wave walks the first position's
+//     contributions, the high half the second's, lane = node of the group;
+//     a finished DIM x DIM block goes to the node's row block in the stage;
+//   - store waves (8..11) write group s-1 from stage (s-1)&1: every node's
+//     DIM rows are contiguous in CSR and go out as one run.  They issue
+//     stores only and never wait for them, so the CU's stores stream while
+//     the next groups are computed;
+//   - load waves (12..15) load group s+1 (G' = sqrt(E(rho) det J) J^-1, or
+//     for an axis-aligned group the products G'_aa G'_bb, the slot table and
+//     the row offsets) into the other LDS buffers.  They load only, so their
+//     waits cover their own loads and none of the stores.
+// One workgroup barrier ends a step.  Summation order of a stored block: the
+// signature's contribution order (ascending element within the block), then
+// L(A) = lam A + mu A^T + mu tr(A) I; fixed by the mesh, independent of waves
+// and streams.
+constexpr int kAsmThreads = 1024;
+constexpr int kCompWaves = 8, kStoreWaves = 4, kLoadWaves = 4;
+static_assert(kCompWaves + kStoreWaves + kLoadWaves == kAsmThreads / 64, "wave roles");
+static_assert(2 * kGroupNodes == 64, "two positions per wavefront");
 
 template <int DIM, int NEN, int PREC>
 __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
     using T = typename CT<PREC>::T;
+    using R = typename std::conditional<PREC == kF64, double, float>::type;  // rho as stored
     constexpr int D2 = DIM * DIM;
-    constexpr int NT = kAsmThreads;
-    constexpr int NPF = (kMaxAdjacent * 64 + NT - 1) / NT;  // slot-table entries prefetched per thread
+    constexpr int NG = kGroupNodes;
+    constexpr int kLoadBase = (kCompWaves + kStoreWaves) * 64;
+    constexpr int kSetThreads = kLoadWaves / 2 * 64;  // threads of one load set
+    constexpr int NPF = (kMaxAdjacent * NG + kSetThreads - 1) / kSetThreads;  // slot entries per load thread
+    static_assert(kGroupElems <= 2 * kSetThreads, "two elements per load thread");
+    static_assert(2 * NG <= kSetThreads, "row offsets: one per load thread");
     extern __shared__ __align__(16) unsigned char smem[];
-    double *stage = reinterpret_cast<double *>(smem);                           // [P.stage]
-    T *sG = reinterpret_cast<T *>(stage + P.stage);                              // [D2][kGroupElems]
-    int32_t *srows = reinterpret_cast<int32_t *>(sG + D2 * kGroupElems);         // [64][2]
-    uint16_t *sn2l = reinterpret_cast<uint16_t *>(srows + 128);                  // [kmax][64]
-    __shared__ int ticket;
+    double *stage = reinterpret_cast<double *>(smem);                      // [2][P.stage]
+    T *sG = reinterpret_cast<T *>(stage + 2 * P.stage);                     // [2][D2][kGroupElems]
+    T *sM = sG + 2 * D2 * kGroupElems;                                      // [NEN][NEN][D2]
+    int32_t *srows = reinterpret_cast<int32_t *>(sM + NEN * NEN * D2);      // [3][NG][2]
+    uint16_t *sn2l = reinterpret_cast<uint16_t *>(srows + 3 * NG * 2);      // [2][kmax][NG]
+    __shared__ int ticket[2];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int w = wave_uniform(tid >> 6);
     const int64_t NC = P.n_cells;
+    const int ngr = P.n_groups;
+    const int stride = gridDim.x;
+    const int g0 = blockIdx.x;
+    if (g0 >= ngr) return;
+    const int nsteps = (ngr - 1 - g0) / stride + 2;  // groups of this workgroup, plus the last store step
+    const int n2l_stride = P.kmax * NG;
 
-    int g = blockIdx.x;
-    if (g >= P.n_groups) return;
-
-    // next group, prefetched to registers: one element per thread (geometry and
-    // density), the slot table and the row offsets
-    int pid;
-    double pd[D2 + 2];
-    int pn2l[NPF];
-    int prow;
-    auto load_ids = [&](int gg) {
-        const int eoff = ldc(P.grp_info, 5 * gg + 2);
-        const int ne = ldc(P.grp_info, 5 * gg + 3);
-        pid = tid < ne ? P.grp_elems[eoff + tid] : -1;
-        const int sg = ldc(P.grp_info, 5 * gg + 0);
-        const int off = ldc(P.grp_info, 5 * gg + 4);
-        const int nk = ldc(P.sig_info, 4 * sg + 0) * 64;
-#pragma unroll
-        for (int r = 0; r < NPF; r++) pn2l[r] = tid + r * NT < nk ? P.grp_n2l[off + tid + r * NT] : 0;
-        prow = tid < 128 ? P.grp_rows[(int64_t)gg * 128 + tid] : 0;
-    };
-    auto load_data = [&]() {
-        if (pid >= 0) {
-#pragma unroll
-            for (int c = 0; c <= D2; c++) pd[c] = P.geo[(int64_t)c * NC + pid];
-            pd[D2 + 1] = load_rho<PREC>(P.rho, pid);
-        }
-    };
-    auto write_group = [&](int gg) {
-        if (pid >= 0) {
-            const double E = P.Emin + simp_pow(pd[D2 + 1], P.p, P.ip) * (P.E0 - P.Emin);
-            const double q = sqrt(E * pd[D2]);
-#pragma unroll
-            for (int c = 0; c < D2; c++) sG[c * kGroupElems + tid] = (T)(q * pd[c]);
-        }
-        const int sg = ldc(P.grp_info, 5 * gg + 0);
-        const int nk = ldc(P.sig_info, 4 * sg + 0) * 64;
-#pragma unroll
-        for (int r = 0; r < NPF; r++)
-            if (tid + r * NT < nk) sn2l[tid + r * NT] = (uint16_t)pn2l[r];
-        if (tid < 128) srows[tid] = prow;
-        if (tid == 0) ticket = 0;
-    };
-
-    load_ids(g);
-    load_data();
-    write_group(g);
-    int gn = g + gridDim.x;
-    if (gn < P.n_groups) load_ids(gn);
-    // workgroups alternate between a compute phase and a store phase; odd
-    // ones start half a period late so that the device's stores are spread
-    // over time instead of arriving in waves
-    if (blockIdx.x & 1) {
-        for (int k = 0; k < P.desync; k++) __builtin_amdgcn_s_sleep(127);
+    for (int x = tid; x < NEN * NEN * D2; x += kAsmThreads) {
+        if (PREC == kF64) sM[x] = (T)P.M[x];
+        else if (PREC == kF32) sM[x] = (T)P.M32[x];
+        else sM[x] = (T)P.Mbf[x];
     }
 
-    for (;;) {
-        __syncthreads();  // LDS of group g complete; stage free
-        if (gn < P.n_groups) load_data();  // in flight while group g is assembled
-        const int sig = ldc(P.grp_info, 5 * g + 0);
-        const int nn = ldc(P.grp_info, 5 * g + 1);
+    // ---- load role: two sets of kLoadWaves / 2 waves; set x puts the groups
+    // of the steps of parity x and has two steps to bring each one in.  A
+    // thread handles elements lt and lt + kSetThreads of the group
+    const int lt = (tid - kLoadBase) & (kSetThreads - 1);
+    const int lset = (tid - kLoadBase) / kSetThreads;
+    struct Ids {
+        int e[2];
+    };
+    auto elem_id = [&](int gg) {
+        Ids r;
+        r.e[0] = r.e[1] = -1;
+        if (gg < ngr) {
+            const int eoff = ldc(P.grp_info, kGrpInfo * gg + 2);
+            const int ne = ldc(P.grp_info, kGrpInfo * gg + 3);
+#pragma unroll
+            for (int h = 0; h < 2; h++)
+                if (lt + h * kSetThreads < ne) r.e[h] = P.grp_elems[eoff + lt + h * kSetThreads];
+        }
+        return r;
+    };
+    struct LoadRegs {
+        double pd[2][D2 + 1];
+        R prho[2];
+        int pn2l[NPF];
+        int prow;
+    };
+    auto issue = [&](LoadRegs &q, int gg, const Ids &id) {
+        const int sg = ldc(P.grp_info, kGrpInfo * gg + 0);
+        const int off = ldc(P.grp_info, kGrpInfo * gg + 4);
+        const bool diag = ldc(P.grp_info, kGrpInfo * gg + 5) & kGrpDiag;
+        const int nk = ldc(P.sig_info, 4 * sg + 0) * NG;
+#pragma unroll
+        for (int h = 0; h < 2; h++)
+            if (id.e[h] >= 0) {
+                if (diag) {
+                    // axis-aligned: the diagonal of J^-1 and det J
+#pragma unroll
+                    for (int a = 0; a < DIM; a++) q.pd[h][a * DIM + a] = P.geo[(int64_t)(a * DIM + a) * NC + id.e[h]];
+                    q.pd[h][D2] = P.geo[(int64_t)D2 * NC + id.e[h]];
+                } else {
+#pragma unroll
+                    for (int c = 0; c <= D2; c++) q.pd[h][c] = P.geo[(int64_t)c * NC + id.e[h]];
+                }
+                q.prho[h] = static_cast<const R *>(P.rho)[id.e[h]];
+            }
+#pragma unroll
+        for (int r = 0; r < NPF; r++)
+            q.pn2l[r] = lt + r * kSetThreads < nk ? P.grp_n2l[off + lt + r * kSetThreads] : 0;
+        q.prow = lt < 2 * NG ? P.grp_rows[(int64_t)gg * 2 * NG + lt] : 0;
+    };
+    auto put = [&](const LoadRegs &q, int gg, int b, int rb) {
+        const int ne = ldc(P.grp_info, kGrpInfo * gg + 3);
+        const int flags = ldc(P.grp_info, kGrpInfo * gg + 5);
+        const int sg = ldc(P.grp_info, kGrpInfo * gg + 0);
+        const int nk = ldc(P.sig_info, 4 * sg + 0) * NG;
+        T *G = sG + b * D2 * kGroupElems;
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int slot = lt + h * kSetThreads;
+            if (slot < ne) {
+                const double E = P.Emin + simp_pow((double)q.prho[h], P.p, P.ip) * (P.E0 - P.Emin);
+                const double qq = sqrt(E * q.pd[h][D2]);
+                if (flags & kGrpDiag) {
+                    T d[DIM];
+#pragma unroll
+                    for (int a = 0; a < DIM; a++) d[a] = (T)(qq * q.pd[h][a * DIM + a]);
+#pragma unroll
+                    for (int a = 0; a < DIM; a++)
+#pragma unroll
+                        for (int c = 0; c < DIM; c++) {
+                            T v;
+                            if (PREC == kF64) v = d[a] * d[c];
+                            else if (PREC == kF32) v = (T)((float)d[a] * (float)d[c]);
+                            else v = (T)bf16_round((float)d[a] * (float)d[c]);
+                            G[(a * DIM + c) * kGroupElems + slot] = v;
+                        }
+                } else {
+#pragma unroll
+                    for (int c = 0; c < D2; c++) G[c * kGroupElems + slot] = (T)(qq * q.pd[h][c]);
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < NPF; r++)
+            if (lt + r * kSetThreads < nk) sn2l[b * n2l_stride + lt + r * kSetThreads] = (uint16_t)q.pn2l[r];
+        if (lt < 2 * NG) srows[rb * 2 * NG + lt] = q.prow;
+        if (lt == 0) ticket[b] = 0;
+    };
+
+    // ---- compute role: group gg from buffers b into stage b
+    auto compute_group = [&](int gg, int b) {
+        const int sig = ldc(P.grp_info, kGrpInfo * gg + 0);
+        const int nn = ldc(P.grp_info, kGrpInfo * gg + 1);
+        const bool diag = ldc(P.grp_info, kGrpInfo * gg + 5) & kGrpDiag;
         const int deg = ldc(P.sig_info, 4 * sig + 1);
         const int posoff = ldc(P.sig_info, 4 * sig + 2);
         const int blk = ldc(P.sig_info, 4 * sig + 3);
-        const int rl = DIM * deg;  // row length
-        const bool active = lane < nn;
-        double *mystage = stage + lane * blk;
-
+        const int rl = DIM * deg;
+        const bool hi = lane >= NG;
+        const int node = lane & (NG - 1);
+        double *st = stage + b * P.stage + node * blk;
+        const T *G = sG + b * D2 * kGroupElems;
+        const uint16_t *n2l = sn2l + b * n2l_stride + node;
         for (;;) {
             int r = 0;
-            if (lane == 0) r = atomicAdd(&ticket, 1);
+            if (lane == 0) r = atomicAdd(&ticket[b], 1);
             r = wave_uniform(r);
-            if (r >= deg) break;
-            const int p = ldc(P.sig_order, posoff + r);
-            const int c0 = ldc(P.sig_pos_ptr, posoff + p), c1 = ldc(P.sig_pos_ptr, posoff + p + 1);
+            // the signature's slice holds deg + 1 items, the last ones -1;
+            // late waves draw tickets past the end
+            if (r > deg) break;
+            const int pa = ldc(P.sig_pairs, 2 * posoff + 2 * r);
+            if (pa < 0) break;
+            const int pb = ldc(P.sig_pairs, 2 * posoff + 2 * r + 1);
+            const bool split = pb == pa;
+            const int c0 = ldc(P.sig_pos_ptr, posoff + pa);
+            const int na = ldc(P.sig_pos_ptr, posoff + pa + 1) - c0;
+            // contribution ranges of the two halves: [lo0, lo0 + nlo), [hi0, hi0 + nhi)
+            int lo0 = c0, nlo = na, hi0 = c0, nhi = 0;
+            if (split) {
+                nlo = (na + 1) / 2;
+                hi0 = c0 + nlo;
+                nhi = na - nlo;
+            } else if (pb >= 0) {
+                hi0 = ldc(P.sig_pos_ptr, posoff + pb);
+                nhi = ldc(P.sig_pos_ptr, posoff + pb + 1) - hi0;
+            }
+            const int mycnt = hi ? nhi : nlo;
             double acc[DIM][DIM];
 #pragma unroll
             for (int a = 0; a < DIM; a++)
 #pragma unroll
-                for (int b = 0; b < DIM; b++) acc[a][b] = 0.0;
-            for (int t = c0; t < c1; t += 2) {
-                // two contributions per round trip
-                const int pk0 = ldc(P.sig_contrib, t);
-                const bool two = t + 1 < c1;
-                const int pk1 = two ? ldc(P.sig_contrib, t + 1) : pk0;
-                const int s0 = sn2l[(pk0 >> 16) * 64 + lane];
-                const int s1 = sn2l[(pk1 >> 16) * 64 + lane];
-                T G0[DIM][DIM], G1[DIM][DIM], M0[D2], M1[D2];
-                fetch_contrib<DIM, NEN, PREC>(P, sG, s0, pk0, G0, M0);
-                fetch_contrib<DIM, NEN, PREC>(P, sG, s1, pk1, G1, M1);
-                accumulate<DIM, PREC>(G0, M0, acc);
-                if (two) accumulate<DIM, PREC>(G1, M1, acc);
+                for (int c = 0; c < DIM; c++) acc[a][c] = 0.0;
+            // nlo >= nhi: the low half has the longer list
+            for (int t = 0; t < nlo; t += 2) {
+                int pk[2];
+                bool ok[2];
+#pragma unroll
+                for (int u = 0; u < 2; u++) {
+                    const int tl = t + u < nlo ? t + u : nlo - 1;
+                    const int kl = ldc(P.sig_contrib, lo0 + tl);
+                    const int kh = nhi > 0 ? ldc(P.sig_contrib, hi0 + (t + u < nhi ? t + u : nhi - 1)) : kl;
+                    pk[u] = hi ? kh : kl;
+                    ok[u] = t + u < mycnt;
+                }
+#pragma unroll
+                for (int u = 0; u < 2; u++) {
+                    const int k = pk[u] >> 16, i = (pk[u] >> 8) & 255, j = pk[u] & 255;
+                    const int slot = n2l[k * NG];
+                    const T *Mij = sM + (i * NEN + j) * D2;
+                    T Mv[D2];
+#pragma unroll
+                    for (int x = 0; x < D2; x++) Mv[x] = Mij[x];
+                    if (diag) {
+                        T dd[DIM][DIM];
+#pragma unroll
+                        for (int a = 0; a < DIM; a++)
+#pragma unroll
+                            for (int c = a; c < DIM; c++) {
+                                dd[a][c] = G[(a * DIM + c) * kGroupElems + slot];
+                                dd[c][a] = dd[a][c];
+                            }
+                        if (ok[u]) accumulate_diag<DIM, PREC>(dd, Mv, acc);
+                    } else {
+                        T Gv[DIM][DIM];
+#pragma unroll
+                        for (int m = 0; m < DIM; m++)
+#pragma unroll
+                            for (int a = 0; a < DIM; a++) Gv[m][a] = G[(m * DIM + a) * kGroupElems + slot];
+                        if (ok[u]) accumulate<DIM, PREC>(Gv, Mv, acc);
+                    }
+                }
+            }
+            if (split) {
+                // low half's sum + high half's sum (the same in both halves:
+                // addition is commutative)
+#pragma unroll
+                for (int a = 0; a < DIM; a++)
+#pragma unroll
+                    for (int c = 0; c < DIM; c++) acc[a][c] += __shfl_xor(acc[a][c], NG);
             }
             double tr = 0.0;
 #pragma unroll
             for (int a = 0; a < DIM; a++) tr += acc[a][a];
-            if (active) {
+            const int p = hi ? pb : pa;
+            if (node < nn && p >= 0 && !(split && hi)) {
 #pragma unroll
                 for (int a = 0; a < DIM; a++)
 #pragma unroll
-                    for (int b = 0; b < DIM; b++) {
-                        double o = P.lam * acc[a][b] + P.mu * acc[b][a];
-                        if (a == b) o += P.mu * tr;
-                        mystage[a * rl + DIM * p + b] = o;
+                    for (int c = 0; c < DIM; c++) {
+                        double o = P.lam * acc[a][c] + P.mu * acc[c][a];
+                        if (a == c) o += P.mu * tr;
+                        st[a * rl + DIM * p + c] = o;
                     }
             }
         }
-        __syncthreads();  // all row blocks of the group staged
-        // node n's DIM rows are contiguous in CSR: one run of DIM * rl values
-        const int bsz = DIM * rl;
-        for (int n = w; n < nn; n += NT / 64) {
-            const int base = srows[2 * n];
-            const double *src = stage + n * blk;
-            for (int o = lane; o < bsz; o += 64) P.K[base + o] = src[o];
+    };
+
+    // ---- store role: group gg from stage b, row offsets rb.  Each store
+    // wave takes every kStoreWaves-th node, two nodes and four values per
+    // lane at a time, so that eight LDS reads are in flight per batch
+    auto store_group = [&](int gg, int b, int rb) {
+        const int sig = ldc(P.grp_info, kGrpInfo * gg + 0);
+        const int nn = ldc(P.grp_info, kGrpInfo * gg + 1);
+        const int deg = ldc(P.sig_info, 4 * sig + 1);
+        const int blk = ldc(P.sig_info, 4 * sig + 3);
+        const int bsz = DIM * DIM * deg;  // the node's DIM rows, contiguous in CSR
+        const int32_t *rows = srows + rb * 2 * NG;
+        const double *sb = stage + b * P.stage;
+        for (int n0 = w - kCompWaves; n0 < nn; n0 += 2 * kStoreWaves) {
+            const int n1 = n0 + kStoreWaves;
+            const bool two = n1 < nn;
+            const int base0 = rows[2 * n0];
+            const int base1 = two ? rows[2 * n1] : base0;
+            const double *s0 = sb + n0 * blk;
+            const double *s1 = sb + (two ? n1 : n0) * blk;
+            for (int o0 = lane; o0 < bsz; o0 += 4 * 64) {
+                double v0[4], v1[4];
+#pragma unroll
+                for (int c = 0; c < 4; c++) {
+                    const int o = o0 + 64 * c;
+                    v0[c] = o < bsz ? s0[o] : 0.0;
+                    v1[c] = o < bsz ? s1[o] : 0.0;
+                }
+#pragma unroll
+                for (int c = 0; c < 4; c++) {
+                    const int o = o0 + 64 * c;
+                    if (o < bsz) {
+                        P.K[base0 + o] = v0[c];
+                        if (two) P.K[base1 + o] = v1[c];
+                    }
+                }
+            }
         }
-        __syncthreads();  // every stage value has been read
-        if (gn >= P.n_groups) break;
-        g = gn;
-        write_group(g);
-        gn = g + gridDim.x;
-        if (gn < P.n_groups) load_ids(gn);
+    };
+
+    // Every wave runs nsteps + 1 barriers: one after the prologue, one per
+    // step.  The roles run separate loops so that a load in flight across a
+    // barrier on a load wave is no wait on another role's path.
+    if (w < kCompWaves) {
+        __syncthreads();
+        for (int s = 0; s < nsteps; s++) {
+            const int g = g0 + s * stride;
+            if (g < ngr) compute_group(g, s & 1);
+            __syncthreads();
+        }
+    } else if (w < kCompWaves + kStoreWaves) {
+        __syncthreads();
+        for (int s = 0; s < nsteps; s++) {
+            if (s > 0) store_group(g0 + (s - 1) * stride, (s - 1) & 1, (s - 1) % 3);
+            __syncthreads();
+        }
+    } else {
+        // group k stands for g0 + k stride.  Set 1 puts group 0 now; at step
+        // s, set s & 1 puts group s + 1 (loaded at step s - 2, or before the
+        // first barrier), issues the loads of group s + 3 and the element ids
+        // of group s + 5; the other set only meets the barrier
+        auto grp = [&](int k) { return g0 + k * stride; };
+        // the load waves' few loads go ahead of the store waves' stream
+        __builtin_amdgcn_s_setprio(3);
+        LoadRegs q;
+        Ids id;
+        if (lset == 1) {
+            const Ids i0 = elem_id(grp(0));
+            issue(q, grp(0), i0);
+            put(q, grp(0), 0, 0);
+        }
+        const int k1 = lset == 0 ? 1 : 2;  // first group this set brings in
+        if (grp(k1) < ngr) issue(q, grp(k1), elem_id(grp(k1)));
+        id = elem_id(grp(k1 + 2));
+        __syncthreads();
+        for (int s = 0; s < nsteps; s++) {
+            if ((s & 1) == lset && grp(s + 1) < ngr) {
+                put(q, grp(s + 1), (s + 1) & 1, (s + 1) % 3);
+                if (grp(s + 3) < ngr) issue(q, grp(s + 3), id);
+                id = elem_id(grp(s + 5));
+            }
+            __syncthreads();
+        }
     }
 }
 
@@ -644,16 +832,35 @@ __global__ __launch_bounds__(256) void k_backward(BwdParams P) {
 template <int DIM, int NEN, int PREC>
 static hipError_t launch_assemble_t(const AsmParams &P, int64_t ngroups, hipStream_t st) {
     if (ngroups <= 0) return hipSuccess;
-    const size_t lds = assemble_lds_bytes(DIM, PREC, P.stage, P.kmax);
-    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    const size_t lds = assemble_lds_bytes(DIM, NEN, PREC, P.stage, P.kmax);
+    if (lds + 64 > 160 * 1024) return hipErrorInvalidValue;  // dynamic + static LDS
     const void *fn = reinterpret_cast<const void *>(&k_assemble<DIM, NEN, PREC>);
-    if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-    }
+    // the dynamic LDS limit only grows (per device, to the largest size
+    // requested so far); the occupancy query runs once per device and size
+    static std::mutex mu;
+    static std::map<int, size_t> lds_limit;
+    static std::map<std::pair<int, size_t>, int> occupancy;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kAsmThreads, lds);
-    if (e != hipSuccess || per_cu < 1) per_cu = 1;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        size_t &lim = lds_limit[dev];
+        if (lds > lim) {
+            e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+            lim = lds;
+        }
+        auto it = occupancy.find({dev, lds});
+        if (it != occupancy.end()) {
+            per_cu = it->second;
+        } else {
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kAsmThreads, lds);
+            if (e != hipSuccess || per_cu < 1) per_cu = 1;
+            occupancy[{dev, lds}] = per_cu;
+        }
+    }
     const int ncu = P.n_cu > 0 ? P.n_cu : 256;
     const int64_t grid = std::min<int64_t>(ngroups, (int64_t)per_cu * ncu);
     hipLaunchKernelGGL((k_assemble<DIM, NEN, PREC>), dim3((unsigned)grid), dim3(kAsmThreads), lds, st, P);

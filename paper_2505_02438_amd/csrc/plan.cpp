@@ -273,7 +273,7 @@ int build_host_plan(const soptx_mesh *mesh, HostPlan &hp) {
     hp.sig_info.assign(nsig * 4, 0);
     hp.sig_pos_ptr.clear();
     hp.sig_contrib.clear();
-    hp.sig_order.clear();
+    hp.sig_pairs.clear();
     hp.kmax = 0;
     hp.blk_max = 0;
     for (int64_t s = 0; s < nsig; s++) {
@@ -296,18 +296,44 @@ int build_host_plan(const soptx_mesh *mesh, HostPlan &hp) {
             for (int r = 0; r < c; r++) hp.sig_contrib.push_back(v[q++]);
         }
         hp.sig_pos_ptr.push_back((int32_t)hp.sig_contrib.size());
-        // order in which the waves of a workgroup pick positions: costliest first
+        // work items of the assembly kernel, one per wavefront (two halves):
+        // a pair of positions (pa, pb), pb = -1 for a lone position, or a
+        // position split between the halves (pb == pa).  Positions of
+        // similar cost are paired; one that costs more than twice the next is
+        // split.  Items are picked costliest first.
+        const int32_t *pp = hp.sig_pos_ptr.data() + hp.sig_info[s * 4 + 2];
+        auto cnt = [&](int p) { return pp[p + 1] - pp[p]; };
         std::vector<int32_t> order(dg);
         for (int p = 0; p < dg; p++) order[p] = p;
-        const int32_t *pp = hp.sig_pos_ptr.data() + hp.sig_info[s * 4 + 2];
-        std::stable_sort(order.begin(), order.end(),
-                         [&](int32_t x, int32_t y) { return pp[x + 1] - pp[x] > pp[y + 1] - pp[y]; });
-        hp.sig_order.insert(hp.sig_order.end(), order.begin(), order.end());
-        hp.sig_order.push_back(-1);  // same stride as sig_pos_ptr (deg + 1 per signature)
+        std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return cnt(x) > cnt(y); });
+        std::vector<std::array<int32_t, 3>> items;  // cost, pa, pb
+        for (int i = 0; i < dg;) {
+            const int p = order[i], c = cnt(p);
+            if (i + 1 < dg && 2 * cnt(order[i + 1]) > c) {
+                items.push_back({c, p, order[i + 1]});
+                i += 2;
+            } else if (c >= 2) {
+                items.push_back({(c + 1) / 2, p, p});
+                i += 1;
+            } else {
+                items.push_back({c, p, -1});
+                i += 1;
+            }
+        }
+        std::stable_sort(items.begin(), items.end(), [](const auto &x, const auto &y) { return x[0] > y[0]; });
+        // 2 (deg + 1) entries per signature (offset 2 pos_off), -1 after the last item
+        for (const auto &it : items) {
+            hp.sig_pairs.push_back(it[1]);
+            hp.sig_pairs.push_back(it[2]);
+        }
+        for (size_t k = items.size(); k < (size_t)dg + 1; k++) {
+            hp.sig_pairs.push_back(-1);
+            hp.sig_pairs.push_back(-1);
+        }
     }
     if (hp.sig_contrib.size() >= (size_t)INT32_MAX) return SOPTX_E_OVERFLOW;
 
-    // ---- groups: same-signature nodes in ascending order; at most 64 nodes,
+    // ---- groups: same-signature nodes in ascending order; at most kGroupNodes nodes,
     // at most kGroupElems distinct elements, and the group's row blocks must
     // fit the LDS stage of the assembly kernel
     hp.emax = kGroupElems;
@@ -333,6 +359,14 @@ int build_host_plan(const soptx_mesh *mesh, HostPlan &hp) {
         hp.grp_info.push_back((int32_t)hp.grp_elems.size());
         hp.grp_info.push_back((int32_t)o.elems.size());
         hp.grp_info.push_back((int32_t)hp.grp_n2l.size());
+        // axis-aligned elements (off-diagonal entries of J^-1 exactly zero)
+        // let the kernel form G'^T M G' from the diagonal alone
+        bool diag = true;
+        for (int32_t e : o.elems)
+            for (int m = 0; m < dim && diag; m++)
+                for (int a = 0; a < dim; a++)
+                    if (m != a && hp.geo[(size_t)(m * dim + a) * NC + e] != 0.0) { diag = false; break; }
+        hp.grp_info.push_back(diag ? kGrpDiag : 0);
         for (int l = 0; l < kGroupNodes; l++) hp.grp_nodes.push_back(l < (int)o.nodes.size() ? o.nodes[l] : -1);
         for (int32_t e : o.elems) hp.grp_elems.push_back(e);
         for (int k = 0; k < K; k++)
@@ -373,7 +407,7 @@ int build_host_plan(const soptx_mesh *mesh, HostPlan &hp) {
     }
     for (int64_t s = 0; s < nsig; s++) flush(s);
     hp.ne_max = 0;
-    for (int64_t g = 0; g < hp.n_groups(); g++) hp.ne_max = std::max(hp.ne_max, hp.grp_info[5 * g + 3]);
+    for (int64_t g = 0; g < hp.n_groups(); g++) hp.ne_max = std::max(hp.ne_max, hp.grp_info[kGrpInfo * g + 3]);
     if (hp.grp_elems.size() >= (size_t)INT32_MAX || hp.grp_n2l.size() >= (size_t)INT32_MAX)
         return SOPTX_E_OVERFLOW;
     return SOPTX_OK;

@@ -132,6 +132,28 @@ _PERMS = [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]
 _EDGES = [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]
 
 
+def skew_mesh(mesh: Mesh, kind: str) -> Mesh:
+    """Coordinate maps that keep every Q1 element affine.
+
+    'global': x -> A x with one fixed well-conditioned A (all Jacobians full).
+    'kink': the last coordinate sheared by 0.4 (x0 - x_mid)_+, x_mid a grid
+    plane, so elements left of it keep diagonal Jacobians and those right of
+    it do not (a mesh with both kinds of element groups).
+    """
+    x = mesh.coords.copy()
+    d = x.shape[1]
+    if kind == "global":
+        A = np.array([[1.0, 0.3, 0.1], [-0.2, 1.0, 0.25], [0.15, -0.1, 1.0]])[:d, :d]
+        x = x @ A.T
+    elif kind == "kink":
+        xs = np.unique(x[:, 0])
+        xm = xs[len(xs) // 2]
+        x[:, d - 1] += 0.4 * np.maximum(x[:, 0] - xm, 0.0)
+    else:
+        raise ValueError(kind)
+    return Mesh(mesh.elem, x, mesh.cells)
+
+
 def _perm_sign(p):
     s = 1
     p = list(p)
@@ -287,14 +309,19 @@ def cantilever_tri(nx: int = 600, ny: int = 200, seed: int = 1002) -> Problem:
     return Problem(f"cantilever_tri_{nx}x{ny}", mesh, rho, mask, f, u)
 
 
-def cantilever_hex(nx: int = 120, ny: int = 40, nz: int = 40, seed: int = 1003) -> Problem:
-    """3D cantilever of unit Q1 hexes, rho ~ Beta(2, 2), synthetic u."""
+def cantilever_hex(nx: int = 120, ny: int = 40, nz: int = 40, seed: int = 1003,
+                   skew: Optional[str] = None) -> Problem:
+    """3D cantilever of unit Q1 hexes, rho ~ Beta(2, 2), synthetic u.
+
+    skew maps the coordinates after the supports are chosen (skew_mesh)."""
     rng = np.random.default_rng(seed)
     mesh = hex_grid(nx, ny, nz)
     rho = rng.beta(2.0, 2.0, mesh.n_cells)
     mask, f = clamp_x0_bc(mesh)
     u = synthetic_u(rng, mask)
-    return Problem(f"cantilever_hex_{nx}x{ny}x{nz}", mesh, rho, mask, f, u)
+    if skew:
+        mesh = skew_mesh(mesh, skew)
+    return Problem(f"cantilever_hex_{nx}x{ny}x{nz}" + (f"_{skew}" if skew else ""), mesh, rho, mask, f, u)
 
 
 def box_p2(n: int = 48, seed: int = 1004) -> Problem:
@@ -317,8 +344,11 @@ def serving_request(rid: int):
     return kind, n, p, rng
 
 
-def small_problem(elem: int, seed: int = 7, jitter: bool = True, dims=None) -> Problem:
-    """Tiny meshes for oracle pins and parity tests (several tiles, ragged sizes)."""
+def small_problem(elem: int, seed: int = 7, jitter: bool = True, dims=None, skew: Optional[str] = None) -> Problem:
+    """Tiny meshes for oracle pins and parity tests (several tiles, ragged sizes).
+
+    skew ('global' or 'kink', Q1 only) maps the coordinates after the supports
+    are chosen (skew_mesh)."""
     rng = np.random.default_rng(seed)
     if elem == QUAD4:
         nx, ny = dims or (7, 5)
@@ -340,4 +370,8 @@ def small_problem(elem: int, seed: int = 7, jitter: bool = True, dims=None) -> P
         raise ValueError(elem)
     rho = rng.uniform(0.001, 1.0, mesh.n_cells)
     u = synthetic_u(rng, mask)
-    return Problem(f"small_{ELEM_NAMES[elem]}", mesh, rho, mask, f, u)
+    if skew:
+        if elem not in (QUAD4, HEX8):
+            raise ValueError("skew applies to Q1 meshes")
+        mesh = skew_mesh(mesh, skew)
+    return Problem(f"small_{ELEM_NAMES[elem]}" + (f"_{skew}" if skew else ""), mesh, rho, mask, f, u)

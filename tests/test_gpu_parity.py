@@ -17,8 +17,8 @@ MAT = api.Material()
 TOL = {api.FP64: 1e-12, api.FP32: 1e-5}
 
 
-def _setup(elem, seed=7, dims=None, ref=api.REF_SYMBOLIC):
-    pr = I.small_problem(elem, seed=seed, dims=dims)
+def _setup(elem, seed=7, dims=None, ref=api.REF_SYMBOLIC, skew=None):
+    pr = I.small_problem(elem, seed=seed, dims=dims, skew=skew)
     m = pr.mesh
     pat = api.Pattern(elem, m.coords, m.cells, ref_method=ref)
     rp, ci = O.pattern(elem, m.n_nodes, m.cells)
@@ -46,9 +46,27 @@ def test_assemble_fp64(elem, use_mask, ref):
     assert err <= TOL[api.FP64]
 
 
+@pytest.mark.parametrize("elem", [I.QUAD4, I.HEX8])
+@pytest.mark.parametrize("skew", ["global", "kink"])
+@pytest.mark.parametrize("use_mask", [False, True])
+def test_assemble_fp64_skewed_q1(elem, skew, use_mask):
+    """General-Jacobian groups ('global') and a mix of axis-aligned and general
+    groups ('kink') on Q1 meshes, with several groups per signature."""
+    pr, m, pat, rp, ci = _setup(elem, skew=skew, dims=(23, 9) if elem == I.QUAD4 else (9, 6, 7))
+    mask = pr.mask if use_mask else None
+    K = host(pat.assemble(MAT, dev(pr.rho), None if mask is None else dev(mask)))
+    Kref = O.assemble(elem, m.coords, m.cells, pr.rho, rp, ci, mask=mask)
+    err = row_scaled_err(rp, K, Kref)
+    print(f"elem={elem} skew={skew} mask={use_mask} K row-scaled err {err:.2e}")
+    assert err <= TOL[api.FP64]
+
+
 @pytest.mark.parametrize("elem", ELEMS)
-def test_assemble_fp32_and_bf16(elem):
-    pr, m, pat, rp, ci = _setup(elem)
+@pytest.mark.parametrize("skew", [None, "kink"])
+def test_assemble_fp32_and_bf16(elem, skew):
+    if skew and elem not in (I.QUAD4, I.HEX8):
+        pytest.skip("skew applies to Q1 meshes")
+    pr, m, pat, rp, ci = _setup(elem, skew=skew)
     Kref = O.assemble(elem, m.coords, m.cells, pr.rho, rp, ci, mask=pr.mask)
     K32 = host(pat.assemble(MAT, dev(pr.rho, torch.float32), dev(pr.mask), prec=api.FP32))
     rho32 = pr.rho.astype(np.float32).astype(np.float64)

@@ -161,29 +161,48 @@ def walk_plan(hp, mesh, rho, M, E0=1.0, Emin=1e-9, p=3.0, nu=0.3, mask=None):
     rp, ci = hp["row_ptr"], hp["col_idx"]
     K = np.full(hp["nnz"], np.nan)
     seen = np.zeros((NC, nen, nen), dtype=np.int32)
-    gi = hp["grp_info"].reshape(-1, 5)
+    gi = hp["grp_info"].reshape(-1, 6)
     si = hp["sig_info"].reshape(-1, 4)
+    NG = hp["grp_nodes"].size // gi.shape[0]  # nodes per group (slots of the node tables)
+    assert NG == 32
     for g in range(gi.shape[0]):
-        sig, nn, eoff, ne, n2loff = gi[g]
+        sig, nn, eoff, ne, n2loff, flags = gi[g]
         Kk, deg, posoff, blk = si[sig]
         assert blk % 2 == 1 and blk >= D * D * deg
-        order = hp["sig_order"][posoff:posoff + deg + 1]
-        assert sorted(order[:deg]) == list(range(deg)) and order[deg] == -1
         cnt = np.diff(hp["sig_pos_ptr"][posoff:posoff + deg + 1])
-        assert np.all(np.diff(cnt[order[:deg]]) <= 0)
+        items = hp["sig_pairs"][2 * posoff:2 * posoff + 2 * (deg + 1)].reshape(deg + 1, 2)
+        nit = int(np.argmax(items[:, 0] < 0))
+        assert np.all(items[nit:] == -1)
+        split = {}  # position -> number of contributions taken by the low half
+        covered = []
+        costs = []
+        for pa, pb in items[:nit]:
+            assert pa >= 0
+            if pb == pa:
+                split[pa] = (cnt[pa] + 1) // 2
+                covered.append(pa)
+                costs.append((cnt[pa] + 1) // 2)
+            else:
+                covered += [pa] + ([pb] if pb >= 0 else [])
+                assert pb < 0 or cnt[pa] >= cnt[pb]  # the low half runs the longer list
+                costs.append(cnt[pa])
+        assert sorted(covered) == list(range(deg))  # every position exactly once
+        assert np.all(np.diff(costs) <= 0)  # costliest first
         elems = hp["grp_elems"][eoff:eoff + ne]
         assert ne <= hp["emax"] and np.all(np.diff(elems) > 0)
-        n2l = hp["grp_n2l"][n2loff:n2loff + Kk * 64].reshape(Kk, 64)
+        offdiag = G[elems][:, ~np.eye(D, dtype=bool)]
+        assert flags == (1 if np.all(offdiag == 0.0) else 0)
+        n2l = hp["grp_n2l"][n2loff:n2loff + Kk * NG].reshape(Kk, NG)
         for lane in range(nn):
-            Inode = hp["grp_nodes"][64 * g + lane]
+            Inode = hp["grp_nodes"][NG * g + lane]
             base = rp[D * Inode]
             rowlen = rp[D * Inode + 1] - base
-            assert hp["grp_rows"][128 * g + 2 * lane] == base and hp["grp_rows"][128 * g + 2 * lane + 1] == rowlen
+            assert hp["grp_rows"][2 * NG * g + 2 * lane] == base and hp["grp_rows"][2 * NG * g + 2 * lane + 1] == rowlen
             assert rowlen == D * deg
             prev_e = None
             for pp in range(deg):
                 c0, c1 = hp["sig_pos_ptr"][posoff + pp], hp["sig_pos_ptr"][posoff + pp + 1]
-                acc = np.zeros((D, D))
+                parts = [np.zeros((D, D)), np.zeros((D, D))]
                 last = -1
                 Jcol = ci[base + D * pp] // D
                 for t in range(c0, c1):
@@ -194,7 +213,9 @@ def walk_plan(hp, mesh, rho, M, E0=1.0, Emin=1e-9, p=3.0, nu=0.3, mask=None):
                     assert e > last  # ascending elements within a stored block
                     last = e
                     seen[e, i, j] += 1
-                    acc += Gp[e].T @ M[i, j] @ Gp[e]
+                    half = 1 if pp in split and t - c0 >= split[pp] else 0
+                    parts[half] += Gp[e].T @ M[i, j] @ Gp[e]
+                acc = parts[0] + parts[1]  # a split position: low half's sum + high half's
                 out = lam * acc + mu * acc.T + mu * np.trace(acc) * np.eye(D)
                 if mask is not None:
                     for a in range(D):
@@ -233,6 +254,31 @@ def test_plan_walk_model_matches_oracle(elem, use_mask):
     Kref = O.assemble(elem, m.coords, m.cells, pr.rho, rp, ci, mask=mask)
     assert not np.isnan(K).any()
     assert row_scaled_err(rp, K, Kref) <= 1e-13
+
+
+@pytest.mark.parametrize("elem", [I.QUAD4, I.HEX8])
+@pytest.mark.parametrize("skew", ["global", "kink"])
+def test_plan_walk_skewed_q1(elem, skew):
+    """Sheared Q1 meshes: the axis-aligned flag is off for every group ('global')
+    or for the groups that touch the sheared half ('kink')."""
+    pr = I.small_problem(elem, seed=6, skew=skew, dims=(8, 5) if elem == I.QUAD4 else (6, 4, 5))
+    m = pr.mesh
+    hp = api.host_plan(elem, m.coords, m.cells)
+    flags = hp["grp_info"].reshape(-1, 6)[:, 5]
+    if skew == "global":
+        assert np.all(flags == 0)
+    else:
+        assert np.any(flags == 1) and np.any(flags == 0)
+    K = walk_plan(hp, m, pr.rho, api.reference_tensor(elem), mask=pr.mask)
+    rp, ci = O.pattern(elem, m.n_nodes, m.cells)
+    Kref = O.assemble(elem, m.coords, m.cells, pr.rho, rp, ci, mask=pr.mask)
+    assert row_scaled_err(rp, K, Kref) <= 1e-13
+
+
+def test_plan_axis_aligned_flag_set_on_grids():
+    for mesh in [I.quad_grid(9, 4), I.hex_grid(5, 3, 4)]:
+        hp = api.host_plan(mesh.elem, mesh.coords, mesh.cells)
+        assert np.all(hp["grp_info"].reshape(-1, 6)[:, 5] == 1)
 
 
 def test_backward_position_table():
