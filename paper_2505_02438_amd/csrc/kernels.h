@@ -48,7 +48,9 @@ struct EnergyParams {
     const double *cgrad;   // [nen][dim] reference gradients at the centroid
     const double *xref;    // [nen][dim] reference node coordinates
     void *dc;              // or null
-    double *partials;      // [ceil(NC/256)] or null
+    const double *f;       // [ndof] or null: f^T u as well
+    int64_t ndof;
+    double *partials;      // [2][grid] block partials of c and f^T u, or null (no compliance)
     int64_t n_cells;
     double E0, Emin, p;
     int ip;
@@ -73,12 +75,10 @@ struct BwdParams {
 };
 
 hipError_t launch_assemble(int elem, int prec, const AsmParams &P, int64_t ngroups, hipStream_t st);
-hipError_t launch_dirichlet(int dim, const int32_t *row_ptr, const int32_t *col_idx, const uint8_t *mask,
-                            double *K, int64_t n_nodes, hipStream_t st);
+hipError_t launch_dirichlet(int dim, const int32_t *row_ptr, const int32_t *col_idx, const uint16_t *nb_rev,
+                            const uint8_t *mask, double *K, int64_t ndof, hipStream_t st);
 hipError_t launch_energy(int elem, int prec, const EnergyParams &P, hipStream_t st);
-hipError_t launch_dot_partials(const double *f, const double *u, int64_t n, double *partials, int nblocks,
-                               hipStream_t st);
-hipError_t launch_finalize(const double *p0, int n0, const double *p1, int n1, double *c, hipStream_t st);
+hipError_t launch_finalize(const double *partials, int n, int with_f, double *c, hipStream_t st);
 hipError_t launch_backward(int elem, int prec, const BwdParams &P, hipStream_t st);
 
 }  // namespace soptx

@@ -490,33 +490,51 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
     }
 }
 
-// Dirichlet rows and columns (zero prescribed values): for every fixed dof r,
-// K[r,:] = 0, K[:,r] = 0, K[r,r] = 1, pattern unchanged.  Runs after the
-// assembly on the same stream.  16 lanes per node; entry (c, r) of a fixed
-// column is found by binary search in row c (the pattern is symmetric).
+// Dirichlet rows and columns (zero prescribed values): for a fixed dof r,
+// K[r, :] = 0, K[:, r] = 0, K[r, r] = 1.  A workgroup takes 64 dofs, lane =
+// dof; its four waves split the dof's row entries and the neighbours J of
+// its node, whose DIM rows hold the column entries (where the node sits in
+// nb(J) comes from the reverse position table).  Fixed dofs are often
+// contiguous (a clamped face), so the work is spread over lanes rather than
+// walked dof by dof.  Entries in two fixed lines get the same value from
+// both, so the order of the writes does not matter.
 template <int DIM>
 __global__ __launch_bounds__(256) void k_dirichlet(const int32_t *__restrict__ row_ptr,
                                                    const int32_t *__restrict__ col_idx,
-                                                   const uint8_t *__restrict__ mask, double *K,
-                                                   int64_t n_nodes) {
-    const int64_t I = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
-    const int l = threadIdx.x & 15;
-    if (I >= n_nodes) return;
-    for (int a = 0; a < DIM; a++) {
-        const int r = (int)(DIM * I + a);
-        if (!mask[r]) continue;
-        const int b0 = row_ptr[r], b1 = row_ptr[r + 1];
-        for (int k = b0 + l; k < b1; k += 16) {
-            const int c = col_idx[k];
-            K[k] = (c == r) ? 1.0 : 0.0;
-            // entry (c, r)
-            int lo = row_ptr[c], hi = row_ptr[c + 1] - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (col_idx[mid] < r) lo = mid + 1; else hi = mid;
-            }
-            K[lo] = (c == r) ? 1.0 : 0.0;
+                                                   const uint16_t *__restrict__ nb_rev,
+                                                   const uint8_t *__restrict__ mask, double *K, int64_t ndof) {
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int64_t r64 = (int64_t)blockIdx.x * 64 + lane;
+    if (r64 >= ndof || !mask[r64]) return;
+    const int r = (int)r64;
+    const int I = r / DIM, a = r - DIM * I;
+    const int b0 = row_ptr[r], b1 = row_ptr[r + 1];
+    for (int k = b0 + w; k < b1; k += 4) K[k] = col_idx[k] == r ? 1.0 : 0.0;
+    const int deg = (b1 - b0) / DIM;
+    const int nptr = row_ptr[DIM * I] / (DIM * DIM);
+    // neighbours q = w, w + 4, ... in batches of 8, each batch's loads in flight together
+    constexpr int B = 8;
+    for (int q0 = w; q0 < deg; q0 += 4 * B) {
+        int J[B], t[B], jb[B], jl[B];
+#pragma unroll
+        for (int c = 0; c < B; c++) {
+            const int q = q0 + 4 * c;
+            J[c] = q < deg ? col_idx[b0 + DIM * q] / DIM : I;
+            t[c] = q < deg ? nb_rev[nptr + q] : 0;
         }
+#pragma unroll
+        for (int c = 0; c < B; c++) {
+            jb[c] = row_ptr[DIM * J[c]];
+            jl[c] = row_ptr[DIM * J[c] + 1] - jb[c];  // row length of J's rows
+        }
+#pragma unroll
+        for (int c = 0; c < B; c++)
+            if (q0 + 4 * c < deg) {
+#pragma unroll
+                for (int a2 = 0; a2 < DIM; a2++)
+                    K[jb[c] + a2 * jl[c] + DIM * t[c] + a] = (J[c] == I && a2 == a) ? 1.0 : 0.0;
+            }
     }
 }
 
@@ -530,6 +548,129 @@ __global__ __launch_bounds__(256) void k_dirichlet(const int32_t *__restrict__ r
 // motion (translation of node 0 and the rotation of the centroid gradient) is
 // removed in FP64 first; it is in the null space of K_e^0, so s_e is unchanged
 // in exact arithmetic while the FP32 part sees only the deforming part.
+// Sum over a block of 256 threads in a fixed order (tree); the result is
+// returned to thread 0.  red: 256 doubles of LDS.
+__device__ __forceinline__ double block_sum_256(double x, double *red) {
+    __syncthreads();  // red may still be read by a previous call
+    red[threadIdx.x] = x;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    return red[0];
+}
+
+// Q1 elements, FP64: the reference gradient of u at the 2^d Gauss points of
+// [0,1]^d by tensor-product factorisation.  The derivative along one axis does
+// not depend on that axis' coordinate: it is the (bi)linear interpolation, in
+// the other coordinates, of the nodal differences along the axis.  Energy
+// lambda tr(eps)^2 + 2 mu eps:eps with eps = sym(grad_xi u G) at each point,
+// equal weights.
+__device__ __forceinline__ double q1_point_energy3(const double (&H)[3][3], const double (&G)[3][3], bool diag,
+                                                   double lam, double mu) {
+    double eps[3][3];
+    if (diag) {
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+#pragma unroll
+            for (int b = 0; b < 3; b++) eps[a][b] = H[a][b] * G[b][b];
+    } else {
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+#pragma unroll
+            for (int b = 0; b < 3; b++) eps[a][b] = H[a][0] * G[0][b] + H[a][1] * G[1][b] + H[a][2] * G[2][b];
+    }
+    const double tr = eps[0][0] + eps[1][1] + eps[2][2];
+    const double h01 = 0.5 * (eps[0][1] + eps[1][0]), h02 = 0.5 * (eps[0][2] + eps[2][0]),
+                 h12 = 0.5 * (eps[1][2] + eps[2][1]);
+    const double ee = eps[0][0] * eps[0][0] + eps[1][1] * eps[1][1] + eps[2][2] * eps[2][2] +
+                      2.0 * (h01 * h01 + h02 * h02 + h12 * h12);
+    return lam * tr * tr + 2.0 * mu * ee;
+}
+
+__device__ __forceinline__ double q1_hex_energy(const double (&u)[8][3], const double (&G)[3][3], double lam,
+                                                double mu) {
+    // local node of corner (x, y, z): bottom face counter-clockwise, then top
+    constexpr int N[2][2][2] = {{{0, 4}, {3, 7}}, {{1, 5}, {2, 6}}};
+    const double gp[2] = {0.5 - 0.5 / 1.7320508075688772935, 0.5 + 0.5 / 1.7320508075688772935};
+    const bool diag = G[0][1] == 0.0 && G[0][2] == 0.0 && G[1][0] == 0.0 && G[1][2] == 0.0 && G[2][0] == 0.0 &&
+                      G[2][1] == 0.0;
+    // d[ax][a][p][q]: nodal differences of u_a along axis ax, at the corners
+    // (p, q) of the two other axes (in increasing axis order)
+    double d[3][3][2][2];
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+#pragma unroll
+        for (int p = 0; p < 2; p++)
+#pragma unroll
+            for (int q = 0; q < 2; q++) {
+                d[0][a][p][q] = u[N[1][p][q]][a] - u[N[0][p][q]][a];
+                d[1][a][p][q] = u[N[p][1][q]][a] - u[N[p][0][q]][a];
+                d[2][a][p][q] = u[N[p][q][1]][a] - u[N[p][q][0]][a];
+            }
+    auto lerp2 = [&](const double (&f)[2][2], double s, double t) {
+        const double lo = f[0][0] + s * (f[1][0] - f[0][0]);
+        const double hi = f[0][1] + s * (f[1][1] - f[0][1]);
+        return lo + t * (hi - lo);
+    };
+    double sum = 0.0;
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++)
+#pragma unroll
+            for (int k = 0; k < 2; k++) {
+                double H[3][3];
+#pragma unroll
+                for (int a = 0; a < 3; a++) {
+                    H[a][0] = lerp2(d[0][a], gp[j], gp[k]);
+                    H[a][1] = lerp2(d[1][a], gp[i], gp[k]);
+                    H[a][2] = lerp2(d[2][a], gp[i], gp[j]);
+                }
+                sum += q1_point_energy3(H, G, diag, lam, mu);
+            }
+    return 0.125 * sum;
+}
+
+__device__ __forceinline__ double q1_quad_energy(const double (&u)[4][2], const double (&G)[2][2], double lam,
+                                                 double mu) {
+    constexpr int N[2][2] = {{0, 3}, {1, 2}};  // local node of corner (x, y)
+    const double gp[2] = {0.5 - 0.5 / 1.7320508075688772935, 0.5 + 0.5 / 1.7320508075688772935};
+    double D[2][2][2];  // D[axis][a][s]
+#pragma unroll
+    for (int a = 0; a < 2; a++) {
+        const double dx0 = u[N[1][0]][a] - u[N[0][0]][a], dx1 = u[N[1][1]][a] - u[N[0][1]][a];
+        const double dy0 = u[N[0][1]][a] - u[N[0][0]][a], dy1 = u[N[1][1]][a] - u[N[1][0]][a];
+#pragma unroll
+        for (int s = 0; s < 2; s++) {
+            D[0][a][s] = dx0 + gp[s] * (dx1 - dx0);
+            D[1][a][s] = dy0 + gp[s] * (dy1 - dy0);
+        }
+    }
+    double sum = 0.0;
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++) {
+            double H[2][2], eps[2][2];
+#pragma unroll
+            for (int a = 0; a < 2; a++) {
+                H[a][0] = D[0][a][j];
+                H[a][1] = D[1][a][i];
+            }
+#pragma unroll
+            for (int a = 0; a < 2; a++)
+#pragma unroll
+                for (int b = 0; b < 2; b++) eps[a][b] = H[a][0] * G[0][b] + H[a][1] * G[1][b];
+            const double tr = eps[0][0] + eps[1][1];
+            const double h = 0.5 * (eps[0][1] + eps[1][0]);
+            const double ee = eps[0][0] * eps[0][0] + eps[1][1] * eps[1][1] + 2.0 * h * h;
+            sum += lam * tr * tr + 2.0 * mu * ee;
+        }
+    return 0.25 * sum;
+}
+
 template <int DIM, int NEN, int NQ, int PREC>
 __global__ __launch_bounds__(256) void k_energy(EnergyParams P) {
     __shared__ double red[256];
@@ -552,7 +693,11 @@ __global__ __launch_bounds__(256) void k_energy(EnergyParams P) {
             for (int a = 0; a < DIM; a++) u[i][a] = P.u[(int64_t)DIM * n + a];
         }
         double s = 0.0;
-        if (PREC == kF64) {
+        if constexpr (PREC == kF64 && DIM == 3 && NEN == 8) {
+            s = q1_hex_energy(u, G, P.lam, P.mu);
+        } else if constexpr (PREC == kF64 && DIM == 2 && NEN == 4) {
+            s = q1_quad_energy(u, G, P.lam, P.mu);
+        } else if (PREC == kF64) {
 #pragma unroll
             for (int q = 0; q < NQ; q++) {
                 const double *dq = P.qgrad + q * NEN * DIM;
@@ -699,53 +844,34 @@ __global__ __launch_bounds__(256) void k_energy(EnergyParams P) {
         if (P.dc) store_out<PREC>(P.dc, e, -P.p * rp1 * (P.E0 - P.Emin) * s);
         cpart = E * s;
     }
-    if (P.partials) {
-        red[threadIdx.x] = cpart;
-        __syncthreads();
-        for (int st = 128; st > 0; st >>= 1) {
-            if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) P.partials[blockIdx.x] = red[0];
+    if (!P.partials) return;
+    // compliance: fixed-order block partials of c and f^T u; k_finalize adds
+    // them in index order.  (A last-block-done reduction in this kernel would
+    // need a device-scope release per block, i.e. an L2 write-back on this
+    // chip, which costs more than the extra launch.)
+    double fpart = 0.0;
+    if (P.f)
+        for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < P.ndof; r += (int64_t)gridDim.x * 256)
+            fpart += P.f[r] * P.u[r];
+    const int nb = gridDim.x;
+    const double bc = block_sum_256(cpart, red);
+    const double bf = P.f ? block_sum_256(fpart, red) : 0.0;
+    if (threadIdx.x == 0) {
+        P.partials[blockIdx.x] = bc;
+        P.partials[nb + blockIdx.x] = bf;
     }
 }
 
-// f^T u partials: fixed grid, grid-stride, fixed tree per block
-__global__ __launch_bounds__(256) void k_dot_partials(const double *__restrict__ f,
-                                                      const double *__restrict__ u, int64_t n,
-                                                      double *partials) {
-    __shared__ double red[256];
-    double s = 0.0;
-    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < n; r += (int64_t)gridDim.x * 256)
-        s += f[r] * u[r];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
-}
-
-// c[0] = sum of p0[0:n0] (0 when n0 == 0); c[1] = sum of p1[0:n1] when p1 is
-// given.  Fixed order: one block of 256 threads, strided sums then a tree.
-__global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ p0, int n0,
-                                                  const double *__restrict__ p1, int n1, double *c) {
+// c[0] = sum of partials[0:n]; c[1] = sum of partials[n:2n] (f^T u, or 0).
+// One block, strided sums then a tree: a fixed order.
+__global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ partials, int n, int with_f, double *c) {
     __shared__ double red[256];
     for (int which = 0; which < 2; which++) {
-        const double *pp = which ? p1 : p0;
-        const int n = which ? n1 : n0;
-        if (which == 1 && !pp) break;
-        double s = 0.0;
-        for (int k = threadIdx.x; k < n; k += 256) s += pp[k];
-        red[threadIdx.x] = s;
-        __syncthreads();
-        for (int st = 128; st > 0; st >>= 1) {
-            if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) c[which] = red[0];
-        __syncthreads();
+        double t = 0.0;
+        if (which == 0 || with_f)
+            for (int k = threadIdx.x; k < n; k += 256) t += partials[which * n + k];
+        t = block_sum_256(t, red);
+        if (threadIdx.x == 0) c[which] = t;
     }
 }
 
@@ -886,7 +1012,8 @@ hipError_t launch_assemble(int elem, int prec, const AsmParams &P, int64_t ngrou
 
 template <int DIM, int NEN, int NQ, int PREC>
 static hipError_t launch_energy_t(const EnergyParams &P, hipStream_t st) {
-    const unsigned nb = (unsigned)((P.n_cells + 255) / 256);
+    unsigned nb = (unsigned)((P.n_cells + 255) / 256);
+    if (nb == 0 && P.partials) nb = 1;  // c (and f^T u) still written
     if (nb == 0) return hipSuccess;
     hipLaunchKernelGGL((k_energy<DIM, NEN, NQ, PREC>), dim3(nb), dim3(256), 0, st, P);
     return hipGetLastError();
@@ -909,25 +1036,20 @@ hipError_t launch_energy(int elem, int prec, const EnergyParams &P, hipStream_t 
 #undef SOPTX_EN
 }
 
-hipError_t launch_dirichlet(int dim, const int32_t *row_ptr, const int32_t *col_idx, const uint8_t *mask,
-                            double *K, int64_t n_nodes, hipStream_t st) {
-    const unsigned nb = (unsigned)((n_nodes + 15) / 16);
+hipError_t launch_dirichlet(int dim, const int32_t *row_ptr, const int32_t *col_idx, const uint16_t *nb_rev,
+                            const uint8_t *mask, double *K, int64_t ndof, hipStream_t st) {
+    const unsigned nb = (unsigned)((ndof + 63) / 64);
     if (nb == 0) return hipSuccess;
-    if (dim == 2) hipLaunchKernelGGL(k_dirichlet<2>, dim3(nb), dim3(256), 0, st, row_ptr, col_idx, mask, K, n_nodes);
-    else hipLaunchKernelGGL(k_dirichlet<3>, dim3(nb), dim3(256), 0, st, row_ptr, col_idx, mask, K, n_nodes);
+    if (dim == 2) hipLaunchKernelGGL(k_dirichlet<2>, dim3(nb), dim3(256), 0, st, row_ptr, col_idx, nb_rev, mask, K, ndof);
+    else hipLaunchKernelGGL(k_dirichlet<3>, dim3(nb), dim3(256), 0, st, row_ptr, col_idx, nb_rev, mask, K, ndof);
     return hipGetLastError();
 }
 
-hipError_t launch_dot_partials(const double *f, const double *u, int64_t n, double *partials, int nblocks,
-                               hipStream_t st) {
-    hipLaunchKernelGGL(k_dot_partials, dim3(nblocks), dim3(256), 0, st, f, u, n, partials);
+hipError_t launch_finalize(const double *partials, int n, int with_f, double *c, hipStream_t st) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, partials, n, with_f, c);
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const double *p0, int n0, const double *p1, int n1, double *c, hipStream_t st) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, p0, n0, p1, n1, c);
-    return hipGetLastError();
-}
 
 template <int DIM, int NEN, int PREC>
 static hipError_t launch_backward_t(const BwdParams &P, hipStream_t st) {

@@ -2,6 +2,7 @@
 // kernel dispatch.  Every numeric step runs in the HIP kernels of kernels.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -28,7 +29,7 @@ struct soptx_pattern_s {
     int32_t *grp_rows = nullptr;
     int n_cu = 0;
     int32_t *sig_info = nullptr, *sig_pos_ptr = nullptr, *sig_contrib = nullptr, *sig_pairs = nullptr;
-    uint16_t *pos = nullptr;
+    uint16_t *pos = nullptr, *nb_rev = nullptr;
     double *M = nullptr;
     float *M32 = nullptr, *Mbf = nullptr;
     double *qw = nullptr, *qgrad = nullptr, *cgrad = nullptr, *xref = nullptr;
@@ -233,7 +234,7 @@ int soptx_build_pattern_ex(const soptx_mesh *mesh, int32_t ref_method, soptx_pat
             free_handle(h); return rc;
         }
         h->stats.plan_bytes = h->stats.device_bytes - base_bytes;
-        if ((rc = upload(h, hp.pos, &h->pos, st)) || (rc = upload(h, M, &h->M, st)) ||
+        if ((rc = upload(h, hp.pos, &h->pos, st)) || (rc = upload(h, hp.nb_rev, &h->nb_rev, st)) || (rc = upload(h, M, &h->M, st)) ||
             (rc = upload(h, M32, &h->M32, st)) || (rc = upload(h, Mbf, &h->Mbf, st)) ||
             (rc = upload(h, qw, &h->qw, st)) || (rc = upload(h, qg, &h->qgrad, st)) ||
             (rc = upload(h, qg32, &h->qgrad32, st)) || (rc = upload(h, cg, &h->cgrad, st)) ||
@@ -305,7 +306,7 @@ int soptx_assemble(soptx_pattern h, const soptx_material *m, const void *d_rho, 
     P.kmax = h->kmax; P.stage = h->stage;
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (launch_assemble(h->elem, prec, P, h->ngroups, st) != hipSuccess) return SOPTX_E_DEVICE;
-    if (d_dirichlet && launch_dirichlet(h->dim, h->row_ptr, h->col_idx, d_dirichlet, d_K_vals, h->n_nodes, st) != hipSuccess)
+    if (d_dirichlet && launch_dirichlet(h->dim, h->row_ptr, h->col_idx, h->nb_rev, d_dirichlet, d_K_vals, h->ndof, st) != hipSuccess)
         return SOPTX_E_DEVICE;
     return SOPTX_OK;
 }
@@ -320,28 +321,24 @@ int soptx_evaluate(soptx_pattern h, const soptx_material *m, const void *d_rho, 
     DeviceGuard dg(h->device);
     if (!dg.ok) return SOPTX_E_DEVICE;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const int nblk = (int)((h->n_cells + 255) / 256);
-    const int ndot = 512;
+    const int nblk = std::max(1, (int)((h->n_cells + 255) / 256));
     double *ws = nullptr;
     if (d_c) {
-        rc = get_workspace(h->device, st, (size_t)nblk + ndot + 1, &ws);
+        // block partials of c, then of f^T u
+        rc = get_workspace(h->device, st, 2 * (size_t)nblk, &ws);
         if (rc) return rc;
     }
     EnergyParams P{};
     P.cells = h->cells; P.geo = h->geo; P.rho = d_rho; P.u = d_u;
     P.qw = h->qw; P.qgrad = h->qgrad; P.qgrad32 = h->qgrad32; P.cgrad = h->cgrad; P.xref = h->xref;
-    P.dc = d_dc; P.partials = d_c ? ws : nullptr;
+    P.dc = d_dc;
+    P.f = d_c ? d_f : nullptr;
+    P.ndof = h->ndof;
+    P.partials = d_c ? ws : nullptr;
     P.n_cells = h->n_cells; P.E0 = m->E0; P.Emin = m->Emin; P.p = m->p; P.ip = int_exponent(m->p);
     lame(h, m, &P.lam, &P.mu);
     if (launch_energy(h->elem, prec, P, st) != hipSuccess) return SOPTX_E_DEVICE;
-    if (d_c) {
-        double *p1 = nullptr;
-        if (d_f) {
-            p1 = ws + nblk;
-            if (launch_dot_partials(d_f, d_u, h->ndof, p1, ndot, st) != hipSuccess) return SOPTX_E_DEVICE;
-        }
-        if (launch_finalize(ws, nblk, p1, ndot, d_c, st) != hipSuccess) return SOPTX_E_DEVICE;
-    }
+    if (d_c && launch_finalize(ws, nblk, d_f ? 1 : 0, d_c, st) != hipSuccess) return SOPTX_E_DEVICE;
     return SOPTX_OK;
 }
 
@@ -414,7 +411,7 @@ int soptx_debug_host_plan_array(soptx_host_plan p, const char *name, const void 
     }
     SOPTX_ARR(row_ptr) SOPTX_ARR(col_idx) SOPTX_ARR(geo) SOPTX_ARR(sig_info) SOPTX_ARR(sig_pos_ptr)
     SOPTX_ARR(sig_contrib) SOPTX_ARR(sig_pairs) SOPTX_ARR(grp_info) SOPTX_ARR(grp_nodes) SOPTX_ARR(grp_elems)
-    SOPTX_ARR(grp_n2l) SOPTX_ARR(grp_rows) SOPTX_ARR(pos)
+    SOPTX_ARR(grp_n2l) SOPTX_ARR(grp_rows) SOPTX_ARR(pos) SOPTX_ARR(nb_rev)
 #undef SOPTX_ARR
     return SOPTX_E_INVALID_ARG;
 }

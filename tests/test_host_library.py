@@ -281,6 +281,24 @@ def test_plan_axis_aligned_flag_set_on_grids():
         assert np.all(hp["grp_info"].reshape(-1, 6)[:, 5] == 1)
 
 
+@pytest.mark.parametrize("elem", ELEMS)
+def test_reverse_neighbour_table(elem):
+    """nb_rev[node n, neighbour q] = position of n in the neighbour list of that
+    neighbour (used to reach the column entries of a fixed dof)."""
+    pr = I.small_problem(elem, seed=5)
+    m = pr.mesh
+    hp = api.host_plan(elem, m.coords, m.cells)
+    D = m.dim
+    rp, ci = hp["row_ptr"], hp["col_idx"]
+    nbrs = [ci[rp[D * n]:rp[D * n + 1]:D] // D for n in range(m.n_nodes)]
+    ptr = np.concatenate([[0], np.cumsum([len(x) for x in nbrs])])
+    assert hp["nb_rev"].size == ptr[-1]
+    for n in range(m.n_nodes):
+        assert rp[D * n] == D * D * ptr[n]
+        for q, J in enumerate(nbrs[n]):
+            assert nbrs[J][hp["nb_rev"][ptr[n] + q]] == n
+
+
 def test_backward_position_table():
     pr = I.small_problem(I.TET10, seed=2)
     m = pr.mesh
