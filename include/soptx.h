@@ -148,6 +148,13 @@ int soptx_pattern_copy(soptx_pattern h, int32_t *h_row_ptr, int32_t *h_col_idx);
 int soptx_assemble(soptx_pattern h, const soptx_material *m, const void *d_rho,
                    const uint8_t *d_dirichlet, double *d_K_vals, int32_t prec, void *stream);
 
+/* The Dirichlet step of soptx_assemble on its own: for every fixed dof r of
+ * d_dirichlet ([ndof] uint8, nonzero = fixed), K[r,:] = 0, K[:,r] = 0,
+ * K[r,r] = 1 in d_K_vals ([nnz] double, the other entries untouched).
+ * soptx_assemble with a mask equals soptx_assemble without one followed by
+ * this call (zero prescribed values, Appendices A-C). */
+int soptx_apply_dirichlet(soptx_pattern h, const uint8_t *d_dirichlet, double *d_K_vals, void *stream);
+
 /* dc_e = -p rho_e^(p-1) (E0-Emin) u_e^T K_e^0 u_e  (Appendix D).
  * d_u: [ndof] double; d_dc: [n_cells] (double for SOPTX_FP64, float otherwise). */
 int soptx_sensitivity(soptx_pattern h, const soptx_material *m, const void *d_rho,

@@ -65,6 +65,7 @@ def lib():
         "soptx_pattern_info": [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_P), ctypes.POINTER(_P)],
         "soptx_pattern_stats_get": [_P, ctypes.POINTER(PatternStats)],
         "soptx_assemble": [_P, ctypes.POINTER(Material), _P, _P, _P, _I32, _P],
+        "soptx_apply_dirichlet": [_P, _P, _P, _P],
         "soptx_sensitivity": [_P, ctypes.POINTER(Material), _P, _P, _P, _I32, _P],
         "soptx_compliance": [_P, ctypes.POINTER(Material), _P, _P, _P, _P, _I32, _P],
         "soptx_evaluate": [_P, ctypes.POINTER(Material), _P, _P, _P, _P, _P, _I32, _P],

@@ -173,6 +173,14 @@ class Pattern:
               "soptx_assemble")
         return out
 
+    def apply_dirichlet(self, mask, K, stream=None):
+        """K[r,:] = K[:,r] = 0, K[r,r] = 1 for every fixed dof r of mask, in place."""
+        import torch
+        check(lib().soptx_apply_dirichlet(self._h, _dptr(mask, "mask", torch.uint8, self.ndof),
+                                          _dptr(K, "K", torch.float64, self.nnz), _stream_ptr(stream)),
+              "soptx_apply_dirichlet")
+        return K
+
     def sensitivity(self, material: Material, rho, u, out=None, prec: int = FP64, stream=None):
         """dc_e = -E'(rho_e) u_e^T K_e^0 u_e (Appendix D)."""
         import torch

@@ -311,6 +311,17 @@ int soptx_assemble(soptx_pattern h, const soptx_material *m, const void *d_rho, 
     return SOPTX_OK;
 }
 
+int soptx_apply_dirichlet(soptx_pattern h, const uint8_t *d_dirichlet, double *d_K_vals, void *stream) {
+    if (!h || !d_dirichlet || (h->nnz > 0 && !d_K_vals)) return SOPTX_E_INVALID_ARG;
+    if (h->nnz == 0) return SOPTX_OK;
+    DeviceGuard dg(h->device);
+    if (!dg.ok) return SOPTX_E_DEVICE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (launch_dirichlet(h->dim, h->row_ptr, h->col_idx, h->nb_rev, d_dirichlet, d_K_vals, h->ndof, st) != hipSuccess)
+        return SOPTX_E_DEVICE;
+    return SOPTX_OK;
+}
+
 int soptx_evaluate(soptx_pattern h, const soptx_material *m, const void *d_rho, const double *d_u,
                    const double *d_f, void *d_dc, double *d_c, int32_t prec, void *stream) {
     if (!h || !valid_prec(prec)) return SOPTX_E_INVALID_ARG;

@@ -46,6 +46,16 @@ def test_assemble_fp64(elem, use_mask, ref):
     assert err <= TOL[api.FP64]
 
 
+@pytest.mark.parametrize("elem", ELEMS)
+def test_apply_dirichlet_separately(elem):
+    """assemble(mask) == assemble() then apply_dirichlet(mask), bit for bit."""
+    pr, m, pat, rp, ci = _setup(elem)
+    K1 = host(pat.assemble(MAT, dev(pr.rho), dev(pr.mask)))
+    K2 = pat.assemble(MAT, dev(pr.rho), None)
+    K2 = host(pat.apply_dirichlet(dev(pr.mask), K2))
+    assert np.array_equal(K1, K2)
+
+
 @pytest.mark.parametrize("elem", [I.QUAD4, I.HEX8])
 @pytest.mark.parametrize("skew", ["global", "kink"])
 @pytest.mark.parametrize("use_mask", [False, True])
