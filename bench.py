@@ -65,6 +65,27 @@ def cpu_baseline(pr, rp, ci, min_seconds=10.0):
     return m.n_cells / statistics.median(times), times
 
 
+def serving_run(count, slots=4, budget=32 << 30):
+    """Serving form: seeded requests (2D Q1 n^2, n in 32..512; 3D Q1 n^3,
+    n in 16..96; p in {3, 4}), first as a burst (saturated elements/s), then
+    with Poisson arrivals at 0.7 x that rate (p50/p99 latency)."""
+    from paper_2505_02438_amd import serving as S
+    ex = S.GpuExecutor(slots)
+    burst = S.make_requests(count)
+    ex.prepare(burst)
+    ex.t0 = time.perf_counter()
+    st_b = S.latency_stats(S.Scheduler(ex, slots, budget).run(burst))
+    lam = 0.7 * st_b["elements_per_s"]
+    arr = S.make_requests(count, rate_elems_per_s=lam)
+    ex.prepare(arr)
+    ex.t0 = time.perf_counter()
+    st_p = S.latency_stats(S.Scheduler(ex, slots, budget).run(arr))
+    return {"requests": count, "slots": slots, "hbm_budget_bytes": budget,
+            "burst_elements_per_s": st_b["elements_per_s"], "burst_makespan_s": st_b["makespan_s"],
+            "poisson_lambda_elements_per_s": lam, "p50_ms": st_p["p50_ms"], "p99_ms": st_p["p99_ms"],
+            "poisson_elements_per_s": st_p["elements_per_s"]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +94,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="minimum CPU time of the oracle baseline (whole passes over the workload)")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -198,6 +221,8 @@ def main():
         "plan": {"groups": stats["n_groups"], "signatures": stats["n_signatures"],
                  "plan_bytes": stats["plan_bytes"]},
     }
+    if not args.no_serving:
+        out["serving"] = serving_run(args.serve_requests)
     if not args.no_cpu_baseline:
         from oracle import oracle as O
         rp, ci = O.pattern(m.elem, m.n_nodes, m.cells)

@@ -191,6 +191,10 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
     int32_t *srows = reinterpret_cast<int32_t *>(sM + NEN * NEN * D2);      // [3][NG][2]
     uint16_t *sn2l = reinterpret_cast<uint16_t *>(srows + 3 * NG * 2);      // [2][kmax][NG]
     __shared__ int ticket[2];
+    // group headers, one per row-offset buffer: nn, deg, posoff, blk, flags.
+    // Written by the load waves with the group's other data, so that the
+    // compute and store waves start a step without a chain of scalar loads
+    __shared__ int shdr[3][5];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -295,17 +299,23 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
         for (int r = 0; r < NPF; r++)
             if (lt + r * kSetThreads < nk) sn2l[b * n2l_stride + lt + r * kSetThreads] = (uint16_t)q.pn2l[r];
         if (lt < 2 * NG) srows[rb * 2 * NG + lt] = q.prow;
-        if (lt == 0) ticket[b] = 0;
+        if (lt == 0) {
+            ticket[b] = 0;
+            shdr[rb][0] = ldc(P.grp_info, kGrpInfo * gg + 1);
+            shdr[rb][1] = ldc(P.sig_info, 4 * sg + 1);
+            shdr[rb][2] = ldc(P.sig_info, 4 * sg + 2);
+            shdr[rb][3] = ldc(P.sig_info, 4 * sg + 3);
+            shdr[rb][4] = flags;
+        }
     };
 
     // ---- compute role: group gg from buffers b into stage b
-    auto compute_group = [&](int gg, int b) {
-        const int sig = ldc(P.grp_info, kGrpInfo * gg + 0);
-        const int nn = ldc(P.grp_info, kGrpInfo * gg + 1);
-        const bool diag = ldc(P.grp_info, kGrpInfo * gg + 5) & kGrpDiag;
-        const int deg = ldc(P.sig_info, 4 * sig + 1);
-        const int posoff = ldc(P.sig_info, 4 * sig + 2);
-        const int blk = ldc(P.sig_info, 4 * sig + 3);
+    auto compute_group = [&](int b, int rb) {
+        const int nn = wave_uniform(shdr[rb][0]);
+        const int deg = wave_uniform(shdr[rb][1]);
+        const int posoff = wave_uniform(shdr[rb][2]);
+        const int blk = wave_uniform(shdr[rb][3]);
+        const bool diag = wave_uniform(shdr[rb][4]) & kGrpDiag;
         const int rl = DIM * deg;
         const bool hi = lane >= NG;
         const int node = lane & (NG - 1);
@@ -409,11 +419,10 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
     // ---- store role: group gg from stage b, row offsets rb.  Each store
     // wave takes every kStoreWaves-th node, two nodes and four values per
     // lane at a time, so that eight LDS reads are in flight per batch
-    auto store_group = [&](int gg, int b, int rb) {
-        const int sig = ldc(P.grp_info, kGrpInfo * gg + 0);
-        const int nn = ldc(P.grp_info, kGrpInfo * gg + 1);
-        const int deg = ldc(P.sig_info, 4 * sig + 1);
-        const int blk = ldc(P.sig_info, 4 * sig + 3);
+    auto store_group = [&](int b, int rb) {
+        const int nn = wave_uniform(shdr[rb][0]);
+        const int deg = wave_uniform(shdr[rb][1]);
+        const int blk = wave_uniform(shdr[rb][3]);
         const int bsz = DIM * DIM * deg;  // the node's DIM rows, contiguous in CSR
         const int32_t *rows = srows + rb * 2 * NG;
         const double *sb = stage + b * P.stage;
@@ -451,13 +460,13 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
         __syncthreads();
         for (int s = 0; s < nsteps; s++) {
             const int g = g0 + s * stride;
-            if (g < ngr) compute_group(g, s & 1);
+            if (g < ngr) compute_group(s & 1, s % 3);
             __syncthreads();
         }
     } else if (w < kCompWaves + kStoreWaves) {
         __syncthreads();
         for (int s = 0; s < nsteps; s++) {
-            if (s > 0) store_group(g0 + (s - 1) * stride, (s - 1) & 1, (s - 1) % 3);
+            if (s > 0) store_group((s - 1) & 1, (s - 1) % 3);
             __syncthreads();
         }
     } else {

@@ -359,9 +359,18 @@ int build_host_plan(const soptx_mesh *mesh, HostPlan &hp) {
     std::vector<Open> open(nsig);
     hp.grp_info.clear(); hp.grp_nodes.clear(); hp.grp_elems.clear(); hp.grp_n2l.clear(); hp.grp_rows.clear();
     hp.stage_max = 0;
+    struct Closed { int32_t sig; std::vector<int32_t> nodes, elems; };
+    std::vector<Closed> closed;
     auto flush = [&](int64_t s) {
         Open &o = open[s];
         if (o.nodes.empty()) return;
+        closed.push_back({(int32_t)s, std::move(o.nodes), std::move(o.elems)});
+        o.nodes.clear();
+        o.elems.clear();
+        o.in.clear();
+    };
+    auto emit = [&](Closed &o) {
+        const int64_t s = o.sig;
         const int K = hp.sig_info[s * 4 + 0];
         const int blk = hp.sig_info[s * 4 + 3];
         hp.stage_max = std::max<int64_t>(hp.stage_max, (int64_t)o.nodes.size() * blk);
@@ -400,9 +409,6 @@ int build_host_plan(const soptx_mesh *mesh, HostPlan &hp) {
                 hp.grp_rows.push_back(0);
             }
         }
-        o.nodes.clear();
-        o.elems.clear();
-        o.in.clear();
     };
     for (int64_t n = 0; n < NN; n++) {
         const int32_t s = node_sig[n];
@@ -420,6 +426,12 @@ int build_host_plan(const soptx_mesh *mesh, HostPlan &hp) {
         }
     }
     for (int64_t s = 0; s < nsig; s++) flush(s);
+    // groups in the order of their first node: the assembly kernel's
+    // workgroups take consecutive groups at the same time, so the device
+    // writes one contiguous window of K at a time and neighbouring groups
+    // share element data in cache
+    std::sort(closed.begin(), closed.end(), [](const Closed &x, const Closed &y) { return x.nodes[0] < y.nodes[0]; });
+    for (Closed &c : closed) emit(c);
     hp.ne_max = 0;
     for (int64_t g = 0; g < hp.n_groups(); g++) hp.ne_max = std::max(hp.ne_max, hp.grp_info[kGrpInfo * g + 3]);
     if (hp.grp_elems.size() >= (size_t)INT32_MAX || hp.grp_n2l.size() >= (size_t)INT32_MAX)
