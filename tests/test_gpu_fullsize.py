@@ -1,0 +1,221 @@
+"""GPU checks at the workloads' full sizes, through the calls bench.py times
+(assemble, apply_dirichlet, evaluate):
+
+* MBB 60x20 Q1: everything against the oracle, u from the oracle's solve;
+* cantilever 600x200 P1 tris, 3D cantilever 120x40x40 Q1 hexes, box 48^3 P2
+  tets: pattern (closed form / oracle), rows of seeded sample nodes against
+  the oracle's assembly of the elements around them (every contribution to
+  those rows), FP32 and BF16 forms, sensitivities of seeded sample elements,
+  compliance, rigid-body modes, the linear patch test, Dirichlet rows and
+  columns.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O
+from paper_2505_02438_amd import api
+from paper_2505_02438_amd import inputs as I
+
+from gpu_util import E, abs_energy, dE, dev, host
+
+pytestmark = pytest.mark.gpu
+MAT = api.Material()
+
+CONFIGS = {"tri": I.cantilever_tri, "hex": I.cantilever_hex, "p2": I.box_p2}
+_cache = {}
+
+
+def _setup(name):
+    if name not in _cache:
+        pr = CONFIGS[name]()
+        pat = api.Pattern.from_mesh(pr.mesh)
+        rp, ci = pat.pattern()
+        _cache[name] = (pr, pat, rp.astype(np.int64), ci)
+    return _cache[name]
+
+
+def _sample_rows_oracle(pr, nodes, rho):
+    """Oracle assembly of the elements touching `nodes` (full node numbering,
+    the sub-mesh's own pattern): complete rows for those nodes."""
+    m = pr.mesh
+    touch = np.isin(m.cells, nodes).any(axis=1)
+    sub = m.cells[touch]
+    srp, sci = O.pattern(m.elem, m.n_nodes, sub)
+    sK = O.assemble(m.elem, m.coords, sub, rho[touch], srp, sci)
+    return srp, sci, sK
+
+
+def _compare_rows(m, nodes, rp, ci, K, srp, sci, sK):
+    """Row-scaled error on the sampled nodes' rows; the column sets must match."""
+    worst = 0.0
+    for n in nodes:
+        for a in range(m.dim):
+            r = m.dim * n + a
+            g = slice(rp[r], rp[r + 1])
+            o = slice(srp[r], srp[r + 1])
+            assert np.array_equal(ci[g], sci[o]), f"row {r} columns differ"
+            ref = sK[o]
+            worst = max(worst, np.max(np.abs(K[g] - ref)) / np.max(np.abs(ref)))
+    return worst
+
+
+def test_mbb_full_against_oracle():
+    pr = I.mbb_q1()
+    m = pr.mesh
+    pat = api.Pattern.from_mesh(m)
+    rp, ci = O.pattern(m.elem, m.n_nodes, m.cells)
+    drp, dci = pat.pattern()
+    assert np.array_equal(drp.astype(np.int64), rp) and np.array_equal(dci, ci)
+    K = host(pat.apply_dirichlet(dev(pr.mask), pat.assemble(MAT, dev(pr.rho))))
+    Kref = O.assemble(m.elem, m.coords, m.cells, pr.rho, rp, ci, mask=pr.mask)
+    rows = np.repeat(np.arange(m.ndof), np.diff(rp))
+    den = np.zeros(m.ndof)
+    np.maximum.at(den, rows, np.abs(Kref))
+    num = np.zeros(m.ndof)
+    np.maximum.at(num, rows, np.abs(K - Kref))
+    assert np.max(num / den) <= 1e-12
+    u = O.solve(rp, ci, Kref, pr.f)
+    dc, c = pat.evaluate(MAT, dev(pr.rho), dev(u), f=dev(pr.f))
+    dc, c = host(dc), host(c)
+    dref = O.sensitivity(m.elem, m.coords, m.cells, pr.rho, u)
+    cref = O.compliance(m.elem, m.coords, m.cells, pr.rho, u, f=pr.f)
+    ae = abs_energy(m, u, np.arange(m.n_cells))
+    sc = dE(pr.rho) * ae
+    cscale = np.sum(E(pr.rho) * ae)  # c's forward-error scale (solved fields cancel strongly)
+    print(f"MBB: dc err {np.max(np.abs(dc - dref) / sc):.2e}, c {c[0]:.13g} vs {cref[0]:.13g} "
+          f"(scaled err {abs(c[0] - cref[0]) / cscale:.2e}), f.u {c[1]:.13g}")
+    assert np.max(np.abs(dc - dref) / sc) <= 1e-12
+    assert abs(c[0] - cref[0]) <= 1e-12 * cscale and abs(c[1] - cref[1]) <= 1e-12 * abs(cref[1])
+    assert abs(c[0] - c[1]) <= 1e-9 * abs(c[1])  # u^T K u = f^T u on the solved field
+
+
+@pytest.mark.parametrize("name", ["tri", "hex", "p2"])
+def test_pattern_full(name):
+    pr, pat, rp, ci = _setup(name)
+    m = pr.mesh
+    if name == "hex":
+        assert pat.nnz == 9 * (3 * 120 + 1) * (3 * 40 + 1) * (3 * 40 + 1)
+    if name == "tri":
+        nx, ny = 600, 200
+        E_ = nx * (ny + 1) + (nx + 1) * ny + nx * ny
+        assert pat.nnz == 4 * ((nx + 1) * (ny + 1) + 2 * E_)
+    if name == "p2":
+        assert pat.nnz == 9 * 25_755_265
+    assert pat.ndof == m.ndof and rp[0] == 0 and rp[-1] == pat.nnz
+    # node-pair structure: a node's dim rows have the same columns, interleaved dofs
+    lens = np.diff(rp).reshape(-1, m.dim)
+    assert np.all(lens == lens[:, :1]) and np.all(lens % m.dim == 0)
+    if name in ("tri", "hex"):
+        orp, oci = O.pattern(m.elem, m.n_nodes, m.cells)
+        assert np.array_equal(rp, orp) and np.array_equal(ci, oci)
+
+
+@pytest.mark.parametrize("name", ["tri", "hex", "p2"])
+def test_sampled_rows_fp64_fp32_bf16(name):
+    pr, pat, rp, ci = _setup(name)
+    m = pr.mesh
+    rng = np.random.default_rng(77)
+    nodes = np.unique(rng.choice(m.n_nodes, size=60, replace=False))
+    srp, sci, sK = _sample_rows_oracle(pr, nodes, pr.rho)
+    K64 = host(pat.assemble(MAT, dev(pr.rho)))
+    e64 = _compare_rows(m, nodes, rp, ci, K64, srp, sci, sK)
+    rho32 = dev(pr.rho, torch.float32)
+    K32 = host(pat.assemble(MAT, rho32, prec=api.FP32))
+    rho_r = pr.rho.astype(np.float32).astype(np.float64)
+    srp2, sci2, sK2 = _sample_rows_oracle(pr, nodes, rho_r)
+    e32 = _compare_rows(m, nodes, rp, ci, K32, srp2, sci2, sK2)
+    K16 = host(pat.assemble(MAT, rho32, prec=api.BF16_FP32ACC))
+    e16 = _compare_rows(m, nodes, rp, ci, K16, srp2, sci2, sK2)
+    print(f"{name}: sampled rows FP64 {e64:.2e}  FP32 {e32:.2e}  BF16-in/FP32-acc {e16:.2e}")
+    assert e64 <= 1e-12 and e32 <= 1e-5
+    assert np.isfinite(K16).all() and e16 < 5e-2
+
+
+@pytest.mark.parametrize("name", ["tri", "hex", "p2"])
+def test_sensitivity_compliance_full(name):
+    pr, pat, rp, ci = _setup(name)
+    m = pr.mesh
+    dc, c = pat.evaluate(MAT, dev(pr.rho), dev(pr.u))
+    dc, c = host(dc), host(c)
+    rng = np.random.default_rng(78)
+    idx = np.sort(rng.choice(m.n_cells, size=2000, replace=False))
+    dref = O.sensitivity(m.elem, m.coords, m.cells[idx], pr.rho[idx], pr.u)
+    sc = dE(pr.rho[idx]) * abs_energy(m, pr.u, idx)
+    err = np.max(np.abs(dc[idx] - dref) / sc)
+    cref = O.compliance(m.elem, m.coords, m.cells, pr.rho, pr.u)
+    cerr = abs(c[0] - cref[0]) / abs(cref[0])
+    dc32, c32 = pat.evaluate(MAT, dev(pr.rho, torch.float32), dev(pr.u), prec=api.FP32)
+    rho_r = pr.rho.astype(np.float32).astype(np.float64)
+    dref32 = O.sensitivity(m.elem, m.coords, m.cells[idx], rho_r[idx], pr.u)
+    sc32 = dE(rho_r[idx]) * abs_energy(m, pr.u, idx)
+    err32 = np.max(np.abs(host(dc32)[idx].astype(np.float64) - dref32) / sc32)
+    print(f"{name}: dc err FP64 {err:.2e} FP32 {err32:.2e}; c rel err {cerr:.2e}")
+    assert err <= 1e-12 and cerr <= 1e-12 and err32 <= 1e-5
+
+
+def _spmv(rp, ci, K, x):
+    rows = torch.from_numpy(np.repeat(np.arange(rp.size - 1), np.diff(rp))).cuda()
+    cols = torch.from_numpy(ci.astype(np.int64)).cuda()
+    y = torch.zeros(rp.size - 1, dtype=torch.float64, device="cuda")
+    return y.index_add_(0, rows, K * x[cols])
+
+
+@pytest.mark.parametrize("name", ["tri", "hex", "p2"])
+def test_rigid_modes_and_patch_test_full(name):
+    pr, pat, rp, ci = _setup(name)
+    m = pr.mesh
+    K = pat.assemble(MAT, dev(pr.rho))
+    x = m.coords - m.coords.mean(axis=0)
+    modes = [np.eye(m.dim)[a][None, :].repeat(m.n_nodes, 0) for a in range(m.dim)]
+    if m.dim == 2:
+        modes.append(np.stack([-x[:, 1], x[:, 0]], axis=1))
+    else:
+        for a, b in ((0, 1), (1, 2), (0, 2)):
+            r = np.zeros_like(x)
+            r[:, a], r[:, b] = -x[:, b], x[:, a]
+            modes.append(r)
+    Kmax = float(K.abs().max())
+    worst = 0.0
+    for r in modes:
+        rv = dev(r.ravel())
+        worst = max(worst, float(_spmv(rp, ci, K, rv).abs().max()) / (Kmax * float(rv.abs().max())))
+    # linear patch test: u = Gu x, s_e = |e| eps^T D eps exactly
+    rng = np.random.default_rng(79)
+    Gu = rng.standard_normal((m.dim, m.dim))
+    u = (m.coords @ Gu.T).ravel()
+    eps = 0.5 * (Gu + Gu.T)
+    D = O.D_matrix(m.dim, 1.0, 0.3)
+    ev = (np.array([eps[0, 0], eps[1, 1], 2 * eps[0, 1]]) if m.dim == 2 else
+          np.array([eps[0, 0], eps[1, 1], eps[2, 2], 2 * eps[1, 2], 2 * eps[0, 2], 2 * eps[0, 1]]))
+    X = m.coords[m.cells]
+    if m.dim == 2:
+        a, b = X[:, 1] - X[:, 0], X[:, 2] - X[:, 0]
+        vol = 0.5 * np.abs(a[:, 0] * b[:, 1] - a[:, 1] * b[:, 0])
+    else:
+        J = np.stack([X[:, 1] - X[:, 0], X[:, 3 if m.elem == I.HEX8 else 2] - X[:, 0],
+                      X[:, 4 if m.elem == I.HEX8 else 3] - X[:, 0]], axis=2)
+        vol = np.abs(np.linalg.det(J)) / (1.0 if m.elem == I.HEX8 else 6.0)
+    dens = ev @ D @ ev
+    dc, c = pat.evaluate(MAT, dev(pr.rho), dev(u))
+    dref = -dE(pr.rho) * vol * dens
+    perr = np.max(np.abs(host(dc) - dref) / np.abs(dref))
+    cerr = abs(host(c)[0] - np.sum(E(pr.rho) * vol) * dens) / abs(np.sum(E(pr.rho) * vol) * dens)
+    print(f"{name}: rigid modes |K r| / (|K| |r|) {worst:.2e}; patch test dc {perr:.2e} c {cerr:.2e}")
+    assert worst <= 1e-13 and perr <= 1e-12 and cerr <= 1e-12
+
+
+def test_dirichlet_full_hex():
+    pr, pat, rp, ci = _setup("hex")
+    m = pr.mesh
+    K0 = pat.assemble(MAT, dev(pr.rho))
+    K1 = pat.apply_dirichlet(dev(pr.mask), K0.clone())
+    rows = torch.from_numpy(np.repeat(np.arange(m.ndof), np.diff(rp))).cuda()
+    cols = torch.from_numpy(ci.astype(np.int64)).cuda()
+    mask = dev(pr.mask).bool()
+    fixed = mask[rows] | mask[cols]
+    diag = rows == cols
+    assert torch.equal(K1[~fixed], K0[~fixed])  # every other entry untouched, bit for bit
+    assert bool((K1[fixed & diag] == 1.0).all()) and bool((K1[fixed & ~diag] == 0.0).all())
+    assert int(fixed.sum()) > 0
