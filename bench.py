@@ -94,6 +94,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="minimum CPU time of the oracle baseline (whole passes over the workload)")
+    ap.add_argument("--graph", action="store_true", help="replay the step as a captured HIP graph")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--copy-probe", action="store_true",
@@ -150,6 +151,18 @@ def main():
         step(i)
     torch.cuda.synchronize()
 
+    graphs = None
+    if args.graph:
+        # one captured step per output buffer (HIP graph replay; the kernels
+        # and their order are those of step())
+        graphs = []
+        for b in range(nbuf):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=stream):
+                step(b)
+            graphs.append(g)
+        torch.cuda.synchronize()
+
     events = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -157,6 +170,18 @@ def main():
         step(i, events[i])
     torch.cuda.synchronize()
     total_s = time.perf_counter() - t0
+    eager_s = total_s
+    if graphs is not None:
+        with torch.cuda.stream(stream):
+            for i in range(args.warmup):
+                graphs[i % nbuf].replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with torch.cuda.stream(stream):
+            for i in range(args.steps):
+                graphs[i % nbuf].replay()
+        torch.cuda.synchronize()
+        total_s = time.perf_counter() - t0
     asm_ms = [e[0].elapsed_time(e[1]) for e in events]
     bc_ms = [e[1].elapsed_time(e[2]) for e in events]
     ev_ms = [e[2].elapsed_time(e[3]) for e in events]
@@ -216,6 +241,8 @@ def main():
         },
         "stage_ms": {"assemble": statistics.mean(asm_ms), "dirichlet": statistics.mean(bc_ms),
                      "evaluate": statistics.mean(ev_ms)},
+        "launch": "hip graph replay (kernels timed eagerly for the roofline)" if graphs is not None else "eager",
+        "eager_ms_per_step": eager_s / args.steps * 1e3,
         "evaluate_algorithmic_bytes": ev_bytes,
         "pattern_build_s": build_s,
         "plan": {"groups": stats["n_groups"], "signatures": stats["n_signatures"],

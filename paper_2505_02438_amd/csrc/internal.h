@@ -72,9 +72,10 @@ struct HostPlan {
     std::vector<int32_t> grp_rows;   // [ngroups][kGroupNodes][2]: first CSR slot of the node's rows, row length
     // backward: position of cells[e][j] in the neighbour list of cells[e][i]
     std::vector<uint16_t> pos;       // [n_cells][nen][nen]
-    // per node n and neighbour q (offset row_ptr[dim n] / dim^2 + q): the
-    // position of n in the neighbour list of that neighbour
-    std::vector<uint16_t> nb_rev;
+    // per node n and neighbour J = nb(n)[q] (offset row_ptr[dim n] / dim^2 + q):
+    // the CSR slot of (row dim J, column dim n) and the degree of J
+    std::vector<int32_t> nb_tslot;
+    std::vector<uint16_t> nb_tdeg;
     int kmax = 0, emax = 0, ne_max = 0;  // emax: grouping limit; ne_max: largest group
     int blk_max = 0;                     // largest padded row block (doubles)
     int64_t stage_max = 0;               // largest group stage (doubles)

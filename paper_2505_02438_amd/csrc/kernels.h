@@ -75,7 +75,7 @@ struct BwdParams {
 };
 
 hipError_t launch_assemble(int elem, int prec, const AsmParams &P, int64_t ngroups, hipStream_t st);
-hipError_t launch_dirichlet(int dim, const int32_t *row_ptr, const int32_t *col_idx, const uint16_t *nb_rev,
+hipError_t launch_dirichlet(int dim, const int32_t *row_ptr, const int32_t *nb_tslot, const uint16_t *nb_tdeg,
                             const uint8_t *mask, double *K, int64_t ndof, hipStream_t st);
 hipError_t launch_energy(int elem, int prec, const EnergyParams &P, hipStream_t st);
 hipError_t launch_finalize(const double *partials, int n, int with_f, double *c, hipStream_t st);

@@ -499,18 +499,19 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
     }
 }
 
-// Dirichlet rows and columns (zero prescribed values): for a fixed dof r,
-// K[r, :] = 0, K[:, r] = 0, K[r, r] = 1.  A workgroup takes 64 dofs, lane =
-// dof; its four waves split the dof's row entries and the neighbours J of
-// its node, whose DIM rows hold the column entries (where the node sits in
-// nb(J) comes from the reverse position table).  Fixed dofs are often
-// contiguous (a clamped face), so the work is spread over lanes rather than
-// walked dof by dof.  Entries in two fixed lines get the same value from
-// both, so the order of the writes does not matter.
+// Dirichlet rows and columns (zero prescribed values): for a fixed dof r =
+// DIM I + a, K[r, :] = 0, K[:, r] = 0, K[r, r] = 1.  A workgroup takes 64
+// dofs, lane = dof; its four waves split the neighbours J of node I.  For
+// each neighbour a thread writes the DIM entries of row r in J's columns and
+// the DIM entries of column r in J's rows, the latter through the plan's
+// transposed-slot table (slot of (row DIM J, column DIM I), degree of J).  J
+// is I itself exactly when that slot is I's own block start + DIM q.  Where a
+// row and a column write meet they write the same value, so the order of the
+// writes does not matter.
 template <int DIM>
 __global__ __launch_bounds__(256) void k_dirichlet(const int32_t *__restrict__ row_ptr,
-                                                   const int32_t *__restrict__ col_idx,
-                                                   const uint16_t *__restrict__ nb_rev,
+                                                   const int32_t *__restrict__ nb_tslot,
+                                                   const uint16_t *__restrict__ nb_tdeg,
                                                    const uint8_t *__restrict__ mask, double *K, int64_t ndof) {
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
@@ -519,31 +520,31 @@ __global__ __launch_bounds__(256) void k_dirichlet(const int32_t *__restrict__ r
     const int r = (int)r64;
     const int I = r / DIM, a = r - DIM * I;
     const int b0 = row_ptr[r], b1 = row_ptr[r + 1];
-    for (int k = b0 + w; k < b1; k += 4) K[k] = col_idx[k] == r ? 1.0 : 0.0;
+    const int ib = row_ptr[DIM * I];  // first slot of node I's rows
     const int deg = (b1 - b0) / DIM;
-    const int nptr = row_ptr[DIM * I] / (DIM * DIM);
-    // neighbours q = w, w + 4, ... in batches of 8, each batch's loads in flight together
-    constexpr int B = 8;
+    const int nptr = ib / (DIM * DIM);
+    constexpr int B = 8;  // neighbours per thread with their loads in flight together
     for (int q0 = w; q0 < deg; q0 += 4 * B) {
-        int J[B], t[B], jb[B], jl[B];
+        int ts[B], jl[B];
 #pragma unroll
         for (int c = 0; c < B; c++) {
             const int q = q0 + 4 * c;
-            J[c] = q < deg ? col_idx[b0 + DIM * q] / DIM : I;
-            t[c] = q < deg ? nb_rev[nptr + q] : 0;
+            ts[c] = q < deg ? nb_tslot[nptr + q] : 0;
+            jl[c] = q < deg ? DIM * (int)nb_tdeg[nptr + q] : 0;
         }
 #pragma unroll
         for (int c = 0; c < B; c++) {
-            jb[c] = row_ptr[DIM * J[c]];
-            jl[c] = row_ptr[DIM * J[c] + 1] - jb[c];  // row length of J's rows
-        }
+            const int q = q0 + 4 * c;
+            if (q < deg) {
+                const bool self = ts[c] == ib + DIM * q;
 #pragma unroll
-        for (int c = 0; c < B; c++)
-            if (q0 + 4 * c < deg) {
-#pragma unroll
-                for (int a2 = 0; a2 < DIM; a2++)
-                    K[jb[c] + a2 * jl[c] + DIM * t[c] + a] = (J[c] == I && a2 == a) ? 1.0 : 0.0;
+                for (int e = 0; e < DIM; e++) {
+                    const double v = (self && e == a) ? 1.0 : 0.0;
+                    K[b0 + DIM * q + e] = v;           // row r, column DIM J + e
+                    K[ts[c] + e * jl[c] + a] = v;      // row DIM J + e, column r
+                }
             }
+        }
     }
 }
 
@@ -1045,12 +1046,12 @@ hipError_t launch_energy(int elem, int prec, const EnergyParams &P, hipStream_t 
 #undef SOPTX_EN
 }
 
-hipError_t launch_dirichlet(int dim, const int32_t *row_ptr, const int32_t *col_idx, const uint16_t *nb_rev,
+hipError_t launch_dirichlet(int dim, const int32_t *row_ptr, const int32_t *nb_tslot, const uint16_t *nb_tdeg,
                             const uint8_t *mask, double *K, int64_t ndof, hipStream_t st) {
     const unsigned nb = (unsigned)((ndof + 63) / 64);
     if (nb == 0) return hipSuccess;
-    if (dim == 2) hipLaunchKernelGGL(k_dirichlet<2>, dim3(nb), dim3(256), 0, st, row_ptr, col_idx, nb_rev, mask, K, ndof);
-    else hipLaunchKernelGGL(k_dirichlet<3>, dim3(nb), dim3(256), 0, st, row_ptr, col_idx, nb_rev, mask, K, ndof);
+    if (dim == 2) hipLaunchKernelGGL(k_dirichlet<2>, dim3(nb), dim3(256), 0, st, row_ptr, nb_tslot, nb_tdeg, mask, K, ndof);
+    else hipLaunchKernelGGL(k_dirichlet<3>, dim3(nb), dim3(256), 0, st, row_ptr, nb_tslot, nb_tdeg, mask, K, ndof);
     return hipGetLastError();
 }
 

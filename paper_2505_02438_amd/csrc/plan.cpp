@@ -209,17 +209,20 @@ int build_host_plan(const soptx_mesh *mesh, HostPlan &hp) {
             }
     });
 
-    // ---- reverse neighbour positions: for J = nb(n)[q], where n sits in nb(J)
-    // (the neighbour relation is symmetric); the Dirichlet fix-up reaches the
-    // column entries of a fixed dof through it
-    hp.nb_rev.assign(nb_ptr[NN], 0);
+    // ---- transposed slots: for J = nb(n)[q], the CSR slot of (row dim J,
+    // column dim n) (n sits in nb(J): the neighbour relation is symmetric) and
+    // the degree of J; the Dirichlet fix-up reaches the column entries of a
+    // fixed dof through them
+    hp.nb_tslot.assign(nb_ptr[NN], 0);
+    hp.nb_tdeg.assign(nb_ptr[NN], 0);
     parallel_for(NN, [&](int64_t a0, int64_t a1) {
         for (int64_t n = a0; n < a1; n++)
             for (int64_t k = nb_ptr[n]; k < nb_ptr[n + 1]; k++) {
                 const int32_t J = nb[k];
                 const int32_t *nj = nb.data() + nb_ptr[J];
                 const int64_t t = std::lower_bound(nj, nj + deg[J], (int32_t)n) - nj;
-                hp.nb_rev[k] = (uint16_t)t;
+                hp.nb_tslot[k] = (int32_t)(dim * dim * nb_ptr[J] + dim * t);
+                hp.nb_tdeg[k] = (uint16_t)deg[J];
             }
     });
 

@@ -29,7 +29,8 @@ struct soptx_pattern_s {
     int32_t *grp_rows = nullptr;
     int n_cu = 0;
     int32_t *sig_info = nullptr, *sig_pos_ptr = nullptr, *sig_contrib = nullptr, *sig_pairs = nullptr;
-    uint16_t *pos = nullptr, *nb_rev = nullptr;
+    uint16_t *pos = nullptr, *nb_tdeg = nullptr;
+    int32_t *nb_tslot = nullptr;
     double *M = nullptr;
     float *M32 = nullptr, *Mbf = nullptr;
     double *qw = nullptr, *qgrad = nullptr, *cgrad = nullptr, *xref = nullptr;
@@ -234,7 +235,7 @@ int soptx_build_pattern_ex(const soptx_mesh *mesh, int32_t ref_method, soptx_pat
             free_handle(h); return rc;
         }
         h->stats.plan_bytes = h->stats.device_bytes - base_bytes;
-        if ((rc = upload(h, hp.pos, &h->pos, st)) || (rc = upload(h, hp.nb_rev, &h->nb_rev, st)) || (rc = upload(h, M, &h->M, st)) ||
+        if ((rc = upload(h, hp.pos, &h->pos, st)) || (rc = upload(h, hp.nb_tslot, &h->nb_tslot, st)) || (rc = upload(h, hp.nb_tdeg, &h->nb_tdeg, st)) || (rc = upload(h, M, &h->M, st)) ||
             (rc = upload(h, M32, &h->M32, st)) || (rc = upload(h, Mbf, &h->Mbf, st)) ||
             (rc = upload(h, qw, &h->qw, st)) || (rc = upload(h, qg, &h->qgrad, st)) ||
             (rc = upload(h, qg32, &h->qgrad32, st)) || (rc = upload(h, cg, &h->cgrad, st)) ||
@@ -306,7 +307,7 @@ int soptx_assemble(soptx_pattern h, const soptx_material *m, const void *d_rho, 
     P.kmax = h->kmax; P.stage = h->stage;
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (launch_assemble(h->elem, prec, P, h->ngroups, st) != hipSuccess) return SOPTX_E_DEVICE;
-    if (d_dirichlet && launch_dirichlet(h->dim, h->row_ptr, h->col_idx, h->nb_rev, d_dirichlet, d_K_vals, h->ndof, st) != hipSuccess)
+    if (d_dirichlet && launch_dirichlet(h->dim, h->row_ptr, h->nb_tslot, h->nb_tdeg, d_dirichlet, d_K_vals, h->ndof, st) != hipSuccess)
         return SOPTX_E_DEVICE;
     return SOPTX_OK;
 }
@@ -317,7 +318,7 @@ int soptx_apply_dirichlet(soptx_pattern h, const uint8_t *d_dirichlet, double *d
     DeviceGuard dg(h->device);
     if (!dg.ok) return SOPTX_E_DEVICE;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (launch_dirichlet(h->dim, h->row_ptr, h->col_idx, h->nb_rev, d_dirichlet, d_K_vals, h->ndof, st) != hipSuccess)
+    if (launch_dirichlet(h->dim, h->row_ptr, h->nb_tslot, h->nb_tdeg, d_dirichlet, d_K_vals, h->ndof, st) != hipSuccess)
         return SOPTX_E_DEVICE;
     return SOPTX_OK;
 }
@@ -422,7 +423,7 @@ int soptx_debug_host_plan_array(soptx_host_plan p, const char *name, const void 
     }
     SOPTX_ARR(row_ptr) SOPTX_ARR(col_idx) SOPTX_ARR(geo) SOPTX_ARR(sig_info) SOPTX_ARR(sig_pos_ptr)
     SOPTX_ARR(sig_contrib) SOPTX_ARR(sig_pairs) SOPTX_ARR(grp_info) SOPTX_ARR(grp_nodes) SOPTX_ARR(grp_elems)
-    SOPTX_ARR(grp_n2l) SOPTX_ARR(grp_rows) SOPTX_ARR(pos) SOPTX_ARR(nb_rev)
+    SOPTX_ARR(grp_n2l) SOPTX_ARR(grp_rows) SOPTX_ARR(pos) SOPTX_ARR(nb_tslot) SOPTX_ARR(nb_tdeg)
 #undef SOPTX_ARR
     return SOPTX_E_INVALID_ARG;
 }

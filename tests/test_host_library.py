@@ -282,9 +282,10 @@ def test_plan_axis_aligned_flag_set_on_grids():
 
 
 @pytest.mark.parametrize("elem", ELEMS)
-def test_reverse_neighbour_table(elem):
-    """nb_rev[node n, neighbour q] = position of n in the neighbour list of that
-    neighbour (used to reach the column entries of a fixed dof)."""
+def test_transposed_slot_table(elem):
+    """For node n and neighbour J = nb(n)[q]: nb_tslot = CSR slot of
+    (row dim J, column dim n), nb_tdeg = degree of J (used to reach the column
+    entries of a fixed dof)."""
     pr = I.small_problem(elem, seed=5)
     m = pr.mesh
     hp = api.host_plan(elem, m.coords, m.cells)
@@ -292,11 +293,15 @@ def test_reverse_neighbour_table(elem):
     rp, ci = hp["row_ptr"], hp["col_idx"]
     nbrs = [ci[rp[D * n]:rp[D * n + 1]:D] // D for n in range(m.n_nodes)]
     ptr = np.concatenate([[0], np.cumsum([len(x) for x in nbrs])])
-    assert hp["nb_rev"].size == ptr[-1]
+    assert hp["nb_tslot"].size == ptr[-1] and hp["nb_tdeg"].size == ptr[-1]
     for n in range(m.n_nodes):
         assert rp[D * n] == D * D * ptr[n]
         for q, J in enumerate(nbrs[n]):
-            assert nbrs[J][hp["nb_rev"][ptr[n] + q]] == n
+            k = ptr[n] + q
+            t = hp["nb_tslot"][k]
+            assert hp["nb_tdeg"][k] == len(nbrs[J])
+            assert rp[D * J] <= t < rp[D * J + 1] and ci[t] == D * n  # row D J, column D n
+            assert (t == rp[D * n] + D * q) == (J == n)  # the kernel's test for J == n
 
 
 def test_backward_position_table():
@@ -311,3 +316,37 @@ def test_backward_position_table():
             for j in range(m.nen):
                 Inode, Jnode = m.cells[e, i], m.cells[e, j]
                 assert ci[rp[D * Inode] + D * pos[e, i, j]] == D * Jnode
+
+
+@pytest.mark.parametrize("elem", [I.QUAD4, I.HEX8, I.TET10])
+def test_dirichlet_slot_walk_matches_oracle(elem):
+    """The Dirichlet kernel's write set, walked on the host from the plan tables
+    (lane per fixed dof r = D n + a; for each neighbour J = nb(n)[q] it writes
+    row r's D slots at rp[r] + D q + e and column r's D slots at
+    nb_tslot + e D deg(J) + a), gives the oracle's K with fixed rows and columns
+    replaced by identity ones."""
+    pr = I.small_problem(elem, seed=17)
+    m = pr.mesh
+    hp = api.host_plan(elem, m.coords, m.cells)
+    D = m.dim
+    rp, ci = hp["row_ptr"], hp["col_idx"]
+    K = O.assemble(elem, m.coords, m.cells, pr.rho, rp, ci)
+    ref = O.assemble(elem, m.coords, m.cells, pr.rho, rp, ci, mask=pr.mask)
+    Kw = K.copy()
+    ts_all, td_all = hp["nb_tslot"].astype(np.int64), hp["nb_tdeg"].astype(np.int64)
+    for r in np.flatnonzero(pr.mask):
+        n, a = divmod(int(r), D)
+        ib = int(rp[D * n])
+        deg = (int(rp[r + 1]) - int(rp[r])) // D
+        nptr = ib // (D * D)
+        for q in range(deg):
+            ts, jl = int(ts_all[nptr + q]), D * int(td_all[nptr + q])
+            self_ = ts == ib + D * q
+            for e in range(D):
+                v = 1.0 if (self_ and e == a) else 0.0
+                i_row, i_col = int(rp[r]) + D * q + e, ts + e * jl + a
+                assert 0 <= i_row < ci.size and 0 <= i_col < ci.size
+                assert ci[i_row] == D * int(ci[ib + D * q] // D) + e and ci[i_col] == r
+                Kw[i_row] = v
+                Kw[i_col] = v
+    assert np.array_equal(Kw, ref)
