@@ -150,7 +150,11 @@ static size_t assemble_lds_bytes(int dim, int nen, int prec, int64_t stage, int 
 }
 
 // Persistent, warp-specialised assembly.  One workgroup of 16 waves per CU
-// walks the node groups g0 = blockIdx.x, g0 + gridDim.x, ...; in step s:
+// walks the node groups g0 = blockIdx.x, g0 + gridDim.x, ...  The groups are
+// in node order, so at any time the whole chip writes one contiguous stretch
+// of K (slicing the groups per XCD instead, to share element loads in an
+// XCD's L2, spreads the writes over eight distant stretches and is slower).
+// In step s:
 //   - compute waves (0..7) assemble group s into LDS stage s&1: each takes a
 //     pair of neighbour positions of the group's signature from a ticket
 //     (costliest first); the low half of the wave walks the first position's
@@ -418,7 +422,9 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
 
     // ---- store role: group gg from stage b, row offsets rb.  Each store
     // wave takes every kStoreWaves-th node, two nodes and four values per
-    // lane at a time, so that eight LDS reads are in flight per batch
+    // lane at a time, so that eight LDS reads are in flight per batch.  K is
+    // written once and never read back here: the stores are non-temporal, so
+    // they stream out instead of taking L2 lines that the element loads use
     auto store_group = [&](int b, int rb) {
         const int nn = wave_uniform(shdr[rb][0]);
         const int deg = wave_uniform(shdr[rb][1]);
@@ -445,8 +451,8 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
                 for (int c = 0; c < 4; c++) {
                     const int o = o0 + 64 * c;
                     if (o < bsz) {
-                        P.K[base0 + o] = v0[c];
-                        if (two) P.K[base1 + o] = v1[c];
+                        __builtin_nontemporal_store(v0[c], P.K + base0 + o);
+                        if (two) __builtin_nontemporal_store(v1[c], P.K + base1 + o);
                     }
                 }
             }
@@ -500,24 +506,18 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
 }
 
 // Dirichlet rows and columns (zero prescribed values): for a fixed dof r =
-// DIM I + a, K[r, :] = 0, K[:, r] = 0, K[r, r] = 1.  A workgroup takes 64
-// dofs, lane = dof; its four waves split the neighbours J of node I.  For
-// each neighbour a thread writes the DIM entries of row r in J's columns and
-// the DIM entries of column r in J's rows, the latter through the plan's
-// transposed-slot table (slot of (row DIM J, column DIM I), degree of J).  J
-// is I itself exactly when that slot is I's own block start + DIM q.  Where a
-// row and a column write meet they write the same value, so the order of the
-// writes does not matter.
+// DIM I + a, K[r, :] = 0, K[:, r] = 0, K[r, r] = 1.
+//
+// The writes of one fixed dof r by wave w of four, which takes the
+// neighbours J = nb(I)[q], q = w, w + 4, ...  For each neighbour it writes
+// the DIM entries of row r in J's columns and the DIM entries of column r in
+// J's rows, the latter through the plan's transposed-slot table (slot of (row
+// DIM J, column DIM I), degree of J).  J is I itself exactly when that slot
+// is I's own block start + DIM q.  Where a row and a column write meet they
+// write the same value, so the order of the writes does not matter.
 template <int DIM>
-__global__ __launch_bounds__(256) void k_dirichlet(const int32_t *__restrict__ row_ptr,
-                                                   const int32_t *__restrict__ nb_tslot,
-                                                   const uint16_t *__restrict__ nb_tdeg,
-                                                   const uint8_t *__restrict__ mask, double *K, int64_t ndof) {
-    const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
-    const int64_t r64 = (int64_t)blockIdx.x * 64 + lane;
-    if (r64 >= ndof || !mask[r64]) return;
-    const int r = (int)r64;
+__device__ __forceinline__ void dirichlet_dof(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ nb_tslot,
+                                              const uint16_t *__restrict__ nb_tdeg, double *K, int r, int w) {
     const int I = r / DIM, a = r - DIM * I;
     const int b0 = row_ptr[r], b1 = row_ptr[r + 1];
     const int ib = row_ptr[DIM * I];  // first slot of node I's rows
@@ -545,6 +545,32 @@ __global__ __launch_bounds__(256) void k_dirichlet(const int32_t *__restrict__ r
                 }
             }
         }
+    }
+}
+
+// The dofs are cut into chunks of 64 (lane = dof); workgroup b takes chunks
+// b + k gridDim.x, k < kDirChunks (the launch makes kDirChunks gridDim.x
+// cover every chunk), and loads all their mask bytes at once.  A mask with
+// few fixed dofs thus costs few workgroups, and a contiguous run of fixed
+// dofs (a clamped face) still spreads over many of them.
+constexpr int kDirChunks = 8;
+template <int DIM>
+__global__ __launch_bounds__(256) void k_dirichlet(const int32_t *__restrict__ row_ptr,
+                                                   const int32_t *__restrict__ nb_tslot,
+                                                   const uint16_t *__restrict__ nb_tdeg,
+                                                   const uint8_t *__restrict__ mask, double *K, int64_t ndof) {
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    uint8_t mk[kDirChunks];
+#pragma unroll
+    for (int k = 0; k < kDirChunks; k++) {
+        const int64_t r64 = ((int64_t)blockIdx.x + (int64_t)k * gridDim.x) * 64 + lane;
+        mk[k] = r64 < ndof ? mask[r64] : 0;
+    }
+    for (int k = 0; k < kDirChunks; k++) {
+        if (!mk[k]) continue;
+        const int r = (int)(((int64_t)blockIdx.x + (int64_t)k * gridDim.x) * 64 + lane);
+        dirichlet_dof<DIM>(row_ptr, nb_tslot, nb_tdeg, K, r, w);
     }
 }
 
@@ -1048,7 +1074,7 @@ hipError_t launch_energy(int elem, int prec, const EnergyParams &P, hipStream_t 
 
 hipError_t launch_dirichlet(int dim, const int32_t *row_ptr, const int32_t *nb_tslot, const uint16_t *nb_tdeg,
                             const uint8_t *mask, double *K, int64_t ndof, hipStream_t st) {
-    const unsigned nb = (unsigned)((ndof + 63) / 64);
+    const unsigned nb = (unsigned)(((ndof + 63) / 64 + kDirChunks - 1) / kDirChunks);
     if (nb == 0) return hipSuccess;
     if (dim == 2) hipLaunchKernelGGL(k_dirichlet<2>, dim3(nb), dim3(256), 0, st, row_ptr, nb_tslot, nb_tdeg, mask, K, ndof);
     else hipLaunchKernelGGL(k_dirichlet<3>, dim3(nb), dim3(256), 0, st, row_ptr, nb_tslot, nb_tdeg, mask, K, ndof);
