@@ -239,3 +239,53 @@ def test_argument_errors_raise():
         pat.assemble(MAT, dev(pr.rho[:-1]))
     with pytest.raises(Exception):
         pat.assemble(api.Material(nu=0.5), dev(pr.rho))
+
+
+@pytest.mark.parametrize("elem", ELEMS)
+def test_shuffled_numbering(elem):
+    """Nodes and elements renumbered by a seeded permutation: a group's nodes
+    are then no longer consecutive rows, and an element's nodes are far apart.
+    K, dc and c against the oracle on the renumbered mesh."""
+    pr = I.small_problem(elem, seed=61)
+    m0 = pr.mesh
+    rng = np.random.default_rng(62)
+    pn = rng.permutation(m0.n_nodes)       # new id of old node i: pn[i]
+    pe = rng.permutation(m0.n_cells)       # old element of new element k: pe[k]
+    coords = np.empty_like(m0.coords)
+    coords[pn] = m0.coords
+    cells = pn[m0.cells[pe]].astype(np.int32)
+    rho = pr.rho[pe]
+    m = I.Mesh(elem, coords, cells)
+    u = np.empty(m.ndof)
+    u.reshape(-1, m.dim)[pn] = pr.u.reshape(-1, m.dim)
+    pat = api.Pattern(elem, coords, cells)
+    rp, ci = O.pattern(elem, m.n_nodes, cells)
+    drp, dci = pat.pattern()
+    assert np.array_equal(drp, rp) and np.array_equal(dci, ci)
+    K = host(pat.assemble(MAT, dev(rho)))
+    err = row_scaled_err(rp, K, O.assemble(elem, coords, cells, rho, rp, ci))
+    dc, c = pat.evaluate(MAT, dev(rho), dev(u))
+    dref = O.sensitivity(elem, coords, cells, rho, u)
+    cref = O.compliance(elem, coords, cells, rho, u)
+    sc = dE(rho) * abs_energy(m, u, np.arange(m.n_cells))
+    derr = float(np.max(np.abs(host(dc) - dref) / sc))
+    cerr = abs(float(host(c)[0]) - cref[0]) / float(np.sum(E(rho) * abs_energy(m, u, np.arange(m.n_cells))))
+    print(f"elem={elem} shuffled: K {err:.2e} dc {derr:.2e} c {cerr:.2e}")
+    assert err <= TOL[api.FP64] and derr <= TOL[api.FP64] and cerr <= TOL[api.FP64]
+
+
+@pytest.mark.parametrize("elem", [I.QUAD4, I.HEX8, I.TET10])
+def test_dirichlet_extreme_masks(elem):
+    """Every dof fixed (K becomes the identity on the pattern) and only the
+    last dof fixed (a ragged last chunk of the Dirichlet launch)."""
+    pr, m, pat, rp, ci = _setup(elem)
+    rows = np.repeat(np.arange(m.ndof), np.diff(rp))
+    K = host(pat.assemble(MAT, dev(pr.rho), dev(np.ones(m.ndof, dtype=np.uint8))))
+    assert np.array_equal(K, (rows == ci).astype(np.float64))
+    last = np.zeros(m.ndof, dtype=np.uint8)
+    last[-1] = 1
+    K = host(pat.assemble(MAT, dev(pr.rho), dev(last)))
+    Kref = O.assemble(elem, m.coords, m.cells, pr.rho, rp, ci, mask=last)
+    touched = (rows == m.ndof - 1) | (ci == m.ndof - 1)
+    assert np.array_equal(K[touched], Kref[touched])  # exact 0 / 1
+    assert row_scaled_err(rp, K, Kref) <= TOL[api.FP64]
