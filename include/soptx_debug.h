@@ -27,7 +27,7 @@ int soptx_debug_host_plan(const soptx_mesh *mesh, soptx_host_plan *out);
 
 /* Borrow one array of the plan by name: "row_ptr", "col_idx" (int32 CSR),
  * "geo" (double, [(dim*dim+1)][n_cells]: J^-1 row-major then det J),
- * "sig_info", "sig_pos_ptr", "sig_contrib", "sig_pairs", "grp_info", "grp_nodes",
+ * "sig_info", "sig_pos_ptr", "sig_contrib", "sig_pairs", "sig_witems", "sig_witem_ptr", "grp_info", "grp_nodes",
  * "grp_elems", "grp_rows", "nb_tslot" (int32), "grp_n2l", "pos", "nb_tdeg" (uint16).
  * The pointer stays valid until soptx_debug_host_plan_free. */
 int soptx_debug_host_plan_array(soptx_host_plan p, const char *name, const void **data, int64_t *count,

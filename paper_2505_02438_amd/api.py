@@ -65,7 +65,7 @@ def host_plan(elem: int, coords, cells) -> dict:
     try:
         out = {}
         dt = {4: np.int32, 2: np.uint16, 8: np.float64}
-        for name in ("row_ptr", "col_idx", "geo", "sig_info", "sig_pos_ptr", "sig_contrib", "sig_pairs",
+        for name in ("row_ptr", "col_idx", "geo", "sig_info", "sig_pos_ptr", "sig_contrib", "sig_pairs", "sig_witems", "sig_witem_ptr",
                      "grp_info", "grp_nodes", "grp_elems", "grp_n2l", "grp_rows", "pos", "nb_tslot", "nb_tdeg"):
             ptr, cnt, eb = ctypes.c_void_p(), ctypes.c_int64(), ctypes.c_int32()
             check(L.soptx_debug_host_plan_array(h, name.encode(), ctypes.byref(ptr), ctypes.byref(cnt),

@@ -19,6 +19,10 @@ constexpr int kMaxNen = 10;
 // fields per group in grp_info, and the flag bits of its last field
 constexpr int kGrpInfo = 6;
 constexpr int kGrpDiag = 1;  // every element of the group has a diagonal J^-1 (axis-aligned)
+// bits 1-2 of a group's flags: log2(32 / N) for a signature whose groups hold
+// at most N = 8 or 16 nodes, run as wide work items (kGrpWideShift)
+constexpr int kGrpWideShift = 1;
+constexpr int kWideInts = 32;  // ints per wide work item: P, Q, T, 0 x 5, p[8], off[8], cnt[8]
 
 inline int elem_dim(int elem) {
     switch (elem) {
@@ -64,6 +68,10 @@ struct HostPlan {
     std::vector<int32_t> sig_pos_ptr;  // per signature deg+1 offsets into sig_contrib
     std::vector<int32_t> sig_contrib;  // (k << 16) | (i << 8) | j
     std::vector<int32_t> sig_pairs;    // per signature 2 (deg + 1) entries: work items (pa, pb), then -1
+    // wide work items of the signatures whose groups hold at most 16 nodes:
+    // signature s owns records sig_witem_ptr[s] .. sig_witem_ptr[s + 1]
+    std::vector<int32_t> sig_witems;    // [n][kWideInts]
+    std::vector<int32_t> sig_witem_ptr; // [nsig + 1]
     // groups
     std::vector<int32_t> grp_info;   // [ngroups][kGrpInfo]: sig, n_nodes, elem_off, n_elem, n2l_off, flags
     std::vector<int32_t> grp_nodes;  // [ngroups][kGroupNodes], -1 padded

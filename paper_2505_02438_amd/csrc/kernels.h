@@ -21,6 +21,8 @@ struct AsmParams {
     const int32_t *sig_pos_ptr;
     const int32_t *sig_contrib;
     const int32_t *sig_pairs;   // per signature (offset 2 pos_off): work items (pa, pb), -1 terminated
+    const int32_t *sig_witems;  // [n][kWideInts]: wide work items
+    const int32_t *sig_witem_ptr;  // [S + 1]
     const double *geo;
     const void *rho;
     const double *M;

@@ -195,10 +195,11 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
     int32_t *srows = reinterpret_cast<int32_t *>(sM + NEN * NEN * D2);      // [3][NG][2]
     uint16_t *sn2l = reinterpret_cast<uint16_t *>(srows + 3 * NG * 2);      // [2][kmax][NG]
     __shared__ int ticket[2];
-    // group headers, one per row-offset buffer: nn, deg, posoff, blk, flags.
+    // group headers, one per row-offset buffer: nn, deg, posoff, blk, flags,
+    // first wide work item, number of wide work items.
     // Written by the load waves with the group's other data, so that the
     // compute and store waves start a step without a chain of scalar loads
-    __shared__ int shdr[3][5];
+    __shared__ int shdr[3][7];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -310,16 +311,127 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
             shdr[rb][2] = ldc(P.sig_info, 4 * sg + 2);
             shdr[rb][3] = ldc(P.sig_info, 4 * sg + 3);
             shdr[rb][4] = flags;
+            const int wi0 = ldc(P.sig_witem_ptr, sg);
+            shdr[rb][5] = wi0;
+            shdr[rb][6] = ldc(P.sig_witem_ptr, sg + 1) - wi0;
+        }
+    };
+
+    // ---- compute role, wide work items (groups of at most N = 8 or 16
+    // nodes): lane = (pp Q + q) N + node takes position p[pp] of the item and
+    // its contributions q, q + Q, ...; the Q phases of a position are then
+    // added by a butterfly over the phase bits of the lane index (a fixed
+    // order), and phase 0 writes the block
+    auto compute_group_wide = [&](int b, int rb) {
+        const int nn = wave_uniform(shdr[rb][0]);
+        const int deg = wave_uniform(shdr[rb][1]);
+        const int blk = wave_uniform(shdr[rb][3]);
+        const int flags = wave_uniform(shdr[rb][4]);
+        const int wi0 = wave_uniform(shdr[rb][5]);
+        const int nwi = wave_uniform(shdr[rb][6]);
+        const bool diag = flags & kGrpDiag;
+        const int lgN = 5 - ((flags >> kGrpWideShift) & 3);  // N = 8 or 16
+        const int N = 1 << lgN;
+        const int rl = DIM * deg;
+        const int node = lane & (N - 1);
+        double *st = stage + b * P.stage + node * blk;
+        const T *G = sG + b * D2 * kGroupElems;
+        const uint16_t *n2l = sn2l + b * n2l_stride + node;
+        for (;;) {
+            int r = 0;
+            if (lane == 0) r = atomicAdd(&ticket[b], 1);
+            r = wave_uniform(r);
+            if (r >= nwi) break;
+            const int32_t *rec = P.sig_witems + (int64_t)(wi0 + r) * kWideInts;
+            const int np = ldc(rec, 0), Q = ldc(rec, 1), nt = ldc(rec, 2);
+            const int lgQ = 31 - __clz(Q);
+            const int grp = lane >> lgN;
+            const int pp = grp >> lgQ, q = grp & (Q - 1);
+            // this lane's position, its contribution offset and count
+            int p = -1, off = 0, cnt = 0;
+#pragma unroll
+            for (int k = 0; k < 8; k++)
+                if (pp == k) {
+                    p = ldc(rec, 8 + k);
+                    off = ldc(rec, 16 + k);
+                    cnt = ldc(rec, 24 + k);
+                }
+            const bool mine = pp < np && node < nn;
+            double acc[DIM][DIM];
+#pragma unroll
+            for (int a = 0; a < DIM; a++)
+#pragma unroll
+                for (int c = 0; c < DIM; c++) acc[a][c] = 0.0;
+            // contributions of this lane: all loads first (nt <= 8)
+            int pk[8];
+#pragma unroll
+            for (int t = 0; t < 8; t++) {
+                const int ti = q + t * Q;
+                pk[t] = (t < nt && mine && ti < cnt) ? P.sig_contrib[off + ti] : -1;
+            }
+#pragma unroll
+            for (int t = 0; t < 8; t++) {
+                if (t >= nt) break;
+                if (pk[t] >= 0) {
+                    const int k = pk[t] >> 16, i = (pk[t] >> 8) & 255, j = pk[t] & 255;
+                    const int slot = n2l[k * NG];
+                    const T *Mij = sM + (i * NEN + j) * D2;
+                    T Mv[D2];
+#pragma unroll
+                    for (int x = 0; x < D2; x++) Mv[x] = Mij[x];
+                    if (diag) {
+                        T dd[DIM][DIM];
+#pragma unroll
+                        for (int a = 0; a < DIM; a++)
+#pragma unroll
+                            for (int c = a; c < DIM; c++) {
+                                dd[a][c] = G[(a * DIM + c) * kGroupElems + slot];
+                                dd[c][a] = dd[a][c];
+                            }
+                        accumulate_diag<DIM, PREC>(dd, Mv, acc);
+                    } else {
+                        T Gv[DIM][DIM];
+#pragma unroll
+                        for (int m = 0; m < DIM; m++)
+#pragma unroll
+                            for (int a = 0; a < DIM; a++) Gv[m][a] = G[(m * DIM + a) * kGroupElems + slot];
+                        accumulate<DIM, PREC>(Gv, Mv, acc);
+                    }
+                }
+            }
+            for (int sh = N; sh < N * Q; sh <<= 1)
+#pragma unroll
+                for (int a = 0; a < DIM; a++)
+#pragma unroll
+                    for (int c = 0; c < DIM; c++) acc[a][c] += __shfl_xor(acc[a][c], sh);
+            if (mine && q == 0) {
+                double tr = 0.0;
+#pragma unroll
+                for (int a = 0; a < DIM; a++) tr += acc[a][a];
+#pragma unroll
+                for (int a = 0; a < DIM; a++)
+#pragma unroll
+                    for (int c = 0; c < DIM; c++) {
+                        double o = P.lam * acc[a][c] + P.mu * acc[c][a];
+                        if (a == c) o += P.mu * tr;
+                        st[a * rl + DIM * p + c] = o;
+                    }
+            }
         }
     };
 
     // ---- compute role: group gg from buffers b into stage b
     auto compute_group = [&](int b, int rb) {
+        const int flags = wave_uniform(shdr[rb][4]);
+        if (flags >> kGrpWideShift) {
+            compute_group_wide(b, rb);
+            return;
+        }
         const int nn = wave_uniform(shdr[rb][0]);
         const int deg = wave_uniform(shdr[rb][1]);
         const int posoff = wave_uniform(shdr[rb][2]);
         const int blk = wave_uniform(shdr[rb][3]);
-        const bool diag = wave_uniform(shdr[rb][4]) & kGrpDiag;
+        const bool diag = flags & kGrpDiag;
         const int rl = DIM * deg;
         const bool hi = lane >= NG;
         const int node = lane & (NG - 1);

@@ -2,6 +2,7 @@
 // pattern and the assembly plan (Sec. 3.2.2: invariant components are built
 // once and reused across optimisation iterations).
 #include <algorithm>
+#include <array>
 #include <climits>
 #include <cmath>
 #include <cstring>
@@ -434,7 +435,69 @@ int build_host_plan(const soptx_mesh *mesh, HostPlan &hp) {
     // writes one contiguous window of K at a time and neighbouring groups
     // share element data in cache
     std::sort(closed.begin(), closed.end(), [](const Closed &x, const Closed &y) { return x.nodes[0] < y.nodes[0]; });
+    // ---- wide work items.  A signature whose groups hold at most N = 8 or 16
+    // nodes would leave most lanes of a half-wave idle.  Its work items
+    // instead cover P positions, each dealt round robin over Q phases
+    // (contribution t to phase t mod Q), with P Q N = 64 lanes: lane =
+    // (pp Q + q) N + node.  A position with c contributions gets the
+    // smallest Q with ceil(c / Q) <= L, L = ceil(c_max / (64 / N)), so that
+    // every lane runs at most L of them; positions with the same Q share
+    // items, costliest first.
+    std::vector<int> gmax(nsig, 0);
+    for (const Closed &c : closed) gmax[c.sig] = std::max(gmax[c.sig], (int)c.nodes.size());
+    std::vector<int> wideN(nsig, 32);
+    hp.sig_witems.clear();
+    hp.sig_witem_ptr.assign(1, 0);
+    for (int64_t s = 0; s < nsig; s++) {
+        if (gmax[s] > 0 && gmax[s] <= 16) wideN[s] = gmax[s] <= 8 ? 8 : 16;
+        if (wideN[s] < 32) {
+            const int PQ = 64 / wideN[s];
+            const int dg = hp.sig_info[s * 4 + 1];
+            const int32_t *pp = hp.sig_pos_ptr.data() + hp.sig_info[s * 4 + 2];
+            int cmax = 1;
+            for (int p = 0; p < dg; p++) cmax = std::max(cmax, pp[p + 1] - pp[p]);
+            const int L = (cmax + PQ - 1) / PQ;
+            std::vector<std::vector<int>> byQ(PQ + 1);
+            for (int p = 0; p < dg; p++) {
+                const int c = pp[p + 1] - pp[p];
+                int Q = 1;
+                while ((c + Q - 1) / Q > L) Q *= 2;
+                byQ[Q].push_back(p);
+            }
+            std::vector<std::array<int32_t, kWideInts>> items;
+            for (int Q = 1; Q <= PQ; Q *= 2) {
+                auto &v = byQ[Q];
+                std::stable_sort(v.begin(), v.end(), [&](int x, int y) { return pp[x + 1] - pp[x] > pp[y + 1] - pp[y]; });
+                const int P = PQ / Q;
+                for (size_t i = 0; i < v.size(); i += P) {
+                    std::array<int32_t, kWideInts> r{};
+                    r[0] = std::min<int>(P, (int)(v.size() - i));
+                    r[1] = Q;
+                    int T = 0;
+                    for (int k = 0; k < 8; k++) {
+                        const bool on = k < r[0];
+                        const int p = on ? v[i + k] : -1;
+                        const int c = on ? pp[p + 1] - pp[p] : 0;
+                        r[8 + k] = p;
+                        r[16 + k] = on ? pp[p] : 0;  // index into sig_contrib
+                        r[24 + k] = c;
+                        T = std::max(T, (c + Q - 1) / Q);
+                    }
+                    r[2] = T;
+                    items.push_back(r);
+                }
+            }
+            std::stable_sort(items.begin(), items.end(), [](const auto &x, const auto &y) { return x[2] > y[2]; });
+            for (const auto &r : items) hp.sig_witems.insert(hp.sig_witems.end(), r.begin(), r.end());
+        }
+        hp.sig_witem_ptr.push_back((int32_t)(hp.sig_witems.size() / kWideInts));
+    }
     for (Closed &c : closed) emit(c);
+    // mark the groups of wide signatures
+    for (int64_t g = 0; g < hp.n_groups(); g++) {
+        const int N = wideN[hp.grp_info[kGrpInfo * g + 0]];
+        if (N < 32) hp.grp_info[kGrpInfo * g + 5] |= (N == 8 ? 2 : 1) << kGrpWideShift;
+    }
     hp.ne_max = 0;
     for (int64_t g = 0; g < hp.n_groups(); g++) hp.ne_max = std::max(hp.ne_max, hp.grp_info[kGrpInfo * g + 3]);
     if (hp.grp_elems.size() >= (size_t)INT32_MAX || hp.grp_n2l.size() >= (size_t)INT32_MAX)

@@ -29,6 +29,7 @@ struct soptx_pattern_s {
     int32_t *grp_rows = nullptr;
     int n_cu = 0;
     int32_t *sig_info = nullptr, *sig_pos_ptr = nullptr, *sig_contrib = nullptr, *sig_pairs = nullptr;
+    int32_t *sig_witems = nullptr, *sig_witem_ptr = nullptr;
     uint16_t *pos = nullptr, *nb_tdeg = nullptr;
     int32_t *nb_tslot = nullptr;
     double *M = nullptr;
@@ -231,7 +232,8 @@ int soptx_build_pattern_ex(const soptx_mesh *mesh, int32_t ref_method, soptx_pat
             (rc = upload(h, hp.grp_elems, &h->grp_elems, st)) || (rc = upload(h, hp.grp_n2l, &h->grp_n2l, st)) ||
             (rc = upload(h, hp.grp_rows, &h->grp_rows, st)) ||
             (rc = upload(h, hp.sig_info, &h->sig_info, st)) || (rc = upload(h, hp.sig_pos_ptr, &h->sig_pos_ptr, st)) ||
-            (rc = upload(h, hp.sig_contrib, &h->sig_contrib, st)) || (rc = upload(h, hp.sig_pairs, &h->sig_pairs, st))) {
+            (rc = upload(h, hp.sig_contrib, &h->sig_contrib, st)) || (rc = upload(h, hp.sig_pairs, &h->sig_pairs, st)) ||
+            (rc = upload(h, hp.sig_witems, &h->sig_witems, st)) || (rc = upload(h, hp.sig_witem_ptr, &h->sig_witem_ptr, st))) {
             free_handle(h); return rc;
         }
         h->stats.plan_bytes = h->stats.device_bytes - base_bytes;
@@ -299,7 +301,7 @@ int soptx_assemble(soptx_pattern h, const soptx_material *m, const void *d_rho, 
     P.grp_info = h->grp_info; P.grp_nodes = h->grp_nodes; P.grp_elems = h->grp_elems; P.grp_n2l = h->grp_n2l;
     P.grp_rows = h->grp_rows; P.n_groups = h->ngroups; P.n_cu = h->n_cu;
     P.sig_info = h->sig_info; P.sig_pos_ptr = h->sig_pos_ptr; P.sig_contrib = h->sig_contrib;
-    P.sig_pairs = h->sig_pairs;
+    P.sig_pairs = h->sig_pairs; P.sig_witems = h->sig_witems; P.sig_witem_ptr = h->sig_witem_ptr;
     P.geo = h->geo; P.rho = d_rho;
     P.M = h->M; P.M32 = h->M32; P.Mbf = h->Mbf; P.K = d_K_vals;
     P.n_cells = h->n_cells; P.E0 = m->E0; P.Emin = m->Emin; P.p = m->p; P.ip = int_exponent(m->p);
@@ -422,7 +424,7 @@ int soptx_debug_host_plan_array(soptx_host_plan p, const char *name, const void 
         return SOPTX_OK;                                        \
     }
     SOPTX_ARR(row_ptr) SOPTX_ARR(col_idx) SOPTX_ARR(geo) SOPTX_ARR(sig_info) SOPTX_ARR(sig_pos_ptr)
-    SOPTX_ARR(sig_contrib) SOPTX_ARR(sig_pairs) SOPTX_ARR(grp_info) SOPTX_ARR(grp_nodes) SOPTX_ARR(grp_elems)
+    SOPTX_ARR(sig_contrib) SOPTX_ARR(sig_pairs) SOPTX_ARR(sig_witems) SOPTX_ARR(sig_witem_ptr) SOPTX_ARR(grp_info) SOPTX_ARR(grp_nodes) SOPTX_ARR(grp_elems)
     SOPTX_ARR(grp_n2l) SOPTX_ARR(grp_rows) SOPTX_ARR(pos) SOPTX_ARR(nb_tslot) SOPTX_ARR(nb_tdeg)
 #undef SOPTX_ARR
     return SOPTX_E_INVALID_ARG;

@@ -188,10 +188,35 @@ def walk_plan(hp, mesh, rho, M, E0=1.0, Emin=1e-9, p=3.0, nu=0.3, mask=None):
                 costs.append(cnt[pa])
         assert sorted(covered) == list(range(deg))  # every position exactly once
         assert np.all(np.diff(costs) <= 0)  # costliest first
+        wsh = (flags >> 1) & 3
+        if wsh:
+            # wide work items: P positions x Q phases x N nodes = 64 lanes
+            N = 32 >> wsh
+            assert nn <= N
+            wr = hp["sig_witems"].reshape(-1, 32)[hp["sig_witem_ptr"][sig]:hp["sig_witem_ptr"][sig + 1]]
+            wcov, wcost = [], []
+            for rec in wr:
+                P, Q, T = (int(x) for x in rec[:3])
+                assert Q & (Q - 1) == 0 and 1 <= P and P * Q * N <= 64 and T <= 8
+                tmax = 0
+                for k in range(8):
+                    p, off, c = int(rec[8 + k]), int(rec[16 + k]), int(rec[24 + k])
+                    if k < P:
+                        assert off == hp["sig_pos_ptr"][posoff + p] and c == cnt[p]
+                        wcov.append(p)
+                        tmax = max(tmax, -(-c // Q))
+                    else:
+                        assert p == -1 and c == 0
+                assert T == tmax
+                wcost.append(T)
+            assert sorted(wcov) == list(range(deg)) and np.all(np.diff(wcost) <= 0)
+            split = {}  # the phases of a position are summed by the kernel's butterfly
+        else:
+            assert hp["sig_witem_ptr"][sig + 1] == hp["sig_witem_ptr"][sig]
         elems = hp["grp_elems"][eoff:eoff + ne]
         assert ne <= hp["emax"] and np.all(np.diff(elems) > 0)
         offdiag = G[elems][:, ~np.eye(D, dtype=bool)]
-        assert flags == (1 if np.all(offdiag == 0.0) else 0)
+        assert (flags & 1) == (1 if np.all(offdiag == 0.0) else 0)
         n2l = hp["grp_n2l"][n2loff:n2loff + Kk * NG].reshape(Kk, NG)
         for lane in range(nn):
             Inode = hp["grp_nodes"][NG * g + lane]
@@ -264,7 +289,7 @@ def test_plan_walk_skewed_q1(elem, skew):
     pr = I.small_problem(elem, seed=6, skew=skew, dims=(8, 5) if elem == I.QUAD4 else (6, 4, 5))
     m = pr.mesh
     hp = api.host_plan(elem, m.coords, m.cells)
-    flags = hp["grp_info"].reshape(-1, 6)[:, 5]
+    flags = hp["grp_info"].reshape(-1, 6)[:, 5] & 1  # bit 0: axis-aligned
     if skew == "global":
         assert np.all(flags == 0)
     else:
@@ -278,7 +303,7 @@ def test_plan_walk_skewed_q1(elem, skew):
 def test_plan_axis_aligned_flag_set_on_grids():
     for mesh in [I.quad_grid(9, 4), I.hex_grid(5, 3, 4)]:
         hp = api.host_plan(mesh.elem, mesh.coords, mesh.cells)
-        assert np.all(hp["grp_info"].reshape(-1, 6)[:, 5] == 1)
+        assert np.all(hp["grp_info"].reshape(-1, 6)[:, 5] & 1 == 1)
 
 
 @pytest.mark.parametrize("elem", ELEMS)
