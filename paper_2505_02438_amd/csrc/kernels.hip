@@ -169,9 +169,10 @@ static size_t assemble_lds_bytes(int dim, int nen, int prec, int64_t stage, int 
 //     the row offsets) into the other LDS buffers.  They load only, so their
 //     waits cover their own loads and none of the stores.
 // One workgroup barrier ends a step.  Summation order of a stored block: the
-// signature's contribution order (ascending element within the block), then
-// L(A) = lam A + mu A^T + mu tr(A) I; fixed by the mesh, independent of waves
-// and streams.
+// signature's contribution order (ascending element within the block; for a
+// wide work item, each phase's contributions in that order, then the phases
+// by a butterfly), then L(A) = lam A + mu A^T + mu tr(A) I; fixed by the
+// mesh, independent of waves and streams.
 constexpr int kAsmThreads = 1024;
 constexpr int kCompWaves = 8, kStoreWaves = 4, kLoadWaves = 4;
 static_assert(kCompWaves + kStoreWaves + kLoadWaves == kAsmThreads / 64, "wave roles");
