@@ -129,6 +129,14 @@ __device__ __forceinline__ void accumulate(const T (&G)[DIM][DIM], const T (&M)[
     }
 }
 
+// G'_aa G'_cc in the form's precision (bf16-rounded in the bf16 form)
+template <int PREC, typename T>
+__device__ __forceinline__ T diag_product(T da, T dc) {
+    if (PREC == kF64) return da * dc;
+    if (PREC == kF32) return (T)((float)da * (float)dc);
+    return (T)bf16_round((float)da * (float)dc);
+}
+
 // acc += G'^T M_ij G' for diagonal G': entry (a, b) is G'_aa G'_bb M_ij[a][b];
 // dd holds the products G'_aa G'_bb (bf16-rounded in the bf16 form)
 template <int DIM, int PREC, typename T>
@@ -165,8 +173,8 @@ static size_t assemble_lds_bytes(int dim, int nen, int prec, int64_t stage, int 
 //     stores only and never wait for them, so the CU's stores stream while
 //     the next groups are computed;
 //   - load waves (12..15) load group s+1 (G' = sqrt(E(rho) det J) J^-1, or
-//     for an axis-aligned group the products G'_aa G'_bb, the slot table and
-//     the row offsets) into the other LDS buffers.  They load only, so their
+//     for an axis-aligned group its diagonal G'_aa, the slot table and the
+//     row offsets) into the other LDS buffers.  They load only, so their
 //     waits cover their own loads and none of the stores.
 // One workgroup barrier ends a step.  Summation order of a stored block: the
 // signature's contribution order (ascending element within the block; for a
@@ -282,19 +290,10 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
                 const double E = P.Emin + simp_pow((double)q.prho[h], P.p, P.ip) * (P.E0 - P.Emin);
                 const double qq = sqrt(E * q.pd[h][D2]);
                 if (flags & kGrpDiag) {
-                    T d[DIM];
+                    // the diagonal G'_aa only; the compute waves form the
+                    // products G'_aa G'_cc
 #pragma unroll
-                    for (int a = 0; a < DIM; a++) d[a] = (T)(qq * q.pd[h][a * DIM + a]);
-#pragma unroll
-                    for (int a = 0; a < DIM; a++)
-#pragma unroll
-                        for (int c = 0; c < DIM; c++) {
-                            T v;
-                            if (PREC == kF64) v = d[a] * d[c];
-                            else if (PREC == kF32) v = (T)((float)d[a] * (float)d[c]);
-                            else v = (T)bf16_round((float)d[a] * (float)d[c]);
-                            G[(a * DIM + c) * kGroupElems + slot] = v;
-                        }
+                    for (int a = 0; a < DIM; a++) G[a * kGroupElems + slot] = (T)(qq * q.pd[h][a * DIM + a]);
                 } else {
 #pragma unroll
                     for (int c = 0; c < D2; c++) G[c * kGroupElems + slot] = (T)(qq * q.pd[h][c]);
@@ -386,7 +385,7 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
                         for (int a = 0; a < DIM; a++)
 #pragma unroll
                             for (int c = a; c < DIM; c++) {
-                                dd[a][c] = G[(a * DIM + c) * kGroupElems + slot];
+                                dd[a][c] = diag_product<PREC>(G[a * kGroupElems + slot], G[c * kGroupElems + slot]);
                                 dd[c][a] = dd[a][c];
                             }
                         accumulate_diag<DIM, PREC>(dd, Mv, acc);
@@ -494,7 +493,7 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
                         for (int a = 0; a < DIM; a++)
 #pragma unroll
                             for (int c = a; c < DIM; c++) {
-                                dd[a][c] = G[(a * DIM + c) * kGroupElems + slot];
+                                dd[a][c] = diag_product<PREC>(G[a * kGroupElems + slot], G[c * kGroupElems + slot]);
                                 dd[c][a] = dd[a][c];
                             }
                         if (ok[u]) accumulate_diag<DIM, PREC>(dd, Mv, acc);
