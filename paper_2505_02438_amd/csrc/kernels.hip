@@ -544,6 +544,29 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
         const int bsz = DIM * DIM * deg;  // the node's DIM rows, contiguous in CSR
         const int32_t *rows = srows + rb * 2 * NG;
         const double *sb = stage + b * P.stage;
+        if (DIM == 2 && bsz <= 64) {
+            // short row blocks (2D elements): lane = (node j of npi, value o),
+            // so that one batch of four stores covers 4 npi of the wave's
+            // nodes w', w' + kStoreWaves, ... instead of one node per store
+            const int npi = 64 / bsz;  // nodes per store instruction
+            const int j = lane / bsz, o = lane - j * bsz;
+            const int sw = w - kCompWaves;
+            for (int b0 = 0; b0 * kStoreWaves + sw < nn; b0 += 4 * npi) {
+                double v[4];
+                int dst[4];
+#pragma unroll
+                for (int c = 0; c < 4; c++) {
+                    const int n = sw + kStoreWaves * (b0 + c * npi + j);
+                    const bool ok = j < npi && n < nn;
+                    v[c] = ok ? sb[n * blk + o] : 0.0;
+                    dst[c] = ok ? rows[2 * n] + o : -1;
+                }
+#pragma unroll
+                for (int c = 0; c < 4; c++)
+                    if (dst[c] >= 0) __builtin_nontemporal_store(v[c], P.K + dst[c]);
+            }
+            return;
+        }
         for (int n0 = w - kCompWaves; n0 < nn; n0 += 2 * kStoreWaves) {
             const int n1 = n0 + kStoreWaves;
             const bool two = n1 < nn;
