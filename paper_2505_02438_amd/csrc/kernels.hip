@@ -533,8 +533,9 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
     };
 
     // ---- store role: group gg from stage b, row offsets rb.  Each store
-    // wave takes every kStoreWaves-th node, two nodes and four values per
-    // lane at a time, so that eight LDS reads are in flight per batch.  K is
+    // wave takes every kStoreWaves-th node of the group's first half together
+    // with its partner half a group later, four values per lane and node at
+    // a time, so that eight LDS reads are in flight per batch.  K is
     // written once and never read back here: the stores are non-temporal, so
     // they stream out instead of taking L2 lines that the element loads use
     auto store_group = [&](int b, int rb) {
@@ -567,8 +568,10 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
             }
             return;
         }
-        for (int n0 = w - kCompWaves; n0 < nn; n0 += 2 * kStoreWaves) {
-            const int n1 = n0 + kStoreWaves;
+        // a wave's two nodes of a batch lie half a group apart
+        const int half = (nn + 1) / 2;
+        for (int n0 = w - kCompWaves; n0 < half; n0 += kStoreWaves) {
+            const int n1 = n0 + half;
             const bool two = n1 < nn;
             const int base0 = rows[2 * n0];
             const int base1 = two ? rows[2 * n1] : base0;
