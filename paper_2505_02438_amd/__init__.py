@@ -7,6 +7,6 @@ Submodules are imported lazily so that the seeded input generators
 * ``api``      -- Pattern / Material binding of the C ABI (include/soptx.h)
 * ``autograd`` -- torch.autograd.Function around assembly with the
                   hand-written backward kernel
-* ``serve``    -- continuous-batching request loop
+* ``serving``  -- continuous-batching request loop
 * ``inputs``   -- seeded synthetic meshes, loads, boundary conditions
 """

@@ -72,8 +72,6 @@ template <class T>
 __device__ __forceinline__ T ldc(const T *base, int64_t idx) {
     return ((const __attribute__((address_space(4))) T *)(base))[idx];
 }
-__device__ __forceinline__ double ref_f64(const double *base, int idx) { return ldc(base, idx); }
-__device__ __forceinline__ float ref_f32(const float *base, int idx) { return ldc(base, idx); }
 
 }  // namespace
 
