@@ -186,6 +186,25 @@ int soptx_assemble_backward(soptx_pattern h, const soptx_material *m, const void
                             const uint8_t *d_dirichlet, const double *d_Kbar, void *d_drho,
                             int32_t prec, void *stream);
 
+/* y = K x for K in the pattern's CSR (d_K_vals: [nnz] double), x and y
+ * [ndof] double (the matrix-vector product of the equilibrium system
+ * K u = f, Sec. 2.2).  Each row is summed in a fixed order.  Asynchronous on
+ * stream. */
+int soptx_spmv(soptx_pattern h, const double *d_K_vals, const double *d_x, double *d_y, void *stream);
+
+/* Solve K u = f (Sec. 2.2) by conjugate gradients with the Jacobi
+ * preconditioner (the solver module's iterative solver, Sec. 3.2), for K
+ * symmetric positive definite: assembled with a Dirichlet mask, f zero on
+ * the fixed dofs.  d_u ([ndof] double) is the initial guess on entry and
+ * the solution on return; d_f: [ndof] double.  Stops when
+ * ||r_k|| <= rtol ||r_0|| (the recurrence residual, read back every 8
+ * iterations) or after max_iter iterations; *h_iters and *h_relres (host)
+ * give the count and ||r_k|| / ||r_0|| (NaN after a breakdown, i.e. K not
+ * SPD).  Synchronizes stream at those read-backs and at the start.  The
+ * vectors live in a per-stream workspace of the library. */
+int soptx_pcg(soptx_pattern h, const double *d_K_vals, const double *d_f, double *d_u, double rtol,
+              int32_t max_iter, int32_t *h_iters, double *h_relres, void *stream);
+
 /* Release every device and host resource of h (NULL is allowed). */
 void soptx_destroy_pattern(soptx_pattern h);
 

@@ -70,6 +70,9 @@ def lib():
         "soptx_compliance": [_P, ctypes.POINTER(Material), _P, _P, _P, _P, _I32, _P],
         "soptx_evaluate": [_P, ctypes.POINTER(Material), _P, _P, _P, _P, _P, _I32, _P],
         "soptx_assemble_backward": [_P, ctypes.POINTER(Material), _P, _P, _P, _P, _I32, _P],
+        "soptx_spmv": [_P, _P, _P, _P, _P],
+        "soptx_pcg": [_P, _P, _P, _P, ctypes.c_double, _I32, ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_double),
+                      _P],
         "soptx_pattern_copy": [_P, _P, _P],
         "soptx_reference_tensor": [_I32, _I32, _P],
         "soptx_validate_mesh": [ctypes.POINTER(Mesh)],

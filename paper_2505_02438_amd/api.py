@@ -223,6 +223,29 @@ class Pattern:
                                    _dptr(c, "c", torch.float64, 2), prec, _stream_ptr(stream)), "soptx_evaluate")
         return dc, c
 
+    def spmv(self, K, x, out=None, stream=None):
+        """y = K x on the pattern (FP64)."""
+        import torch
+        if out is None:
+            out = torch.empty(self.ndof, dtype=torch.float64, device=x.device)
+        check(lib().soptx_spmv(self._h, _dptr(K, "K", torch.float64, self.nnz), _dptr(x, "x", torch.float64, self.ndof),
+                               _dptr(out, "y", torch.float64, self.ndof), _stream_ptr(stream)), "soptx_spmv")
+        return out
+
+    def pcg(self, K, f, u=None, rtol: float = 1e-10, max_iter: int = 10000, stream=None):
+        """Solve K u = f by Jacobi-preconditioned CG (K SPD: assembled with a
+        Dirichlet mask).  u: initial guess, overwritten (zeros if None).
+        Returns (u, iterations, ||r_k|| / ||r_0||)."""
+        import torch
+        if u is None:
+            u = torch.zeros(self.ndof, dtype=torch.float64, device=f.device)
+        it = ctypes.c_int32()
+        rel = ctypes.c_double()
+        check(lib().soptx_pcg(self._h, _dptr(K, "K", torch.float64, self.nnz), _dptr(f, "f", torch.float64, self.ndof),
+                              _dptr(u, "u", torch.float64, self.ndof), float(rtol), int(max_iter), ctypes.byref(it),
+                              ctypes.byref(rel), _stream_ptr(stream)), "soptx_pcg")
+        return u, it.value, rel.value
+
     def backward(self, material: Material, rho, Kbar, mask=None, out=None, prec: int = FP64, stream=None):
         """drho_e = E'(rho_e) <Kbar, K_e^0> over the element's slots (reverse of assemble)."""
         import torch

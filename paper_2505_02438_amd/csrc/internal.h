@@ -83,6 +83,8 @@ struct HostPlan {
     // per node n and neighbour J = nb(n)[q] (offset row_ptr[dim n] / dim^2 + q):
     // the CSR slot of (row dim J, column dim n) and the degree of J
     std::vector<int32_t> nb_tslot;
+    // per node n (offset row_ptr[dim n] / dim^2): its neighbour nodes, ascending
+    std::vector<int32_t> nb;
     std::vector<uint16_t> nb_tdeg;
     int kmax = 0, emax = 0, ne_max = 0;  // emax: grouping limit; ne_max: largest group
     int blk_max = 0;                     // largest padded row block (doubles)

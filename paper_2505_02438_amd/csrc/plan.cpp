@@ -182,7 +182,8 @@ int build_host_plan(const soptx_mesh *mesh, HostPlan &hp) {
     for (int64_t n = 0; n < NN; n++)
         if (deg[n] > 65535) return SOPTX_E_OVERFLOW;
     hp.nnz = nnz;
-    std::vector<int32_t> nb(nb_ptr[NN]);
+    std::vector<int32_t> &nb = hp.nb;
+    nb.assign(nb_ptr[NN], 0);
     parallel_for(NN, [&](int64_t a0, int64_t a1) {
         std::vector<int32_t> buf;
         for (int64_t n = a0; n < a1; n++) {

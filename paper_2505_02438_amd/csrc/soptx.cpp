@@ -8,6 +8,7 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <tuple>
 #include <vector>
 
 #include "../../include/soptx.h"
@@ -32,6 +33,7 @@ struct soptx_pattern_s {
     int32_t *sig_witems = nullptr, *sig_witem_ptr = nullptr;
     uint16_t *pos = nullptr, *nb_tdeg = nullptr;
     int32_t *nb_tslot = nullptr;
+    int32_t *nb = nullptr;
     double *M = nullptr;
     float *M32 = nullptr, *Mbf = nullptr;
     double *qw = nullptr, *qgrad = nullptr, *cgrad = nullptr, *xref = nullptr;
@@ -46,18 +48,19 @@ struct soptx_host_plan_s {
 
 namespace {
 
-// Per-(device, stream) scratch for the fixed-order reduction partials.  Work
-// on one stream is ordered, so one buffer per stream is race-free.
+// Per-(device, stream, use) scratch: the fixed-order reduction partials of
+// the energy kernel (use 0) and the vectors of the CG solve (use 1).  Work on
+// one stream is ordered, so one buffer per stream and use is race-free.
 struct Workspace {
     double *buf = nullptr;
     size_t n = 0;
 };
 std::mutex g_ws_mu;
-std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
+std::map<std::tuple<int, hipStream_t, int>, Workspace> g_ws;
 
-int get_workspace(int device, hipStream_t st, size_t n, double **out) {
+int get_workspace(int device, hipStream_t st, size_t n, double **out, int use = 0) {
     std::lock_guard<std::mutex> lk(g_ws_mu);
-    Workspace &w = g_ws[{device, st}];
+    Workspace &w = g_ws[std::make_tuple(device, st, use)];
     if (w.n < n) {
         if (w.buf) {
             if (hipStreamSynchronize(st) != hipSuccess) return SOPTX_E_DEVICE;
@@ -237,7 +240,8 @@ int soptx_build_pattern_ex(const soptx_mesh *mesh, int32_t ref_method, soptx_pat
             free_handle(h); return rc;
         }
         h->stats.plan_bytes = h->stats.device_bytes - base_bytes;
-        if ((rc = upload(h, hp.pos, &h->pos, st)) || (rc = upload(h, hp.nb_tslot, &h->nb_tslot, st)) || (rc = upload(h, hp.nb_tdeg, &h->nb_tdeg, st)) || (rc = upload(h, M, &h->M, st)) ||
+        if ((rc = upload(h, hp.pos, &h->pos, st)) || (rc = upload(h, hp.nb_tslot, &h->nb_tslot, st)) ||
+            (rc = upload(h, hp.nb, &h->nb, st)) || (rc = upload(h, hp.nb_tdeg, &h->nb_tdeg, st)) || (rc = upload(h, M, &h->M, st)) ||
             (rc = upload(h, M32, &h->M32, st)) || (rc = upload(h, Mbf, &h->Mbf, st)) ||
             (rc = upload(h, qw, &h->qw, st)) || (rc = upload(h, qg, &h->qgrad, st)) ||
             (rc = upload(h, qg32, &h->qgrad32, st)) || (rc = upload(h, cg, &h->cgrad, st)) ||
@@ -322,6 +326,75 @@ int soptx_apply_dirichlet(soptx_pattern h, const uint8_t *d_dirichlet, double *d
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (launch_dirichlet(h->dim, h->row_ptr, h->nb_tslot, h->nb_tdeg, d_dirichlet, d_K_vals, h->ndof, st) != hipSuccess)
         return SOPTX_E_DEVICE;
+    return SOPTX_OK;
+}
+
+int soptx_spmv(soptx_pattern h, const double *d_K_vals, const double *d_x, double *d_y, void *stream) {
+    if (!h || (h->nnz > 0 && (!d_K_vals || !d_x)) || (h->ndof > 0 && !d_y)) return SOPTX_E_INVALID_ARG;
+    if (h->ndof == 0) return SOPTX_OK;
+    DeviceGuard dg(h->device);
+    if (!dg.ok) return SOPTX_E_DEVICE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (launch_spmv(h->dim, h->row_ptr, h->nb, d_K_vals, d_x, d_y, nullptr, h->n_nodes, st) != hipSuccess)
+        return SOPTX_E_DEVICE;
+    return SOPTX_OK;
+}
+
+int soptx_pcg(soptx_pattern h, const double *d_K_vals, const double *d_f, double *d_u, double rtol,
+              int32_t max_iter, int32_t *h_iters, double *h_relres, void *stream) {
+    if (!h || !h_iters || !h_relres || max_iter < 0 || !(rtol >= 0.0)) return SOPTX_E_INVALID_ARG;
+    if (h->ndof > 0 && (!d_K_vals || !d_f || !d_u)) return SOPTX_E_INVALID_ARG;
+    *h_iters = 0;
+    *h_relres = 0.0;
+    if (h->ndof == 0) return SOPTX_OK;
+    DeviceGuard dg(h->device);
+    if (!dg.ok) return SOPTX_E_DEVICE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t n = h->ndof;
+    const int64_t nbv = (n + 255) / 256;                      // blocks of the vector kernels
+    const int64_t nbs = spmv_blocks(h->dim, h->n_nodes);      // blocks of the SpMV
+    const int64_t npart = std::max<int64_t>(2 * nbv, nbs);
+    // r, z, p, q, dinv, partials, 8 scalars
+    double *ws = nullptr;
+    int rc = get_workspace(h->device, st, 5 * (size_t)n + (size_t)npart + 8, &ws, 1);
+    if (rc) return rc;
+    double *r = ws, *z = r + n, *p = z + n, *q = p + n, *dinv = q + n, *part = dinv + n, *sc = part + npart;
+    double hs[8];
+    auto scalars = [&]() {
+        if (hipMemcpyAsync(hs, sc, sizeof(hs), hipMemcpyDeviceToHost, st) != hipSuccess) return false;
+        return hipStreamSynchronize(st) == hipSuccess;
+    };
+    // r = f - K u, z = D^-1 r, p = z
+    if (launch_diag_inv(h->dim, h->row_ptr, h->nb, d_K_vals, dinv, n, st) != hipSuccess ||
+        launch_spmv(h->dim, h->row_ptr, h->nb, d_K_vals, d_u, q, nullptr, h->n_nodes, st) != hipSuccess ||
+        launch_cg_vec(0, d_f, d_u, r, z, p, q, dinv, sc, part, n, st) != hipSuccess ||
+        launch_cg_scalars(0, part, (int)nbv, sc, st) != hipSuccess || !scalars())
+        return SOPTX_E_DEVICE;
+    const double rr0 = hs[4];
+    if (!(rr0 > 0.0)) {  // u already solves the system (or the data hold a NaN)
+        *h_relres = rr0 == 0.0 ? 0.0 : NAN;
+        return SOPTX_OK;
+    }
+    // the residual is read back every kCheck iterations
+    constexpr int kCheck = 8;
+    int it = 0;
+    double rel = 1.0;
+    while (it < max_iter) {
+        if (launch_spmv(h->dim, h->row_ptr, h->nb, d_K_vals, p, q, part, h->n_nodes, st) != hipSuccess ||
+            launch_cg_scalars(1, part, (int)nbs, sc, st) != hipSuccess ||
+            launch_cg_vec(1, d_f, d_u, r, z, p, q, dinv, sc, part, n, st) != hipSuccess ||
+            launch_cg_scalars(2, part, (int)nbv, sc, st) != hipSuccess ||
+            launch_cg_p(p, z, sc, n, st) != hipSuccess)
+            return SOPTX_E_DEVICE;
+        it++;
+        if (it % kCheck == 0 || it == max_iter) {
+            if (!scalars()) return SOPTX_E_DEVICE;
+            rel = std::sqrt(hs[3] / rr0);
+            if (!(rel > rtol)) break;  // converged, or broke down (NaN)
+        }
+    }
+    *h_iters = it;
+    *h_relres = rel;
     return SOPTX_OK;
 }
 

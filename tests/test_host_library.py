@@ -93,6 +93,10 @@ def test_per_call_argument_errors_without_device():
     assert L.soptx_compliance(None, ctypes.byref(mat), None, None, None, None, 0, None) == -1
     assert L.soptx_evaluate(None, ctypes.byref(mat), None, None, None, None, None, 0, None) == -1
     assert L.soptx_assemble_backward(None, ctypes.byref(mat), None, None, None, None, 0, None) == -1
+    assert L.soptx_apply_dirichlet(None, None, None, None) == -1
+    assert L.soptx_spmv(None, None, None, None, None) == -1
+    it, rel = ctypes.c_int32(5), ctypes.c_double(5.0)
+    assert L.soptx_pcg(None, None, None, None, 1e-10, 10, ctypes.byref(it), ctypes.byref(rel), None) == -1
     assert L.soptx_pattern_info(None, None, None, None, None) == -1
     assert L.soptx_pattern_copy(None, None, None) == -1
     L.soptx_destroy_pattern(None)
