@@ -89,6 +89,35 @@ def cpu_baseline(pr, rp, ci, min_seconds=10.0):
     return m.n_cells / statistics.median(times), times
 
 
+def solve_run(pat, m, K, f, stream, rtol, reps=20):
+    """The equilibrium solve on the assembled K (Dirichlet applied): the SpMV
+    timed with HIP events on the bench stream against its algorithmic bytes
+    (K values, one neighbour id per DIM x DIM block, row offsets, x read, y
+    written), and one full Jacobi-PCG solve."""
+    import torch
+    x = torch.ones(pat.ndof, dtype=torch.float64, device=K.device)
+    y = torch.empty_like(x)
+    ms = []
+    for _ in range(reps + 3):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        pat.spmv(K, x, out=y, stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms.append(a.elapsed_time(b))
+    spmv_s = statistics.mean(ms[3:]) / 1e3
+    nbytes = pat.nnz * 8 + (pat.nnz // (m.dim * m.dim)) * 4 + m.n_nodes * 2 * 4 + 2 * pat.ndof * 8
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u, iters, rel = pat.pcg(K, f, rtol=rtol, max_iter=50000, stream=stream)
+    torch.cuda.synchronize()
+    solve_s = time.perf_counter() - t0
+    return {"spmv_avg_ms": spmv_s * 1e3, "spmv_algorithmic_bytes": nbytes,
+            "spmv_achieved_GBs": nbytes / spmv_s / 1e9, "spmv_frac_of_hbm_peak": nbytes / spmv_s / 1e9 / HBM_PEAK_GBS,
+            "pcg_rtol": rtol, "pcg_iterations": iters, "pcg_relres": rel, "pcg_seconds": solve_s,
+            "pcg_ms_per_iteration": solve_s / max(iters, 1) * 1e3}
+
+
 def serving_run(count, slots=4, budget=32 << 30):
     """Serving form: seeded requests (2D Q1 n^2, n in 32..512; 3D Q1 n^3,
     n in 16..96; p in {3, 4}), first as a burst (saturated elements/s), then
@@ -122,6 +151,8 @@ def main():
                     help="skip the second timed region (the same step replayed as a captured HIP graph)")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="hex120x40x40")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-solve", action="store_true", help="skip the SpMV / Jacobi-PCG measurement")
+    ap.add_argument("--solve-rtol", type=float, default=1e-9)
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
@@ -274,6 +305,9 @@ def main():
         "plan": {"groups": stats["n_groups"], "signatures": stats["n_signatures"],
                  "plan_bytes": stats["plan_bytes"]},
     }
+    if not args.no_solve:
+        f = torch.from_numpy(pr.f).to(dev)
+        out["solve"] = solve_run(pat, m, Ks[0], f, stream, args.solve_rtol)
     if not args.no_serving:
         out["serving"] = serving_run(args.serve_requests)
     if not args.no_cpu_baseline:

@@ -1,0 +1,224 @@
+// gfx950 kernels of the equilibrium solve K u = f (arXiv 2505.02438,
+// Sec. 2.2): a block-structured sparse product over the assembled CSR
+// values and Jacobi-preconditioned conjugate gradients (the iterative solver
+// of the solver module, Sec. 3.2).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "block_sum.h"
+#include "internal.h"
+#include "kernels.h"
+
+namespace soptx {
+
+namespace {
+
+// ------------------------------------------------------- solve (CG)
+//
+// The equilibrium system K u = f of the compliance problem, solved by
+// Jacobi-preconditioned conjugate gradients on the assembled CSR values.
+//
+// y = K x.  K is a sum of DIM x DIM blocks, so a node's DIM rows share one
+// neighbour list: row DIM I + a holds, for neighbour J = nb(I)[q], the
+// entries of columns DIM J .. DIM J + DIM - 1 at row_ptr[DIM I + a] + DIM q.
+// The kernel reads the neighbour lists (one id per block) instead of the
+// column indices.  L lanes per node; lane s takes q = s, s + L, ...; the L
+// partial sums of a row are added by an xor tree (a fixed order).  With
+// xy_part, also the block partial of sum_r x_r y_r.
+template <int DIM, int L>
+__global__ __launch_bounds__(256) void k_spmv(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ nb,
+                                              const double *__restrict__ K, const double *__restrict__ x,
+                                              double *__restrict__ y, double *__restrict__ xy_part,
+                                              int64_t n_nodes) {
+    __shared__ double red[256];
+    const int sub = threadIdx.x % L;
+    const int64_t I = ((int64_t)blockIdx.x * 256 + threadIdx.x) / L;
+    double acc[DIM];
+#pragma unroll
+    for (int a = 0; a < DIM; a++) acc[a] = 0.0;
+    if (I < n_nodes) {
+        const int b = row_ptr[DIM * I];
+        const int rl = row_ptr[DIM * I + 1] - b;
+        const int deg = rl / DIM;
+        const int nbo = b / (DIM * DIM);
+        for (int q = sub; q < deg; q += L) {
+            const int J = nb[nbo + q];
+            double xj[DIM];
+#pragma unroll
+            for (int e = 0; e < DIM; e++) xj[e] = x[(int64_t)DIM * J + e];
+#pragma unroll
+            for (int a = 0; a < DIM; a++)
+#pragma unroll
+                for (int e = 0; e < DIM; e++) acc[a] += K[b + a * rl + DIM * q + e] * xj[e];
+        }
+    }
+#pragma unroll
+    for (int off = L / 2; off > 0; off >>= 1)
+#pragma unroll
+        for (int a = 0; a < DIM; a++) acc[a] += __shfl_xor(acc[a], off);
+    double xy = 0.0;
+    if (I < n_nodes && sub == 0) {
+#pragma unroll
+        for (int a = 0; a < DIM; a++) {
+            y[DIM * I + a] = acc[a];
+            xy += x[DIM * I + a] * acc[a];
+        }
+    }
+    if (!xy_part) return;
+    const double bs = block_sum_256(xy, red);
+    if (threadIdx.x == 0) xy_part[blockIdx.x] = bs;
+}
+
+// dinv_r = 1 / K_rr (0 for an empty row: an isolated node's dofs stay put)
+template <int DIM>
+__global__ __launch_bounds__(256) void k_diag_inv(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ nb,
+                                                  const double *__restrict__ K, double *__restrict__ dinv,
+                                                  int64_t ndof) {
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= ndof) return;
+    const int64_t I = r / DIM;
+    const int a = (int)(r - DIM * I);
+    const int b = row_ptr[DIM * I];
+    const int rl = row_ptr[DIM * I + 1] - b;
+    const int nbo = b / (DIM * DIM);
+    double d = 0.0;
+    for (int q = 0; q < rl / DIM; q++)
+        if (nb[nbo + q] == I) d = K[b + a * rl + DIM * q + a];
+    dinv[r] = d != 0.0 ? 1.0 / d : 0.0;
+}
+
+// CG vector steps, one thread per dof, block partials in a fixed order.
+// Scalars sc: [0] r.z, [1] alpha, [2] beta, [3] r.r, [4] r0.r0, [5] p.q.
+// mode 0 (start, q = K u): r = f - q, z = dinv r, p = z.
+// mode 1 (iteration, q = K p): u += alpha p, r -= alpha q, z = dinv r.
+// Both leave block partials of r.z (part[b]) and r.r (part[nb + b]).
+__global__ __launch_bounds__(256) void k_cg_vec(int mode, const double *__restrict__ f, double *__restrict__ u,
+                                                double *__restrict__ r, double *__restrict__ z,
+                                                double *__restrict__ p, const double *__restrict__ q,
+                                                const double *__restrict__ dinv, const double *__restrict__ sc,
+                                                double *__restrict__ part, int64_t n) {
+    __shared__ double red[256];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double rz = 0.0, rr = 0.0;
+    if (i < n) {
+        double ri, zi;
+        if (mode == 0) {
+            ri = f[i] - q[i];
+            zi = dinv[i] * ri;
+            p[i] = zi;
+        } else {
+            const double al = sc[1];
+            u[i] += al * p[i];
+            ri = r[i] - al * q[i];
+            zi = dinv[i] * ri;
+        }
+        r[i] = ri;
+        z[i] = zi;
+        rz = ri * zi;
+        rr = ri * ri;
+    }
+    const double brz = block_sum_256(rz, red);
+    const double brr = block_sum_256(rr, red);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = brz;
+        part[gridDim.x + blockIdx.x] = brr;
+    }
+}
+
+// p = z + beta p
+__global__ __launch_bounds__(256) void k_cg_p(double *__restrict__ p, const double *__restrict__ z,
+                                              const double *__restrict__ sc, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = z[i] + sc[2] * p[i];
+}
+
+// One block of kScalThreads: sums of n block partials, thread t taking
+// k = t, t + kScalThreads, ... in order, then a fixed tree.
+// what 0 (start):     r.z and r.r from part -> sc[0], sc[3], sc[4] = sc[3]
+// what 1 (alpha):     p.q from part -> sc[5], sc[1] = sc[0] / p.q
+// what 2 (beta):      r.z, r.r from part -> sc[2] = new r.z / sc[0], sc[0], sc[3]
+constexpr int kScalThreads = 1024;
+__global__ __launch_bounds__(kScalThreads) void k_cg_scalars(int what, const double *__restrict__ part, int n,
+                                                             double *sc) {
+    __shared__ double red[2][kScalThreads];
+    double t0 = 0.0, t1 = 0.0;
+    for (int k = threadIdx.x; k < n; k += kScalThreads) {
+        t0 += part[k];
+        if (what != 1) t1 += part[n + k];
+    }
+    red[0][threadIdx.x] = t0;
+    red[1][threadIdx.x] = t1;
+    __syncthreads();
+    for (int st = kScalThreads / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + st];
+            red[1][threadIdx.x] += red[1][threadIdx.x + st];
+        }
+        __syncthreads();
+    }
+    t0 = red[0][0];
+    t1 = red[1][0];
+    if (threadIdx.x != 0) return;
+    if (what == 0) {
+        sc[0] = t0;
+        sc[3] = t1;
+        sc[4] = t1;
+    } else if (what == 1) {
+        sc[5] = t0;
+        sc[1] = sc[0] / t0;
+    } else {
+        sc[2] = t0 / sc[0];
+        sc[0] = t0;
+        sc[3] = t1;
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+
+int64_t spmv_blocks(int dim, int64_t n_nodes) {
+    const int L = dim == 3 ? 16 : 8;
+    return (n_nodes * L + 255) / 256;
+}
+
+hipError_t launch_spmv(int dim, const int32_t *row_ptr, const int32_t *nb, const double *K, const double *x,
+                       double *y, double *xy_part, int64_t n_nodes, hipStream_t st) {
+    const unsigned g = (unsigned)spmv_blocks(dim, n_nodes);
+    if (g == 0) return hipSuccess;
+    if (dim == 3) hipLaunchKernelGGL((k_spmv<3, 16>), dim3(g), dim3(256), 0, st, row_ptr, nb, K, x, y, xy_part, n_nodes);
+    else hipLaunchKernelGGL((k_spmv<2, 8>), dim3(g), dim3(256), 0, st, row_ptr, nb, K, x, y, xy_part, n_nodes);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag_inv(int dim, const int32_t *row_ptr, const int32_t *nb, const double *K, double *dinv,
+                           int64_t ndof, hipStream_t st) {
+    const unsigned g = (unsigned)((ndof + 255) / 256);
+    if (g == 0) return hipSuccess;
+    if (dim == 3) hipLaunchKernelGGL(k_diag_inv<3>, dim3(g), dim3(256), 0, st, row_ptr, nb, K, dinv, ndof);
+    else hipLaunchKernelGGL(k_diag_inv<2>, dim3(g), dim3(256), 0, st, row_ptr, nb, K, dinv, ndof);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_vec(int mode, const double *f, double *u, double *r, double *z, double *p, const double *q,
+                         const double *dinv, const double *sc, double *part, int64_t n, hipStream_t st) {
+    const unsigned g = (unsigned)((n + 255) / 256);
+    if (g == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cg_vec, dim3(g), dim3(256), 0, st, mode, f, u, r, z, p, q, dinv, sc, part, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_p(double *p, const double *z, const double *sc, int64_t n, hipStream_t st) {
+    const unsigned g = (unsigned)((n + 255) / 256);
+    if (g == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cg_p, dim3(g), dim3(256), 0, st, p, z, sc, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_scalars(int what, const double *part, int n, double *sc, hipStream_t st) {
+    hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(kScalThreads), 0, st, what, part, n, sc);
+    return hipGetLastError();
+}
+
+}  // namespace soptx
