@@ -38,6 +38,14 @@ int soptx_debug_host_plan_scalars(soptx_host_plan p, int64_t *out8);
 
 void soptx_debug_host_plan_free(soptx_host_plan p);
 
+/* The filter matrix of soptx_build_filter (soptx_filter.h), built on the host
+ * only (no device): sizes into *n and *nnz, and, for non-NULL buffers,
+ * row_ptr [n+1], col [nnz], w [nnz], element measures vol [n] and the row
+ * sums hsv [n] (sum_j H_ij v_j) and hs [n] (sum_j H_ij).  Call once with NULL
+ * buffers to learn nnz. */
+int soptx_debug_filter_matrix(const soptx_mesh *mesh, double rmin, int64_t *n, int64_t *nnz, int32_t *row_ptr,
+                              int32_t *col, double *w, double *vol, double *hsv, double *hs);
+
 #ifdef __cplusplus
 }
 #endif

@@ -83,6 +83,24 @@ def filter_matrix(cent, rmin: float, block: int = 2048):
     return np.cumsum(row_ptr), cols, vals
 
 
+def filter_rows(cent, rmin: float, rows):
+    """Rows `rows` of H alone (for meshes too large for the whole matrix):
+    a list of (columns ascending, weights), by the same brute force."""
+    cent = np.asarray(cent, np.float64)
+    d = cent.shape[1]
+    out = []
+    for i in rows:
+        diff = cent[i, 0] - cent[:, 0]
+        s = diff * diff
+        for a in range(1, d):
+            diff = cent[i, a] - cent[:, a]
+            s = s + diff * diff
+        w = rmin - np.sqrt(s)
+        j = np.nonzero(w > 0.0)[0]
+        out.append((j.astype(np.int32), w[j]))
+    return out
+
+
 def h_product(H, x) -> np.ndarray:
     """y = H x, each row summed in ascending column order."""
     row_ptr, col, w = H

@@ -80,6 +80,14 @@ def lib():
         "soptx_debug_host_plan_array": [_P, ctypes.c_char_p, ctypes.POINTER(_P), ctypes.POINTER(_I64),
                                         ctypes.POINTER(_I32)],
         "soptx_debug_host_plan_scalars": [_P, _P],
+        "soptx_debug_filter_matrix": [ctypes.POINTER(Mesh), ctypes.c_double, ctypes.POINTER(_I64),
+                                      ctypes.POINTER(_I64), _P, _P, _P, _P, _P, _P],
+        "soptx_build_filter": [ctypes.POINTER(Mesh), ctypes.c_double, ctypes.POINTER(_P), _P],
+        "soptx_filter_info": [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I32)],
+        "soptx_filter_copy": [_P, _P, _P, _P, _P],
+        "soptx_filter_sensitivity": [_P, _P, _P, _P, _P],
+        "soptx_filter_density": [_P, _P, ctypes.c_double, _P, _P, _P],
+        "soptx_filter_density_backward": [_P, _P, ctypes.c_double, _P, _P, _P],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -87,6 +95,8 @@ def lib():
         fn.restype = _I
     L.soptx_destroy_pattern.argtypes = [_P]
     L.soptx_destroy_pattern.restype = None
+    L.soptx_destroy_filter.argtypes = [_P]
+    L.soptx_destroy_filter.restype = None
     L.soptx_debug_host_plan_free.argtypes = [_P]
     L.soptx_debug_host_plan_free.restype = None
     L.soptx_status_string.argtypes = [_I]

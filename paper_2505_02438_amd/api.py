@@ -259,3 +259,120 @@ class Pattern:
                                             _dptr(out, "drho", self._rho_dtype(prec), self.n_cells), prec,
                                             _stream_ptr(stream)), "soptx_assemble_backward")
         return out
+
+
+def filter_matrix_host(elem: int, coords, cells, rmin: float) -> dict:
+    """The filter matrix soptx_build_filter uploads, built on the host only:
+    row_ptr, col, w, element measures vol, row sums hsv (H v) and hs (H 1)."""
+    m, keep = _mesh_struct(elem, coords, cells)
+    n, nnz = ctypes.c_int64(), ctypes.c_int64()
+    check(lib().soptx_debug_filter_matrix(ctypes.byref(m), float(rmin), ctypes.byref(n), ctypes.byref(nnz),
+                                          None, None, None, None, None, None), "soptx_debug_filter_matrix")
+    out = {"row_ptr": np.zeros(n.value + 1, np.int32), "col": np.zeros(max(nnz.value, 1), np.int32),
+           "w": np.zeros(max(nnz.value, 1)), "vol": np.zeros(max(n.value, 1)), "hsv": np.zeros(max(n.value, 1)),
+           "hs": np.zeros(max(n.value, 1))}
+    check(lib().soptx_debug_filter_matrix(ctypes.byref(m), float(rmin), ctypes.byref(n), ctypes.byref(nnz),
+                                          *(out[k].ctypes.data for k in ("row_ptr", "col", "w", "vol", "hsv", "hs"))),
+          "soptx_debug_filter_matrix")
+    for k in ("col", "w"):
+        out[k] = out[k][: nnz.value]
+    for k in ("vol", "hsv", "hs"):
+        out[k] = out[k][: n.value]
+    return out
+
+
+class Filter:
+    """The filter matrix H of a mesh (Sec. 2.4), resident on the device:
+    H_ij = max(0, rmin - dist(i, j)) over element centroids, built once per
+    mesh; the sensitivity filter, the density filter with the Heaviside
+    projection, and the density filter's chain rule run per call (FP64)."""
+
+    def __init__(self, elem: int, coords, cells, rmin: float, stream=None):
+        m, keep = _mesh_struct(elem, coords, cells)
+        h = ctypes.c_void_p()
+        check(lib().soptx_build_filter(ctypes.byref(m), float(rmin), ctypes.byref(h), _stream_ptr(stream)),
+              "soptx_build_filter")
+        self._h = h
+        self.rmin = float(rmin)
+        n, nnz, lanes = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        check(lib().soptx_filter_info(h, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(lanes)), "filter_info")
+        self.n, self.nnz, self.lanes = n.value, nnz.value, lanes.value
+
+    @classmethod
+    def from_mesh(cls, mesh, rmin: float, **kw) -> "Filter":
+        return cls(mesh.elem, mesh.coords, mesh.cells, rmin, **kw)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().soptx_destroy_filter(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def matrix(self):
+        """(row_ptr int32, col int32, w float64, element measures float64) on the host."""
+        rp = np.zeros(self.n + 1, dtype=np.int32)
+        col = np.zeros(max(self.nnz, 1), dtype=np.int32)
+        w = np.zeros(max(self.nnz, 1))
+        v = np.zeros(max(self.n, 1))
+        check(lib().soptx_filter_copy(self._h, rp.ctypes.data, col.ctypes.data, w.ctypes.data, v.ctypes.data),
+              "soptx_filter_copy")
+        return rp, col[: self.nnz], w[: self.nnz], v[: self.n]
+
+    def sensitivity(self, rho, dc, out=None, stream=None):
+        """dc~_i = sum_j H_ij rho_j dc_j / (max(1e-3, rho_i) sum_j H_ij)."""
+        import torch
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.float64, device=rho.device)
+        check(lib().soptx_filter_sensitivity(self._h, _dptr(rho, "rho", torch.float64, self.n),
+                                             _dptr(dc, "dc", torch.float64, self.n),
+                                             _dptr(out, "dc_out", torch.float64, self.n), _stream_ptr(stream)),
+              "soptx_filter_sensitivity")
+        return out
+
+    def density(self, rho, beta: Optional[float] = None, rho_tilde=None, rho_bar=None, stream=None):
+        """rho~ = (H (v rho)) / (H v); with beta, also the Heaviside projection
+        rho_bar = 1 - exp(-beta rho~) + rho~ exp(-beta).  Returns rho~, or
+        (rho~, rho_bar) with beta."""
+        import torch
+        if rho_tilde is None:
+            rho_tilde = torch.empty(self.n, dtype=torch.float64, device=rho.device)
+        if beta is not None and rho_bar is None:
+            rho_bar = torch.empty(self.n, dtype=torch.float64, device=rho.device)
+        check(lib().soptx_filter_density(self._h, _dptr(rho, "rho", torch.float64, self.n),
+                                         float(beta if beta is not None else 0.0),
+                                         _dptr(rho_tilde, "rho_tilde", torch.float64, self.n),
+                                         _dptr(rho_bar, "rho_bar", torch.float64, self.n) if beta is not None else None,
+                                         _stream_ptr(stream)), "soptx_filter_density")
+        return rho_tilde if beta is None else (rho_tilde, rho_bar)
+
+    def density_backward(self, grad, rho_tilde=None, beta: Optional[float] = None, out=None, stream=None):
+        """dpsi/drho from dpsi/drho~ (rho_tilde None), or from dpsi/drho_bar
+        through the Heaviside projection at beta and rho_tilde."""
+        import torch
+        if (rho_tilde is None) != (beta is None):
+            raise ValueError("rho_tilde and beta go together")
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.float64, device=grad.device)
+        check(lib().soptx_filter_density_backward(
+            self._h, _dptr(rho_tilde, "rho_tilde", torch.float64, self.n), float(beta if beta is not None else 0.0),
+            _dptr(grad, "grad", torch.float64, self.n), _dptr(out, "grad_rho", torch.float64, self.n),
+            _stream_ptr(stream)), "soptx_filter_density_backward")
+        return out
+
+
+def heaviside_beta(iteration: int, beta0: float = 1.0, max_beta: float = 512.0, every: int = 50) -> float:
+    """Continuation of the projection parameter: beta0 doubled every `every`
+    iterations, capped at max_beta (Sec. 5.2 uses 1, 512 and 50)."""
+    if iteration < 0 or every <= 0:
+        raise ValueError("iteration >= 0 and every > 0")
+    beta = float(beta0)
+    for _ in range(iteration // every):
+        if beta >= max_beta:
+            break
+        beta *= 2.0
+    return float(min(max_beta, beta))

@@ -1,0 +1,366 @@
+// Filter step of libsoptx (arXiv 2505.02438, Sec. 2.4; Sec. 3.2 filter
+// module): the filter matrix H built once per mesh on the host, its device
+// copy, and the C ABI of the filter products (kernels in filter.hip).
+//
+// Neighbourhood search: the centroids are binned into a uniform grid of cells
+// of side h >= r_min, so every j with dist(i, j) < r_min lies in the 3^d
+// cells around i's cell.  (The paper names a KD-tree; on the meshes of a
+// topology-optimisation domain a uniform grid finds the same sets with less
+// work.)  A row keeps the j with r_min - dist > 0, in ascending order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "../../include/soptx_debug.h"
+#include "../../include/soptx_filter.h"
+#include "host_util.h"
+#include "internal.h"
+#include "kernels.h"
+
+using namespace soptx;
+
+struct soptx_filter_s {
+    int device = 0, dim = 0, lanes = 8;
+    int64_t n = 0, nnz = 0;
+    int32_t *row_ptr = nullptr, *col = nullptr;
+    double *w = nullptr, *v = nullptr, *hsv = nullptr, *hs = nullptr;
+    std::vector<void *> allocs;
+};
+
+namespace {
+
+// vertex (corner) nodes: Q1 quad 4, P1 triangle 3, Q1 hex 8, P2 tet 4
+int n_vertex(int elem) {
+    switch (elem) {
+    case SOPTX_QUAD4: return 4;
+    case SOPTX_TRI3: return 3;
+    case SOPTX_HEX8: return 8;
+    case SOPTX_TET10: return 4;
+    default: return -1;
+    }
+}
+
+// Centroids (vertex mean, summed in local order) and measures |det J| times
+// the reference measure (the maps are affine: validated before).
+void centroids_volumes(const soptx_mesh *m, std::vector<double> &c, std::vector<double> &v) {
+    const int dim = m->dim, nen = elem_nen(m->elem), nv = n_vertex(m->elem);
+    const int64_t n = m->n_cells;
+    c.assign((size_t)n * dim, 0.0);
+    v.assign((size_t)n, 0.0);
+    // map-defining vertices and the reference measure
+    int def[3];
+    double ref = 1.0;
+    if (m->elem == SOPTX_QUAD4) { def[0] = 1; def[1] = 3; }
+    else if (m->elem == SOPTX_HEX8) { def[0] = 1; def[1] = 3; def[2] = 4; }
+    else { for (int a = 0; a < dim; a++) def[a] = a + 1; ref = dim == 2 ? 0.5 : 1.0 / 6.0; }
+    for (int64_t e = 0; e < n; e++) {
+        const int32_t *cell = m->cells + e * nen;
+        auto X = [&](int i, int a) { return m->coords[(int64_t)cell[i] * dim + a]; };
+        for (int a = 0; a < dim; a++) {
+            double s = X(0, a);
+            for (int i = 1; i < nv; i++) s += X(i, a);
+            c[(size_t)e * dim + a] = s / nv;
+        }
+        double J[3][3];
+        for (int a = 0; a < dim; a++)
+            for (int b = 0; b < dim; b++) J[a][b] = X(def[b], a) - X(0, a);
+        double det;
+        if (dim == 2) det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        else
+            det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                  J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+        v[(size_t)e] = std::fabs(det) * ref;
+    }
+}
+
+struct Rows {
+    std::vector<int32_t> col;
+    std::vector<double> w;
+    std::vector<int64_t> cnt;
+};
+
+// rows [r0, r1) of H into out (per-row counts, then columns and weights)
+void search_rows(int dim, const std::vector<double> &c, double rmin, const double *lo, double h, const int64_t *nc,
+                 const std::vector<int64_t> &cell_ptr, const std::vector<int32_t> &cell_el, int64_t r0, int64_t r1,
+                 Rows &out) {
+    std::vector<std::pair<int32_t, double>> buf;
+    for (int64_t i = r0; i < r1; i++) {
+        buf.clear();
+        const double *ci = &c[(size_t)i * dim];
+        int64_t ic[3] = {0, 0, 0};
+        for (int a = 0; a < dim; a++)
+            ic[a] = std::min<int64_t>(nc[a] - 1, std::max<int64_t>(0, (int64_t)std::floor((ci[a] - lo[a]) / h)));
+        const int64_t z0 = dim == 3 ? std::max<int64_t>(0, ic[2] - 1) : 0;
+        const int64_t z1 = dim == 3 ? std::min<int64_t>(nc[2] - 1, ic[2] + 1) : 0;
+        for (int64_t x = std::max<int64_t>(0, ic[0] - 1); x <= std::min<int64_t>(nc[0] - 1, ic[0] + 1); x++)
+            for (int64_t y = std::max<int64_t>(0, ic[1] - 1); y <= std::min<int64_t>(nc[1] - 1, ic[1] + 1); y++)
+                for (int64_t z = z0; z <= z1; z++) {
+                    const int64_t cell = (x * nc[1] + y) * nc[2] + z;
+                    for (int64_t q = cell_ptr[cell]; q < cell_ptr[cell + 1]; q++) {
+                        const int32_t j = cell_el[q];
+                        const double *cj = &c[(size_t)j * dim];
+                        double d = ci[0] - cj[0];
+                        double s = d * d;
+                        for (int a = 1; a < dim; a++) {
+                            d = ci[a] - cj[a];
+                            s = s + d * d;
+                        }
+                        const double wij = rmin - std::sqrt(s);
+                        if (wij > 0.0) buf.emplace_back(j, wij);
+                    }
+                }
+        std::sort(buf.begin(), buf.end(), [](const auto &p, const auto &q) { return p.first < q.first; });
+        out.cnt.push_back((int64_t)buf.size());
+        for (const auto &p : buf) {
+            out.col.push_back(p.first);
+            out.w.push_back(p.second);
+        }
+    }
+}
+
+template <class T>
+int upload(soptx_filter_s *h, const std::vector<T> &v, T **dst, hipStream_t st) {
+    *dst = nullptr;
+    if (v.empty()) return SOPTX_OK;
+    void *p = nullptr;
+    if (hipMalloc(&p, v.size() * sizeof(T)) != hipSuccess) return SOPTX_E_OOM;
+    h->allocs.push_back(p);
+    if (hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st) != hipSuccess)
+        return SOPTX_E_DEVICE;
+    *dst = static_cast<T *>(p);
+    return SOPTX_OK;
+}
+
+void free_filter(soptx_filter_s *h) {
+    if (!h) return;
+    for (void *p : h->allocs) (void)hipFree(p);
+    delete h;
+}
+
+FilterArgs args(const soptx_filter_s *h) {
+    return FilterArgs{h->row_ptr, h->col, h->w, h->v, h->hsv, h->hs, h->n};
+}
+
+int finish(hipError_t e) { return e == hipSuccess ? SOPTX_OK : SOPTX_E_DEVICE; }
+
+struct HostFilter {
+    int64_t n = 0;
+    std::vector<int32_t> row_ptr, col;
+    std::vector<double> w, v, hsv, hs;
+};
+
+int build_filter_host(const soptx_mesh *mesh, double rmin, HostFilter &F) {
+    if (!(rmin > 0.0) || !std::isfinite(rmin)) return SOPTX_E_INVALID_ARG;
+    int rc = validate_mesh(mesh);
+    if (rc) return rc;
+    const int dim = mesh->dim;
+    const int64_t n = mesh->n_cells;
+    F.n = n;
+    std::vector<double> c;
+    std::vector<double> &v = F.v, &w = F.w, &hsv = F.hsv, &hs = F.hs;
+    std::vector<int32_t> &row_ptr = F.row_ptr, &col = F.col;
+    row_ptr.assign((size_t)n + 1, 0);
+    hsv.assign((size_t)n, 0.0);
+    hs.assign((size_t)n, 0.0);
+    try {
+        centroids_volumes(mesh, c, v);
+        // bounding box and cell grid (side h >= rmin, at most ~2 cells per element)
+        double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+        for (int a = 0; a < dim; a++) {
+            lo[a] = n ? c[a] : 0.0;
+            hi[a] = lo[a];
+        }
+        for (int64_t e = 0; e < n; e++)
+            for (int a = 0; a < dim; a++) {
+                lo[a] = std::min(lo[a], c[(size_t)e * dim + a]);
+                hi[a] = std::max(hi[a], c[(size_t)e * dim + a]);
+            }
+        double h = rmin;
+        int64_t nc[3] = {1, 1, 1};
+        for (;;) {
+            double cells = 1.0;
+            for (int a = 0; a < dim; a++) cells *= std::floor((hi[a] - lo[a]) / h) + 1.0;
+            if (cells <= 2.0 * (double)std::max<int64_t>(n, 1) + 64.0) break;
+            h *= 2.0;
+        }
+        for (int a = 0; a < dim; a++) nc[a] = (int64_t)std::floor((hi[a] - lo[a]) / h) + 1;
+        const int64_t ncell = nc[0] * nc[1] * nc[2];
+        std::vector<int64_t> cell_ptr((size_t)ncell + 1, 0);
+        std::vector<int64_t> cell_of((size_t)n);
+        for (int64_t e = 0; e < n; e++) {
+            int64_t ic[3] = {0, 0, 0};
+            for (int a = 0; a < dim; a++)
+                ic[a] = std::min<int64_t>(nc[a] - 1,
+                                          std::max<int64_t>(0, (int64_t)std::floor((c[(size_t)e * dim + a] - lo[a]) / h)));
+            cell_of[(size_t)e] = (ic[0] * nc[1] + ic[1]) * nc[2] + ic[2];
+            cell_ptr[(size_t)cell_of[(size_t)e] + 1]++;
+        }
+        for (int64_t k = 0; k < ncell; k++) cell_ptr[(size_t)k + 1] += cell_ptr[(size_t)k];
+        std::vector<int32_t> cell_el((size_t)n);
+        {
+            std::vector<int64_t> fill(cell_ptr.begin(), cell_ptr.end() - 1);
+            for (int64_t e = 0; e < n; e++) cell_el[(size_t)fill[(size_t)cell_of[(size_t)e]]++] = (int32_t)e;
+        }
+        // rows in parallel chunks, concatenated in row order
+        const int nth = (int)std::max<int64_t>(1, std::min<int64_t>(16, std::min<int64_t>(
+                                                         (int64_t)std::thread::hardware_concurrency(), n / 4096 + 1)));
+        std::vector<Rows> parts((size_t)nth);
+        std::vector<std::thread> th;
+        for (int t = 0; t < nth; t++) {
+            const int64_t r0 = n * t / nth, r1 = n * (t + 1) / nth;
+            th.emplace_back([&, t, r0, r1] {
+                search_rows(dim, c, rmin, lo, h, nc, cell_ptr, cell_el, r0, r1, parts[(size_t)t]);
+            });
+        }
+        for (auto &x : th) x.join();
+        int64_t nnz = 0;
+        for (const auto &p : parts) nnz += (int64_t)p.col.size();
+        if (nnz > INT32_MAX) return SOPTX_E_OVERFLOW;
+        col.reserve((size_t)nnz);
+        w.reserve((size_t)nnz);
+        int64_t r = 0;
+        for (const auto &p : parts) {
+            for (int64_t k : p.cnt) {
+                row_ptr[(size_t)r + 1] = row_ptr[(size_t)r] + (int32_t)k;
+                r++;
+            }
+            col.insert(col.end(), p.col.begin(), p.col.end());
+            w.insert(w.end(), p.w.begin(), p.w.end());
+        }
+        // row sums in ascending column order
+        for (int64_t i = 0; i < n; i++) {
+            double a = 0.0, b = 0.0;
+            for (int32_t k = row_ptr[(size_t)i]; k < row_ptr[(size_t)i + 1]; k++) {
+                a += w[(size_t)k] * v[(size_t)col[(size_t)k]];
+                b += w[(size_t)k];
+            }
+            hsv[(size_t)i] = a;
+            hs[(size_t)i] = b;
+        }
+    } catch (const std::bad_alloc &) {
+        return SOPTX_E_OOM;
+    }
+    return SOPTX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int soptx_build_filter(const soptx_mesh *mesh, double rmin, soptx_filter *out, void *stream) {
+    if (!out) return SOPTX_E_INVALID_ARG;
+    *out = nullptr;
+    HostFilter F;
+    int rc = build_filter_host(mesh, rmin, F);
+    if (rc) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t n = F.n;
+
+    soptx_filter_s *f = new (std::nothrow) soptx_filter_s();
+    if (!f) return SOPTX_E_OOM;
+    f->dim = mesh->dim;
+    f->n = n;
+    f->nnz = (int64_t)F.col.size();
+    // lanes per row: the largest power of two not above half the mean row
+    // length, within 4..64 (each lane then takes about two entries)
+    const double mean = n ? (double)f->nnz / (double)n : 0.0;
+    f->lanes = 4;
+    while (f->lanes < 64 && 2.0 * f->lanes <= 0.5 * mean) f->lanes *= 2;
+    if (hipGetDevice(&f->device) != hipSuccess) { free_filter(f); return SOPTX_E_DEVICE; }
+    if ((rc = upload(f, F.row_ptr, &f->row_ptr, st)) || (rc = upload(f, F.col, &f->col, st)) ||
+        (rc = upload(f, F.w, &f->w, st)) || (rc = upload(f, F.v, &f->v, st)) || (rc = upload(f, F.hsv, &f->hsv, st)) ||
+        (rc = upload(f, F.hs, &f->hs, st))) {
+        free_filter(f);
+        return rc;
+    }
+    if (hipStreamSynchronize(st) != hipSuccess) { free_filter(f); return SOPTX_E_DEVICE; }
+    *out = f;
+    return SOPTX_OK;
+}
+
+int soptx_filter_info(soptx_filter h, int64_t *n, int64_t *nnz, int32_t *lanes) {
+    if (!h || !n || !nnz) return SOPTX_E_INVALID_ARG;
+    *n = h->n;
+    *nnz = h->nnz;
+    if (lanes) *lanes = h->lanes;
+    return SOPTX_OK;
+}
+
+int soptx_filter_copy(soptx_filter h, int32_t *h_row_ptr, int32_t *h_col, double *h_w, double *h_vol) {
+    if (!h) return SOPTX_E_INVALID_ARG;
+    DeviceGuard g(h->device);
+    if (!g.ok) return SOPTX_E_DEVICE;
+    hipError_t e = hipSuccess;
+    if (h_row_ptr && h->row_ptr) e = hipMemcpy(h_row_ptr, h->row_ptr, (h->n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && h_col && h->col) e = hipMemcpy(h_col, h->col, h->nnz * sizeof(int32_t), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && h_w && h->w) e = hipMemcpy(h_w, h->w, h->nnz * sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && h_vol && h->v) e = hipMemcpy(h_vol, h->v, h->n * sizeof(double), hipMemcpyDeviceToHost);
+    return finish(e);
+}
+
+int soptx_filter_sensitivity(soptx_filter h, const double *d_rho, const double *d_dc, double *d_dc_out,
+                             void *stream) {
+    if (!h) return SOPTX_E_INVALID_ARG;
+    if (h->n == 0) return SOPTX_OK;
+    if (!d_rho || !d_dc || !d_dc_out || d_dc_out == d_rho || d_dc_out == d_dc) return SOPTX_E_INVALID_ARG;
+    DeviceGuard g(h->device);
+    if (!g.ok) return SOPTX_E_DEVICE;
+    return finish(launch_filter_sensitivity(args(h), h->lanes, d_rho, d_dc, d_dc_out, static_cast<hipStream_t>(stream)));
+}
+
+int soptx_filter_density(soptx_filter h, const double *d_rho, double beta, double *d_rho_tilde, double *d_rho_bar,
+                         void *stream) {
+    if (!h) return SOPTX_E_INVALID_ARG;
+    if (d_rho_bar && (!(beta >= 0.0) || !std::isfinite(beta))) return SOPTX_E_INVALID_ARG;
+    if (h->n == 0) return SOPTX_OK;
+    if (!d_rho || !d_rho_tilde || d_rho_tilde == d_rho || d_rho_bar == d_rho || d_rho_bar == d_rho_tilde)
+        return SOPTX_E_INVALID_ARG;
+    DeviceGuard g(h->device);
+    if (!g.ok) return SOPTX_E_DEVICE;
+    return finish(launch_filter_density(args(h), h->lanes, d_rho, beta, d_rho_tilde, d_rho_bar,
+                                        static_cast<hipStream_t>(stream)));
+}
+
+int soptx_filter_density_backward(soptx_filter h, const double *d_rho_tilde, double beta, const double *d_grad,
+                                  double *d_grad_rho, void *stream) {
+    if (!h) return SOPTX_E_INVALID_ARG;
+    if (d_rho_tilde && (!(beta >= 0.0) || !std::isfinite(beta))) return SOPTX_E_INVALID_ARG;
+    if (h->n == 0) return SOPTX_OK;
+    if (!d_grad || !d_grad_rho || d_grad_rho == d_grad || d_grad_rho == d_rho_tilde) return SOPTX_E_INVALID_ARG;
+    DeviceGuard g(h->device);
+    if (!g.ok) return SOPTX_E_DEVICE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double *tmp = nullptr;
+    int rc = get_workspace(h->device, st, (size_t)h->n, &tmp, 2);
+    if (rc) return rc;
+    return finish(launch_filter_backward(args(h), h->lanes, d_rho_tilde, beta, d_grad, tmp, d_grad_rho, st));
+}
+
+int soptx_debug_filter_matrix(const soptx_mesh *mesh, double rmin, int64_t *n, int64_t *nnz, int32_t *row_ptr,
+                              int32_t *col, double *w, double *vol, double *hsv, double *hs) {
+    if (!n || !nnz) return SOPTX_E_INVALID_ARG;
+    HostFilter F;
+    int rc = build_filter_host(mesh, rmin, F);
+    if (rc) return rc;
+    *n = F.n;
+    *nnz = (int64_t)F.col.size();
+    if (row_ptr) std::copy(F.row_ptr.begin(), F.row_ptr.end(), row_ptr);
+    if (col) std::copy(F.col.begin(), F.col.end(), col);
+    if (w) std::copy(F.w.begin(), F.w.end(), w);
+    if (vol) std::copy(F.v.begin(), F.v.end(), vol);
+    if (hsv) std::copy(F.hsv.begin(), F.hsv.end(), hsv);
+    if (hs) std::copy(F.hs.begin(), F.hs.end(), hs);
+    return SOPTX_OK;
+}
+
+void soptx_destroy_filter(soptx_filter h) {
+    if (!h) return;
+    DeviceGuard g(h->device);
+    free_filter(h);
+}
+
+}  // extern "C"

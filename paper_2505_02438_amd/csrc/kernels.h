@@ -94,4 +94,22 @@ hipError_t launch_cg_p(double *p, const double *z, const double *sc, int64_t n, 
 hipError_t launch_cg_scalars(int what, const double *part, int n, double *sc, hipStream_t st);
 hipError_t launch_backward(int elem, int prec, const BwdParams &P, hipStream_t st);
 
+// filter step: H in CSR (int32 columns, FP64 weights), element measures v,
+// row sums hsv_i = sum_j H_ij v_j and hs_i = sum_j H_ij
+struct FilterArgs {
+    const int32_t *row_ptr;
+    const int32_t *col;
+    const double *w;
+    const double *v;
+    const double *hsv;
+    const double *hs;
+    int64_t n;
+};
+hipError_t launch_filter_density(const FilterArgs &F, int lanes, const double *rho, double beta, double *rho_tilde,
+                                 double *rho_bar, hipStream_t st);
+hipError_t launch_filter_sensitivity(const FilterArgs &F, int lanes, const double *rho, const double *dc,
+                                     double *dc_out, hipStream_t st);
+hipError_t launch_filter_backward(const FilterArgs &F, int lanes, const double *rho_tilde, double beta,
+                                  const double *g, double *tmp, double *grad, hipStream_t st);
+
 }  // namespace soptx

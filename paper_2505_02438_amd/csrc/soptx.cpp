@@ -13,10 +13,44 @@
 
 #include "../../include/soptx.h"
 #include "../../include/soptx_debug.h"
+#include "host_util.h"
 #include "internal.h"
 #include "kernels.h"
 
 using namespace soptx;
+
+namespace soptx {
+
+// Per-(device, stream, use) scratch; see host_util.h.
+namespace {
+struct Workspace {
+    double *buf = nullptr;
+    size_t n = 0;
+};
+std::mutex g_ws_mu;
+std::map<std::tuple<int, hipStream_t, int>, Workspace> g_ws;
+}  // namespace
+
+int get_workspace(int device, hipStream_t st, size_t n, double **out, int use) {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    Workspace &w = g_ws[std::make_tuple(device, st, use)];
+    if (w.n < n) {
+        if (w.buf) {
+            if (hipStreamSynchronize(st) != hipSuccess) return SOPTX_E_DEVICE;
+            (void)hipFree(w.buf);
+            w.buf = nullptr;
+            w.n = 0;
+        }
+        size_t cap = n < 4096 ? 4096 : n;
+        if (hipMalloc(&w.buf, cap * sizeof(double)) != hipSuccess) return SOPTX_E_OOM;
+        w.n = cap;
+    }
+    *out = w.buf;
+    return SOPTX_OK;
+}
+
+}  // namespace soptx
+
 
 struct soptx_pattern_s {
     int elem = 0, dim = 0, nen = 0, ref_method = 0, device = 0, nq = 0;
@@ -47,34 +81,6 @@ struct soptx_host_plan_s {
 };
 
 namespace {
-
-// Per-(device, stream, use) scratch: the fixed-order reduction partials of
-// the energy kernel (use 0) and the vectors of the CG solve (use 1).  Work on
-// one stream is ordered, so one buffer per stream and use is race-free.
-struct Workspace {
-    double *buf = nullptr;
-    size_t n = 0;
-};
-std::mutex g_ws_mu;
-std::map<std::tuple<int, hipStream_t, int>, Workspace> g_ws;
-
-int get_workspace(int device, hipStream_t st, size_t n, double **out, int use = 0) {
-    std::lock_guard<std::mutex> lk(g_ws_mu);
-    Workspace &w = g_ws[std::make_tuple(device, st, use)];
-    if (w.n < n) {
-        if (w.buf) {
-            if (hipStreamSynchronize(st) != hipSuccess) return SOPTX_E_DEVICE;
-            (void)hipFree(w.buf);
-            w.buf = nullptr;
-            w.n = 0;
-        }
-        size_t cap = n < 4096 ? 4096 : n;
-        if (hipMalloc(&w.buf, cap * sizeof(double)) != hipSuccess) return SOPTX_E_OOM;
-        w.n = cap;
-    }
-    *out = w.buf;
-    return SOPTX_OK;
-}
 
 template <class T>
 int upload(soptx_pattern_s *h, const std::vector<T> &v, T **dst, hipStream_t st) {
@@ -116,19 +122,6 @@ int int_exponent(double p) {
     if (p == std::floor(p) && p >= 0.0 && p <= 16.0) return (int)p;
     return -1;
 }
-
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = true;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
-        if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
-    }
-    ~DeviceGuard() {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-    }
-};
 
 bool valid_prec(int32_t prec) { return prec == SOPTX_FP64 || prec == SOPTX_FP32 || prec == SOPTX_BF16_FP32ACC; }
 
@@ -412,7 +405,7 @@ int soptx_evaluate(soptx_pattern h, const soptx_material *m, const void *d_rho, 
     double *ws = nullptr;
     if (d_c) {
         // block partials of c, then of f^T u
-        rc = get_workspace(h->device, st, 2 * (size_t)nblk, &ws);
+        rc = get_workspace(h->device, st, 2 * (size_t)nblk, &ws, 0);
         if (rc) return rc;
     }
     EnergyParams P{};

@@ -1,0 +1,88 @@
+"""Host side of the filter step (Sec. 2.4): the filter matrix H, the element
+measures and the row sums that soptx_build_filter uploads, built on the host
+by the library's uniform-cell search, against the oracle's brute-force
+construction; the argument checks of the filter entry points.  No GPU."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle import filters as OF
+from paper_2505_02438_amd import _lib, api
+from paper_2505_02438_amd import inputs as I
+
+CASES = [(I.QUAD4, 1.5), (I.QUAD4, 6.0), (I.TRI3, 2.0), (I.HEX8, 1.5), (I.HEX8, 2.6), (I.TET10, 1.2)]
+
+
+def _oracle(elem, m, rmin):
+    c = OF.centroids(elem, m.coords, m.cells)
+    v = OF.volumes(elem, m.coords, m.cells)
+    H = OF.filter_matrix(c, rmin)
+    return H, v
+
+
+@pytest.mark.parametrize("elem,rmin", CASES)
+def test_filter_matrix_matches_oracle(elem, rmin):
+    m = I.small_problem(elem, seed=21).mesh
+    got = api.filter_matrix_host(elem, m.coords, m.cells, rmin)
+    (rp, col, w), v = _oracle(elem, m, rmin)
+    # the neighbour sets and their order: exact
+    np.testing.assert_array_equal(got["row_ptr"], rp)
+    np.testing.assert_array_equal(got["col"], col)
+    # weights: the same operations on the same centroids
+    np.testing.assert_allclose(got["w"], w, rtol=1e-15, atol=0)
+    np.testing.assert_allclose(got["vol"], v, rtol=1e-13, atol=0)
+    np.testing.assert_allclose(got["hsv"], OF.h_product((rp, col, w), v), rtol=1e-14)
+    np.testing.assert_allclose(got["hs"], OF.h_product((rp, col, w), np.ones(len(v))), rtol=1e-14)
+
+
+def test_filter_matrix_larger_grid_and_radius_edge():
+    """A radius equal to a neighbour distance keeps that neighbour out (H = 0),
+    and a radius far above the domain's size puts every element in every row."""
+    m = I.quad_grid(20, 10)
+    got = api.filter_matrix_host(I.QUAD4, m.coords, m.cells, 1.0)
+    assert np.all(np.diff(got["row_ptr"]) == 1)          # distance 1 exactly: only the element itself
+    got = api.filter_matrix_host(I.QUAD4, m.coords, m.cells, 100.0)
+    assert np.all(np.diff(got["row_ptr"]) == 200)
+    mh = I.hex_grid(12, 7, 5)
+    got = api.filter_matrix_host(I.HEX8, mh.coords, mh.cells, 1.5)
+    (rp, col, w), _ = _oracle(I.HEX8, mh, 1.5)
+    np.testing.assert_array_equal(got["row_ptr"], rp)
+    np.testing.assert_array_equal(got["col"], col)
+
+
+def test_filter_matrix_tiny_radius_many_cells():
+    """A radius tiny against the domain: the cell grid is coarsened (bounded
+    memory) and each row holds only its element."""
+    m = I.quad_grid(30, 30, h=1000.0)
+    got = api.filter_matrix_host(I.QUAD4, m.coords, m.cells, 1e-3)
+    assert np.all(np.diff(got["row_ptr"]) == 1) and np.all(got["w"] == 1e-3)
+
+
+def test_filter_argument_errors():
+    m = I.quad_grid(3, 2)
+    for bad in (0.0, -1.0, float("nan"), float("inf")):
+        with pytest.raises(_lib.SoptxError) as e:
+            api.filter_matrix_host(I.QUAD4, m.coords, m.cells, bad)
+        assert e.value.code == -1
+    cells = m.cells.copy()
+    cells[0, 1] = 999
+    with pytest.raises(_lib.SoptxError) as e:
+        api.filter_matrix_host(I.QUAD4, m.coords, cells, 1.5)
+    assert e.value.code == -3
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    assert L.soptx_build_filter(None, 1.5, ctypes.byref(h), None) == -1
+    assert L.soptx_filter_sensitivity(None, None, None, None, None) == -1
+    assert L.soptx_filter_density(None, None, 1.0, None, None, None) == -1
+    assert L.soptx_filter_density_backward(None, None, 1.0, None, None, None) == -1
+    n, nnz = ctypes.c_int64(), ctypes.c_int64()
+    assert L.soptx_filter_info(None, ctypes.byref(n), ctypes.byref(nnz), None) == -1
+    L.soptx_destroy_filter(None)
+
+
+def test_heaviside_beta_continuation():
+    assert api.heaviside_beta(0) == 1.0 and api.heaviside_beta(49) == 1.0 and api.heaviside_beta(50) == 2.0
+    assert api.heaviside_beta(50 * 9) == 512.0 and api.heaviside_beta(10 ** 6) == 512.0
+    with pytest.raises(ValueError):
+        api.heaviside_beta(-1)

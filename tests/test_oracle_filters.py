@@ -51,6 +51,16 @@ def test_filter_matrix_matches_kdtree(elem, rmin):
     assert np.all(np.diag(A) == rmin)
 
 
+def test_filter_rows_match_whole_matrix():
+    m = I.small_problem(I.TRI3, seed=8).mesh
+    c = F.centroids(I.TRI3, m.coords, m.cells)
+    row_ptr, col, w = F.filter_matrix(c, 2.2)
+    rows = [0, 5, len(c) - 1]
+    for i, (cj, wj) in zip(rows, F.filter_rows(c, 2.2, rows)):
+        np.testing.assert_array_equal(cj, col[row_ptr[i]:row_ptr[i + 1]])
+        np.testing.assert_array_equal(wj, w[row_ptr[i]:row_ptr[i + 1]])
+
+
 def test_filter_row_on_uniform_grid_by_hand():
     """Unit squares, r_min = 1.5: an interior row holds the element (1.5), its
     4 edge neighbours (0.5) and 4 diagonal ones (1.5 - sqrt 2); the next ring
