@@ -161,7 +161,7 @@ def filter_run(pat, m, mat, rho, K, stream, beta=8.0, reps=20):
     # once, plus each distinct vector read or written once
     hbytes = flt.nnz * 12 + (n + 1) * 4
     vec = {"density_heaviside": 5, "sensitivity": 4, "chain_rule": 7}
-    out = {"rmin": rmin, "beta": beta, "elements": n, "nnz": flt.nnz, "lanes": flt.lanes, "build_s": build_s}
+    out = {"rmin": rmin, "beta": beta, "elements": n, "nnz": flt.nnz, "rows_per_block": flt.rows_per_block, "build_s": build_s}
     for k in names:
         avg = statistics.mean(ms[k]) / 1e3
         nb = hbytes + vec[k] * n * 8

@@ -15,7 +15,9 @@
  *   Heaviside projection rho_bar_i = 1 - exp(-beta rho~_i) + rho~_i exp(-beta)
  *   their chain rule     dpsi/drho_j = v_j sum_i H_ij (dpsi/drho~_i) / (sum_k H_ik v_k),
  *                        dpsi/drho~_i = dpsi/drho_bar_i (beta exp(-beta rho~_i) + exp(-beta))
- * Each row is summed in a fixed order (bitwise reproducible, no atomics).
+ * Each row is summed in ascending column order, each product rounded and
+ * then added from zero: the order of a sequential CSR product (bitwise
+ * reproducible, no atomics).
  *
  * Status codes are the SOPTX_* codes of soptx.h.  Device arrays must not
  * overlap between inputs and outputs of one call (SOPTX_E_INVALID_ARG when
@@ -44,9 +46,9 @@ typedef struct soptx_filter_s *soptx_filter;
  * with soptx_destroy_filter. */
 int soptx_build_filter(const soptx_mesh *mesh, double rmin, soptx_filter *out, void *stream);
 
-/* Number of elements and of stored entries of H; lanes per row the product
- * kernels use (lanes may be NULL). */
-int soptx_filter_info(soptx_filter h, int64_t *n, int64_t *nnz, int32_t *lanes);
+/* Number of elements and of stored entries of H; rows of H per thread block
+ * of the product kernels (rows_per_block may be NULL). */
+int soptx_filter_info(soptx_filter h, int64_t *n, int64_t *nnz, int32_t *rows_per_block);
 
 /* Host copies of H (row_ptr [n+1], col [nnz], w [nnz]) and of the element
  * measures v [n]; any pointer may be NULL. */

@@ -294,9 +294,9 @@ class Filter:
               "soptx_build_filter")
         self._h = h
         self.rmin = float(rmin)
-        n, nnz, lanes = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
-        check(lib().soptx_filter_info(h, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(lanes)), "filter_info")
-        self.n, self.nnz, self.lanes = n.value, nnz.value, lanes.value
+        n, nnz, rpb = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        check(lib().soptx_filter_info(h, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(rpb)), "filter_info")
+        self.n, self.nnz, self.rows_per_block = n.value, nnz.value, rpb.value
 
     @classmethod
     def from_mesh(cls, mesh, rmin: float, **kw) -> "Filter":

@@ -24,7 +24,7 @@
 using namespace soptx;
 
 struct soptx_filter_s {
-    int device = 0, dim = 0, lanes = 8;
+    int device = 0, dim = 0, rows_per_block = 1;
     int64_t n = 0, nnz = 0;
     int32_t *row_ptr = nullptr, *col = nullptr;
     double *w = nullptr, *v = nullptr, *hsv = nullptr, *hs = nullptr;
@@ -265,11 +265,10 @@ int soptx_build_filter(const soptx_mesh *mesh, double rmin, soptx_filter *out, v
     f->dim = mesh->dim;
     f->n = n;
     f->nnz = (int64_t)F.col.size();
-    // lanes per row: the largest power of two not above half the mean row
-    // length, within 4..64 (each lane then takes about two entries)
-    const double mean = n ? (double)f->nnz / (double)n : 0.0;
-    f->lanes = 4;
-    while (f->lanes < 64 && 2.0 * f->lanes <= 0.5 * mean) f->lanes *= 2;
+    // rows per block of the product kernels: about kFilterChunk entries per
+    // block (one LDS chunk) at the mean row length, within 1..256
+    const double mean = n ? (double)f->nnz / (double)n : 1.0;
+    f->rows_per_block = (int)std::max(1.0, std::min(256.0, std::floor((double)kFilterChunk / std::max(mean, 1.0))));
     if (hipGetDevice(&f->device) != hipSuccess) { free_filter(f); return SOPTX_E_DEVICE; }
     if ((rc = upload(f, F.row_ptr, &f->row_ptr, st)) || (rc = upload(f, F.col, &f->col, st)) ||
         (rc = upload(f, F.w, &f->w, st)) || (rc = upload(f, F.v, &f->v, st)) || (rc = upload(f, F.hsv, &f->hsv, st)) ||
@@ -282,11 +281,11 @@ int soptx_build_filter(const soptx_mesh *mesh, double rmin, soptx_filter *out, v
     return SOPTX_OK;
 }
 
-int soptx_filter_info(soptx_filter h, int64_t *n, int64_t *nnz, int32_t *lanes) {
+int soptx_filter_info(soptx_filter h, int64_t *n, int64_t *nnz, int32_t *rows_per_block) {
     if (!h || !n || !nnz) return SOPTX_E_INVALID_ARG;
     *n = h->n;
     *nnz = h->nnz;
-    if (lanes) *lanes = h->lanes;
+    if (rows_per_block) *rows_per_block = h->rows_per_block;
     return SOPTX_OK;
 }
 
@@ -309,7 +308,7 @@ int soptx_filter_sensitivity(soptx_filter h, const double *d_rho, const double *
     if (!d_rho || !d_dc || !d_dc_out || d_dc_out == d_rho || d_dc_out == d_dc) return SOPTX_E_INVALID_ARG;
     DeviceGuard g(h->device);
     if (!g.ok) return SOPTX_E_DEVICE;
-    return finish(launch_filter_sensitivity(args(h), h->lanes, d_rho, d_dc, d_dc_out, static_cast<hipStream_t>(stream)));
+    return finish(launch_filter_sensitivity(args(h), h->rows_per_block, d_rho, d_dc, d_dc_out, static_cast<hipStream_t>(stream)));
 }
 
 int soptx_filter_density(soptx_filter h, const double *d_rho, double beta, double *d_rho_tilde, double *d_rho_bar,
@@ -321,7 +320,7 @@ int soptx_filter_density(soptx_filter h, const double *d_rho, double beta, doubl
         return SOPTX_E_INVALID_ARG;
     DeviceGuard g(h->device);
     if (!g.ok) return SOPTX_E_DEVICE;
-    return finish(launch_filter_density(args(h), h->lanes, d_rho, beta, d_rho_tilde, d_rho_bar,
+    return finish(launch_filter_density(args(h), h->rows_per_block, d_rho, beta, d_rho_tilde, d_rho_bar,
                                         static_cast<hipStream_t>(stream)));
 }
 
@@ -337,7 +336,7 @@ int soptx_filter_density_backward(soptx_filter h, const double *d_rho_tilde, dou
     double *tmp = nullptr;
     int rc = get_workspace(h->device, st, (size_t)h->n, &tmp, 2);
     if (rc) return rc;
-    return finish(launch_filter_backward(args(h), h->lanes, d_rho_tilde, beta, d_grad, tmp, d_grad_rho, st));
+    return finish(launch_filter_backward(args(h), h->rows_per_block, d_rho_tilde, beta, d_grad, tmp, d_grad_rho, st));
 }
 
 int soptx_debug_filter_matrix(const soptx_mesh *mesh, double rmin, int64_t *n, int64_t *nnz, int32_t *row_ptr,

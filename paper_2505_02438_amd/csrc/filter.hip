@@ -3,11 +3,15 @@
 // (with the Heaviside projection fused into its output) and the density
 // filter's chain rule.
 //
-// H is CSR (int32 columns, FP64 weights, separate arrays).  L lanes take one
-// row: lane s reads entries s, s + L, ... of the row (L consecutive entries
-// per step, so the column and weight loads are contiguous), gathers the
-// neighbour values (small vectors, resident in L2 / MALL) and the L partial
-// sums are added by an xor tree, a fixed order.
+// H is CSR (int32 columns, FP64 weights, separate arrays).  A block takes R
+// consecutive rows, whose entries are contiguous in the CSR arrays: its 256
+// threads stream them in chunks of kFilterChunk entries (fully coalesced
+// column and weight loads, one gather of the neighbour values per entry, the
+// small vectors staying in L2 / MALL) and store each product w * t to LDS;
+// then thread r adds row r's products in ascending column order.  The sum of
+// a row is therefore formed exactly as a sequential CSR product forms it:
+// each product rounded, then added left to right from zero.  R <= 256; rows
+// longer than a chunk carry their running sum across chunks.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -21,31 +25,39 @@ namespace {
 
 constexpr double kSensGamma = 1e-3;
 
-// MODE 0: density filter      out0 = sum w v_j x_j / hsv_i; out1 = Heaviside(out0) if non-null
+// MODE 0: density filter      out0 = sum w (v_j x_j) / hsv_i; out1 = Heaviside(out0) if non-null
 // MODE 1: chain rule product  out0 = v_i sum w x_j
-// MODE 2: sensitivity filter  out0 = sum w x_j y_j / (max(gamma, x_i) hs_i)
-template <int L, int MODE>
-__global__ __launch_bounds__(256) void k_filter(FilterArgs F, const double *__restrict__ x,
+// MODE 2: sensitivity filter  out0 = sum w (x_j y_j) / (max(gamma, x_i) hs_i)
+template <int MODE>
+__global__ __launch_bounds__(256) void k_filter(FilterArgs F, int R, const double *__restrict__ x,
                                                 const double *__restrict__ y, double beta,
                                                 double *__restrict__ out0, double *__restrict__ out1) {
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t i = t / L;
-    const int s = (int)(t % L);
-    const bool live = i < F.n;
+    __shared__ double prod[kFilterChunk];
+    const int64_t r0 = (int64_t)blockIdx.x * R;
+    const int64_t r1 = r0 + R < F.n ? r0 + R : F.n;
+    const int32_t e0 = F.row_ptr[r0], e1 = F.row_ptr[r1];
+    const int64_t i = r0 + threadIdx.x;  // this thread's row
+    const bool owner = i < r1;
+    const int32_t rb = owner ? F.row_ptr[i] : 0, re = owner ? F.row_ptr[i + 1] : 0;
     double acc = 0.0;
-    if (live) {
-        const int32_t beg = F.row_ptr[i], end = F.row_ptr[i + 1];
-        for (int32_t k = beg + s; k < end; k += L) {
+    for (int32_t c0 = e0; c0 < e1; c0 += kFilterChunk) {
+        const int32_t c1 = c0 + kFilterChunk < e1 ? c0 + kFilterChunk : e1;
+        for (int32_t k = c0 + (int32_t)threadIdx.x; k < c1; k += 256) {
             const int32_t j = F.col[k];
-            const double w = F.w[k];
-            if (MODE == 0) acc += w * (F.v[j] * x[j]);
-            else if (MODE == 1) acc += w * x[j];
-            else acc += w * (x[j] * y[j]);
+            double t;
+            if (MODE == 0) t = F.v[j] * x[j];
+            else if (MODE == 1) t = x[j];
+            else t = x[j] * y[j];
+            prod[k - c0] = F.w[k] * t;
         }
+        __syncthreads();
+        if (owner) {
+            const int32_t b = rb > c0 ? rb : c0, e = re < c1 ? re : c1;
+            for (int32_t k = b; k < e; k++) acc += prod[k - c0];
+        }
+        __syncthreads();
     }
-#pragma unroll
-    for (int m = L / 2; m > 0; m >>= 1) acc += __shfl_xor(acc, m, L);
-    if (!live || s != 0) return;
+    if (!owner) return;
     if (MODE == 0) {
         const double r = acc / F.hsv[i];
         out0[i] = r;
@@ -70,41 +82,35 @@ __global__ __launch_bounds__(256) void k_filter_scale(const double *__restrict__
 }
 
 template <int MODE>
-hipError_t launch_mode(const FilterArgs &F, int lanes, const double *x, const double *y, double beta, double *o0,
+hipError_t launch_mode(const FilterArgs &F, int R, const double *x, const double *y, double beta, double *o0,
                        double *o1, hipStream_t st) {
     if (F.n <= 0) return hipSuccess;
-    const unsigned g = (unsigned)((F.n * lanes + 255) / 256);
-    switch (lanes) {
-    case 4: hipLaunchKernelGGL((k_filter<4, MODE>), dim3(g), dim3(256), 0, st, F, x, y, beta, o0, o1); break;
-    case 8: hipLaunchKernelGGL((k_filter<8, MODE>), dim3(g), dim3(256), 0, st, F, x, y, beta, o0, o1); break;
-    case 16: hipLaunchKernelGGL((k_filter<16, MODE>), dim3(g), dim3(256), 0, st, F, x, y, beta, o0, o1); break;
-    case 32: hipLaunchKernelGGL((k_filter<32, MODE>), dim3(g), dim3(256), 0, st, F, x, y, beta, o0, o1); break;
-    case 64: hipLaunchKernelGGL((k_filter<64, MODE>), dim3(g), dim3(256), 0, st, F, x, y, beta, o0, o1); break;
-    default: return hipErrorInvalidValue;
-    }
+    if (R < 1 || R > 256) return hipErrorInvalidValue;
+    const unsigned g = (unsigned)((F.n + R - 1) / R);
+    hipLaunchKernelGGL(k_filter<MODE>, dim3(g), dim3(256), 0, st, F, R, x, y, beta, o0, o1);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_filter_density(const FilterArgs &F, int lanes, const double *rho, double beta, double *rho_tilde,
+hipError_t launch_filter_density(const FilterArgs &F, int R, const double *rho, double beta, double *rho_tilde,
                                  double *rho_bar, hipStream_t st) {
-    return launch_mode<0>(F, lanes, rho, nullptr, beta, rho_tilde, rho_bar, st);
+    return launch_mode<0>(F, R, rho, nullptr, beta, rho_tilde, rho_bar, st);
 }
 
-hipError_t launch_filter_sensitivity(const FilterArgs &F, int lanes, const double *rho, const double *dc,
+hipError_t launch_filter_sensitivity(const FilterArgs &F, int R, const double *rho, const double *dc,
                                      double *dc_out, hipStream_t st) {
-    return launch_mode<2>(F, lanes, rho, dc, 0.0, dc_out, nullptr, st);
+    return launch_mode<2>(F, R, rho, dc, 0.0, dc_out, nullptr, st);
 }
 
-hipError_t launch_filter_backward(const FilterArgs &F, int lanes, const double *rho_tilde, double beta,
+hipError_t launch_filter_backward(const FilterArgs &F, int R, const double *rho_tilde, double beta,
                                   const double *g, double *tmp, double *grad, hipStream_t st) {
     if (F.n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_filter_scale, dim3((unsigned)((F.n + 255) / 256)), dim3(256), 0, st, g, rho_tilde, beta,
                        F.hsv, tmp, F.n);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_mode<1>(F, lanes, tmp, nullptr, 0.0, grad, nullptr, st);
+    return launch_mode<1>(F, R, tmp, nullptr, 0.0, grad, nullptr, st);
 }
 
 }  // namespace soptx

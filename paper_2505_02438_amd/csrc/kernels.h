@@ -95,7 +95,9 @@ hipError_t launch_cg_scalars(int what, const double *part, int n, double *sc, hi
 hipError_t launch_backward(int elem, int prec, const BwdParams &P, hipStream_t st);
 
 // filter step: H in CSR (int32 columns, FP64 weights), element measures v,
-// row sums hsv_i = sum_j H_ij v_j and hs_i = sum_j H_ij
+// row sums hsv_i = sum_j H_ij v_j and hs_i = sum_j H_ij; R rows per block
+// (1..256), entries staged through LDS in chunks of kFilterChunk
+constexpr int kFilterChunk = 2048;
 struct FilterArgs {
     const int32_t *row_ptr;
     const int32_t *col;
@@ -105,11 +107,11 @@ struct FilterArgs {
     const double *hs;
     int64_t n;
 };
-hipError_t launch_filter_density(const FilterArgs &F, int lanes, const double *rho, double beta, double *rho_tilde,
+hipError_t launch_filter_density(const FilterArgs &F, int R, const double *rho, double beta, double *rho_tilde,
                                  double *rho_bar, hipStream_t st);
-hipError_t launch_filter_sensitivity(const FilterArgs &F, int lanes, const double *rho, const double *dc,
+hipError_t launch_filter_sensitivity(const FilterArgs &F, int R, const double *rho, const double *dc,
                                      double *dc_out, hipStream_t st);
-hipError_t launch_filter_backward(const FilterArgs &F, int lanes, const double *rho_tilde, double beta,
+hipError_t launch_filter_backward(const FilterArgs &F, int R, const double *rho_tilde, double beta,
                                   const double *g, double *tmp, double *grad, hipStream_t st);
 
 }  // namespace soptx
