@@ -44,6 +44,16 @@ class PatternStats(ctypes.Structure):
                                                "n_contributions", "plan_bytes", "device_bytes")]
 
 
+class OcParams(ctypes.Structure):
+    _fields_ = [("move", ctypes.c_double), ("eta", ctypes.c_double), ("lmax", ctypes.c_double),
+                ("tol", ctypes.c_double), ("max_steps", ctypes.c_int32)]
+
+
+class OcResult(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.c_double), ("volume", ctypes.c_double), ("change", ctypes.c_double),
+                ("steps", ctypes.c_int32)]
+
+
 _lib = None
 _P = ctypes.c_void_p
 _I = ctypes.c_int
@@ -82,6 +92,8 @@ def lib():
         "soptx_debug_host_plan_scalars": [_P, _P],
         "soptx_debug_filter_matrix": [ctypes.POINTER(Mesh), ctypes.c_double, ctypes.POINTER(_I64),
                                       ctypes.POINTER(_I64), _P, _P, _P, _P, _P, _P],
+        "soptx_oc_update": [_I64, _P, _P, _P, ctypes.c_double, ctypes.POINTER(OcParams), _P,
+                            ctypes.POINTER(OcResult), _P],
         "soptx_build_filter": [ctypes.POINTER(Mesh), ctypes.c_double, ctypes.POINTER(_P), _P],
         "soptx_filter_info": [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I32)],
         "soptx_filter_copy": [_P, _P, _P, _P, _P],

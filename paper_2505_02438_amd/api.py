@@ -376,3 +376,21 @@ def heaviside_beta(iteration: int, beta0: float = 1.0, max_beta: float = 512.0, 
             break
         beta *= 2.0
     return float(min(max_beta, beta))
+
+
+def oc_update(rho, dc, dv, vol_target: float, move: float = 0.2, eta: float = 0.5, lmax: float = 1e9,
+              tol: float = 1e-3, max_steps: int = 200, out=None, stream=None):
+    """One optimality-criteria update (Sec. 2.3): rho_new = rho B^eta clamped by
+    the move limit, B = max(0, -dc) / (lambda dv), lambda by bisection so that
+    sum dv rho_new = vol_target.  Returns (rho_new, {lambda, volume, change, steps})."""
+    import torch
+    n = int(rho.numel())
+    if out is None:
+        out = torch.empty(n, dtype=torch.float64, device=rho.device)
+    prm = _lib.OcParams(float(move), float(eta), float(lmax), float(tol), int(max_steps))
+    res = _lib.OcResult()
+    check(lib().soptx_oc_update(n, _dptr(rho, "rho", torch.float64, n), _dptr(dc, "dc", torch.float64, n),
+                                _dptr(dv, "dv", torch.float64, n), float(vol_target), ctypes.byref(prm),
+                                _dptr(out, "rho_new", torch.float64, n), ctypes.byref(res), _stream_ptr(stream)),
+          "soptx_oc_update")
+    return out, {"lambda": res.lambda_, "volume": res.volume, "change": res.change, "steps": res.steps}

@@ -111,6 +111,16 @@ hipError_t launch_filter_density(const FilterArgs &F, int R, const double *rho, 
                                  double *rho_bar, hipStream_t st);
 hipError_t launch_filter_sensitivity(const FilterArgs &F, int R, const double *rho, const double *dc,
                                      double *dc_out, hipStream_t st);
+// OC update: bisection subtree depth and node count per pass, block cap
+constexpr int kOcDepth = 4;
+constexpr int kOcNodes = (1 << kOcDepth) - 1;
+constexpr int kOcMaxBlocks = 1024;
+int oc_blocks(int64_t n);
+hipError_t launch_oc_init(double *st, double lmax, hipStream_t s);
+hipError_t launch_oc_pass(const double *rho, const double *dc, const double *dv, int64_t n, double move, double eta,
+                          double vol_target, double tol, int max_steps, double *st, double *part, hipStream_t s);
+hipError_t launch_oc_apply(const double *rho, const double *dc, const double *dv, int64_t n, double move, double eta,
+                           double *st, double *out, double *part, hipStream_t s);
 hipError_t launch_filter_backward(const FilterArgs &F, int R, const double *rho_tilde, double beta,
                                   const double *g, double *tmp, double *grad, hipStream_t st);
 

@@ -81,6 +81,27 @@ def test_filter_argument_errors():
     L.soptx_destroy_filter(None)
 
 
+def test_oc_argument_errors():
+    """soptx_oc_update rejects bad parameters before touching the device."""
+    L = _lib.lib()
+    res = _lib.OcResult()
+    good = dict(move=0.2, eta=0.5, lmax=1e9, tol=1e-3, max_steps=200)
+    bad = [dict(move=0.0), dict(move=1.5), dict(eta=0.0), dict(eta=1.2), dict(lmax=0.0), dict(lmax=float("inf")),
+           dict(tol=0.0), dict(tol=1.0), dict(max_steps=0), dict(max_steps=1001)]
+    for b in bad:
+        p = _lib.OcParams(**{**good, **b})
+        assert L.soptx_oc_update(10, 8, 8, 8, 1.0, ctypes.byref(p), 16, ctypes.byref(res), None) == -1, b
+    p = _lib.OcParams(**good)
+    assert L.soptx_oc_update(-1, None, None, None, 1.0, ctypes.byref(p), None, ctypes.byref(res), None) == -1
+    assert L.soptx_oc_update(10, None, None, None, 1.0, ctypes.byref(p), None, ctypes.byref(res), None) == -1
+    assert L.soptx_oc_update(10, 8, 8, 8, float("nan"), ctypes.byref(p), 16, ctypes.byref(res), None) == -1
+    assert L.soptx_oc_update(10, 8, 8, 8, 1.0, None, 16, ctypes.byref(res), None) == -1
+    assert L.soptx_oc_update(10, 8, 8, 8, 1.0, ctypes.byref(p), 8, ctypes.byref(res), None) == -1   # aliasing
+    # n = 0: nothing runs, a zero result
+    assert L.soptx_oc_update(0, None, None, None, 1.0, ctypes.byref(p), None, ctypes.byref(res), None) == 0
+    assert res.steps == 0 and res.lambda_ == 0.0
+
+
 def test_heaviside_beta_continuation():
     assert api.heaviside_beta(0) == 1.0 and api.heaviside_beta(49) == 1.0 and api.heaviside_beta(50) == 2.0
     assert api.heaviside_beta(50 * 9) == 512.0 and api.heaviside_beta(10 ** 6) == 512.0
