@@ -170,6 +170,71 @@ def filter_run(pat, m, mat, rho, K, stream, beta=8.0, reps=20):
     return out
 
 
+def oc_run(pat, n, dc, stream, reps=20):
+    """The OC update alone on the workload's elements: densities and
+    sensitivities of the bench step, unit constraint sensitivities, volume
+    fraction 0.3 (the 3D cantilever's), m = 0.2, eta = 0.5, bisection to a
+    relative bracket of 1e-3 from [0, 1e9].  Host-synchronous calls, wall time."""
+    import torch
+    from paper_2505_02438_amd import api
+    rho = torch.full((n,), 0.3, dtype=torch.float64, device=dc.device)
+    ones = torch.ones_like(rho)
+    out = torch.empty_like(rho)
+    torch.cuda.synchronize()
+    ts, info = [], None
+    for r in range(reps + 3):
+        t0 = time.perf_counter()
+        _, info = api.oc_update(rho, dc, ones, 0.3 * n, out=out, stream=stream)
+        ts.append(time.perf_counter() - t0)
+    return {"avg_ms": statistics.mean(ts[3:]) * 1e3, "bisection_steps": info["steps"],
+            "device_passes": (info["steps"] + 3) // 4, "lambda": info["lambda"]}
+
+
+def to_loop_run(iters, stream, rtol=1e-8):
+    """Whole optimisation iterations (Algorithm 1) on the GPU, on the 3D
+    cantilever of the paper's CPU/GPU comparison: 120 x 40 x 8 unit Q1
+    hexahedra, x = 0 face clamped, f_y = -1 at the nodes of the edge x = 120,
+    y = 0; volume fraction 0.3 from a uniform 0.3; sensitivity filter r = 3.0;
+    OC with m = 0.2, eta = 0.5; Jacobi-PCG from zero to a relative residual of
+    rtol.  An iteration: assemble K with the Dirichlet rows, solve, element
+    sensitivities and compliance, sensitivity filter, OC update."""
+    import torch
+    from paper_2505_02438_amd import api
+    from paper_2505_02438_amd import inputs as I
+    mesh = I.hex_grid(120, 40, 8)
+    mask_h, f_h = I.clamp_x0_bc(mesh)
+    d = torch.device("cuda:0")
+    pat = api.Pattern.from_mesh(mesh)
+    flt = api.Filter.from_mesh(mesh, 3.0)
+    mat = api.Material(E0=1.0, Emin=1e-9, nu=0.3, p=3.0)
+    n = mesh.n_cells
+    mask = torch.from_numpy(mask_h).to(d)
+    f = torch.from_numpy(f_h).to(d)
+    rho = torch.full((n,), 0.3, dtype=torch.float64, device=d)
+    ones = torch.ones_like(rho)
+    K = torch.empty(pat.nnz, dtype=torch.float64, device=d)
+    torch.cuda.synchronize()
+    times, cgs, cs = [], [], []
+    t_all = time.perf_counter()
+    for it in range(iters):
+        t0 = time.perf_counter()
+        pat.assemble(mat, rho, mask, out=K, stream=stream)
+        u, cg_it, _ = pat.pcg(K, f, rtol=rtol, max_iter=50000, stream=stream)
+        dc, c = pat.evaluate(mat, rho, u, f=f, stream=stream)
+        dcf = flt.sensitivity(rho, dc, stream=stream)
+        rho, info = api.oc_update(rho, dcf, ones, 0.3 * n, move=0.2, eta=0.5, stream=stream)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        cgs.append(cg_it)
+        cs.append(float(c[1]))
+    total = time.perf_counter() - t_all
+    return {"mesh": "120x40x8 Q1 hex", "elements": n, "ndof": pat.ndof, "iterations": iters, "total_s": total,
+            "first_iter_s": times[0], "avg_iter_s": (total - times[0]) / max(iters - 1, 1),
+            "cg_rtol": rtol, "cg_iterations_avg": statistics.mean(cgs), "cg_iterations_last": cgs[-1],
+            "compliance_first": cs[0], "compliance_last": cs[-1],
+            "volume_fraction_last": float(rho.sum()) / n}
+
+
 def serving_run(count, slots=4, budget=32 << 30):
     """Serving form: seeded requests (2D Q1 n^2, n in 32..512; 3D Q1 n^3,
     n in 16..96; p in {3, 4}), first as a burst (saturated elements/s), then
@@ -206,6 +271,9 @@ def main():
     ap.add_argument("--no-solve", action="store_true", help="skip the SpMV / Jacobi-PCG measurement")
     ap.add_argument("--solve-rtol", type=float, default=1e-9)
     ap.add_argument("--no-filter", action="store_true", help="skip the filter-step measurement")
+    ap.add_argument("--no-oc", action="store_true", help="skip the OC-update measurement")
+    ap.add_argument("--to-iters", type=int, default=3,
+                    help="whole optimisation iterations on the 120x40x8 cantilever (0 = skip; the paper ran 155)")
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
@@ -363,6 +431,10 @@ def main():
         out["solve"] = solve_run(pat, m, Ks[0], f, stream, args.solve_rtol)
     if not args.no_filter:
         out["filter"] = filter_run(pat, m, mat, rho, Ks[0], stream)
+    if not args.no_oc:
+        out["oc"] = oc_run(pat, pat.n_cells, dcs[0], stream)
+    if args.to_iters > 0:
+        out["optimisation_loop"] = to_loop_run(args.to_iters, stream)
     if not args.no_serving:
         out["serving"] = serving_run(args.serve_requests)
     if not args.no_cpu_baseline:
