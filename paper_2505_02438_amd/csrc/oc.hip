@@ -16,7 +16,6 @@
 
 #include <cstdint>
 
-#include "block_sum.h"
 #include "internal.h"
 #include "kernels.h"
 
@@ -75,9 +74,18 @@ __global__ __launch_bounds__(256) void k_oc_init(double *st, double lmax) {
     }
 }
 
-// part[node * gridDim.x + block] = sum over the block's elements of dv rho_new(lambda_node)
+// sum over the 64 lanes of a wave by a fixed butterfly (every lane gets it)
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) x += __shfl_xor(x, m, 64);
+    return x;
+}
+
+// part[node * gridDim.x + block] = sum over the block's elements of dv rho_new(lambda_node):
+// per thread in element order, then each wave by a butterfly, then the 4
+// waves in order
 __global__ __launch_bounds__(256) void k_oc_eval(OcArgs A, const double *__restrict__ st, double *__restrict__ part) {
-    __shared__ double red[256];
+    __shared__ double red[4][kOcNodes];
     if (st[5] != 0.0) return;  // uniform: the bisection has ended
     double lam[kOcNodes], acc[kOcNodes];
     tree_mids(st[0], st[1], lam);
@@ -88,24 +96,34 @@ __global__ __launch_bounds__(256) void k_oc_eval(OcArgs A, const double *__restr
 #pragma unroll
         for (int k = 0; k < kOcNodes; k++) acc[k] += v * oc_new(r, d, v, lam[k], A.move, A.eta);
     }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < kOcNodes; k++) {
-        const double s = block_sum_256(acc[k], red);
-        if (threadIdx.x == 0) part[(int64_t)k * gridDim.x + blockIdx.x] = s;
+        const double s = wave_sum(acc[k]);
+        if (lane == 0) red[w][k] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < kOcNodes) {
+        const int k = threadIdx.x;
+        part[(int64_t)k * gridDim.x + blockIdx.x] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
     }
 }
 
-__global__ __launch_bounds__(256) void k_oc_decide(const double *__restrict__ part, int nblk, double vol_target,
-                                                   double tol, int max_steps, double *st) {
-    __shared__ double red[256];
+// one wave per tree node (kOcNodes <= 16 waves of the 1024-thread block):
+// lane l sums blocks l, l + 64, ... in order, then a butterfly
+static_assert(kOcNodes <= 16, "one wave per tree node in a 1024-thread block");
+__global__ __launch_bounds__(1024) void k_oc_decide(const double *__restrict__ part, int nblk, double vol_target,
+                                                    double tol, int max_steps, double *st) {
     __shared__ double vol[kOcNodes];
     if (st[5] != 0.0) return;
-    for (int k = 0; k < kOcNodes; k++) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (w < kOcNodes) {
         double t = 0.0;
-        for (int b = threadIdx.x; b < nblk; b += 256) t += part[(int64_t)k * nblk + b];
-        t = block_sum_256(t, red);
-        if (threadIdx.x == 0) vol[k] = t;
+        for (int b = lane; b < nblk; b += 64) t += part[(int64_t)w * nblk + b];
+        t = wave_sum(t);
+        if (lane == 0) vol[w] = t;
     }
+    __syncthreads();
     if (threadIdx.x != 0) return;
     double l1 = st[0], l2 = st[1], lam = st[2], vl = st[3];
     int steps = (int)st[4];
@@ -195,7 +213,7 @@ hipError_t launch_oc_pass(const double *rho, const double *dc, const double *dv,
     hipLaunchKernelGGL(k_oc_eval, dim3(g), dim3(256), 0, s, A, st, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_oc_decide, dim3(1), dim3(256), 0, s, part, g, vol_target, tol, max_steps, st);
+    hipLaunchKernelGGL(k_oc_decide, dim3(1), dim3(1024), 0, s, part, g, vol_target, tol, max_steps, st);
     return hipGetLastError();
 }
 
