@@ -157,11 +157,14 @@ def filter_run(pat, m, mat, rho, K, stream, beta=8.0, reps=20):
         if r >= 3:
             for k, (a, b) in zip(names, ((0, 1), (2, 3), (4, 5))):
                 ms[k].append(ev[a].elapsed_time(ev[b]))
-    # algorithmic bytes: H (int32 column + FP64 weight per entry, row offsets)
-    # once, plus each distinct vector read or written once
-    hbytes = flt.nnz * 12 + (n + 1) * 4
+    # algorithmic bytes: each distinct vector read or written once, plus H
+    # once (int32 column + FP64 weight per entry, row offsets) in the CSR form;
+    # the stencil form reads no H (its table of offsets is a few hundred bytes)
+    hbytes = 0 if flt.stencil_size else flt.nnz * 12 + (n + 1) * 4
     vec = {"density_heaviside": 5, "sensitivity": 4, "chain_rule": 7}
-    out = {"rmin": rmin, "beta": beta, "elements": n, "nnz": flt.nnz, "rows_per_block": flt.rows_per_block, "build_s": build_s}
+    out = {"rmin": rmin, "beta": beta, "elements": n, "nnz": flt.nnz,
+           "form": f"stencil ({flt.stencil_size} offsets)" if flt.stencil_size else "csr",
+           "rows_per_block": flt.rows_per_block, "build_s": build_s}
     for k in names:
         avg = statistics.mean(ms[k]) / 1e3
         nb = hbytes + vec[k] * n * 8

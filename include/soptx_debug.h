@@ -46,6 +46,11 @@ void soptx_debug_host_plan_free(soptx_host_plan p);
 int soptx_debug_filter_matrix(const soptx_mesh *mesh, double rmin, int64_t *n, int64_t *nnz, int32_t *row_ptr,
                               int32_t *col, double *w, double *vol, double *hsv, double *hs);
 
+/* Whether soptx_build_filter_ex would use the stencil form of H for this mesh
+ * and radius (host only): *S = number of offsets (0: CSR form) and N [3] the
+ * grid sizes, slowest axis first (zeros without a stencil). */
+int soptx_debug_filter_stencil(const soptx_mesh *mesh, double rmin, int32_t *S, int64_t *N);
+
 #ifdef __cplusplus
 }
 #endif

@@ -46,6 +46,20 @@ typedef struct soptx_filter_s *soptx_filter;
  * with soptx_destroy_filter. */
 int soptx_build_filter(const soptx_mesh *mesh, double rmin, soptx_filter *out, void *stream);
 
+/* Flags of soptx_build_filter_ex. */
+#define SOPTX_FILTER_CSR_ONLY 1 /* always apply H from its CSR form */
+
+/* As soptx_build_filter.  Without SOPTX_FILTER_CSR_ONLY, H is also checked for
+ * a stencil form: elements on a structured grid numbered lexicographically
+ * (any axis order) and every row holding the same grid offsets with bitwise
+ * equal weights (at most 512 offsets).  Then the products use the stencil and
+ * read no H; the sums and results are the same as from the CSR form.
+ * Unknown flag bits: SOPTX_E_INVALID_ARG. */
+int soptx_build_filter_ex(const soptx_mesh *mesh, double rmin, int32_t flags, soptx_filter *out, void *stream);
+
+/* Number of offsets of the stencil form of H, 0 when the CSR form is used. */
+int soptx_filter_stencil_size(soptx_filter h, int32_t *S);
+
 /* Number of elements and of stored entries of H; rows of H per thread block
  * of the product kernels (rows_per_block may be NULL). */
 int soptx_filter_info(soptx_filter h, int64_t *n, int64_t *nnz, int32_t *rows_per_block);

@@ -20,6 +20,7 @@ STATUS = {
 }
 
 FP64, FP32, BF16_FP32ACC = 0, 1, 2
+FILTER_CSR_ONLY = 1
 REF_SYMBOLIC, REF_QUADRATURE = 0, 1
 
 
@@ -95,6 +96,9 @@ def lib():
         "soptx_oc_update": [_I64, _P, _P, _P, ctypes.c_double, ctypes.POINTER(OcParams), _P,
                             ctypes.POINTER(OcResult), _P],
         "soptx_build_filter": [ctypes.POINTER(Mesh), ctypes.c_double, ctypes.POINTER(_P), _P],
+        "soptx_build_filter_ex": [ctypes.POINTER(Mesh), ctypes.c_double, _I32, ctypes.POINTER(_P), _P],
+        "soptx_filter_stencil_size": [_P, ctypes.POINTER(_I32)],
+        "soptx_debug_filter_stencil": [ctypes.POINTER(Mesh), ctypes.c_double, ctypes.POINTER(_I32), _P],
         "soptx_filter_info": [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I32)],
         "soptx_filter_copy": [_P, _P, _P, _P, _P],
         "soptx_filter_sensitivity": [_P, _P, _P, _P, _P],

@@ -261,6 +261,17 @@ class Pattern:
         return out
 
 
+def filter_stencil_host(elem: int, coords, cells, rmin: float):
+    """(offsets, grid sizes) of the stencil form soptx_build_filter_ex would use
+    for this mesh and radius; (0, (0, 0, 0)) when it would use the CSR form."""
+    m, keep = _mesh_struct(elem, coords, cells)
+    S = ctypes.c_int32()
+    N = (ctypes.c_int64 * 3)()
+    check(lib().soptx_debug_filter_stencil(ctypes.byref(m), float(rmin), ctypes.byref(S), N),
+          "soptx_debug_filter_stencil")
+    return S.value, tuple(N)
+
+
 def filter_matrix_host(elem: int, coords, cells, rmin: float) -> dict:
     """The filter matrix soptx_build_filter uploads, built on the host only:
     row_ptr, col, w, element measures vol, row sums hsv (H v) and hs (H 1)."""
@@ -287,16 +298,18 @@ class Filter:
     mesh; the sensitivity filter, the density filter with the Heaviside
     projection, and the density filter's chain rule run per call (FP64)."""
 
-    def __init__(self, elem: int, coords, cells, rmin: float, stream=None):
+    def __init__(self, elem: int, coords, cells, rmin: float, csr_only: bool = False, stream=None):
         m, keep = _mesh_struct(elem, coords, cells)
         h = ctypes.c_void_p()
-        check(lib().soptx_build_filter(ctypes.byref(m), float(rmin), ctypes.byref(h), _stream_ptr(stream)),
-              "soptx_build_filter")
+        check(lib().soptx_build_filter_ex(ctypes.byref(m), float(rmin), _lib.FILTER_CSR_ONLY if csr_only else 0,
+                                          ctypes.byref(h), _stream_ptr(stream)), "soptx_build_filter")
         self._h = h
         self.rmin = float(rmin)
-        n, nnz, rpb = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        n, nnz, rpb, S = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
         check(lib().soptx_filter_info(h, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(rpb)), "filter_info")
+        check(lib().soptx_filter_stencil_size(h, ctypes.byref(S)), "filter_stencil_size")
         self.n, self.nnz, self.rows_per_block = n.value, nnz.value, rpb.value
+        self.stencil_size = S.value        # offsets of the stencil form (0: CSR form)
 
     @classmethod
     def from_mesh(cls, mesh, rmin: float, **kw) -> "Filter":

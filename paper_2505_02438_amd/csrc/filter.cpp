@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <unordered_map>
 #include <cmath>
 #include <new>
 #include <thread>
@@ -28,6 +30,11 @@ struct soptx_filter_s {
     int64_t n = 0, nnz = 0;
     int32_t *row_ptr = nullptr, *col = nullptr;
     double *w = nullptr, *v = nullptr, *hsv = nullptr, *hs = nullptr;
+    // stencil form of H (S > 0): grid sizes in numbering order, offsets, weights
+    int S = 0;
+    int64_t N[3] = {1, 1, 1};
+    int32_t *sdel = nullptr;
+    double *sw = nullptr;
     std::vector<void *> allocs;
 };
 
@@ -142,16 +149,126 @@ void free_filter(soptx_filter_s *h) {
 }
 
 FilterArgs args(const soptx_filter_s *h) {
-    return FilterArgs{h->row_ptr, h->col, h->w, h->v, h->hsv, h->hs, h->n};
+    return FilterArgs{h->row_ptr, h->col, h->w, h->v, h->hsv, h->hs, h->n,
+                      h->S, h->sdel, h->sw, {h->N[0], h->N[1], h->N[2]}};
 }
 
 int finish(hipError_t e) { return e == hipSuccess ? SOPTX_OK : SOPTX_E_DEVICE; }
 
 struct HostFilter {
     int64_t n = 0;
+    int dim = 0;
     std::vector<int32_t> row_ptr, col;
-    std::vector<double> w, v, hsv, hs;
+    std::vector<double> c, w, v, hsv, hs;
 };
+
+// H as a stencil: grid sizes N (slowest axis first, 1 for a missing axis),
+// offsets del [S][3] in the same axis order sorted by linear offset, weights.
+struct HostStencil {
+    int64_t N[3] = {1, 1, 1};
+    std::vector<int32_t> del;
+    std::vector<double> w;
+};
+
+// H is a stencil when the elements form a structured grid numbered in
+// lexicographic order of some axis order, and every row holds the same
+// offsets (those inside the grid) with bitwise-equal weights.  Then the
+// stencil, added in ascending offset order, reproduces each row's sum in
+// ascending column order.
+bool detect_stencil(const HostFilter &F, HostStencil &T) {
+    const int64_t n = F.n;
+    const int dim = F.dim;
+    if (n == 0) return false;
+    std::vector<double> uq[3];
+    int64_t cnt[3] = {1, 1, 1};
+    for (int a = 0; a < dim; a++) {
+        uq[a].resize((size_t)n);
+        for (int64_t e = 0; e < n; e++) uq[a][(size_t)e] = F.c[(size_t)e * dim + a];
+        std::sort(uq[a].begin(), uq[a].end());
+        uq[a].erase(std::unique(uq[a].begin(), uq[a].end()), uq[a].end());
+        cnt[a] = (int64_t)uq[a].size();
+    }
+    if (cnt[0] * cnt[1] * cnt[2] != n) return false;
+    std::vector<int64_t> g((size_t)n * 3, 0);
+    for (int64_t e = 0; e < n; e++)
+        for (int a = 0; a < dim; a++)
+            g[(size_t)e * 3 + a] = std::lower_bound(uq[a].begin(), uq[a].end(), F.c[(size_t)e * dim + a]) - uq[a].begin();
+    // axis orders, slowest first; a 2D grid gets a leading axis of size 1
+    std::vector<std::array<int, 3>> perms;
+    if (dim == 2) perms = {{-1, 0, 1}, {-1, 1, 0}};
+    else perms = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    int found = -1;
+    for (size_t pi = 0; pi < perms.size() && found < 0; pi++) {
+        const auto &p = perms[pi];
+        int64_t N[3];
+        for (int k = 0; k < 3; k++) N[k] = p[k] < 0 ? 1 : cnt[p[k]];
+        bool ok = true;
+        for (int64_t e = 0; e < n && ok; e++) {
+            int64_t co[3];
+            for (int k = 0; k < 3; k++) co[k] = p[k] < 0 ? 0 : g[(size_t)e * 3 + p[k]];
+            ok = (co[0] * N[1] + co[1]) * N[2] + co[2] == e;
+        }
+        if (ok) {
+            found = (int)pi;
+            for (int k = 0; k < 3; k++) T.N[k] = N[k];
+        }
+    }
+    if (found < 0) return false;
+    const int64_t N1 = T.N[1], N2 = T.N[2];
+    auto coords = [&](int64_t e, int64_t *co) {
+        co[2] = e % N2;
+        co[1] = (e / N2) % N1;
+        co[0] = e / (N1 * N2);
+    };
+    // offsets and weights over every entry; key: the offset in a grid of
+    // sizes 2N - 1 (unique for offsets between two points of the grid)
+    const int64_t M1 = 2 * N1 + 1, M2 = 2 * N2 + 1;
+    std::unordered_map<int64_t, size_t> idx;
+    std::vector<std::pair<std::array<int64_t, 3>, double>> st;
+    for (int64_t i = 0; i < n; i++) {
+        int64_t ci[3], cj[3];
+        coords(i, ci);
+        for (int32_t k = F.row_ptr[(size_t)i]; k < F.row_ptr[(size_t)i + 1]; k++) {
+            coords(F.col[(size_t)k], cj);
+            const std::array<int64_t, 3> d{cj[0] - ci[0], cj[1] - ci[1], cj[2] - ci[2]};
+            const int64_t key = (d[0] * M1 + d[1]) * M2 + d[2];
+            auto it = idx.find(key);
+            if (it == idx.end()) {
+                if ((int)st.size() >= kFilterStencilMax) return false;
+                idx.emplace(key, st.size());
+                st.push_back({d, F.w[(size_t)k]});
+            } else if (!(st[it->second].second == F.w[(size_t)k])) {
+                return false;
+            }
+        }
+    }
+    // every row holds exactly the offsets that land inside the grid (its
+    // entries are distinct offsets of the stencil, so equal counts suffice)
+    for (int64_t i = 0; i < n; i++) {
+        int64_t ci[3];
+        coords(i, ci);
+        int64_t in = 0;
+        for (const auto &kv : st) {
+            bool inside = true;
+            for (int k = 0; k < 3; k++) {
+                const int64_t x = ci[k] + kv.first[k];
+                inside = inside && x >= 0 && x < T.N[k];
+            }
+            in += inside;
+        }
+        if (in != F.row_ptr[(size_t)i + 1] - F.row_ptr[(size_t)i]) return false;
+    }
+    // ascending linear offset = ascending column within every row
+    std::vector<std::pair<int64_t, std::pair<std::array<int64_t, 3>, double>>> ent;
+    for (const auto &kv : st) ent.push_back({(kv.first[0] * N1 + kv.first[1]) * N2 + kv.first[2], kv});
+    // distinct offsets within the grid have distinct linear offsets
+    std::sort(ent.begin(), ent.end(), [](const auto &a, const auto &b) { return a.first < b.first; });
+    for (const auto &e : ent) {
+        for (int k = 0; k < 3; k++) T.del.push_back((int32_t)e.second.first[k]);
+        T.w.push_back(e.second.second);
+    }
+    return true;
+}
 
 int build_filter_host(const soptx_mesh *mesh, double rmin, HostFilter &F) {
     if (!(rmin > 0.0) || !std::isfinite(rmin)) return SOPTX_E_INVALID_ARG;
@@ -160,7 +277,8 @@ int build_filter_host(const soptx_mesh *mesh, double rmin, HostFilter &F) {
     const int dim = mesh->dim;
     const int64_t n = mesh->n_cells;
     F.n = n;
-    std::vector<double> c;
+    F.dim = dim;
+    std::vector<double> &c = F.c;
     std::vector<double> &v = F.v, &w = F.w, &hsv = F.hsv, &hs = F.hs;
     std::vector<int32_t> &row_ptr = F.row_ptr, &col = F.col;
     row_ptr.assign((size_t)n + 1, 0);
@@ -252,11 +370,23 @@ int build_filter_host(const soptx_mesh *mesh, double rmin, HostFilter &F) {
 extern "C" {
 
 int soptx_build_filter(const soptx_mesh *mesh, double rmin, soptx_filter *out, void *stream) {
+    return soptx_build_filter_ex(mesh, rmin, 0, out, stream);
+}
+
+int soptx_build_filter_ex(const soptx_mesh *mesh, double rmin, int32_t flags, soptx_filter *out, void *stream) {
     if (!out) return SOPTX_E_INVALID_ARG;
     *out = nullptr;
+    if (flags & ~SOPTX_FILTER_CSR_ONLY) return SOPTX_E_INVALID_ARG;
     HostFilter F;
     int rc = build_filter_host(mesh, rmin, F);
     if (rc) return rc;
+    HostStencil T;
+    bool stencil = false;
+    try {
+        stencil = !(flags & SOPTX_FILTER_CSR_ONLY) && detect_stencil(F, T);
+    } catch (const std::bad_alloc &) {
+        return SOPTX_E_OOM;
+    }
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t n = F.n;
 
@@ -276,8 +406,22 @@ int soptx_build_filter(const soptx_mesh *mesh, double rmin, soptx_filter *out, v
         free_filter(f);
         return rc;
     }
+    if (stencil) {
+        f->S = (int)T.w.size();
+        for (int k = 0; k < 3; k++) f->N[k] = T.N[k];
+        if ((rc = upload(f, T.del, &f->sdel, st)) || (rc = upload(f, T.w, &f->sw, st))) {
+            free_filter(f);
+            return rc;
+        }
+    }
     if (hipStreamSynchronize(st) != hipSuccess) { free_filter(f); return SOPTX_E_DEVICE; }
     *out = f;
+    return SOPTX_OK;
+}
+
+int soptx_filter_stencil_size(soptx_filter h, int32_t *S) {
+    if (!h || !S) return SOPTX_E_INVALID_ARG;
+    *S = h->S;
     return SOPTX_OK;
 }
 
@@ -353,6 +497,21 @@ int soptx_debug_filter_matrix(const soptx_mesh *mesh, double rmin, int64_t *n, i
     if (vol) std::copy(F.v.begin(), F.v.end(), vol);
     if (hsv) std::copy(F.hsv.begin(), F.hsv.end(), hsv);
     if (hs) std::copy(F.hs.begin(), F.hs.end(), hs);
+    return SOPTX_OK;
+}
+
+int soptx_debug_filter_stencil(const soptx_mesh *mesh, double rmin, int32_t *S, int64_t *N) {
+    if (!S || !N) return SOPTX_E_INVALID_ARG;
+    HostFilter F;
+    int rc = build_filter_host(mesh, rmin, F);
+    if (rc) return rc;
+    HostStencil T;
+    try {
+        *S = detect_stencil(F, T) ? (int32_t)T.w.size() : 0;
+    } catch (const std::bad_alloc &) {
+        return SOPTX_E_OOM;
+    }
+    for (int k = 0; k < 3; k++) N[k] = *S ? T.N[k] : 0;
     return SOPTX_OK;
 }
 

@@ -106,7 +106,14 @@ struct FilterArgs {
     const double *hsv;
     const double *hs;
     int64_t n;
+    // stencil form (S > 0): offsets [S][3] and weights over a grid of sizes N,
+    // slowest axis first
+    int S;
+    const int32_t *sdel;
+    const double *sw;
+    int64_t N[3];
 };
+constexpr int kFilterStencilMax = 512;
 hipError_t launch_filter_density(const FilterArgs &F, int R, const double *rho, double beta, double *rho_tilde,
                                  double *rho_bar, hipStream_t st);
 hipError_t launch_filter_sensitivity(const FilterArgs &F, int R, const double *rho, const double *dc,

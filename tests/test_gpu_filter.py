@@ -26,9 +26,9 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-13
 
 
-def _case(elem, rmin, seed, mesh=None):
+def _case(elem, rmin, seed, mesh=None, csr_only=False):
     m = mesh if mesh is not None else I.small_problem(elem, seed=seed).mesh
-    flt = api.Filter(m.elem, m.coords, m.cells, rmin)
+    flt = api.Filter(m.elem, m.coords, m.cells, rmin, csr_only=csr_only)
     c = OF.centroids(m.elem, m.coords, m.cells)
     v = OF.volumes(m.elem, m.coords, m.cells)
     H = OF.filter_matrix(c, rmin)
@@ -90,15 +90,17 @@ def test_filter_upload_and_products(elem, rmin):
     assert e_s <= TOL and e_b <= TOL and e_h <= TOL
 
 
+@pytest.mark.parametrize("csr_only", [False, True])
 @pytest.mark.parametrize("nx,ny,rmin", [(37, 23, 1.2), (37, 23, 2.5), (37, 23, 6.0), (37, 23, 10.0),
                                          (60, 60, 30.0)])
-def test_rows_per_block_and_long_rows(nx, ny, rmin):
+def test_rows_per_block_and_long_rows(nx, ny, rmin, csr_only):
     """Unit grids (element measures exact on both sides, so every product is
     bitwise equal to the oracle's): short rows (256 rows per block), long rows
     (few rows per block), and rows longer than one LDS chunk (60 x 60, r = 30:
     up to ~2800 entries), on element counts that leave a ragged last block."""
     m = I.quad_grid(nx, ny)
-    _, flt, H, v, rng = _case(I.QUAD4, rmin, 32, mesh=m)
+    _, flt, H, v, rng = _case(I.QUAD4, rmin, 32, mesh=m, csr_only=csr_only)
+    assert (flt.stencil_size > 0) == (not csr_only and rmin != 30.0)
     # unit squares: the measure is exactly 1 (the oracle's quadrature of
     # |det J|, with J summed from coordinates up to 60, agrees to rounding);
     # the exact value enters the oracle
@@ -119,11 +121,44 @@ def test_rows_per_block_and_long_rows(nx, ny, rmin):
     gh = host(flt.density_backward(dev(g), rho_tilde=rt, beta=16.0))
     e_h = _scaled(gh, OF.density_filter_backward(H, v, gt), OF.density_filter_backward(H, v, np.abs(gt)))
     row_len = np.diff(H[0])
-    print(f"{nx}x{ny} rmin={rmin} R={flt.rows_per_block} mean row {flt.nnz / n:.1f} max {row_len.max()}: "
+    print(f"{nx}x{ny} rmin={rmin} S={flt.stencil_size} R={flt.rows_per_block} mean row {flt.nnz / n:.1f} max {row_len.max()}: "
           f"heaviside chain {e_h:.1e}")
     assert e_h <= TOL
     if rmin == 30.0:
         assert row_len.max() > 2048 and flt.rows_per_block == 1
+
+
+def _all_products(flt, rho, dc, g, beta):
+    rt, rb = flt.density(rho, beta=beta)
+    return [flt.sensitivity(rho, dc), rt, rb, flt.density_backward(g), flt.density_backward(g, rho_tilde=rt, beta=beta)]
+
+
+@pytest.mark.parametrize("case", ["quad_r1.5", "quad_x_fastest_r4", "hex_r1.5", "hex_r2.6", "quad_h0.5_r1.1"])
+def test_stencil_equals_csr(case):
+    """Where H has a stencil form, both forms give bitwise equal results for
+    every product (the stencil adds in the CSR order, without contraction)."""
+    if case.startswith("quad_x"):
+        m0 = I.quad_grid(31, 17)
+        ei, ej = np.meshgrid(np.arange(31), np.arange(17), indexing="ij")
+        order = np.lexsort((ei.ravel(), ej.ravel()))
+        m = I.Mesh(m0.elem, m0.coords, np.ascontiguousarray(m0.cells[order]))
+        rmin = 4.0
+    elif case.startswith("quad_h"):
+        m, rmin = I.quad_grid(29, 13, h=0.5), 1.1
+    elif case.startswith("quad"):
+        m, rmin = I.quad_grid(40, 25), 1.5
+    else:
+        m, rmin = I.hex_grid(23, 11, 9), float(case.split("_r")[1])
+    fs = api.Filter(m.elem, m.coords, m.cells, rmin)
+    fc = api.Filter(m.elem, m.coords, m.cells, rmin, csr_only=True)
+    assert fs.stencil_size > 0 and fc.stencil_size == 0
+    rng = np.random.default_rng(35)
+    rho = dev(rng.uniform(0.0, 1.0, fs.n))
+    dc = dev(-rng.exponential(1.0, fs.n))
+    g = dev(rng.standard_normal(fs.n))
+    for a, b in zip(_all_products(fs, rho, dc, g, 6.0), _all_products(fc, rho, dc, g, 6.0)):
+        assert torch.equal(a, b)
+    print(f"{case}: stencil {fs.stencil_size} offsets, bitwise equal to the CSR form")
 
 
 def test_rows_per_block_choice():
@@ -171,7 +206,7 @@ def test_filter_full_cantilever_sampled_rows():
     m = pr.mesh
     flt = api.Filter.from_mesh(m, 1.5)
     n = flt.n
-    assert n == 192000
+    assert n == 192000 and flt.stencil_size == 19
     c = OF.centroids(m.elem, m.coords, m.cells)
     v = OF.volumes(m.elem, m.coords, m.cells)
     assert np.max(np.abs(v - 1.0)) <= 1e-13          # unit cubes: exactly 1, used as such below

@@ -59,6 +59,46 @@ def test_filter_matrix_tiny_radius_many_cells():
     assert np.all(np.diff(got["row_ptr"]) == 1) and np.all(got["w"] == 1e-3)
 
 
+def _renumber(m, order):
+    """The same mesh with its elements listed in another order."""
+    return I.Mesh(m.elem, m.coords, np.ascontiguousarray(m.cells[order]))
+
+
+def test_stencil_form_detection():
+    """The stencil form is found on structured grids in any lexicographic
+    numbering, with the grid sizes in numbering order, and refused where rows
+    differ (sheared or shuffled meshes, weights differing in the last bit,
+    more than 512 offsets)."""
+    m = I.quad_grid(37, 23)
+    assert api.filter_stencil_host(m.elem, m.coords, m.cells, 1.5) == (9, (1, 37, 23))
+    assert api.filter_stencil_host(m.elem, m.coords, m.cells, 6.0)[0] == 109
+    h = I.hex_grid(9, 7, 5)
+    assert api.filter_stencil_host(h.elem, h.coords, h.cells, 1.5) == (19, (9, 7, 5))
+    # x fastest instead of slowest: found with the axes swapped
+    ei, ej = np.meshgrid(np.arange(37), np.arange(23), indexing="ij")
+    order = np.lexsort((ei.ravel(), ej.ravel()))          # sort by j, then i
+    mt = _renumber(m, order)
+    assert api.filter_stencil_host(mt.elem, mt.coords, mt.cells, 1.5) == (9, (1, 23, 37))
+    # a shuffled numbering, triangles, a sheared grid: no stencil
+    rng = np.random.default_rng(1)
+    ms = _renumber(m, rng.permutation(m.n_cells))
+    assert api.filter_stencil_host(ms.elem, ms.coords, ms.cells, 1.5)[0] == 0
+    t = I.small_problem(I.TRI3, seed=3).mesh
+    assert api.filter_stencil_host(t.elem, t.coords, t.cells, 2.0)[0] == 0
+    sk = I.skew_mesh(I.quad_grid(9, 6), "global")
+    assert api.filter_stencil_host(sk.elem, sk.coords, sk.cells, 1.5)[0] == 0
+    # spacing 0.1: centroid differences, hence weights, vary in the last bit
+    m1 = I.quad_grid(30, 20, h=0.1)
+    assert api.filter_stencil_host(m1.elem, m1.coords, m1.cells, 0.15)[0] == 0
+    # rows of up to 2,809 offsets: over the cap
+    big = I.quad_grid(60, 60)
+    assert api.filter_stencil_host(big.elem, big.coords, big.cells, 30.0)[0] == 0
+    # the stencil is the matrix: every row's entries are its in-grid offsets
+    hh = api.filter_matrix_host(h.elem, h.coords, h.cells, 1.5)
+    assert hh["row_ptr"][-1] == 19 * 9 * 7 * 5 - 2 * (7 * 5 * (1 + 4) + 9 * 5 * (1 + 4) + 9 * 7 * (1 + 4)) + \
+        4 * (9 + 7 + 5)
+
+
 def test_filter_argument_errors():
     m = I.quad_grid(3, 2)
     for bad in (0.0, -1.0, float("nan"), float("inf")):
