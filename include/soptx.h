@@ -192,8 +192,9 @@ int soptx_assemble_backward(soptx_pattern h, const soptx_material *m, const void
  * stream. */
 int soptx_spmv(soptx_pattern h, const double *d_K_vals, const double *d_x, double *d_y, void *stream);
 
-/* Solve K u = f (Sec. 2.2) by conjugate gradients with the Jacobi
- * preconditioner (the solver module's iterative solver, Sec. 3.2), for K
+/* Solve K u = f (Sec. 2.2) by conjugate gradients preconditioned by the
+ * inverses of the DIM x DIM diagonal blocks of the nodes (node-block Jacobi;
+ * the solver module's iterative solver, Sec. 3.2), for K
  * symmetric positive definite: assembled with a Dirichlet mask, f zero on
  * the fixed dofs.  d_u ([ndof] double) is the initial guess on entry and
  * the solution on return; d_f: [ndof] double.  Stops when

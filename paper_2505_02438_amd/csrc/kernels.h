@@ -82,14 +82,16 @@ hipError_t launch_dirichlet(int dim, const int32_t *row_ptr, const int32_t *nb_t
 hipError_t launch_energy(int elem, int prec, const EnergyParams &P, hipStream_t st);
 hipError_t launch_finalize(const double *partials, int n, int with_f, double *c, hipStream_t st);
 
-// solve (Jacobi-preconditioned CG); nb = neighbour lists, K's block structure
+// solve (node-block Jacobi preconditioned CG); nb = neighbour lists, K's block structure
 int64_t spmv_blocks(int dim, int64_t n_nodes);
 hipError_t launch_spmv(int dim, const int32_t *row_ptr, const int32_t *nb, const double *K, const double *x,
                        double *y, double *xy_part, int64_t n_nodes, hipStream_t st);
-hipError_t launch_diag_inv(int dim, const int32_t *row_ptr, const int32_t *nb, const double *K, double *dinv,
-                           int64_t ndof, hipStream_t st);
-hipError_t launch_cg_vec(int mode, const double *f, double *u, double *r, double *z, double *p, const double *q,
-                         const double *dinv, const double *sc, double *part, int64_t n, hipStream_t st);
+int64_t cg_vec_blocks(int dim, int64_t ndof);
+hipError_t launch_block_inv(int dim, const int32_t *row_ptr, const int32_t *nb, const double *K, double *binv,
+                            int64_t n_nodes, hipStream_t st);
+hipError_t launch_cg_vec(int dim, int mode, const double *f, double *u, double *r, double *z, double *p,
+                         const double *q, const double *binv, const double *sc, double *part, int64_t ndof,
+                         hipStream_t st);
 hipError_t launch_cg_p(double *p, const double *z, const double *sc, int64_t n, hipStream_t st);
 hipError_t launch_cg_scalars(int what, const double *part, int n, double *sc, hipStream_t st);
 hipError_t launch_backward(int elem, int prec, const BwdParams &P, hipStream_t st);

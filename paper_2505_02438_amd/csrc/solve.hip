@@ -70,53 +70,111 @@ __global__ __launch_bounds__(256) void k_spmv(const int32_t *__restrict__ row_pt
     if (threadIdx.x == 0) xy_part[blockIdx.x] = bs;
 }
 
-// dinv_r = 1 / K_rr (0 for an empty row: an isolated node's dofs stay put)
+// Node-block Jacobi preconditioner: binv[I] = the inverse of node I's
+// DIM x DIM diagonal block of K (row-major), by the adjugate.  A singular
+// block (an isolated node) gives the inverse of its diagonal, 0 where that
+// is 0, so such dofs stay put.
 template <int DIM>
-__global__ __launch_bounds__(256) void k_diag_inv(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ nb,
-                                                  const double *__restrict__ K, double *__restrict__ dinv,
-                                                  int64_t ndof) {
-    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (r >= ndof) return;
-    const int64_t I = r / DIM;
-    const int a = (int)(r - DIM * I);
-    const int b = row_ptr[DIM * I];
-    const int rl = row_ptr[DIM * I + 1] - b;
-    const int nbo = b / (DIM * DIM);
-    double d = 0.0;
+__global__ __launch_bounds__(256) void k_block_inv(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ nb,
+                                                   const double *__restrict__ K, double *__restrict__ binv,
+                                                   int64_t n_nodes) {
+    const int64_t I = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (I >= n_nodes) return;
+    const int b0 = row_ptr[DIM * I];
+    const int rl = row_ptr[DIM * I + 1] - b0;
+    const int nbo = b0 / (DIM * DIM);
+    double B[DIM][DIM];
+#pragma unroll
+    for (int a = 0; a < DIM; a++)
+#pragma unroll
+        for (int c = 0; c < DIM; c++) B[a][c] = 0.0;
     for (int q = 0; q < rl / DIM; q++)
-        if (nb[nbo + q] == I) d = K[b + a * rl + DIM * q + a];
-    dinv[r] = d != 0.0 ? 1.0 / d : 0.0;
+        if (nb[nbo + q] == I) {
+#pragma unroll
+            for (int a = 0; a < DIM; a++)
+#pragma unroll
+                for (int c = 0; c < DIM; c++) B[a][c] = K[b0 + a * rl + DIM * q + c];
+        }
+    double X[DIM][DIM];
+    double det;
+    if (DIM == 2) {
+        det = B[0][0] * B[1][1] - B[0][1] * B[1][0];
+        X[0][0] = B[1][1];
+        X[0][1] = -B[0][1];
+        X[1][0] = -B[1][0];
+        X[1][1] = B[0][0];
+    } else {
+        X[0][0] = B[1][1] * B[2][2] - B[1][2] * B[2][1];
+        X[0][1] = B[0][2] * B[2][1] - B[0][1] * B[2][2];
+        X[0][2] = B[0][1] * B[1][2] - B[0][2] * B[1][1];
+        X[1][0] = B[1][2] * B[2][0] - B[1][0] * B[2][2];
+        X[1][1] = B[0][0] * B[2][2] - B[0][2] * B[2][0];
+        X[1][2] = B[0][2] * B[1][0] - B[0][0] * B[1][2];
+        X[2][0] = B[1][0] * B[2][1] - B[1][1] * B[2][0];
+        X[2][1] = B[0][1] * B[2][0] - B[0][0] * B[2][1];
+        X[2][2] = B[0][0] * B[1][1] - B[0][1] * B[1][0];
+        det = B[0][0] * X[0][0] + B[0][1] * X[1][0] + B[0][2] * X[2][0];
+    }
+    double *o = binv + (int64_t)DIM * DIM * I;
+    if (det != 0.0 && det == det) {
+        const double id = 1.0 / det;
+#pragma unroll
+        for (int a = 0; a < DIM; a++)
+#pragma unroll
+            for (int c = 0; c < DIM; c++) o[a * DIM + c] = X[a][c] * id;
+    } else {
+#pragma unroll
+        for (int a = 0; a < DIM; a++)
+#pragma unroll
+            for (int c = 0; c < DIM; c++) o[a * DIM + c] = (a == c && B[a][a] != 0.0) ? 1.0 / B[a][a] : 0.0;
+    }
 }
 
-// CG vector steps, one thread per dof, block partials in a fixed order.
+// CG vector steps, one thread per node (its DIM dofs, so that z = B^-1 r
+// uses the node's updated residual), block partials in a fixed order.
 // Scalars sc: [0] r.z, [1] alpha, [2] beta, [3] r.r, [4] r0.r0, [5] p.q.
-// mode 0 (start, q = K u): r = f - q, z = dinv r, p = z.
-// mode 1 (iteration, q = K p): u += alpha p, r -= alpha q, z = dinv r.
+// mode 0 (start, q = K u): r = f - q, z = B^-1 r, p = z.
+// mode 1 (iteration, q = K p): u += alpha p, r -= alpha q, z = B^-1 r.
 // Both leave block partials of r.z (part[b]) and r.r (part[nb + b]).
+template <int DIM>
 __global__ __launch_bounds__(256) void k_cg_vec(int mode, const double *__restrict__ f, double *__restrict__ u,
                                                 double *__restrict__ r, double *__restrict__ z,
                                                 double *__restrict__ p, const double *__restrict__ q,
-                                                const double *__restrict__ dinv, const double *__restrict__ sc,
-                                                double *__restrict__ part, int64_t n) {
+                                                const double *__restrict__ binv, const double *__restrict__ sc,
+                                                double *__restrict__ part, int64_t n_nodes) {
     __shared__ double red[256];
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t I = (int64_t)blockIdx.x * 256 + threadIdx.x;
     double rz = 0.0, rr = 0.0;
-    if (i < n) {
-        double ri, zi;
+    if (I < n_nodes) {
+        const int64_t d0 = DIM * I;
+        double ri[DIM], zi[DIM];
         if (mode == 0) {
-            ri = f[i] - q[i];
-            zi = dinv[i] * ri;
-            p[i] = zi;
+#pragma unroll
+            for (int a = 0; a < DIM; a++) ri[a] = f[d0 + a] - q[d0 + a];
         } else {
             const double al = sc[1];
-            u[i] += al * p[i];
-            ri = r[i] - al * q[i];
-            zi = dinv[i] * ri;
+#pragma unroll
+            for (int a = 0; a < DIM; a++) {
+                u[d0 + a] += al * p[d0 + a];
+                ri[a] = r[d0 + a] - al * q[d0 + a];
+            }
         }
-        r[i] = ri;
-        z[i] = zi;
-        rz = ri * zi;
-        rr = ri * ri;
+        const double *bi = binv + (int64_t)DIM * DIM * I;
+#pragma unroll
+        for (int a = 0; a < DIM; a++) {
+            double t = 0.0;
+#pragma unroll
+            for (int c = 0; c < DIM; c++) t += bi[a * DIM + c] * ri[c];
+            zi[a] = t;
+        }
+#pragma unroll
+        for (int a = 0; a < DIM; a++) {
+            r[d0 + a] = ri[a];
+            z[d0 + a] = zi[a];
+            if (mode == 0) p[d0 + a] = zi[a];
+            rz += ri[a] * zi[a];
+            rr += ri[a] * ri[a];
+        }
     }
     const double brz = block_sum_256(rz, red);
     const double brr = block_sum_256(rr, red);
@@ -192,20 +250,26 @@ hipError_t launch_spmv(int dim, const int32_t *row_ptr, const int32_t *nb, const
     return hipGetLastError();
 }
 
-hipError_t launch_diag_inv(int dim, const int32_t *row_ptr, const int32_t *nb, const double *K, double *dinv,
-                           int64_t ndof, hipStream_t st) {
-    const unsigned g = (unsigned)((ndof + 255) / 256);
+int64_t cg_vec_blocks(int dim, int64_t ndof) { return (ndof / dim + 255) / 256; }
+
+hipError_t launch_block_inv(int dim, const int32_t *row_ptr, const int32_t *nb, const double *K, double *binv,
+                            int64_t n_nodes, hipStream_t st) {
+    const unsigned g = (unsigned)((n_nodes + 255) / 256);
     if (g == 0) return hipSuccess;
-    if (dim == 3) hipLaunchKernelGGL(k_diag_inv<3>, dim3(g), dim3(256), 0, st, row_ptr, nb, K, dinv, ndof);
-    else hipLaunchKernelGGL(k_diag_inv<2>, dim3(g), dim3(256), 0, st, row_ptr, nb, K, dinv, ndof);
+    if (dim == 3) hipLaunchKernelGGL(k_block_inv<3>, dim3(g), dim3(256), 0, st, row_ptr, nb, K, binv, n_nodes);
+    else hipLaunchKernelGGL(k_block_inv<2>, dim3(g), dim3(256), 0, st, row_ptr, nb, K, binv, n_nodes);
     return hipGetLastError();
 }
 
-hipError_t launch_cg_vec(int mode, const double *f, double *u, double *r, double *z, double *p, const double *q,
-                         const double *dinv, const double *sc, double *part, int64_t n, hipStream_t st) {
-    const unsigned g = (unsigned)((n + 255) / 256);
+hipError_t launch_cg_vec(int dim, int mode, const double *f, double *u, double *r, double *z, double *p,
+                         const double *q, const double *binv, const double *sc, double *part, int64_t ndof,
+                         hipStream_t st) {
+    const unsigned g = (unsigned)cg_vec_blocks(dim, ndof);
     if (g == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_cg_vec, dim3(g), dim3(256), 0, st, mode, f, u, r, z, p, q, dinv, sc, part, n);
+    if (dim == 3)
+        hipLaunchKernelGGL(k_cg_vec<3>, dim3(g), dim3(256), 0, st, mode, f, u, r, z, p, q, binv, sc, part, ndof / 3);
+    else
+        hipLaunchKernelGGL(k_cg_vec<2>, dim3(g), dim3(256), 0, st, mode, f, u, r, z, p, q, binv, sc, part, ndof / 2);
     return hipGetLastError();
 }
 

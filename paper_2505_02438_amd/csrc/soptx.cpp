@@ -344,23 +344,25 @@ int soptx_pcg(soptx_pattern h, const double *d_K_vals, const double *d_f, double
     if (!dg.ok) return SOPTX_E_DEVICE;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t n = h->ndof;
-    const int64_t nbv = (n + 255) / 256;                      // blocks of the vector kernels
+    const int64_t nbv = cg_vec_blocks(h->dim, n);            // blocks of the vector kernels
     const int64_t nbs = spmv_blocks(h->dim, h->n_nodes);      // blocks of the SpMV
     const int64_t npart = std::max<int64_t>(2 * nbv, nbs);
-    // r, z, p, q, dinv, partials, 8 scalars
+    // r, z, p, q, the node blocks of the preconditioner (DIM doubles per dof),
+    // partials, 8 scalars
     double *ws = nullptr;
-    int rc = get_workspace(h->device, st, 5 * (size_t)n + (size_t)npart + 8, &ws, 1);
+    int rc = get_workspace(h->device, st, (4 + (size_t)h->dim) * (size_t)n + (size_t)npart + 8, &ws, 1);
     if (rc) return rc;
-    double *r = ws, *z = r + n, *p = z + n, *q = p + n, *dinv = q + n, *part = dinv + n, *sc = part + npart;
+    double *r = ws, *z = r + n, *p = z + n, *q = p + n, *binv = q + n, *part = binv + h->dim * n,
+           *sc = part + npart;
     double hs[8];
     auto scalars = [&]() {
         if (hipMemcpyAsync(hs, sc, sizeof(hs), hipMemcpyDeviceToHost, st) != hipSuccess) return false;
         return hipStreamSynchronize(st) == hipSuccess;
     };
-    // r = f - K u, z = D^-1 r, p = z
-    if (launch_diag_inv(h->dim, h->row_ptr, h->nb, d_K_vals, dinv, n, st) != hipSuccess ||
+    // r = f - K u, z = B^-1 r, p = z
+    if (launch_block_inv(h->dim, h->row_ptr, h->nb, d_K_vals, binv, h->n_nodes, st) != hipSuccess ||
         launch_spmv(h->dim, h->row_ptr, h->nb, d_K_vals, d_u, q, nullptr, h->n_nodes, st) != hipSuccess ||
-        launch_cg_vec(0, d_f, d_u, r, z, p, q, dinv, sc, part, n, st) != hipSuccess ||
+        launch_cg_vec(h->dim, 0, d_f, d_u, r, z, p, q, binv, sc, part, n, st) != hipSuccess ||
         launch_cg_scalars(0, part, (int)nbv, sc, st) != hipSuccess || !scalars())
         return SOPTX_E_DEVICE;
     const double rr0 = hs[4];
@@ -375,7 +377,7 @@ int soptx_pcg(soptx_pattern h, const double *d_K_vals, const double *d_f, double
     while (it < max_iter) {
         if (launch_spmv(h->dim, h->row_ptr, h->nb, d_K_vals, p, q, part, h->n_nodes, st) != hipSuccess ||
             launch_cg_scalars(1, part, (int)nbs, sc, st) != hipSuccess ||
-            launch_cg_vec(1, d_f, d_u, r, z, p, q, dinv, sc, part, n, st) != hipSuccess ||
+            launch_cg_vec(h->dim, 1, d_f, d_u, r, z, p, q, binv, sc, part, n, st) != hipSuccess ||
             launch_cg_scalars(2, part, (int)nbv, sc, st) != hipSuccess ||
             launch_cg_p(p, z, sc, n, st) != hipSuccess)
             return SOPTX_E_DEVICE;
