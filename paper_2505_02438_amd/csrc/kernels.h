@@ -92,6 +92,11 @@ hipError_t launch_block_inv(int dim, const int32_t *row_ptr, const int32_t *nb, 
 hipError_t launch_cg_vec(int dim, int mode, const double *f, double *u, double *r, double *z, double *p,
                          const double *q, const double *binv, const double *sc, double *part, int64_t ndof,
                          hipStream_t st);
+hipError_t launch_cg_vec_fused(int dim, double *u, double *r, double *z, double *p, const double *q,
+                               const double *binv, const double *pq_part, int n_pq, const double *sc,
+                               double *part_out, int64_t ndof, hipStream_t st);
+hipError_t launch_cg_p_fused(double *p, const double *z, const double *part, int nb, const double *sc_cur,
+                             double *sc_next, int64_t n, hipStream_t st);
 hipError_t launch_cg_p(double *p, const double *z, const double *sc, int64_t n, hipStream_t st);
 hipError_t launch_cg_scalars(int what, const double *part, int n, double *sc, hipStream_t st);
 hipError_t launch_backward(int elem, int prec, const BwdParams &P, hipStream_t st);

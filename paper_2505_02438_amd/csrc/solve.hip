@@ -130,6 +130,39 @@ __global__ __launch_bounds__(256) void k_block_inv(const int32_t *__restrict__ r
     }
 }
 
+// One node's CG vector step (mode 0: r = f - q, p = z; mode 1: u += al p,
+// r -= al q), then z = B^-1 r and the node's terms of r.z and r.r in dof order.
+template <int DIM>
+__device__ __forceinline__ void cg_node(int mode, double al, int64_t I, const double *__restrict__ f,
+                                        double *__restrict__ u, double *__restrict__ r, double *__restrict__ z,
+                                        double *__restrict__ p, const double *__restrict__ q,
+                                        const double *__restrict__ binv, double &rz, double &rr) {
+    const int64_t d0 = DIM * I;
+    double ri[DIM];
+    if (mode == 0) {
+#pragma unroll
+        for (int a = 0; a < DIM; a++) ri[a] = f[d0 + a] - q[d0 + a];
+    } else {
+#pragma unroll
+        for (int a = 0; a < DIM; a++) {
+            u[d0 + a] += al * p[d0 + a];
+            ri[a] = r[d0 + a] - al * q[d0 + a];
+        }
+    }
+    const double *bi = binv + (int64_t)DIM * DIM * I;
+#pragma unroll
+    for (int a = 0; a < DIM; a++) {
+        double t = 0.0;
+#pragma unroll
+        for (int c = 0; c < DIM; c++) t += bi[a * DIM + c] * ri[c];
+        r[d0 + a] = ri[a];
+        z[d0 + a] = t;
+        if (mode == 0) p[d0 + a] = t;
+        rz += ri[a] * t;
+        rr += ri[a] * ri[a];
+    }
+}
+
 // CG vector steps, one thread per node (its DIM dofs, so that z = B^-1 r
 // uses the node's updated residual), block partials in a fixed order.
 // Scalars sc: [0] r.z, [1] alpha, [2] beta, [3] r.r, [4] r0.r0, [5] p.q.
@@ -145,37 +178,7 @@ __global__ __launch_bounds__(256) void k_cg_vec(int mode, const double *__restri
     __shared__ double red[256];
     const int64_t I = (int64_t)blockIdx.x * 256 + threadIdx.x;
     double rz = 0.0, rr = 0.0;
-    if (I < n_nodes) {
-        const int64_t d0 = DIM * I;
-        double ri[DIM], zi[DIM];
-        if (mode == 0) {
-#pragma unroll
-            for (int a = 0; a < DIM; a++) ri[a] = f[d0 + a] - q[d0 + a];
-        } else {
-            const double al = sc[1];
-#pragma unroll
-            for (int a = 0; a < DIM; a++) {
-                u[d0 + a] += al * p[d0 + a];
-                ri[a] = r[d0 + a] - al * q[d0 + a];
-            }
-        }
-        const double *bi = binv + (int64_t)DIM * DIM * I;
-#pragma unroll
-        for (int a = 0; a < DIM; a++) {
-            double t = 0.0;
-#pragma unroll
-            for (int c = 0; c < DIM; c++) t += bi[a * DIM + c] * ri[c];
-            zi[a] = t;
-        }
-#pragma unroll
-        for (int a = 0; a < DIM; a++) {
-            r[d0 + a] = ri[a];
-            z[d0 + a] = zi[a];
-            if (mode == 0) p[d0 + a] = zi[a];
-            rz += ri[a] * zi[a];
-            rr += ri[a] * ri[a];
-        }
-    }
+    if (I < n_nodes) cg_node<DIM>(mode, mode == 0 ? 0.0 : sc[1], I, f, u, r, z, p, q, binv, rz, rr);
     const double brz = block_sum_256(rz, red);
     const double brr = block_sum_256(rr, red);
     if (threadIdx.x == 0) {
@@ -189,6 +192,68 @@ __global__ __launch_bounds__(256) void k_cg_p(double *__restrict__ p, const doub
                                               const double *__restrict__ sc, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i < n) p[i] = z[i] + sc[2] * p[i];
+}
+
+// The sum of n block partials in the order of k_cg_scalars (1024 strided
+// sums, then a halving tree), computed by one block of 256 threads: thread t
+// holds the strided sums t, t + 256, t + 512 and t + 768, does the tree's
+// first two levels itself and block_sum_256 the rest.  Every block that calls
+// it gets the same bits.
+__device__ __forceinline__ double sum_as_scalars(const double *__restrict__ part, int n, double *red) {
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int g = 0; g < 4; g++)
+        for (int k = (int)threadIdx.x + 256 * g; k < n; k += 1024) v[g] += part[k];
+    v[0] += v[2];
+    v[1] += v[3];
+    v[0] += v[1];
+    return block_sum_256(v[0], red);
+}
+
+// Fused iteration step for small systems: every block first forms
+// alpha = r.z / p.q from the SpMV's partials (as k_cg_scalars would), then
+// does k_cg_vec's mode 1.  Scalars are double-buffered by iteration parity
+// (slot sc + 8 par holds this iteration's r.z); partials of r.z, r.r go to
+// part_out, a different array from the p.q partials every block is reading.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_cg_vec_fused(double *__restrict__ u, double *__restrict__ r,
+                                                      double *__restrict__ z, double *__restrict__ p,
+                                                      const double *__restrict__ q, const double *__restrict__ binv,
+                                                      const double *__restrict__ pq_part, int n_pq,
+                                                      const double *__restrict__ sc, double *__restrict__ part_out,
+                                                      int64_t n_nodes) {
+    __shared__ double red[256];
+    const double al = sc[0] / sum_as_scalars(pq_part, n_pq, red);
+    const int64_t I = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double rz = 0.0, rr = 0.0;
+    if (I < n_nodes) cg_node<DIM>(1, al, I, nullptr, u, r, z, p, q, binv, rz, rr);
+    const double brz = block_sum_256(rz, red);
+    const double brr = block_sum_256(rr, red);
+    if (threadIdx.x == 0) {
+        part_out[blockIdx.x] = brz;
+        part_out[gridDim.x + blockIdx.x] = brr;
+    }
+}
+
+// Fused p step: every block forms beta = new r.z / r.z from the partials and
+// updates p; block 0 writes the next iteration's scalars (new r.z, r.r) into
+// the other parity slot, which no block of this launch reads.
+__global__ __launch_bounds__(256) void k_cg_p_fused(double *__restrict__ p, const double *__restrict__ z,
+                                                    const double *__restrict__ part, int nb, const double *sc_cur,
+                                                    double *sc_next, int64_t n) {
+    __shared__ double red[256];
+    const double rz = sum_as_scalars(part, nb, red);
+    const double beta = rz / sc_cur[0];
+    if (blockIdx.x == 0) {
+        const double rr = sum_as_scalars(part + nb, nb, red);
+        if (threadIdx.x == 0) {
+            sc_next[0] = rz;
+            sc_next[2] = beta;
+            sc_next[3] = rr;
+        }
+    }
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        p[i] = z[i] + beta * p[i];
 }
 
 // One block of kScalThreads: sums of n block partials, thread t taking
@@ -270,6 +335,29 @@ hipError_t launch_cg_vec(int dim, int mode, const double *f, double *u, double *
         hipLaunchKernelGGL(k_cg_vec<3>, dim3(g), dim3(256), 0, st, mode, f, u, r, z, p, q, binv, sc, part, ndof / 3);
     else
         hipLaunchKernelGGL(k_cg_vec<2>, dim3(g), dim3(256), 0, st, mode, f, u, r, z, p, q, binv, sc, part, ndof / 2);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_vec_fused(int dim, double *u, double *r, double *z, double *p, const double *q,
+                               const double *binv, const double *pq_part, int n_pq, const double *sc,
+                               double *part_out, int64_t ndof, hipStream_t st) {
+    const unsigned g = (unsigned)cg_vec_blocks(dim, ndof);
+    if (g == 0) return hipSuccess;
+    if (dim == 3)
+        hipLaunchKernelGGL(k_cg_vec_fused<3>, dim3(g), dim3(256), 0, st, u, r, z, p, q, binv, pq_part, n_pq, sc,
+                           part_out, ndof / 3);
+    else
+        hipLaunchKernelGGL(k_cg_vec_fused<2>, dim3(g), dim3(256), 0, st, u, r, z, p, q, binv, pq_part, n_pq, sc,
+                           part_out, ndof / 2);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_p_fused(double *p, const double *z, const double *part, int nb, const double *sc_cur,
+                             double *sc_next, int64_t n, hipStream_t st) {
+    const int64_t g0 = (n + 255) / 256;
+    const unsigned g = (unsigned)(g0 < 1024 ? g0 : 1024);
+    if (g == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cg_p_fused, dim3(g), dim3(256), 0, st, p, z, part, nb, sc_cur, sc_next, n);
     return hipGetLastError();
 }
 

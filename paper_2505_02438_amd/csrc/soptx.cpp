@@ -347,16 +347,22 @@ int soptx_pcg(soptx_pattern h, const double *d_K_vals, const double *d_f, double
     const int64_t nbv = cg_vec_blocks(h->dim, n);            // blocks of the vector kernels
     const int64_t nbs = spmv_blocks(h->dim, h->n_nodes);      // blocks of the SpMV
     const int64_t npart = std::max<int64_t>(2 * nbv, nbs);
+    // Small systems fuse the scalar steps into the vector kernels: each of
+    // their blocks re-reads the SpMV's partials, which pays while that is a few
+    // MB (nbs * nbv doubles); the fused and separate steps give the same bits.
+    const bool fused = nbs * nbv <= (int64_t)1 << 22;
     // r, z, p, q, the node blocks of the preconditioner (DIM doubles per dof),
-    // partials, 8 scalars
+    // partials, the fused path's second partials, 2 x 8 scalars (parity slots)
     double *ws = nullptr;
-    int rc = get_workspace(h->device, st, (4 + (size_t)h->dim) * (size_t)n + (size_t)npart + 8, &ws, 1);
+    int rc = get_workspace(h->device, st, (4 + (size_t)h->dim) * (size_t)n + (size_t)npart + 2 * (size_t)nbv + 16,
+                           &ws, 1);
     if (rc) return rc;
     double *r = ws, *z = r + n, *p = z + n, *q = p + n, *binv = q + n, *part = binv + h->dim * n,
-           *sc = part + npart;
+           *part2 = part + npart, *sc = part2 + 2 * nbv;
+    int par = 0;  // fused path: the scalar slot sc + 8 par holds this iteration's r.z
     double hs[8];
     auto scalars = [&]() {
-        if (hipMemcpyAsync(hs, sc, sizeof(hs), hipMemcpyDeviceToHost, st) != hipSuccess) return false;
+        if (hipMemcpyAsync(hs, sc + 8 * par, sizeof(hs), hipMemcpyDeviceToHost, st) != hipSuccess) return false;
         return hipStreamSynchronize(st) == hipSuccess;
     };
     // r = f - K u, z = B^-1 r, p = z
@@ -375,12 +381,20 @@ int soptx_pcg(soptx_pattern h, const double *d_K_vals, const double *d_f, double
     int it = 0;
     double rel = 1.0;
     while (it < max_iter) {
-        if (launch_spmv(h->dim, h->row_ptr, h->nb, d_K_vals, p, q, part, h->n_nodes, st) != hipSuccess ||
-            launch_cg_scalars(1, part, (int)nbs, sc, st) != hipSuccess ||
-            launch_cg_vec(h->dim, 1, d_f, d_u, r, z, p, q, binv, sc, part, n, st) != hipSuccess ||
-            launch_cg_scalars(2, part, (int)nbv, sc, st) != hipSuccess ||
-            launch_cg_p(p, z, sc, n, st) != hipSuccess)
+        if (launch_spmv(h->dim, h->row_ptr, h->nb, d_K_vals, p, q, part, h->n_nodes, st) != hipSuccess)
             return SOPTX_E_DEVICE;
+        if (fused) {
+            if (launch_cg_vec_fused(h->dim, d_u, r, z, p, q, binv, part, (int)nbs, sc + 8 * par, part2, n, st) !=
+                    hipSuccess ||
+                launch_cg_p_fused(p, z, part2, (int)nbv, sc + 8 * par, sc + 8 * (1 - par), n, st) != hipSuccess)
+                return SOPTX_E_DEVICE;
+            par = 1 - par;
+        } else if (launch_cg_scalars(1, part, (int)nbs, sc, st) != hipSuccess ||
+                   launch_cg_vec(h->dim, 1, d_f, d_u, r, z, p, q, binv, sc, part, n, st) != hipSuccess ||
+                   launch_cg_scalars(2, part, (int)nbv, sc, st) != hipSuccess ||
+                   launch_cg_p(p, z, sc, n, st) != hipSuccess) {
+            return SOPTX_E_DEVICE;
+        }
         it++;
         if (it % kCheck == 0 || it == max_iter) {
             if (!scalars()) return SOPTX_E_DEVICE;
