@@ -238,6 +238,39 @@ def to_loop_run(iters, stream, rtol=1e-8):
             "volume_fraction_last": float(rho.sum()) / n}
 
 
+def paper_runs():
+    """Whole optimisation runs (Algorithm 1) of the paper's examples, on the
+    GPU: final compliance and volume fraction, iterations and wall time, with
+    the values the paper prints beside them (tests/golden/paper_values.json)."""
+    from paper_2505_02438_amd import inputs as I
+    from paper_2505_02438_amd import loop
+    golden = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_values.json")))
+    cases = [
+        ("cantilever2d_160x100_rho0.4", lambda: I.quad_grid(160, 100), lambda m: I.cantilever2d_bc(m), 0.4, 6.0,
+         "sensitivity", 0.4, golden["loop_cantilever2d_160x100_rho0.4"]["printed"][-1][1:]),
+        ("cantilever2d_160x100_rho1", lambda: I.quad_grid(160, 100), lambda m: I.cantilever2d_bc(m), 0.4, 6.0,
+         "sensitivity", 1.0, golden["loop_cantilever2d_160x100_rho1"]["printed"][-1][1:]),
+        ("mbb_150x50_quad", lambda: I.quad_grid(150, 50), I.mbb_bc, 0.5, 6.0, "sensitivity", None,
+         golden["loop_mbb_150x50_quad"]["final"]),
+        ("mbb_150x50_tri", lambda: I.tri_grid(150, 50), I.mbb_bc, 0.5, 6.0, "sensitivity", None,
+         golden["loop_mbb_150x50_tri"]["final"]),
+        ("cantilever3d_60x20x4", lambda: I.hex_grid(60, 20, 4), I.clamp_x0_bc, 0.3, 1.5, "sensitivity", None,
+         golden["loop_cantilever3d_60x20x4"]["printed"][-1][1:]),
+        ("mbb_150x50_density_filter", lambda: I.quad_grid(150, 50), I.mbb_bc, 0.5, 6.0, "density", None,
+         golden["loop_mbb_150x50_density_filter"]["final_density_filter"]),
+    ]
+    out = []
+    for name, mk, bc, vf, r, filt, rho0, printed in cases:
+        m = mk()
+        mask, f = bc(m)
+        t0 = time.perf_counter()
+        res = loop.run(m, mask, f, vf, r, filt=filt, rho0=rho0)
+        out.append({"case": name, "filter": f"{filt} r={r}", "iterations": len(res.compliance),
+                    "seconds": time.perf_counter() - t0, "compliance": round(res.compliance[-1], 4),
+                    "volume_fraction": round(res.volume_fraction[-1], 4), "paper": printed})
+    return out
+
+
 def serving_run(count, slots=4, budget=32 << 30):
     """Serving form: seeded requests (2D Q1 n^2, n in 32..512; 3D Q1 n^3,
     n in 16..96; p in {3, 4}), first as a burst (saturated elements/s), then
@@ -275,6 +308,8 @@ def main():
     ap.add_argument("--solve-rtol", type=float, default=1e-9)
     ap.add_argument("--no-filter", action="store_true", help="skip the filter-step measurement")
     ap.add_argument("--no-oc", action="store_true", help="skip the OC-update measurement")
+    ap.add_argument("--no-paper-runs", action="store_true",
+                    help="skip the whole optimisation runs of the paper's examples")
     ap.add_argument("--to-iters", type=int, default=3,
                     help="whole optimisation iterations on the 120x40x8 cantilever (0 = skip; the paper ran 155)")
     ap.add_argument("--serve-requests", type=int, default=512)
@@ -438,6 +473,8 @@ def main():
         out["oc"] = oc_run(pat, pat.n_cells, dcs[0], stream)
     if args.to_iters > 0:
         out["optimisation_loop"] = to_loop_run(args.to_iters, stream)
+    if not args.no_paper_runs:
+        out["paper_runs"] = paper_runs()
     if not args.no_serving:
         out["serving"] = serving_run(args.serve_requests)
     if not args.no_cpu_baseline:
