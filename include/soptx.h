@@ -192,6 +192,32 @@ int soptx_assemble_backward(soptx_pattern h, const soptx_material *m, const void
  * stream. */
 int soptx_spmv(soptx_pattern h, const double *d_K_vals, const double *d_x, double *d_y, void *stream);
 
+/* Build a pattern that also accepts Q1 elements whose map is not affine
+ * (jittered or curved quadrilaterals and hexahedra), for the assembly with
+ * per-quadrature-point geometry below: the same checks as
+ * soptx_build_pattern, except that a non-affine Q1 element needs det J > 0
+ * at every quadrature point (SOPTX_E_JACOBIAN otherwise).  Besides the
+ * pattern it holds the node coordinates and, for every DIM x DIM block of K,
+ * the list of its element contributions in ascending element order.  On a
+ * handle of a mesh that has non-affine elements the affine-only calls
+ * (soptx_assemble, soptx_evaluate and its variants, soptx_assemble_backward)
+ * return SOPTX_E_NONAFFINE; pattern queries, soptx_apply_dirichlet,
+ * soptx_spmv and soptx_pcg work on any handle. */
+int soptx_build_pattern_general(const soptx_mesh *mesh, soptx_pattern *out, void *stream);
+
+/* SIMP stiffness assembly (Sec. 2.1, Sec. 2.2) with the element matrices
+ * integrated by the element's Gauss rule with J evaluated at every quadrature
+ * point (Q1 quadrilaterals and hexahedra, affine or not), FP64: each element's
+ * blocks E(rho_e) sum_q w_q |det J_q| L(g_i g_j^T), g = J_q^-T grad(phi) the
+ * physical gradients, are formed in a workspace (n_cells nen^2 DIM^2 doubles
+ * per (device, stream), allocated on first use), then every CSR block sums
+ * its contributions in ascending element order.  d_rho: [n_cells] double;
+ * d_dirichlet as in soptx_assemble (NULL: none); d_K_vals: [nnz].  Only for
+ * handles of soptx_build_pattern_general (SOPTX_E_INVALID_ARG otherwise);
+ * SOPTX_E_UNSUPPORTED_ELEM for simplices.  Asynchronous on stream. */
+int soptx_assemble_general(soptx_pattern h, const soptx_material *m, const double *d_rho, const uint8_t *d_dirichlet,
+                           double *d_K_vals, void *stream);
+
 /* Solve K u = f (Sec. 2.2) by conjugate gradients preconditioned by the
  * inverses of the DIM x DIM diagonal blocks of the nodes (node-block Jacobi;
  * the solver module's iterative solver, Sec. 3.2), for K

@@ -25,6 +25,11 @@ typedef struct soptx_host_plan_s *soptx_host_plan;
  * soptx_debug_host_plan_free. */
 int soptx_debug_host_plan(const soptx_mesh *mesh, soptx_host_plan *out);
 
+/* As soptx_debug_host_plan; general != 0 builds the plan of
+ * soptx_build_pattern_general (non-affine Q1 accepted, with the arrays gptr,
+ * gent and gnode of the per-quadrature-point assembly). */
+int soptx_debug_host_plan_ex(const soptx_mesh *mesh, int32_t general, soptx_host_plan *out);
+
 /* Borrow one array of the plan by name: "row_ptr", "col_idx" (int32 CSR),
  * "geo" (double, [(dim*dim+1)][n_cells]: J^-1 row-major then det J),
  * "sig_info", "sig_pos_ptr", "sig_contrib", "sig_pairs", "sig_witems", "sig_witem_ptr", "grp_info", "grp_nodes",

@@ -56,17 +56,20 @@ def validate_mesh(elem: int, coords, cells) -> int:
     return lib().soptx_validate_mesh(ctypes.byref(m))
 
 
-def host_plan(elem: int, coords, cells) -> dict:
-    """Host-side pattern, geometry and assembly plan as numpy arrays (copies)."""
+def host_plan(elem: int, coords, cells, general: bool = False) -> dict:
+    """Host-side pattern, geometry and assembly plan as numpy arrays (copies);
+    general: the plan of soptx_build_pattern_general, with its contribution
+    table (gptr, gent, gnode)."""
     m, keep = _mesh_struct(elem, coords, cells)
     L = lib()
     h = ctypes.c_void_p()
-    check(L.soptx_debug_host_plan(ctypes.byref(m), ctypes.byref(h)), "soptx_debug_host_plan")
+    check(L.soptx_debug_host_plan_ex(ctypes.byref(m), 1 if general else 0, ctypes.byref(h)), "soptx_debug_host_plan")
     try:
         out = {}
         dt = {4: np.int32, 2: np.uint16, 8: np.float64}
         for name in ("row_ptr", "col_idx", "geo", "sig_info", "sig_pos_ptr", "sig_contrib", "sig_pairs", "sig_witems", "sig_witem_ptr",
-                     "grp_info", "grp_nodes", "grp_elems", "grp_n2l", "grp_rows", "pos", "nb_tslot", "nb_tdeg"):
+                     "grp_info", "grp_nodes", "grp_elems", "grp_n2l", "grp_rows", "pos", "nb_tslot", "nb_tdeg",
+                     "gptr", "gent", "gnode"):
             ptr, cnt, eb = ctypes.c_void_p(), ctypes.c_int64(), ctypes.c_int32()
             check(L.soptx_debug_host_plan_array(h, name.encode(), ctypes.byref(ptr), ctypes.byref(cnt),
                                                 ctypes.byref(eb)), name)
@@ -114,11 +117,17 @@ class Pattern:
     assemble / sensitivity / compliance / backward run per call.
     """
 
-    def __init__(self, elem: int, coords, cells, ref_method: int = REF_SYMBOLIC, stream=None):
+    def __init__(self, elem: int, coords, cells, ref_method: int = REF_SYMBOLIC, general: bool = False,
+                 stream=None):
         m, keep = _mesh_struct(elem, coords, cells)
         h = ctypes.c_void_p()
-        check(lib().soptx_build_pattern_ex(ctypes.byref(m), ref_method, ctypes.byref(h), _stream_ptr(stream)),
-              "soptx_build_pattern")
+        if general:
+            check(lib().soptx_build_pattern_general(ctypes.byref(m), ctypes.byref(h), _stream_ptr(stream)),
+                  "soptx_build_pattern_general")
+        else:
+            check(lib().soptx_build_pattern_ex(ctypes.byref(m), ref_method, ctypes.byref(h), _stream_ptr(stream)),
+                  "soptx_build_pattern")
+        self.general = general
         self._h = h
         self.elem = elem
         self.dim = _DIM[elem]
@@ -171,6 +180,19 @@ class Pattern:
                                    _dptr(mask, "mask", torch.uint8, self.ndof),
                                    _dptr(out, "out", torch.float64, self.nnz), prec, _stream_ptr(stream)),
               "soptx_assemble")
+        return out
+
+    def assemble_general(self, material: Material, rho, mask=None, out=None, stream=None):
+        """K = sum_e E(rho_e) K_e^0 with K_e^0 integrated at the quadrature points
+        (Q1, affine or not; patterns built with general=True), FP64."""
+        import torch
+        if out is None:
+            out = torch.empty(self.nnz, dtype=torch.float64, device=rho.device)
+        mc = material._c()
+        check(lib().soptx_assemble_general(self._h, ctypes.byref(mc), _dptr(rho, "rho", torch.float64, self.n_cells),
+                                           _dptr(mask, "mask", torch.uint8, self.ndof),
+                                           _dptr(out, "K", torch.float64, self.nnz), _stream_ptr(stream)),
+              "soptx_assemble_general")
         return out
 
     def apply_dirichlet(self, mask, K, stream=None):

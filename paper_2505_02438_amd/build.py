@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libsoptx.so")
-SOURCES = ["reference.cpp", "plan.cpp", "soptx.cpp", "filter.cpp", "oc.cpp", "kernels.hip", "solve.hip", "filter.hip", "oc.hip"]
+SOURCES = ["reference.cpp", "plan.cpp", "soptx.cpp", "filter.cpp", "oc.cpp", "kernels.hip", "solve.hip", "filter.hip", "oc.hip", "general.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed-FP32 instructions in device code

@@ -1,0 +1,178 @@
+// gfx950 kernels of the SIMP stiffness assembly with per-quadrature-point
+// geometry (arXiv 2505.02438, Sec. 2.1-2.2; Q1 elements whose map is not
+// affine, where the separated form of the fast assembly does not hold).
+//
+// k_ke_general: the blocks of every element's matrix,
+//     Ke[i][j] = E(rho_e) sum_q w_q |det J_q| L(g_i g_j^T),  g_k = J_q^-T grad phi_k(xi_q),
+//     L(A) = lambda A + mu A^T + mu tr(A) I,
+// with one thread per node pair (i, j) of an element (NEN^2 threads per
+// element: a wave per hexahedron, 16 lanes per quadrilateral).  The first NQ
+// threads of an element form J_q^-1 and w_q |det J_q| E at the quadrature
+// points in LDS; every thread then accumulates its DIM x DIM block.
+// k_gather_general: one thread per DIM x DIM block of K adds its element
+// contributions in ascending element order (the order of a sequential loop
+// over elements) and writes the block once.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.h"
+#include "kernels.h"
+
+namespace soptx {
+
+namespace {
+
+__device__ __noinline__ double general_pow(double x, double p) { return pow(x, p); }
+
+// E(rho) = Emin + rho^p (E0 - Emin); an integer p by repeated products
+__device__ __forceinline__ double simp_modulus(double r, const GenParams &G) {
+    double t;
+    if (G.ip >= 0) {
+        t = 1.0;
+        for (int k = 0; k < G.ip; k++) t *= r;
+    } else {
+        t = general_pow(r, G.p);
+    }
+    return G.Emin + t * (G.E0 - G.Emin);
+}
+
+template <int DIM, int NEN, int NQ>
+__global__ __launch_bounds__(256) void k_ke_general(GenParams G) {
+    constexpr int NP = NEN * NEN;  // threads per element
+    constexpr int EPB = 256 / NP;  // elements per block
+    constexpr int D2 = DIM * DIM;
+    __shared__ double sg[EPB][NQ][D2 + 1];  // J_q^-1 (row m: d xi_m / d x), then w_q |det J_q| E
+    const int le = threadIdx.x / NP, pr = threadIdx.x % NP;
+    const int64_t e = (int64_t)blockIdx.x * EPB + le;
+    const bool live = le < EPB && e < G.n_cells;
+    if (live && pr < NQ) {
+        const int q = pr;
+        double J[DIM][DIM];
+#pragma unroll
+        for (int a = 0; a < DIM; a++)
+#pragma unroll
+            for (int m = 0; m < DIM; m++) J[a][m] = 0.0;
+        for (int k = 0; k < NEN; k++) {
+            const int64_t nd = G.cells[e * NEN + k];
+#pragma unroll
+            for (int a = 0; a < DIM; a++) {
+                const double x = G.coords[nd * DIM + a];
+#pragma unroll
+                for (int m = 0; m < DIM; m++) J[a][m] += x * G.qgrad[(q * NEN + k) * DIM + m];
+            }
+        }
+        double inv[DIM][DIM], det;
+        if (DIM == 2) {
+            det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+            inv[0][0] = J[1][1] / det;
+            inv[0][1] = -J[0][1] / det;
+            inv[1][0] = -J[1][0] / det;
+            inv[1][1] = J[0][0] / det;
+        } else {
+            const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+            const double c01 = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+            const double c02 = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+            const double c10 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+            const double c11 = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+            const double c12 = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+            const double c20 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+            const double c21 = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+            const double c22 = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+            det = J[0][0] * c00 + J[0][1] * c10 + J[0][2] * c20;
+            inv[0][0] = c00 / det; inv[0][1] = c01 / det; inv[0][2] = c02 / det;
+            inv[1][0] = c10 / det; inv[1][1] = c11 / det; inv[1][2] = c12 / det;
+            inv[2][0] = c20 / det; inv[2][1] = c21 / det; inv[2][2] = c22 / det;
+        }
+#pragma unroll
+        for (int m = 0; m < DIM; m++)
+#pragma unroll
+            for (int a = 0; a < DIM; a++) sg[le][q][m * DIM + a] = inv[m][a];
+        sg[le][q][D2] = G.qw[q] * fabs(det) * simp_modulus(G.rho[e], G);
+    }
+    __syncthreads();
+    if (!live) return;
+    const int i = pr / NEN, j = pr % NEN;
+    double blk[DIM][DIM];
+#pragma unroll
+    for (int a = 0; a < DIM; a++)
+#pragma unroll
+        for (int c = 0; c < DIM; c++) blk[a][c] = 0.0;
+    for (int q = 0; q < NQ; q++) {
+        double gi[DIM], gj[DIM];
+#pragma unroll
+        for (int a = 0; a < DIM; a++) {
+            double si = 0.0, sj = 0.0;
+#pragma unroll
+            for (int m = 0; m < DIM; m++) {
+                const double gm = sg[le][q][m * DIM + a];
+                si += G.qgrad[(q * NEN + i) * DIM + m] * gm;
+                sj += G.qgrad[(q * NEN + j) * DIM + m] * gm;
+            }
+            gi[a] = si;
+            gj[a] = sj;
+        }
+        double tr = 0.0;
+#pragma unroll
+        for (int a = 0; a < DIM; a++) tr += gi[a] * gj[a];
+        const double cq = sg[le][q][D2];
+#pragma unroll
+        for (int a = 0; a < DIM; a++)
+#pragma unroll
+            for (int c = 0; c < DIM; c++)
+                blk[a][c] += cq * (G.lam * gi[a] * gj[c] + G.mu * gi[c] * gj[a] + (a == c ? G.mu * tr : 0.0));
+    }
+    double *o = G.ke + ((e * NEN + i) * NEN + j) * D2;
+#pragma unroll
+    for (int a = 0; a < DIM; a++)
+#pragma unroll
+        for (int c = 0; c < DIM; c++) o[a * DIM + c] = blk[a][c];
+}
+
+template <int DIM>
+__global__ __launch_bounds__(256) void k_gather_general(GenParams G) {
+    constexpr int D2 = DIM * DIM;
+    const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (b >= G.n_blocks) return;
+    const int64_t I = G.gnode[b];
+    const int32_t base = G.row_ptr[DIM * I];
+    const int32_t rl = G.row_ptr[DIM * I + 1] - base;
+    const int64_t q = b - base / D2;
+    double acc[D2];
+#pragma unroll
+    for (int t = 0; t < D2; t++) acc[t] = 0.0;
+    for (int32_t k = G.gptr[b]; k < G.gptr[b + 1]; k++) {
+        const double *s = G.ke + (int64_t)G.gent[k] * D2;
+#pragma unroll
+        for (int t = 0; t < D2; t++) acc[t] += s[t];
+    }
+#pragma unroll
+    for (int a = 0; a < DIM; a++)
+#pragma unroll
+        for (int c = 0; c < DIM; c++) G.K[base + (int64_t)a * rl + DIM * q + c] = acc[a * DIM + c];
+}
+
+template <int DIM, int NEN, int NQ>
+hipError_t launch_t(const GenParams &G, hipStream_t st) {
+    constexpr int EPB = 256 / (NEN * NEN);
+    if (G.nq != NQ) return hipErrorInvalidValue;
+    if (G.n_cells > 0) {
+        hipLaunchKernelGGL((k_ke_general<DIM, NEN, NQ>), dim3((unsigned)((G.n_cells + EPB - 1) / EPB)), dim3(256), 0,
+                           st, G);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (G.n_blocks > 0)
+        hipLaunchKernelGGL(k_gather_general<DIM>, dim3((unsigned)((G.n_blocks + 255) / 256)), dim3(256), 0, st, G);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_assemble_general(int elem, const GenParams &G, hipStream_t st) {
+    if (elem == SOPTX_HEX8) return launch_t<3, 8, 8>(G, st);
+    if (elem == SOPTX_QUAD4) return launch_t<2, 4, 4>(G, st);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace soptx

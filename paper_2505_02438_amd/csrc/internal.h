@@ -89,11 +89,23 @@ struct HostPlan {
     int kmax = 0, emax = 0, ne_max = 0;  // emax: grouping limit; ne_max: largest group
     int blk_max = 0;                     // largest padded row block (doubles)
     int64_t stage_max = 0;               // largest group stage (doubles)
+    bool affine = true;                  // every element map is affine
+    // per-quadrature-point assembly (general = true): for every DIM x DIM block
+    // b of K (b = row_ptr[dim n] / dim^2 + q for neighbour q of node n) its
+    // contributions e * nen^2 + i * nen + j in ascending element order, and n
+    bool general = false;
+    std::vector<int32_t> gptr;   // [nnz / dim^2 + 1]
+    std::vector<int32_t> gent;   // [n_cells * nen^2]
+    std::vector<int32_t> gnode;  // [nnz / dim^2]
     int64_t n_groups() const { return (int64_t)grp_info.size() / kGrpInfo; }
     int64_t n_sigs() const { return (int64_t)sig_info.size() / 4; }
 };
 
-int validate_mesh(const soptx_mesh *mesh);
-int build_host_plan(const soptx_mesh *mesh, HostPlan &hp);
+// allow_nonaffine: Q1 elements whose map is not affine are accepted when
+// det J > 0 at every quadrature point (*affine is then set to false)
+int validate_mesh(const soptx_mesh *mesh, bool allow_nonaffine = false, bool *affine = nullptr);
+// general: also accept non-affine Q1 elements and build the contribution
+// table of the per-quadrature-point assembly
+int build_host_plan(const soptx_mesh *mesh, HostPlan &hp, bool general = false);
 
 }  // namespace soptx

@@ -101,6 +101,26 @@ hipError_t launch_cg_p(double *p, const double *z, const double *sc, int64_t n, 
 hipError_t launch_cg_scalars(int what, const double *part, int n, double *sc, hipStream_t st);
 hipError_t launch_backward(int elem, int prec, const BwdParams &P, hipStream_t st);
 
+// per-quadrature-point assembly (non-affine Q1): element blocks, then a
+// gather of every CSR block's contributions in ascending element order
+struct GenParams {
+    const int32_t *cells;
+    const double *coords;
+    const double *rho;
+    const double *qw;
+    const double *qgrad;  // [nq][nen][dim] reference gradients
+    int64_t n_cells;
+    int nq;
+    double E0, Emin, p;
+    int ip;
+    double lam, mu;
+    double *ke;  // [n_cells][nen][nen][dim][dim]
+    const int32_t *gptr, *gent, *gnode, *row_ptr;
+    double *K;
+    int64_t n_blocks;
+};
+hipError_t launch_assemble_general(int elem, const GenParams &G, hipStream_t st);
+
 // filter step: H in CSR (int32 columns, FP64 weights), element measures v,
 // row sums hsv_i = sum_j H_ij v_j and hs_i = sum_j H_ij; R rows per block
 // (1..256), entries staged through LDS in chunks of kFilterChunk

@@ -55,7 +55,8 @@ double inv_small(int dim, const double *J, double *G) {
 
 }  // namespace
 
-int validate_mesh(const soptx_mesh *mesh) {
+int validate_mesh(const soptx_mesh *mesh, bool allow_nonaffine, bool *affine) {
+    if (affine) *affine = true;
     if (!mesh) return SOPTX_E_INVALID_ARG;
     const int dim = elem_dim(mesh->elem), nen = elem_nen(mesh->elem);
     if (dim < 0) return SOPTX_E_UNSUPPORTED_ELEM;
@@ -73,6 +74,7 @@ int validate_mesh(const soptx_mesh *mesh) {
         }
     }
     // geometry: affine map, positive orientation
+    std::vector<double> qw, qg;  // quadrature weights and reference gradients (non-affine Q1 only)
     for (int64_t e = 0; e < mesh->n_cells; e++) {
         const int32_t *c = mesh->cells + e * nen;
         auto X = [&](int i, int a) { return mesh->coords[(int64_t)c[i] * dim + a]; };
@@ -88,9 +90,11 @@ int validate_mesh(const soptx_mesh *mesh) {
                 scale = std::max(scale, std::fabs(J[a * dim + m]));
             }
         double det = inv_small(dim, J, G);
-        if (!(det > 0.0) || !std::isfinite(det)) return SOPTX_E_JACOBIAN;
+        const bool q1 = mesh->elem == SOPTX_QUAD4 || mesh->elem == SOPTX_HEX8;
+        if (!(allow_nonaffine && q1) && (!(det > 0.0) || !std::isfinite(det))) return SOPTX_E_JACOBIAN;
         // every node must sit at the affine image of its reference position
         const double tol = 1e-10 * scale;
+        bool is_affine = det > 0.0 && std::isfinite(det);
         for (int i = 0; i < nen; i++) {
             double xi[3] = {0, 0, 0};
             if (mesh->elem == SOPTX_QUAD4 || mesh->elem == SOPTX_HEX8) {
@@ -110,16 +114,33 @@ int validate_mesh(const soptx_mesh *mesh) {
             for (int a = 0; a < dim; a++) {
                 double x = X(0, a);
                 for (int m = 0; m < dim; m++) x += J[a * dim + m] * xi[m];
-                if (std::fabs(x - X(i, a)) > tol) return SOPTX_E_NONAFFINE;
+                if (std::fabs(x - X(i, a)) > tol) is_affine = false;
             }
+        }
+        if (is_affine) continue;
+        if (!(allow_nonaffine && q1)) return SOPTX_E_NONAFFINE;
+        // a general Q1 element: det J > 0 at every quadrature point
+        if (affine) *affine = false;
+        if (qw.empty() && reference_qp_grads(mesh->elem, qw, qg)) return SOPTX_E_UNSUPPORTED_ELEM;
+        for (size_t q = 0; q < qw.size(); q++) {
+            double Jq[9], Gq[9];
+            for (int a = 0; a < dim; a++)
+                for (int m = 0; m < dim; m++) {
+                    double t = 0.0;
+                    for (int k = 0; k < nen; k++) t += X(k, a) * qg[(q * nen + k) * dim + m];
+                    Jq[a * dim + m] = t;
+                }
+            const double dq = inv_small(dim, Jq, Gq);
+            if (!(dq > 0.0) || !std::isfinite(dq)) return SOPTX_E_JACOBIAN;
         }
     }
     return SOPTX_OK;
 }
 
-int build_host_plan(const soptx_mesh *mesh, HostPlan &hp) {
-    int rc = validate_mesh(mesh);
+int build_host_plan(const soptx_mesh *mesh, HostPlan &hp, bool general) {
+    int rc = validate_mesh(mesh, general, &hp.affine);
     if (rc) return rc;
+    hp.general = general;
     const int dim = elem_dim(mesh->elem), nen = elem_nen(mesh->elem);
     const int64_t NN = mesh->n_nodes, NC = mesh->n_cells;
     hp.elem = mesh->elem; hp.dim = dim; hp.nen = nen;
@@ -503,6 +524,36 @@ int build_host_plan(const soptx_mesh *mesh, HostPlan &hp) {
     for (int64_t g = 0; g < hp.n_groups(); g++) hp.ne_max = std::max(hp.ne_max, hp.grp_info[kGrpInfo * g + 3]);
     if (hp.grp_elems.size() >= (size_t)INT32_MAX || hp.grp_n2l.size() >= (size_t)INT32_MAX)
         return SOPTX_E_OVERFLOW;
+
+    // ---- contribution table of the per-quadrature-point assembly: block b of
+    // node n's neighbour q gets (e, i, j) for every element e holding both
+    // nodes, in ascending e (the order of a sequential element loop)
+    if (general) {
+        const int d2 = dim * dim;
+        const int64_t nblk = hp.nnz / d2;
+        if (NC * nen * nen >= INT32_MAX || nblk >= INT32_MAX) return SOPTX_E_OVERFLOW;
+        auto blk = [&](int64_t e, int i, int j) {
+            const int64_t I = cells[e * nen + i];
+            return (int64_t)hp.row_ptr[(size_t)(dim * I)] / d2 + hp.pos[((size_t)e * nen + i) * nen + j];
+        };
+        hp.gptr.assign((size_t)nblk + 1, 0);
+        for (int64_t e = 0; e < NC; e++)
+            for (int i = 0; i < nen; i++)
+                for (int j = 0; j < nen; j++) hp.gptr[(size_t)blk(e, i, j) + 1]++;
+        for (int64_t b = 0; b < nblk; b++) hp.gptr[(size_t)b + 1] += hp.gptr[(size_t)b];
+        hp.gent.assign((size_t)NC * nen * nen, 0);
+        std::vector<int32_t> fill(hp.gptr.begin(), hp.gptr.end() - 1);
+        for (int64_t e = 0; e < NC; e++)
+            for (int i = 0; i < nen; i++)
+                for (int j = 0; j < nen; j++)
+                    hp.gent[(size_t)fill[(size_t)blk(e, i, j)]++] = (int32_t)((e * nen + i) * nen + j);
+        hp.gnode.assign((size_t)nblk, 0);
+        for (int64_t n = 0; n < NN; n++) {
+            const int64_t b0 = hp.row_ptr[(size_t)(dim * n)] / d2;
+            const int64_t deg = (hp.row_ptr[(size_t)(dim * n + 1)] - hp.row_ptr[(size_t)(dim * n)]) / dim;
+            for (int64_t q = 0; q < deg; q++) hp.gnode[(size_t)(b0 + q)] = (int32_t)n;
+        }
+    }
     return SOPTX_OK;
 }
 

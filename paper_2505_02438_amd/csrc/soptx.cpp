@@ -71,6 +71,10 @@ struct soptx_pattern_s {
     double *M = nullptr;
     float *M32 = nullptr, *Mbf = nullptr;
     double *qw = nullptr, *qgrad = nullptr, *cgrad = nullptr, *xref = nullptr;
+    // per-quadrature-point assembly (handles built by soptx_build_pattern_general)
+    bool affine = true, general = false;
+    double *coords = nullptr;
+    int32_t *gptr = nullptr, *gent = nullptr, *gnode = nullptr;
     float *qgrad32 = nullptr;
     soptx_pattern_stats stats{};
     std::vector<void *> allocs;
@@ -152,14 +156,15 @@ int soptx_reference_tensor(int32_t elem, int32_t ref_method, double *M_out) {
     return reference_tensor(elem, ref_method, M_out);
 }
 
-int soptx_build_pattern_ex(const soptx_mesh *mesh, int32_t ref_method, soptx_pattern *out, void *stream) {
+static int build_pattern(const soptx_mesh *mesh, int32_t ref_method, bool general, soptx_pattern *out,
+                         void *stream) {
     if (!out) return SOPTX_E_INVALID_ARG;
     *out = nullptr;
     if (ref_method != SOPTX_REF_SYMBOLIC && ref_method != SOPTX_REF_QUADRATURE) return SOPTX_E_INVALID_ARG;
     HostPlan hp;
     int rc;
     try {
-        rc = build_host_plan(mesh, hp);
+        rc = build_host_plan(mesh, hp, general);
     } catch (const std::bad_alloc &) {
         return SOPTX_E_OOM;
     } catch (...) {
@@ -173,6 +178,7 @@ int soptx_build_pattern_ex(const soptx_mesh *mesh, int32_t ref_method, soptx_pat
         h->elem = hp.elem; h->dim = hp.dim; h->nen = hp.nen; h->ref_method = ref_method;
         h->n_nodes = hp.n_nodes; h->n_cells = hp.n_cells; h->ndof = hp.ndof; h->nnz = hp.nnz;
         h->ngroups = hp.n_groups(); h->nsig = hp.n_sigs(); h->emax = hp.ne_max; h->kmax = hp.kmax; h->stage = hp.stage_max;
+        h->affine = hp.affine; h->general = hp.general;
         if (hipGetDevice(&h->device) != hipSuccess) { free_handle(h); return SOPTX_E_DEVICE; }
         if (hipDeviceGetAttribute(&h->n_cu, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess)
             h->n_cu = 0;
@@ -241,6 +247,14 @@ int soptx_build_pattern_ex(const soptx_mesh *mesh, int32_t ref_method, soptx_pat
             (rc = upload(h, xref, &h->xref, st))) {
             free_handle(h); return rc;
         }
+        if (hp.general) {
+            std::vector<double> xy(mesh->coords, mesh->coords + (size_t)mesh->n_nodes * dim);
+            if ((rc = upload(h, xy, &h->coords, st)) || (rc = upload(h, hp.gptr, &h->gptr, st)) ||
+                (rc = upload(h, hp.gent, &h->gent, st)) || (rc = upload(h, hp.gnode, &h->gnode, st))) {
+                free_handle(h);
+                return rc;
+            }
+        }
         if (hipStreamSynchronize(st) != hipSuccess) { free_handle(h); return SOPTX_E_DEVICE; }
         const int64_t ncontrib = hp.n_cells * (int64_t)nen * nen;
         h->stats.ndof = hp.ndof; h->stats.nnz = hp.nnz; h->stats.n_cells = hp.n_cells; h->stats.n_nodes = hp.n_nodes;
@@ -253,8 +267,46 @@ int soptx_build_pattern_ex(const soptx_mesh *mesh, int32_t ref_method, soptx_pat
     return SOPTX_OK;
 }
 
+int soptx_build_pattern_ex(const soptx_mesh *mesh, int32_t ref_method, soptx_pattern *out, void *stream) {
+    return build_pattern(mesh, ref_method, false, out, stream);
+}
+
 int soptx_build_pattern(const soptx_mesh *mesh, soptx_pattern *out, void *stream) {
     return soptx_build_pattern_ex(mesh, SOPTX_REF_SYMBOLIC, out, stream);
+}
+
+int soptx_build_pattern_general(const soptx_mesh *mesh, soptx_pattern *out, void *stream) {
+    return build_pattern(mesh, SOPTX_REF_SYMBOLIC, true, out, stream);
+}
+
+int soptx_assemble_general(soptx_pattern h, const soptx_material *m, const double *d_rho, const uint8_t *d_dirichlet,
+                           double *d_K_vals, void *stream) {
+    if (!h) return SOPTX_E_INVALID_ARG;
+    if (!h->general) return SOPTX_E_INVALID_ARG;
+    int rc = check_material(m);
+    if (rc) return rc;
+    if ((h->n_cells > 0 && !d_rho) || (h->nnz > 0 && !d_K_vals)) return SOPTX_E_INVALID_ARG;
+    if (h->nnz == 0) return SOPTX_OK;
+    if (h->elem != SOPTX_QUAD4 && h->elem != SOPTX_HEX8) return SOPTX_E_UNSUPPORTED_ELEM;
+    DeviceGuard dg(h->device);
+    if (!dg.ok) return SOPTX_E_DEVICE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int nen = h->nen, dim = h->dim;
+    double *ke = nullptr;
+    rc = get_workspace(h->device, st, (size_t)h->n_cells * nen * nen * dim * dim, &ke, 4);
+    if (rc) return rc;
+    double lam, mu;
+    lame(h, m, &lam, &mu);
+    GenParams G{};
+    G.cells = h->cells; G.coords = h->coords; G.rho = d_rho; G.qw = h->qw; G.qgrad = h->qgrad;
+    G.n_cells = h->n_cells; G.nq = h->nq; G.E0 = m->E0; G.Emin = m->Emin; G.p = m->p; G.ip = int_exponent(m->p);
+    G.lam = lam; G.mu = mu; G.ke = ke;
+    G.gptr = h->gptr; G.gent = h->gent; G.gnode = h->gnode; G.row_ptr = h->row_ptr; G.K = d_K_vals;
+    G.n_blocks = h->nnz / (dim * dim);
+    if (launch_assemble_general(h->elem, G, st) != hipSuccess) return SOPTX_E_DEVICE;
+    if (d_dirichlet && launch_dirichlet(h->dim, h->row_ptr, h->nb_tslot, h->nb_tdeg, d_dirichlet, d_K_vals, h->ndof, st) != hipSuccess)
+        return SOPTX_E_DEVICE;
+    return SOPTX_OK;
 }
 
 int soptx_pattern_info(soptx_pattern h, int64_t *ndof, int64_t *nnz, const int32_t **d_row_ptr,
@@ -288,6 +340,7 @@ int soptx_pattern_stats_get(soptx_pattern h, soptx_pattern_stats *out) {
 int soptx_assemble(soptx_pattern h, const soptx_material *m, const void *d_rho, const uint8_t *d_dirichlet,
                    double *d_K_vals, int32_t prec, void *stream) {
     if (!h || !valid_prec(prec)) return SOPTX_E_INVALID_ARG;
+    if (!h->affine) return SOPTX_E_NONAFFINE;
     int rc = check_material(m);
     if (rc) return rc;
     if ((h->n_cells > 0 && !d_rho) || (h->nnz > 0 && !d_K_vals)) return SOPTX_E_INVALID_ARG;
@@ -410,6 +463,7 @@ int soptx_pcg(soptx_pattern h, const double *d_K_vals, const double *d_f, double
 int soptx_evaluate(soptx_pattern h, const soptx_material *m, const void *d_rho, const double *d_u,
                    const double *d_f, void *d_dc, double *d_c, int32_t prec, void *stream) {
     if (!h || !valid_prec(prec)) return SOPTX_E_INVALID_ARG;
+    if (!h->affine) return SOPTX_E_NONAFFINE;
     int rc = check_material(m);
     if (rc) return rc;
     if (h->n_cells > 0 && (!d_rho || !d_u)) return SOPTX_E_INVALID_ARG;
@@ -441,6 +495,7 @@ int soptx_evaluate(soptx_pattern h, const soptx_material *m, const void *d_rho, 
 int soptx_sensitivity(soptx_pattern h, const soptx_material *m, const void *d_rho, const double *d_u,
                       void *d_dc, int32_t prec, void *stream) {
     if (h && h->n_cells > 0 && !d_dc) return SOPTX_E_INVALID_ARG;
+    if (h && !h->affine) return SOPTX_E_NONAFFINE;
     if (h && h->n_cells == 0) return (h && valid_prec(prec) && check_material(m) == 0) ? SOPTX_OK : SOPTX_E_INVALID_ARG;
     return soptx_evaluate(h, m, d_rho, d_u, nullptr, d_dc, nullptr, prec, stream);
 }
@@ -455,6 +510,7 @@ int soptx_assemble_backward(soptx_pattern h, const soptx_material *m, const void
                             const uint8_t *d_dirichlet, const double *d_Kbar, void *d_drho, int32_t prec,
                             void *stream) {
     if (!h || !valid_prec(prec)) return SOPTX_E_INVALID_ARG;
+    if (!h->affine) return SOPTX_E_NONAFFINE;
     int rc = check_material(m);
     if (rc) return rc;
     if (h->n_cells > 0 && (!d_rho || !d_Kbar || !d_drho)) return SOPTX_E_INVALID_ARG;
@@ -479,13 +535,17 @@ void soptx_destroy_pattern(soptx_pattern h) {
 // ----------------------------------------------------------- host-only debug
 
 int soptx_debug_host_plan(const soptx_mesh *mesh, soptx_host_plan *out) {
+    return soptx_debug_host_plan_ex(mesh, 0, out);
+}
+
+int soptx_debug_host_plan_ex(const soptx_mesh *mesh, int32_t general, soptx_host_plan *out) {
     if (!out) return SOPTX_E_INVALID_ARG;
     *out = nullptr;
     soptx_host_plan_s *p = new (std::nothrow) soptx_host_plan_s();
     if (!p) return SOPTX_E_OOM;
     int rc;
     try {
-        rc = build_host_plan(mesh, p->hp);
+        rc = build_host_plan(mesh, p->hp, general != 0);
     } catch (...) {
         rc = SOPTX_E_OOM;
     }
@@ -508,6 +568,7 @@ int soptx_debug_host_plan_array(soptx_host_plan p, const char *name, const void 
     SOPTX_ARR(row_ptr) SOPTX_ARR(col_idx) SOPTX_ARR(geo) SOPTX_ARR(sig_info) SOPTX_ARR(sig_pos_ptr)
     SOPTX_ARR(sig_contrib) SOPTX_ARR(sig_pairs) SOPTX_ARR(sig_witems) SOPTX_ARR(sig_witem_ptr) SOPTX_ARR(grp_info) SOPTX_ARR(grp_nodes) SOPTX_ARR(grp_elems)
     SOPTX_ARR(grp_n2l) SOPTX_ARR(grp_rows) SOPTX_ARR(pos) SOPTX_ARR(nb_tslot) SOPTX_ARR(nb_tdeg)
+    SOPTX_ARR(gptr) SOPTX_ARR(gent) SOPTX_ARR(gnode)
 #undef SOPTX_ARR
     return SOPTX_E_INVALID_ARG;
 }

@@ -126,6 +126,20 @@ def tri_grid(nx: int, ny: int, h: float = 1.0, jitter: float = 0.0,
     return Mesh(TRI3, coords, cells.astype(np.int32))
 
 
+def jitter_interior(mesh: Mesh, amount: float, rng: np.random.Generator) -> Mesh:
+    """The same mesh with every node off the bounding box moved by
+    U(-amount, amount) per coordinate (unit grids: Q1 cells become general,
+    non-affine quadrilaterals or hexahedra; boundary nodes, hence supports and
+    loads, stay put)."""
+    x = mesh.coords
+    lo, hi = x.min(axis=0), x.max(axis=0)
+    inner = np.all((x > lo + 1e-9) & (x < hi - 1e-9), axis=1)
+    c = x.copy()
+    d = rng.uniform(-amount, amount, size=c.shape)
+    c[inner] += d[inner]
+    return Mesh(mesh.elem, c, mesh.cells)
+
+
 # Kuhn split: one tetrahedron per permutation of the axes, walking from (0,0,0)
 # to (1,1,1) one unit step at a time.
 _PERMS = [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]

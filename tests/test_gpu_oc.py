@@ -125,3 +125,44 @@ def test_optimisation_iterations_match_oracle():
         assert float(np.max(np.abs(host(rho_g) - rho_o))) <= 1e-8
     # the constraint holds and the design moved
     assert abs(float(host(rho_g).sum()) - target) <= 2e-3 * target
+
+
+def test_density_filter_iterations_match_oracle():
+    """Five iterations with the density filter (Sec. 2.4) instead: the
+    physical density rho~ = F(rho) is assembled and evaluated, and the
+    objective and volume sensitivities are taken back through the filter's
+    chain rule (dv = F^T v, so the constraint is the filtered volume)."""
+    pr = I.mbb_q1()
+    m = pr.mesh
+    n = m.n_cells
+    target = 0.5 * n
+    rp, ci = O.pattern(m.elem, m.n_nodes, m.cells)
+    H = OF.filter_matrix(OF.centroids(m.elem, m.coords, m.cells), 2.5)
+    v = np.ones(n)                                      # unit squares
+    dv_o = OF.density_filter_backward(H, v, v)
+    pat = api.Pattern.from_mesh(m)
+    flt = api.Filter.from_mesh(m, 2.5)
+    mat = api.Material(E0=pr.E0, Emin=pr.Emin, nu=pr.nu, p=pr.p)
+    mask, f = dev(pr.mask), dev(pr.f)
+    dv_g = flt.density_backward(dev(v))
+    assert np.array_equal(host(dv_g), dv_o)
+    rho_g, rho_o = dev(np.full(n, 0.5)), np.full(n, 0.5)
+    for it in range(5):
+        rt_g = flt.density(rho_g)
+        K = pat.assemble(mat, rt_g, mask)
+        u, iters, rel = pat.pcg(K, f, rtol=1e-12, max_iter=20000)
+        dc, c = pat.evaluate(mat, rt_g, u, f=f)
+        rho_g, info = api.oc_update(rho_g, flt.density_backward(dc), dv_g, target, move=0.2, eta=0.5)
+        rt_o = OF.density_filter(H, v, rho_o)
+        Ko = O.assemble(m.elem, m.coords, m.cells, rt_o, rp, ci, pr.E0, pr.Emin, pr.p, pr.nu, pr.plane_strain, pr.mask)
+        uo = O.solve(rp, ci, Ko, pr.f)
+        co = O.compliance(m.elem, m.coords, m.cells, rt_o, uo, pr.f, pr.E0, pr.Emin, pr.p, pr.nu, pr.plane_strain)[1]
+        dco = O.sensitivity(m.elem, m.coords, m.cells, rt_o, uo, pr.E0, pr.Emin, pr.p, pr.nu, pr.plane_strain)
+        rho_o, lam_o, *_ = OC.oc_update(rho_o, OF.density_filter_backward(H, v, dco), dv_o, target, move=0.2, eta=0.5)
+        c_g = float(host(c)[1])
+        print(f"density filter, iteration {it}: c {c_g:.10f} / {co:.10f}, lambda {info['lambda']:.6e} / {lam_o:.6e}")
+        assert abs(c_g - co) <= 1e-9 * co
+        assert abs(info["lambda"] - lam_o) <= 1e-9 * lam_o
+        assert float(np.max(np.abs(host(rho_g) - rho_o))) <= 1e-8
+    # the filtered volume meets the constraint
+    assert abs(float(host(flt.density(rho_g)).sum()) - target) <= 2e-3 * target

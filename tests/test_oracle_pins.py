@@ -15,6 +15,7 @@ import pytest
 
 import exact_fe
 from oracle import oracle as O
+from paper_2505_02438_amd import api
 from paper_2505_02438_amd import inputs as I
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -506,3 +507,47 @@ def test_paper_cantilever_initial_compliance():
     assert abs(cs[0.4] - ref) <= 0.05 * ref
     E04 = 1e-9 + 0.4 ** 3 * (1 - 1e-9)
     assert abs(cs[0.4] / cs[1.0] - 1.0 / E04) <= 1e-8 / E04
+
+
+@pytest.mark.parametrize("elem", [I.QUAD4, I.HEX8])
+def test_nonaffine_q1_oracle(elem):
+    """General (non-affine) Q1 elements, where K_e^0 is integrated with J at
+    every Gauss point: symmetric, rigid modes in the null space, and the
+    linear patch test: u_e^T K_e^0 u_e = |e| eps^T D eps for a linear field
+    (quads: |e| by the shoelace formula; hexahedra: the energies add up to
+    the box volume, the cells tiling it), and K u = 0 at interior dofs."""
+    rng = np.random.default_rng(31)
+    m0 = I.quad_grid(5, 4) if elem == I.QUAD4 else I.hex_grid(4, 3, 3)
+    m = I.jitter_interior(m0, 0.3, rng)
+    assert api.validate_mesh(m.elem, m.coords, m.cells) == -5          # not affine
+    Gu = rng.standard_normal((m.dim, m.dim))
+    u = (m.coords @ Gu.T).ravel()
+    eps = 0.5 * (Gu + Gu.T)
+    ev = _voigt(eps, m.dim)
+    e_dens = ev @ O.D_matrix(m.dim, 1.0, 0.3) @ ev
+    s = []
+    for e in range(m.n_cells):
+        Ke = O.element_ke0(elem, m.coords[m.cells[e]])
+        assert np.abs(Ke - Ke.T).max() <= 1e-14 * np.abs(Ke).max()
+        ue = u.reshape(-1, m.dim)[m.cells[e]].ravel()
+        s.append(ue @ Ke @ ue)
+    s = np.array(s)
+    if elem == I.QUAD4:
+        X = m.coords[m.cells]
+        area = 0.5 * np.abs(sum(X[:, k, 0] * X[:, (k + 1) % 4, 1] - X[:, (k + 1) % 4, 0] * X[:, k, 1]
+                                for k in range(4)))
+        np.testing.assert_allclose(s, area * e_dens, rtol=1e-12)
+    else:
+        assert abs(s.sum() - 4 * 3 * 3 * e_dens) <= 1e-12 * abs(s.sum())
+    rho1 = np.full(m.n_cells, 0.7)
+    rp, ci = O.pattern(elem, m.n_nodes, m.cells)
+    K = O.assemble(elem, m.coords, m.cells, rho1, rp, ci)
+    Ku = O.spmv(rp, ci, K, u)
+    x = m.coords
+    lo, hi = x.min(axis=0), x.max(axis=0)
+    interior = np.all((x > lo + 1e-9) & (x < hi - 1e-9), axis=1)
+    idx = (m.dim * np.nonzero(interior)[0][:, None] + np.arange(m.dim)).ravel()
+    assert idx.size > 0
+    assert np.abs(Ku[idx]).max() <= 1e-12 * np.abs(K).max() * np.abs(u).max()
+    for r in _rigid_modes(m.coords, m.dim):
+        assert np.abs(O.spmv(rp, ci, K, r)).max() <= 1e-13 * np.abs(K).max() * np.abs(r).max()
