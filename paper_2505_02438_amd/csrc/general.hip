@@ -5,10 +5,11 @@
 // k_ke_general: the blocks of every element's matrix,
 //     Ke[i][j] = E(rho_e) sum_q w_q |det J_q| L(g_i g_j^T),  g_k = J_q^-T grad phi_k(xi_q),
 //     L(A) = lambda A + mu A^T + mu tr(A) I,
-// with one thread per node pair (i, j) of an element (NEN^2 threads per
-// element: a wave per hexahedron, 16 lanes per quadrilateral).  The first NQ
-// threads of an element form J_q^-1 and w_q |det J_q| E at the quadrature
-// points in LDS; every thread then accumulates its DIM x DIM block.
+// with one thread per node pair of an element (NEN^2 threads per element: a
+// wave per hexahedron, 16 lanes per quadrilateral).  The first NQ threads of an element
+// form J_q^-1 and w_q |det J_q| E at the quadrature points in LDS; every
+// thread accumulates its DIM x DIM block, and the block's elements are
+// written out as one contiguous range.
 // k_gather_general: one thread per DIM x DIM block of K adds its element
 // contributions in ascending element order (the order of a sequential loop
 // over elements) and writes the block once.
@@ -39,13 +40,17 @@ __device__ __forceinline__ double simp_modulus(double r, const GenParams &G) {
 
 template <int DIM, int NEN, int NQ>
 __global__ __launch_bounds__(256) void k_ke_general(GenParams G) {
-    constexpr int NP = NEN * NEN;  // threads per element
-    constexpr int EPB = 256 / NP;  // elements per block
+    constexpr int NP = NEN * NEN;            // threads per element
+    constexpr int EPB = 256 / NP;            // elements per block
     constexpr int D2 = DIM * DIM;
     __shared__ double sg[EPB][NQ][D2 + 1];  // J_q^-1 (row m: d xi_m / d x), then w_q |det J_q| E
+    __shared__ double sq[NQ * NEN * DIM];   // reference gradients at the quadrature points
+    __shared__ double so[EPB * NP * D2];    // the block's element matrices, written out contiguously
+    for (int x = threadIdx.x; x < NQ * NEN * DIM; x += 256) sq[x] = G.qgrad[x];
     const int le = threadIdx.x / NP, pr = threadIdx.x % NP;
     const int64_t e = (int64_t)blockIdx.x * EPB + le;
     const bool live = le < EPB && e < G.n_cells;
+    __syncthreads();
     if (live && pr < NQ) {
         const int q = pr;
         double J[DIM][DIM];
@@ -59,16 +64,17 @@ __global__ __launch_bounds__(256) void k_ke_general(GenParams G) {
             for (int a = 0; a < DIM; a++) {
                 const double x = G.coords[nd * DIM + a];
 #pragma unroll
-                for (int m = 0; m < DIM; m++) J[a][m] += x * G.qgrad[(q * NEN + k) * DIM + m];
+                for (int m = 0; m < DIM; m++) J[a][m] += x * sq[(q * NEN + k) * DIM + m];
             }
         }
         double inv[DIM][DIM], det;
         if (DIM == 2) {
             det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
-            inv[0][0] = J[1][1] / det;
-            inv[0][1] = -J[0][1] / det;
-            inv[1][0] = -J[1][0] / det;
-            inv[1][1] = J[0][0] / det;
+            const double id = 1.0 / det;
+            inv[0][0] = J[1][1] * id;
+            inv[0][1] = -J[0][1] * id;
+            inv[1][0] = -J[1][0] * id;
+            inv[1][1] = J[0][0] * id;
         } else {
             const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
             const double c01 = J[0][2] * J[2][1] - J[0][1] * J[2][2];
@@ -80,9 +86,10 @@ __global__ __launch_bounds__(256) void k_ke_general(GenParams G) {
             const double c21 = J[0][1] * J[2][0] - J[0][0] * J[2][1];
             const double c22 = J[0][0] * J[1][1] - J[0][1] * J[1][0];
             det = J[0][0] * c00 + J[0][1] * c10 + J[0][2] * c20;
-            inv[0][0] = c00 / det; inv[0][1] = c01 / det; inv[0][2] = c02 / det;
-            inv[1][0] = c10 / det; inv[1][1] = c11 / det; inv[1][2] = c12 / det;
-            inv[2][0] = c20 / det; inv[2][1] = c21 / det; inv[2][2] = c22 / det;
+            const double id = 1.0 / det;
+            inv[0][0] = c00 * id; inv[0][1] = c01 * id; inv[0][2] = c02 * id;
+            inv[1][0] = c10 * id; inv[1][1] = c11 * id; inv[1][2] = c12 * id;
+            inv[2][0] = c20 * id; inv[2][1] = c21 * id; inv[2][2] = c22 * id;
         }
 #pragma unroll
         for (int m = 0; m < DIM; m++)
@@ -91,13 +98,13 @@ __global__ __launch_bounds__(256) void k_ke_general(GenParams G) {
         sg[le][q][D2] = G.qw[q] * fabs(det) * simp_modulus(G.rho[e], G);
     }
     __syncthreads();
-    if (!live) return;
     const int i = pr / NEN, j = pr % NEN;
     double blk[DIM][DIM];
 #pragma unroll
     for (int a = 0; a < DIM; a++)
 #pragma unroll
         for (int c = 0; c < DIM; c++) blk[a][c] = 0.0;
+#pragma unroll
     for (int q = 0; q < NQ; q++) {
         double gi[DIM], gj[DIM];
 #pragma unroll
@@ -106,8 +113,8 @@ __global__ __launch_bounds__(256) void k_ke_general(GenParams G) {
 #pragma unroll
             for (int m = 0; m < DIM; m++) {
                 const double gm = sg[le][q][m * DIM + a];
-                si += G.qgrad[(q * NEN + i) * DIM + m] * gm;
-                sj += G.qgrad[(q * NEN + j) * DIM + m] * gm;
+                si += sq[(q * NEN + i) * DIM + m] * gm;
+                sj += sq[(q * NEN + j) * DIM + m] * gm;
             }
             gi[a] = si;
             gj[a] = sj;
@@ -122,11 +129,17 @@ __global__ __launch_bounds__(256) void k_ke_general(GenParams G) {
             for (int c = 0; c < DIM; c++)
                 blk[a][c] += cq * (G.lam * gi[a] * gj[c] + G.mu * gi[c] * gj[a] + (a == c ? G.mu * tr : 0.0));
     }
-    double *o = G.ke + ((e * NEN + i) * NEN + j) * D2;
+    double *o = so + (le * NP + pr) * D2;
 #pragma unroll
     for (int a = 0; a < DIM; a++)
 #pragma unroll
         for (int c = 0; c < DIM; c++) o[a * DIM + c] = blk[a][c];
+    __syncthreads();
+    // the block's elements are consecutive: one contiguous range of ke
+    const int64_t e0 = (int64_t)blockIdx.x * EPB;
+    const int64_t ne = G.n_cells - e0 < EPB ? G.n_cells - e0 : EPB;
+    double *dst = G.ke + e0 * NP * D2;
+    for (int64_t x = threadIdx.x; x < ne * NP * D2; x += 256) __builtin_nontemporal_store(so[x], dst + x);
 }
 
 template <int DIM>
