@@ -131,15 +131,7 @@ void search_rows(int dim, const std::vector<double> &c, double rmin, const doubl
 
 template <class T>
 int upload(soptx_filter_s *h, const std::vector<T> &v, T **dst, hipStream_t st) {
-    *dst = nullptr;
-    if (v.empty()) return SOPTX_OK;
-    void *p = nullptr;
-    if (hipMalloc(&p, v.size() * sizeof(T)) != hipSuccess) return SOPTX_E_OOM;
-    h->allocs.push_back(p);
-    if (hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st) != hipSuccess)
-        return SOPTX_E_DEVICE;
-    *dst = static_cast<T *>(p);
-    return SOPTX_OK;
+    return upload_vector(h->allocs, v, dst, st);
 }
 
 void free_filter(soptx_filter_s *h) {

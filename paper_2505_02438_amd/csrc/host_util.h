@@ -3,6 +3,10 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "../../include/soptx.h"
 
 namespace soptx {
 
@@ -12,6 +16,24 @@ namespace soptx {
 // one buffer per (device, stream, use) is race-free.  Held until the process
 // ends; grown (after a synchronisation of the stream) when a call needs more.
 int get_workspace(int device, hipStream_t st, size_t n, double **out, int use);
+
+// Copy a host vector into a new device allocation recorded in `allocs` (freed
+// with its handle); *dst = nullptr for an empty vector.  *bytes, if given,
+// grows by the allocation's size.
+template <class T>
+int upload_vector(std::vector<void *> &allocs, const std::vector<T> &v, T **dst, hipStream_t st,
+                  int64_t *bytes = nullptr) {
+    *dst = nullptr;
+    if (v.empty()) return SOPTX_OK;
+    void *p = nullptr;
+    if (hipMalloc(&p, v.size() * sizeof(T)) != hipSuccess) return SOPTX_E_OOM;
+    allocs.push_back(p);
+    if (hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st) != hipSuccess)
+        return SOPTX_E_DEVICE;
+    *dst = static_cast<T *>(p);
+    if (bytes) *bytes += (int64_t)(v.size() * sizeof(T));
+    return SOPTX_OK;
+}
 
 // Makes `dev` current for the lifetime of the guard and restores the
 // previous device afterwards.

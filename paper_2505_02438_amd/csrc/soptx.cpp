@@ -88,16 +88,7 @@ namespace {
 
 template <class T>
 int upload(soptx_pattern_s *h, const std::vector<T> &v, T **dst, hipStream_t st) {
-    *dst = nullptr;
-    if (v.empty()) return SOPTX_OK;
-    void *p = nullptr;
-    if (hipMalloc(&p, v.size() * sizeof(T)) != hipSuccess) return SOPTX_E_OOM;
-    h->allocs.push_back(p);
-    if (hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st) != hipSuccess)
-        return SOPTX_E_DEVICE;
-    *dst = static_cast<T *>(p);
-    h->stats.device_bytes += (int64_t)(v.size() * sizeof(T));
-    return SOPTX_OK;
+    return upload_vector(h->allocs, v, dst, st, &h->stats.device_bytes);
 }
 
 void free_handle(soptx_pattern_s *h) {

@@ -379,3 +379,16 @@ def test_dirichlet_slot_walk_matches_oracle(elem):
                 Kw[i_row] = v
                 Kw[i_col] = v
     assert np.array_equal(Kw, ref)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU's share: --gpus above 1 exits with a message
+    before touching a device."""
+    import json
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in msg["error"] and msg["n_gpus"] == 2
