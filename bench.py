@@ -450,6 +450,29 @@ def main():
                 torch.mul(x, 2.0, out=y)
         torch.cuda.synchronize()
 
+    # the box's own streaming rates, for the roofline: a 1 GiB fill (writes)
+    # and a 1 GiB copy (reads + writes), HIP events on the bench stream, median
+    # of 10 after 2 warm-ups
+    def stream_rate(fn, nbytes):
+        t = []
+        for r in range(12):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            with torch.cuda.stream(stream):
+                fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            if r >= 2:
+                t.append(a.elapsed_time(b) / 1e3)
+        return nbytes / statistics.median(t) / 1e9
+    with torch.cuda.stream(stream):
+        sx = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+        sy = torch.empty_like(sx)
+    torch.cuda.synchronize()
+    fill_gbs = stream_rate(lambda: sx.fill_(1.0), 1 << 30)
+    copy_gbs = stream_rate(lambda: sy.copy_(sx), 2 << 30)
+    del sx, sy
+
     n = pat.n_cells
     asm_bytes, ev_bytes = algorithmic_bytes(m.n_nodes, n, pat.nnz, m.dim, m.nen, m.ndof)
     asm_avg_s = statistics.mean(asm_ms) / 1e3
@@ -489,6 +512,9 @@ def main():
             "traffic": traffic,
             "algorithmic_bytes_per_launch": asm_bytes,
             "avg_launch_ms": asm_avg_s * 1e3,
+            "measured_fill_GBs": fill_gbs,
+            "measured_copy_GBs": copy_gbs,
+            "frac_of_measured_fill": achieved / fill_gbs,
         },
         "stage_ms": {"assemble": statistics.mean(asm_ms), "dirichlet": statistics.mean(bc_ms),
                      "evaluate": statistics.mean(ev_ms)},
