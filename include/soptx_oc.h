@@ -47,8 +47,9 @@ typedef struct {
     int32_t steps; /* bisection steps taken */
 } soptx_oc_result;
 
-/* One OC update of n design variables (device arrays of n doubles; d_rho_new
- * must not overlap the inputs).  Runs on `stream` (NULL = default) and blocks
+/* One OC update of n design variables (device arrays of n doubles on the
+ * current device; d_rho_new must not overlap the inputs).  Runs on `stream`
+ * (NULL = default) and blocks
  * until the result is on the host (*out).  n = 0: nothing runs, *out is zero.
  * Uses a per-(device, stream) scratch, allocated on first use.
  * SOPTX_E_INVALID_ARG for a null pointer, n < 0, vol_target not finite or a

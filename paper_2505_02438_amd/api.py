@@ -358,6 +358,12 @@ class Filter:
               "soptx_filter_copy")
         return rp, col[: self.nnz], w[: self.nnz], v[: self.n]
 
+    def volumes(self):
+        """The element measures v (float64, host)."""
+        v = np.zeros(max(self.n, 1))
+        check(lib().soptx_filter_copy(self._h, None, None, None, v.ctypes.data), "soptx_filter_copy")
+        return v[: self.n]
+
     def sensitivity(self, rho, dc, out=None, stream=None):
         """dc~_i = sum_j H_ij rho_j dc_j / (max(1e-3, rho_i) sum_j H_ij)."""
         import torch

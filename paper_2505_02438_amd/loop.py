@@ -39,7 +39,7 @@ def run(mesh, mask, f, volfrac: float, rmin: float, filt: str = "sensitivity", r
     flt = api.Filter.from_mesh(mesh, rmin)
     mat = material or api.Material(E0=1.0, Emin=1e-9, nu=0.3, p=3.0)
     n = mesh.n_cells
-    _, _, _, vol = flt.matrix()                    # element measures (built on the host with H)
+    vol = flt.volumes()                            # element measures (built on the host with H)
     v = torch.from_numpy(vol).to(d)
     total = float(vol.sum())
     mask_d = torch.from_numpy(np.asarray(mask, np.uint8)).to(d)
