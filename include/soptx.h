@@ -224,10 +224,11 @@ int soptx_assemble_general(soptx_pattern h, const soptx_material *m, const doubl
  * symmetric positive definite: assembled with a Dirichlet mask, f zero on
  * the fixed dofs.  d_u ([ndof] double) is the initial guess on entry and
  * the solution on return; d_f: [ndof] double.  Stops when
- * ||r_k|| <= rtol ||r_0|| (the recurrence residual, read back every 8
- * iterations) or after max_iter iterations; *h_iters and *h_relres (host)
- * give the count and ||r_k|| / ||r_0|| (NaN after a breakdown, i.e. K not
- * SPD).  Synchronizes stream at those read-backs and at the start.  The
+ * ||r_k|| <= rtol ||f|| (||r_0|| if f = 0; from u = 0 the two are the same)
+ * for the recurrence residual, checked at the start and every 8 iterations,
+ * or after max_iter iterations; *h_iters and *h_relres (host) give the count
+ * and ||r_k|| / ||f|| (NaN after a breakdown, i.e. K not SPD).  A start
+ * already within the tolerance returns after 0 iterations.  Synchronizes stream at those read-backs and at the start.  The
  * vectors live in a per-stream workspace of the library. */
 int soptx_pcg(soptx_pattern h, const double *d_K_vals, const double *d_f, double *d_u, double rtol,
               int32_t max_iter, int32_t *h_iters, double *h_relres, void *stream);

@@ -255,9 +255,10 @@ class Pattern:
         return out
 
     def pcg(self, K, f, u=None, rtol: float = 1e-10, max_iter: int = 10000, stream=None):
-        """Solve K u = f by Jacobi-preconditioned CG (K SPD: assembled with a
-        Dirichlet mask).  u: initial guess, overwritten (zeros if None).
-        Returns (u, iterations, ||r_k|| / ||r_0||)."""
+        """Solve K u = f by CG preconditioned with the nodes' diagonal blocks (K
+        SPD: assembled with a Dirichlet mask).  u: initial guess, overwritten
+        (zeros if None).  Stops at ||r_k|| <= rtol ||f||.
+        Returns (u, iterations, ||r_k|| / ||f||)."""
         import torch
         if u is None:
             u = torch.zeros(self.ndof, dtype=torch.float64, device=f.device)

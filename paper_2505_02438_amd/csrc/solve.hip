@@ -168,7 +168,8 @@ __device__ __forceinline__ void cg_node(int mode, double al, int64_t I, const do
 // Scalars sc: [0] r.z, [1] alpha, [2] beta, [3] r.r, [4] r0.r0, [5] p.q.
 // mode 0 (start, q = K u): r = f - q, z = B^-1 r, p = z.
 // mode 1 (iteration, q = K p): u += alpha p, r -= alpha q, z = B^-1 r.
-// Both leave block partials of r.z (part[b]) and r.r (part[nb + b]).
+// Both leave block partials of r.z (part[b]) and r.r (part[nb + b]); mode 0
+// also of f.f (part[2 nb + b]).
 template <int DIM>
 __global__ __launch_bounds__(256) void k_cg_vec(int mode, const double *__restrict__ f, double *__restrict__ u,
                                                 double *__restrict__ r, double *__restrict__ z,
@@ -177,13 +178,20 @@ __global__ __launch_bounds__(256) void k_cg_vec(int mode, const double *__restri
                                                 double *__restrict__ part, int64_t n_nodes) {
     __shared__ double red[256];
     const int64_t I = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    double rz = 0.0, rr = 0.0;
-    if (I < n_nodes) cg_node<DIM>(mode, mode == 0 ? 0.0 : sc[1], I, f, u, r, z, p, q, binv, rz, rr);
+    double rz = 0.0, rr = 0.0, ff = 0.0;
+    if (I < n_nodes) {
+        cg_node<DIM>(mode, mode == 0 ? 0.0 : sc[1], I, f, u, r, z, p, q, binv, rz, rr);
+        if (mode == 0)
+#pragma unroll
+            for (int a = 0; a < DIM; a++) ff += f[DIM * I + a] * f[DIM * I + a];
+    }
     const double brz = block_sum_256(rz, red);
     const double brr = block_sum_256(rr, red);
+    const double bff = mode == 0 ? block_sum_256(ff, red) : 0.0;
     if (threadIdx.x == 0) {
         part[blockIdx.x] = brz;
         part[gridDim.x + blockIdx.x] = brr;
+        if (mode == 0) part[2 * gridDim.x + blockIdx.x] = bff;
     }
 }
 
@@ -259,6 +267,7 @@ __global__ __launch_bounds__(256) void k_cg_p_fused(double *__restrict__ p, cons
 // One block of kScalThreads: sums of n block partials, thread t taking
 // k = t, t + kScalThreads, ... in order, then a fixed tree.
 // what 0 (start):     r.z and r.r from part -> sc[0], sc[3], sc[4] = sc[3]
+// what 3 (start):     f.f from part -> sc[6]
 // what 1 (alpha):     p.q from part -> sc[5], sc[1] = sc[0] / p.q
 // what 2 (beta):      r.z, r.r from part -> sc[2] = new r.z / sc[0], sc[0], sc[3]
 constexpr int kScalThreads = 1024;
@@ -268,7 +277,7 @@ __global__ __launch_bounds__(kScalThreads) void k_cg_scalars(int what, const dou
     double t0 = 0.0, t1 = 0.0;
     for (int k = threadIdx.x; k < n; k += kScalThreads) {
         t0 += part[k];
-        if (what != 1) t1 += part[n + k];
+        if (what != 1 && what != 3) t1 += part[n + k];
     }
     red[0][threadIdx.x] = t0;
     red[1][threadIdx.x] = t1;
@@ -283,7 +292,9 @@ __global__ __launch_bounds__(kScalThreads) void k_cg_scalars(int what, const dou
     t0 = red[0][0];
     t1 = red[1][0];
     if (threadIdx.x != 0) return;
-    if (what == 0) {
+    if (what == 3) {
+        sc[6] = t0;
+    } else if (what == 0) {
         sc[0] = t0;
         sc[3] = t1;
         sc[4] = t1;

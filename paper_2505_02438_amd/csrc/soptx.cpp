@@ -390,7 +390,7 @@ int soptx_pcg(soptx_pattern h, const double *d_K_vals, const double *d_f, double
     const int64_t n = h->ndof;
     const int64_t nbv = cg_vec_blocks(h->dim, n);            // blocks of the vector kernels
     const int64_t nbs = spmv_blocks(h->dim, h->n_nodes);      // blocks of the SpMV
-    const int64_t npart = std::max<int64_t>(2 * nbv, nbs);
+    const int64_t npart = std::max<int64_t>(3 * nbv, nbs);
     // Small systems fuse the scalar steps into the vector kernels: each of
     // their blocks re-reads the SpMV's partials, which pays while that is a few
     // MB (nbs * nbv doubles); the fused and separate steps give the same bits.
@@ -413,11 +413,19 @@ int soptx_pcg(soptx_pattern h, const double *d_K_vals, const double *d_f, double
     if (launch_block_inv(h->dim, h->row_ptr, h->nb, d_K_vals, binv, h->n_nodes, st) != hipSuccess ||
         launch_spmv(h->dim, h->row_ptr, h->nb, d_K_vals, d_u, q, nullptr, h->n_nodes, st) != hipSuccess ||
         launch_cg_vec(h->dim, 0, d_f, d_u, r, z, p, q, binv, sc, part, n, st) != hipSuccess ||
-        launch_cg_scalars(0, part, (int)nbv, sc, st) != hipSuccess || !scalars())
+        launch_cg_scalars(0, part, (int)nbv, sc, st) != hipSuccess ||
+        launch_cg_scalars(3, part + 2 * nbv, (int)nbv, sc, st) != hipSuccess || !scalars())
         return SOPTX_E_DEVICE;
     const double rr0 = hs[4];
     if (!(rr0 > 0.0)) {  // u already solves the system (or the data hold a NaN)
         *h_relres = rr0 == 0.0 ? 0.0 : NAN;
+        return SOPTX_OK;
+    }
+    // the residual is measured against ||f|| (against ||r_0|| when f = 0): from
+    // u = 0 the two agree, and a start near the solution then needs fewer steps
+    const double ref = hs[6] > 0.0 ? hs[6] : rr0;
+    if (!(std::sqrt(rr0 / ref) > rtol)) {
+        *h_relres = std::sqrt(rr0 / ref);
         return SOPTX_OK;
     }
     // the residual is read back every kCheck iterations
@@ -442,7 +450,7 @@ int soptx_pcg(soptx_pattern h, const double *d_K_vals, const double *d_f, double
         it++;
         if (it % kCheck == 0 || it == max_iter) {
             if (!scalars()) return SOPTX_E_DEVICE;
-            rel = std::sqrt(hs[3] / rr0);
+            rel = std::sqrt(hs[3] / ref);
             if (!(rel > rtol)) break;  // converged, or broke down (NaN)
         }
     }

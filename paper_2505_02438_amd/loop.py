@@ -8,6 +8,8 @@ density rho~ = F(rho) and takes dc and the volume sensitivity back through the
 chain rule (so the constraint is the filtered volume, exactly, since F is
 linear).  The loop stops when the largest density change of an update is at
 most `tol` or after `max_iter` updates (the paper's runs use 0.01 and 200).
+Each CG solve starts from the previous iteration's displacement
+(warm_start), stopping at ||r|| <= cg_rtol ||f||.
 """
 from __future__ import annotations
 
@@ -30,7 +32,7 @@ class LoopResult:
 
 def run(mesh, mask, f, volfrac: float, rmin: float, filt: str = "sensitivity", rho0: Optional[float] = None,
         max_iter: int = 200, tol: float = 0.01, move: float = 0.2, eta: float = 0.5, cg_rtol: float = 1e-8,
-        material: Optional[api.Material] = None, stream=None) -> LoopResult:
+        warm_start: bool = True, material: Optional[api.Material] = None, stream=None) -> LoopResult:
     import torch
     if filt not in ("sensitivity", "density"):
         raise ValueError("filt is 'sensitivity' or 'density'")
@@ -47,12 +49,16 @@ def run(mesh, mask, f, volfrac: float, rmin: float, filt: str = "sensitivity", r
     rho = torch.full((n,), volfrac if rho0 is None else rho0, dtype=torch.float64, device=d)
     dv = flt.density_backward(v, stream=stream) if filt == "density" else v
     K = torch.empty(pat.nnz, dtype=torch.float64, device=d)
+    u = torch.zeros(pat.ndof, dtype=torch.float64, device=d)
     res = LoopResult([], [], [], [], None)
     vf = volfrac if rho0 is None else rho0      # a uniform design: the filter keeps it
     for _ in range(max_iter):
         phys = flt.density(rho, stream=stream) if filt == "density" else rho
         pat.assemble(mat, phys, mask_d, out=K, stream=stream)
-        u, cg_it, _ = pat.pcg(K, f_d, rtol=cg_rtol, max_iter=50000, stream=stream)
+        if not warm_start:
+            u.zero_()
+        # the previous displacement starts the solve (the criterion is relative to ||f||)
+        u, cg_it, _ = pat.pcg(K, f_d, u=u, rtol=cg_rtol, max_iter=50000, stream=stream)
         dc, c = pat.evaluate(mat, phys, u, f=f_d, stream=stream)
         if filt == "density":
             dcd = flt.density_backward(dc, stream=stream)
