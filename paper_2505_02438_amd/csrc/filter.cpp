@@ -291,10 +291,11 @@ int build_filter_host(const soptx_mesh *mesh, double rmin, HostFilter &F) {
             }
         double h = rmin;
         int64_t nc[3] = {1, 1, 1};
-        for (;;) {
+        for (int doubling = 0;; doubling++) {
             double cells = 1.0;
             for (int a = 0; a < dim; a++) cells *= std::floor((hi[a] - lo[a]) / h) + 1.0;
             if (cells <= 2.0 * (double)std::max<int64_t>(n, 1) + 64.0) break;
+            if (doubling >= 2100 || !std::isfinite(h)) return SOPTX_E_INVALID_ARG;  // not a finite box
             h *= 2.0;
         }
         for (int a = 0; a < dim; a++) nc[a] = (int64_t)std::floor((hi[a] - lo[a]) / h) + 1;
@@ -319,14 +320,27 @@ int build_filter_host(const soptx_mesh *mesh, double rmin, HostFilter &F) {
         const int nth = (int)std::max<int64_t>(1, std::min<int64_t>(16, std::min<int64_t>(
                                                          (int64_t)std::thread::hardware_concurrency(), n / 4096 + 1)));
         std::vector<Rows> parts((size_t)nth);
-        std::vector<std::thread> th;
-        for (int t = 0; t < nth; t++) {
+        std::vector<int> failed((size_t)nth, 0);
+        auto work = [&](int t) {
             const int64_t r0 = n * t / nth, r1 = n * (t + 1) / nth;
-            th.emplace_back([&, t, r0, r1] {
+            try {
                 search_rows(dim, c, rmin, lo, h, nc, cell_ptr, cell_el, r0, r1, parts[(size_t)t]);
-            });
+            } catch (...) {
+                failed[(size_t)t] = 1;
+            }
+        };
+        std::vector<std::thread> th;
+        for (int t = 1; t < nth; t++) {
+            try {
+                th.emplace_back(work, t);
+            } catch (...) {
+                work(t);  // no thread available: this one does the chunk
+            }
         }
+        work(0);
         for (auto &x : th) x.join();
+        for (int f : failed)
+            if (f) return SOPTX_E_OOM;
         int64_t nnz = 0;
         for (const auto &p : parts) nnz += (int64_t)p.col.size();
         if (nnz > INT32_MAX) return SOPTX_E_OVERFLOW;
