@@ -93,7 +93,7 @@ def solve_run(pat, m, K, f, stream, rtol, reps=20):
     """The equilibrium solve on the assembled K (Dirichlet applied): the SpMV
     timed with HIP events on the bench stream against its algorithmic bytes
     (K values, one neighbour id per DIM x DIM block, row offsets, x read, y
-    written), and one full Jacobi-PCG solve."""
+    written), and one full preconditioned CG solve."""
     import torch
     x = torch.ones(pat.ndof, dtype=torch.float64, device=K.device)
     y = torch.empty_like(x)
@@ -339,7 +339,7 @@ def main():
                     help="skip the second timed region (the same step replayed as a captured HIP graph)")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="hex120x40x40")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--no-solve", action="store_true", help="skip the SpMV / Jacobi-PCG measurement")
+    ap.add_argument("--no-solve", action="store_true", help="skip the SpMV / preconditioned CG measurement")
     ap.add_argument("--solve-rtol", type=float, default=1e-9)
     ap.add_argument("--no-filter", action="store_true", help="skip the filter-step measurement")
     ap.add_argument("--no-oc", action="store_true", help="skip the OC-update measurement")

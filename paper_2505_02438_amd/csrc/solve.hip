@@ -1,6 +1,6 @@
 // gfx950 kernels of the equilibrium solve K u = f (arXiv 2505.02438,
 // Sec. 2.2): a block-structured sparse product over the assembled CSR
-// values and Jacobi-preconditioned conjugate gradients (the iterative solver
+// values and conjugate gradients preconditioned by the nodes' diagonal blocks (the iterative solver
 // of the solver module, Sec. 3.2).
 #include <hip/hip_runtime.h>
 
@@ -17,7 +17,7 @@ namespace {
 // ------------------------------------------------------- solve (CG)
 //
 // The equilibrium system K u = f of the compliance problem, solved by
-// Jacobi-preconditioned conjugate gradients on the assembled CSR values.
+// conjugate gradients with a node-block Jacobi preconditioner on the assembled CSR values.
 //
 // y = K x.  K is a sum of DIM x DIM blocks, so a node's DIM rows share one
 // neighbour list: row DIM I + a holds, for neighbour J = nb(I)[q], the

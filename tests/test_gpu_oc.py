@@ -94,7 +94,7 @@ def _oracle_iteration(pr, rp, ci, H, rho, vf_target):
 def test_optimisation_iterations_match_oracle():
     """Five iterations of Algorithm 1 on the 60 x 20 MBB half-beam (unit Q1,
     volume fraction 0.5, sensitivity filter r = 1.5, m = 0.2, eta = 0.5):
-    GPU (assemble with Dirichlet, Jacobi-PCG to 1e-12, sensitivity, filter,
+    GPU (assemble with Dirichlet, preconditioned CG to 1e-12, sensitivity, filter,
     OC) against the oracles (direct banded solve).  The compliances agree to
     the solver's accuracy and the densities closely: the bisection's
     decisions are the same."""

@@ -1,5 +1,5 @@
 """The equilibrium solve K u = f (Sec. 2.2) on the assembled CSR values:
-soptx_spmv and the Jacobi-preconditioned CG soptx_pcg (the solver module's
+soptx_spmv and the preconditioned CG soptx_pcg (the solver module's
 iterative solver, Sec. 3.2), through the C ABI.
 
 * SpMV against the oracle's CSR product, row by row (scaled by sum |K| |x|);
