@@ -218,6 +218,18 @@ int soptx_build_pattern_general(const soptx_mesh *mesh, soptx_pattern *out, void
 int soptx_assemble_general(soptx_pattern h, const soptx_material *m, const double *d_rho, const uint8_t *d_dirichlet,
                            double *d_K_vals, void *stream);
 
+/* Element energies, sensitivities and compliance (Appendix D, Eq. cmpd) with
+ * the Jacobian at every Gauss point (Q1, affine or not; handles of
+ * soptx_build_pattern_general), FP64: s_e = sum_q w_q |det J_q|
+ * (lambda tr(eps)^2 + 2 mu eps:eps) = u_e^T K_e^0 u_e, d_dc[e] =
+ * -p rho_e^(p-1) (E0 - Emin) s_e (d_dc may be NULL), d_c[0] = sum_e E(rho_e) s_e
+ * and d_c[1] = f^T u when d_f is given (d_c may be NULL; not both NULL),
+ * summed in a fixed order.  d_rho: [n_cells] double, d_u: [ndof].
+ * SOPTX_E_INVALID_ARG for other handles, SOPTX_E_UNSUPPORTED_ELEM for
+ * simplices.  Asynchronous on stream. */
+int soptx_evaluate_general(soptx_pattern h, const soptx_material *m, const double *d_rho, const double *d_u,
+                           const double *d_f, double *d_dc, double *d_c, void *stream);
+
 /* Solve K u = f (Sec. 2.2) by conjugate gradients preconditioned by the
  * inverses of the DIM x DIM diagonal blocks of the nodes (node-block Jacobi;
  * the solver module's iterative solver, Sec. 3.2), for K

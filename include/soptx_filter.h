@@ -38,8 +38,9 @@ extern "C" {
 typedef struct soptx_filter_s *soptx_filter;
 
 /* Build H, the element measures v and the row sums sum_j H_ij v_j and
- * sum_j H_ij for a mesh (host memory, the same checks as soptx_build_pattern:
- * SOPTX_E_BAD_MESH / _JACOBIAN / _NONAFFINE), by a uniform-cell neighbourhood
+ * sum_j H_ij for a mesh (host memory, the checks of soptx_build_pattern_general:
+ * SOPTX_E_BAD_MESH / _JACOBIAN / _NONAFFINE; Q1 cells may be non-affine, their
+ * measure then the Gauss-rule integral of |det J|), by a uniform-cell neighbourhood
  * search, and copy them to the current device.  r_min > 0 and finite.
  * SOPTX_E_OVERFLOW when the number of stored entries exceeds int32.
  * Blocks until the uploads are complete.  *out receives a handle to release

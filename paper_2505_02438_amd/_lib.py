@@ -75,6 +75,7 @@ def lib():
         "soptx_build_pattern_ex": [ctypes.POINTER(Mesh), _I32, ctypes.POINTER(_P), _P],
         "soptx_build_pattern_general": [ctypes.POINTER(Mesh), ctypes.POINTER(_P), _P],
         "soptx_assemble_general": [_P, ctypes.POINTER(Material), _P, _P, _P, _P],
+        "soptx_evaluate_general": [_P, ctypes.POINTER(Material), _P, _P, _P, _P, _P, _P],
         "soptx_debug_host_plan_ex": [ctypes.POINTER(Mesh), _I32, ctypes.POINTER(_P)],
         "soptx_pattern_info": [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_P), ctypes.POINTER(_P)],
         "soptx_pattern_stats_get": [_P, ctypes.POINTER(PatternStats)],

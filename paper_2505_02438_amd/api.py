@@ -195,6 +195,23 @@ class Pattern:
               "soptx_assemble_general")
         return out
 
+    def evaluate_general(self, material: Material, rho, u, f=None, dc=None, c=None, stream=None):
+        """(dc, c) with the Jacobian at every Gauss point (patterns built with
+        general=True), FP64: dc_e = -E'(rho_e) u_e^T K_e^0 u_e, c = [u^T K u, f^T u]."""
+        import torch
+        if dc is None:
+            dc = torch.empty(self.n_cells, dtype=torch.float64, device=rho.device)
+        if c is None:
+            c = torch.zeros(2, dtype=torch.float64, device=rho.device)
+        mc = material._c()
+        check(lib().soptx_evaluate_general(self._h, ctypes.byref(mc), _dptr(rho, "rho", torch.float64, self.n_cells),
+                                           _dptr(u, "u", torch.float64, self.ndof),
+                                           _dptr(f, "f", torch.float64, self.ndof),
+                                           _dptr(dc, "dc", torch.float64, self.n_cells),
+                                           _dptr(c, "c", torch.float64, 2), _stream_ptr(stream)),
+              "soptx_evaluate_general")
+        return dc, c
+
     def apply_dirichlet(self, mask, K, stream=None):
         """K[r,:] = K[:,r] = 0, K[r,r] = 1 for every fixed dof r of mask, in place."""
         import torch

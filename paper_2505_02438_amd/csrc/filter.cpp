@@ -51,13 +51,15 @@ int n_vertex(int elem) {
     }
 }
 
-// Centroids (vertex mean, summed in local order) and measures |det J| times
-// the reference measure (the maps are affine: validated before).
+// Centroids (vertex mean, summed in local order) and measures: |det J| times
+// the reference measure for an affine map, sum_q w_q |det J_q| over the Gauss
+// points (exact for bilinear and trilinear maps) for a general Q1 element.
 void centroids_volumes(const soptx_mesh *m, std::vector<double> &c, std::vector<double> &v) {
     const int dim = m->dim, nen = elem_nen(m->elem), nv = n_vertex(m->elem);
     const int64_t n = m->n_cells;
     c.assign((size_t)n * dim, 0.0);
     v.assign((size_t)n, 0.0);
+    std::vector<double> qw, qg;  // Gauss rule, for Q1 cells whose map is not affine
     // map-defining vertices and the reference measure
     int def[3];
     double ref = 1.0;
@@ -81,6 +83,33 @@ void centroids_volumes(const soptx_mesh *m, std::vector<double> &c, std::vector<
             det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
                   J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
         v[(size_t)e] = std::fabs(det) * ref;
+        if (m->elem != SOPTX_QUAD4 && m->elem != SOPTX_HEX8) continue;
+        // a Q1 cell whose map is not affine: integrate |det J| at the Gauss points
+        double scale = 0.0;
+        for (int a = 0; a < dim; a++)
+            for (int b = 0; b < dim; b++) scale = std::max(scale, std::fabs(J[a][b]));
+        bool affine = true;
+        for (int i = 0; i < nv && affine; i++)
+            for (int a = 0; a < dim && affine; a++) {
+                double x = X(0, a);
+                for (int b = 0; b < dim; b++) x += J[a][b] * corner_bit(m->elem, i, b);
+                affine = std::fabs(x - X(i, a)) <= 1e-10 * scale;
+            }
+        if (affine) continue;
+        if (qw.empty()) reference_qp_grads(m->elem, qw, qg);
+        double vol = 0.0;
+        for (size_t q = 0; q < qw.size(); q++) {
+            double Jq[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+            for (int k = 0; k < nen; k++)
+                for (int a = 0; a < dim; a++)
+                    for (int b = 0; b < dim; b++) Jq[a][b] += X(k, a) * qg[(q * nen + k) * dim + b];
+            const double dq = dim == 2 ? Jq[0][0] * Jq[1][1] - Jq[0][1] * Jq[1][0]
+                                       : Jq[0][0] * (Jq[1][1] * Jq[2][2] - Jq[1][2] * Jq[2][1]) -
+                                             Jq[0][1] * (Jq[1][0] * Jq[2][2] - Jq[1][2] * Jq[2][0]) +
+                                             Jq[0][2] * (Jq[1][0] * Jq[2][1] - Jq[1][1] * Jq[2][0]);
+            vol += qw[q] * std::fabs(dq);
+        }
+        v[(size_t)e] = vol;
     }
 }
 
@@ -264,7 +293,7 @@ bool detect_stencil(const HostFilter &F, HostStencil &T) {
 
 int build_filter_host(const soptx_mesh *mesh, double rmin, HostFilter &F) {
     if (!(rmin > 0.0) || !std::isfinite(rmin)) return SOPTX_E_INVALID_ARG;
-    int rc = validate_mesh(mesh);
+    int rc = validate_mesh(mesh, true);  // general Q1 cells too (det J > 0 at the Gauss points)
     if (rc) return rc;
     const int dim = mesh->dim;
     const int64_t n = mesh->n_cells;

@@ -10,6 +10,8 @@
 // form J_q^-1 and w_q |det J_q| E at the quadrature points in LDS; every
 // thread accumulates its DIM x DIM block, and the block's elements are
 // written out as one contiguous range.
+// k_energy_general: element energies, sensitivities and the compliance
+// partials with the same per-point geometry.
 // k_gather_general: one thread per DIM x DIM block of K adds its element
 // contributions in ascending element order (the order of a sequential loop
 // over elements) and writes the block once.
@@ -165,6 +167,138 @@ __global__ __launch_bounds__(256) void k_gather_general(GenParams G) {
         for (int c = 0; c < DIM; c++) G.K[base + (int64_t)a * rl + DIM * q + c] = acc[a * DIM + c];
 }
 
+// Element energies with the Jacobian at every Gauss point, one thread per
+// element: s_e = sum_q w_q |det J_q| (lambda tr(eps)^2 + 2 mu eps:eps), eps
+// the symmetric part of grad u = sum_k u_k g_k^T (equal to u_e^T K_e^0 u_e
+// for the same rule), dc_e = -p rho^(p-1) (E0 - Emin) s_e, and block
+// partials of c = sum_e E(rho_e) s_e and of f^T u in a fixed order.
+template <int DIM, int NEN, int NQ>
+__global__ __launch_bounds__(256) void k_energy_general(GenEnergyParams P) {
+    __shared__ double red[256];
+    __shared__ double sq[NQ * NEN * DIM];
+    for (int x = threadIdx.x; x < NQ * NEN * DIM; x += 256) sq[x] = P.qgrad[x];
+    __syncthreads();
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double cpart = 0.0;
+    if (e < P.n_cells) {
+        double x[NEN][DIM], ue[NEN][DIM];
+        for (int k = 0; k < NEN; k++) {
+            const int64_t nd = P.cells[e * NEN + k];
+#pragma unroll
+            for (int a = 0; a < DIM; a++) {
+                x[k][a] = P.coords[nd * DIM + a];
+                ue[k][a] = P.u[nd * DIM + a];
+            }
+        }
+        double s = 0.0;
+        for (int q = 0; q < NQ; q++) {
+            double J[DIM][DIM], Hr[DIM][DIM];  // dx_a / dxi_m and du_a / dxi_m
+#pragma unroll
+            for (int a = 0; a < DIM; a++)
+#pragma unroll
+                for (int m = 0; m < DIM; m++) J[a][m] = Hr[a][m] = 0.0;
+            for (int k = 0; k < NEN; k++)
+#pragma unroll
+                for (int m = 0; m < DIM; m++) {
+                    const double gm = sq[(q * NEN + k) * DIM + m];
+#pragma unroll
+                    for (int a = 0; a < DIM; a++) {
+                        J[a][m] += x[k][a] * gm;
+                        Hr[a][m] += ue[k][a] * gm;
+                    }
+                }
+            double inv[DIM][DIM], det;
+            if (DIM == 2) {
+                det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+                const double id = 1.0 / det;
+                inv[0][0] = J[1][1] * id;
+                inv[0][1] = -J[0][1] * id;
+                inv[1][0] = -J[1][0] * id;
+                inv[1][1] = J[0][0] * id;
+            } else {
+                const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+                const double c01 = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+                const double c02 = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+                const double c10 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+                const double c11 = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+                const double c12 = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+                const double c20 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+                const double c21 = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+                const double c22 = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+                det = J[0][0] * c00 + J[0][1] * c10 + J[0][2] * c20;
+                const double id = 1.0 / det;
+                inv[0][0] = c00 * id; inv[0][1] = c01 * id; inv[0][2] = c02 * id;
+                inv[1][0] = c10 * id; inv[1][1] = c11 * id; inv[1][2] = c12 * id;
+                inv[2][0] = c20 * id; inv[2][1] = c21 * id; inv[2][2] = c22 * id;
+            }
+            // grad u = Hr J^-1, then the energy density of its symmetric part
+            double H[DIM][DIM];
+#pragma unroll
+            for (int a = 0; a < DIM; a++)
+#pragma unroll
+                for (int b = 0; b < DIM; b++) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int m = 0; m < DIM; m++) t += Hr[a][m] * inv[m][b];
+                    H[a][b] = t;
+                }
+            double tr = 0.0, ee = 0.0;
+#pragma unroll
+            for (int a = 0; a < DIM; a++) {
+                tr += H[a][a];
+#pragma unroll
+                for (int b = 0; b < DIM; b++) {
+                    const double eab = 0.5 * (H[a][b] + H[b][a]);
+                    ee += eab * eab;
+                }
+            }
+            s += P.qw[q] * fabs(det) * (P.lam * tr * tr + 2.0 * P.mu * ee);
+        }
+        const double r = P.rho[e];
+        double rp1 = 1.0;  // rho^(p - 1)
+        if (P.ip >= 1) {
+            for (int k = 0; k < P.ip - 1; k++) rp1 *= r;
+        } else {
+            rp1 = general_pow(r, P.p - 1.0);
+        }
+        const double E = P.Emin + rp1 * r * (P.E0 - P.Emin);
+        if (P.dc) P.dc[e] = -P.p * rp1 * (P.E0 - P.Emin) * s;
+        cpart = E * s;
+    }
+    if (!P.partials) return;
+    double fpart = 0.0;
+    if (P.f)
+        for (int64_t rr = (int64_t)blockIdx.x * 256 + threadIdx.x; rr < P.ndof; rr += (int64_t)gridDim.x * 256)
+            fpart += P.f[rr] * P.u[rr];
+    // fixed-order block sums (every thread reaches them)
+    red[threadIdx.x] = cpart;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    const double bc = red[0];
+    __syncthreads();
+    red[threadIdx.x] = fpart;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        P.partials[blockIdx.x] = bc;
+        P.partials[gridDim.x + blockIdx.x] = P.f ? red[0] : 0.0;
+    }
+}
+
+template <int DIM, int NEN, int NQ>
+hipError_t launch_energy_t(const GenEnergyParams &P, hipStream_t st) {
+    if (P.nq != NQ) return hipErrorInvalidValue;
+    const unsigned g = (unsigned)((P.n_cells + 255) / 256);
+    hipLaunchKernelGGL((k_energy_general<DIM, NEN, NQ>), dim3(g > 0 ? g : 1), dim3(256), 0, st, P);
+    return hipGetLastError();
+}
+
 template <int DIM, int NEN, int NQ>
 hipError_t launch_t(const GenParams &G, hipStream_t st) {
     constexpr int EPB = 256 / (NEN * NEN);
@@ -181,6 +315,12 @@ hipError_t launch_t(const GenParams &G, hipStream_t st) {
 }
 
 }  // namespace
+
+hipError_t launch_energy_general(int elem, const GenEnergyParams &P, hipStream_t st) {
+    if (elem == SOPTX_HEX8) return launch_energy_t<3, 8, 8>(P, st);
+    if (elem == SOPTX_QUAD4) return launch_energy_t<2, 4, 4>(P, st);
+    return hipErrorInvalidValue;
+}
 
 hipError_t launch_assemble_general(int elem, const GenParams &G, hipStream_t st) {
     if (elem == SOPTX_HEX8) return launch_t<3, 8, 8>(G, st);

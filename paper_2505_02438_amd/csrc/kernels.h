@@ -120,6 +120,26 @@ struct GenParams {
     int64_t n_blocks;
 };
 hipError_t launch_assemble_general(int elem, const GenParams &G, hipStream_t st);
+// element energies with per-quadrature-point geometry: dc and block partials
+// of c and f^T u (as EnergyParams), FP64
+struct GenEnergyParams {
+    const int32_t *cells;
+    const double *coords;
+    const double *rho;
+    const double *u;
+    const double *qw;
+    const double *qgrad;
+    double *dc;        // or null
+    const double *f;   // or null
+    int64_t ndof;
+    double *partials;  // [2][grid] or null
+    int64_t n_cells;
+    int nq;
+    double E0, Emin, p;
+    int ip;
+    double lam, mu;
+};
+hipError_t launch_energy_general(int elem, const GenEnergyParams &P, hipStream_t st);
 
 // filter step: H in CSR (int32 columns, FP64 weights), element measures v,
 // row sums hsv_i = sum_j H_ij v_j and hs_i = sum_j H_ij; R rows per block

@@ -491,6 +491,33 @@ int soptx_evaluate(soptx_pattern h, const soptx_material *m, const void *d_rho, 
     return SOPTX_OK;
 }
 
+int soptx_evaluate_general(soptx_pattern h, const soptx_material *m, const double *d_rho, const double *d_u,
+                           const double *d_f, double *d_dc, double *d_c, void *stream) {
+    if (!h || !h->general) return SOPTX_E_INVALID_ARG;
+    int rc = check_material(m);
+    if (rc) return rc;
+    if (h->n_cells > 0 && (!d_rho || !d_u)) return SOPTX_E_INVALID_ARG;
+    if (!d_dc && !d_c) return SOPTX_E_INVALID_ARG;
+    if (h->elem != SOPTX_QUAD4 && h->elem != SOPTX_HEX8) return SOPTX_E_UNSUPPORTED_ELEM;
+    DeviceGuard dg(h->device);
+    if (!dg.ok) return SOPTX_E_DEVICE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int nblk = std::max(1, (int)((h->n_cells + 255) / 256));
+    double *ws = nullptr;
+    if (d_c) {
+        rc = get_workspace(h->device, st, 2 * (size_t)nblk, &ws, 0);
+        if (rc) return rc;
+    }
+    GenEnergyParams P{};
+    P.cells = h->cells; P.coords = h->coords; P.rho = d_rho; P.u = d_u; P.qw = h->qw; P.qgrad = h->qgrad;
+    P.dc = d_dc; P.f = d_c ? d_f : nullptr; P.ndof = h->ndof; P.partials = d_c ? ws : nullptr;
+    P.n_cells = h->n_cells; P.nq = h->nq; P.E0 = m->E0; P.Emin = m->Emin; P.p = m->p; P.ip = int_exponent(m->p);
+    lame(h, m, &P.lam, &P.mu);
+    if (launch_energy_general(h->elem, P, st) != hipSuccess) return SOPTX_E_DEVICE;
+    if (d_c && launch_finalize(ws, nblk, d_f ? 1 : 0, d_c, st) != hipSuccess) return SOPTX_E_DEVICE;
+    return SOPTX_OK;
+}
+
 int soptx_sensitivity(soptx_pattern h, const soptx_material *m, const void *d_rho, const double *d_u,
                       void *d_dc, int32_t prec, void *stream) {
     if (h && h->n_cells > 0 && !d_dc) return SOPTX_E_INVALID_ARG;

@@ -8,6 +8,8 @@ density rho~ = F(rho) and takes dc and the volume sensitivity back through the
 chain rule (so the constraint is the filtered volume, exactly, since F is
 linear).  The loop stops when the largest density change of an update is at
 most `tol` or after `max_iter` updates (the paper's runs use 0.01 and 200).
+general: Q1 meshes whose elements are not affine, assembled and evaluated
+with the Jacobian at every Gauss point.
 Each CG solve starts from the previous iteration's displacement
 (warm_start), stopping at ||r|| <= cg_rtol ||f||.
 """
@@ -32,12 +34,13 @@ class LoopResult:
 
 def run(mesh, mask, f, volfrac: float, rmin: float, filt: str = "sensitivity", rho0: Optional[float] = None,
         max_iter: int = 200, tol: float = 0.01, move: float = 0.2, eta: float = 0.5, cg_rtol: float = 1e-8,
-        warm_start: bool = True, material: Optional[api.Material] = None, stream=None) -> LoopResult:
+        warm_start: bool = True, general: bool = False, material: Optional[api.Material] = None,
+        stream=None) -> LoopResult:
     import torch
     if filt not in ("sensitivity", "density"):
         raise ValueError("filt is 'sensitivity' or 'density'")
     d = torch.device("cuda:0")
-    pat = api.Pattern.from_mesh(mesh)
+    pat = api.Pattern.from_mesh(mesh, general=general)
     flt = api.Filter.from_mesh(mesh, rmin)
     mat = material or api.Material(E0=1.0, Emin=1e-9, nu=0.3, p=3.0)
     n = mesh.n_cells
@@ -54,12 +57,18 @@ def run(mesh, mask, f, volfrac: float, rmin: float, filt: str = "sensitivity", r
     vf = volfrac if rho0 is None else rho0      # a uniform design: the filter keeps it
     for _ in range(max_iter):
         phys = flt.density(rho, stream=stream) if filt == "density" else rho
-        pat.assemble(mat, phys, mask_d, out=K, stream=stream)
+        if general:
+            pat.assemble_general(mat, phys, mask_d, out=K, stream=stream)
+        else:
+            pat.assemble(mat, phys, mask_d, out=K, stream=stream)
         if not warm_start:
             u.zero_()
         # the previous displacement starts the solve (the criterion is relative to ||f||)
         u, cg_it, _ = pat.pcg(K, f_d, u=u, rtol=cg_rtol, max_iter=50000, stream=stream)
-        dc, c = pat.evaluate(mat, phys, u, f=f_d, stream=stream)
+        if general:
+            dc, c = pat.evaluate_general(mat, phys, u, f=f_d, stream=stream)
+        else:
+            dc, c = pat.evaluate(mat, phys, u, f=f_d, stream=stream)
         if filt == "density":
             dcd = flt.density_backward(dc, stream=stream)
         else:

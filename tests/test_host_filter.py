@@ -147,3 +147,18 @@ def test_heaviside_beta_continuation():
     assert api.heaviside_beta(50 * 9) == 512.0 and api.heaviside_beta(10 ** 6) == 512.0
     with pytest.raises(ValueError):
         api.heaviside_beta(-1)
+
+
+@pytest.mark.parametrize("elem", [I.QUAD4, I.HEX8])
+def test_filter_on_general_q1(elem):
+    """Non-affine Q1 cells are accepted; their measures are the Gauss-rule
+    integral of |det J| (the oracle's definition) and tile the box."""
+    m0 = I.quad_grid(9, 7) if elem == I.QUAD4 else I.hex_grid(4, 3, 3)
+    m = I.jitter_interior(m0, 0.3, np.random.default_rng(2))
+    hh = api.filter_matrix_host(m.elem, m.coords, m.cells, 1.6)
+    v = OF.volumes(elem, m.coords, m.cells)
+    np.testing.assert_allclose(hh["vol"], v, rtol=1e-14)
+    assert abs(hh["vol"].sum() - (63.0 if elem == I.QUAD4 else 36.0)) <= 1e-12
+    (rp, col, w), _ = _oracle(elem, m, 1.6)
+    np.testing.assert_array_equal(hh["row_ptr"], rp)
+    np.testing.assert_array_equal(hh["col"], col)

@@ -551,3 +551,9 @@ def test_nonaffine_q1_oracle(elem):
     assert np.abs(Ku[idx]).max() <= 1e-12 * np.abs(K).max() * np.abs(u).max()
     for r in _rigid_modes(m.coords, m.dim):
         assert np.abs(O.spmv(rp, ci, K, r)).max() <= 1e-13 * np.abs(K).max() * np.abs(r).max()
+    # the element energy (Gauss-point form) passes the same patch test
+    se = O.element_energy(elem, m.coords, m.cells, u)
+    if elem == I.QUAD4:
+        np.testing.assert_allclose(se, area * e_dens, rtol=1e-12)
+    else:
+        np.testing.assert_allclose(se, s, rtol=1e-12)
