@@ -27,8 +27,9 @@ import numpy as np
 from . import oracle as O
 
 GAMMA = 1e-3
-# corner (vertex) nodes per element type: Q1 quad, P1 triangle, Q1 hex, P2 tet
-N_VERTEX = {1: 4, 2: 3, 3: 8, 4: 4}
+# corner (vertex) nodes per element type: Q1 quad, P1 triangle, Q1 hex, P2 tet,
+# Q2 hex (its corners are nodes 0-7)
+N_VERTEX = {1: 4, 2: 3, 3: 8, 4: 4, 5: 8}
 
 
 def centroids(elem: int, coords, cells) -> np.ndarray:

@@ -22,7 +22,15 @@
  * re-evaluated at every point (no affine shortcut, no separated reference
  * tensor).  Quadrature rules are exact for affine elements:
  *   Q1 quad 2x2 Gauss, Q1 hex 2x2x2 Gauss, P1 tri 1-point centroid,
- *   P2 tet 4-point degree-2 rule (a=(5+3 sqrt5)/20, b=(5-sqrt5)/20).
+ *   P2 tet 4-point degree-2 rule (a=(5+3 sqrt5)/20, b=(5-sqrt5)/20),
+ *   Q2 hex 3x3x3 Gauss (exact to degree 5 in each variable).
+ *
+ * The Q2 hexahedron (27-node triquadratic Lagrange element) is a variant
+ * beyond the paper's examples, which use linear elements (Sec. 3.2.2); the
+ * underlying platform offers elements of any order (Sec. 1).  Node order:
+ * the 8 corners as for Q1, then the other 19 points of the 3x3x3 lattice
+ * {0, 1/2, 1}^3 in ascending a + 3b + 9c, with (a, b, c) the lattice indices
+ * along x, y, z.
  *
  * Elasticity matrix D (Sec. 3.2.1 material module; Sec. 4.2 uses plane
  * stress with E=1, nu=0.3): Voigt notation with engineering shear strains.
@@ -42,16 +50,16 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { E_QUAD4 = 1, E_TRI3 = 2, E_HEX8 = 3, E_TET10 = 4 };
+enum { E_QUAD4 = 1, E_TRI3 = 2, E_HEX8 = 3, E_TET10 = 4, E_HEX27 = 5 };
 
-#define MAXNEN 10
-#define MAXLDOF 30
-#define MAXQ 8
+#define MAXNEN 27
+#define MAXLDOF 81
+#define MAXQ 27
 
 static int elem_dim(int elem) {
     switch (elem) {
     case E_QUAD4: case E_TRI3: return 2;
-    case E_HEX8: case E_TET10: return 3;
+    case E_HEX8: case E_TET10: case E_HEX27: return 3;
     default: return -1;
     }
 }
@@ -62,6 +70,7 @@ static int elem_nen(int elem) {
     case E_TRI3: return 3;
     case E_HEX8: return 8;
     case E_TET10: return 10;
+    case E_HEX27: return 27;
     default: return -1;
     }
 }
@@ -86,6 +95,35 @@ static const int TET_EDGE[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3
 static double lin(int c, double t) { return c ? t : 1.0 - t; }
 static double dlin(int c) { return c ? 1.0 : -1.0; }
 
+/* 1D quadratic Lagrange functions on [0,1] with nodes 0, 1/2, 1 (index k):
+ * l0 = (1-t)(1-2t), l1 = 4t(1-t), l2 = t(2t-1), and their derivatives */
+static double quad1(int k, double t) {
+    return k == 0 ? (1.0 - t) * (1.0 - 2.0 * t) : k == 1 ? 4.0 * t * (1.0 - t) : t * (2.0 * t - 1.0);
+}
+static double dquad1(int k, double t) { return k == 0 ? 4.0 * t - 3.0 : k == 1 ? 4.0 - 8.0 * t : 4.0 * t - 1.0; }
+
+/* lattice indices (a, b, c) of the Q2 hexahedron's node i, in the order
+ * stated at the top of this file */
+static void hex27_node(int i, int *abc) {
+    int n = 8, a, b, c;
+    if (i < 8) {
+        abc[0] = 2 * HEX_CORNER[i][0]; abc[1] = 2 * HEX_CORNER[i][1]; abc[2] = 2 * HEX_CORNER[i][2];
+        return;
+    }
+    for (c = 0; c < 3; c++)
+        for (b = 0; b < 3; b++)
+            for (a = 0; a < 3; a++) {
+                if (a != 1 && b != 1 && c != 1) continue; /* a corner */
+                if (n == i) { abc[0] = a; abc[1] = b; abc[2] = c; return; }
+                n++;
+            }
+}
+int oracle_hex27_node(int i, int *abc) {
+    if (i < 0 || i >= 27) return -1;
+    hex27_node(i, abc);
+    return 0;
+}
+
 int oracle_ref_basis(int elem, const double *xi, double *phi, double *dphi) {
     int i;
     switch (elem) {
@@ -104,6 +142,16 @@ int oracle_ref_basis(int elem, const double *xi, double *phi, double *dphi) {
             dphi[3 * i + 0] = dlin(cx) * lin(cy, xi[1]) * lin(cz, xi[2]);
             dphi[3 * i + 1] = lin(cx, xi[0]) * dlin(cy) * lin(cz, xi[2]);
             dphi[3 * i + 2] = lin(cx, xi[0]) * lin(cy, xi[1]) * dlin(cz);
+        }
+        return 0;
+    case E_HEX27:
+        for (i = 0; i < 27; i++) {
+            int k[3];
+            hex27_node(i, k);
+            phi[i] = quad1(k[0], xi[0]) * quad1(k[1], xi[1]) * quad1(k[2], xi[2]);
+            dphi[3 * i + 0] = dquad1(k[0], xi[0]) * quad1(k[1], xi[1]) * quad1(k[2], xi[2]);
+            dphi[3 * i + 1] = quad1(k[0], xi[0]) * dquad1(k[1], xi[1]) * quad1(k[2], xi[2]);
+            dphi[3 * i + 2] = quad1(k[0], xi[0]) * quad1(k[1], xi[1]) * dquad1(k[2], xi[2]);
         }
         return 0;
     case E_TRI3:
@@ -162,6 +210,22 @@ int oracle_quadrature(int elem, int *nq, double *pts, double *wts) {
                     wts[q] = 0.125; q++;
                 }
         *nq = 8;
+        return 0;
+    }
+    case E_HEX27: {
+        /* 3-point Gauss-Legendre on [0,1]: 1/2 -+ sqrt(3/5)/2 and 1/2,
+         * weights 5/18, 8/18, 5/18 */
+        double g[3] = {0.5 - 0.5 * sqrt(0.6), 0.5, 0.5 + 0.5 * sqrt(0.6)};
+        double w[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+        int a, b, c;
+        q = 0;
+        for (a = 0; a < 3; a++)
+            for (b = 0; b < 3; b++)
+                for (c = 0; c < 3; c++) {
+                    pts[3 * q] = g[a]; pts[3 * q + 1] = g[b]; pts[3 * q + 2] = g[c];
+                    wts[q] = w[a] * w[b] * w[c]; q++;
+                }
+        *nq = 27;
         return 0;
     }
     case E_TRI3:

@@ -59,17 +59,18 @@ def lib():
         L.oracle_ref_basis.argtypes = [_I32, _P, _P, _P]
         L.oracle_quadrature.argtypes = [_I32, _P, _P, _P]
         L.oracle_D.argtypes = [_I32, _I32, _D, _D, _P]
+        L.oracle_hex27_node.argtypes = [_I32, _P]
         for name in ("oracle_pattern_from_pairs", "oracle_assemble", "oracle_element_energy",
                      "oracle_sensitivity", "oracle_compliance", "oracle_assemble_backward",
                      "oracle_spmv", "oracle_solve_banded", "oracle_ref_basis", "oracle_quadrature",
-                     "oracle_D"):
+                     "oracle_D", "oracle_hex27_node"):
             getattr(L, name).restype = _I32
         _lib = L
     return _lib
 
 
-DIM = {1: 2, 2: 2, 3: 3, 4: 3}
-NEN = {1: 4, 2: 3, 3: 8, 4: 10}
+DIM = {1: 2, 2: 2, 3: 3, 4: 3, 5: 3}
+NEN = {1: 4, 2: 3, 3: 8, 4: 10, 5: 27}
 
 
 def _ptr(a: Optional[np.ndarray]):
@@ -111,9 +112,17 @@ def ref_basis(elem: int, xi):
     return phi, dphi
 
 
+def hex27_node(i: int):
+    """Lattice indices (a, b, c) in {0, 1, 2}^3 of the Q2 hexahedron's node i
+    (position (a, b, c) / 2 on the reference cube)."""
+    abc = np.zeros(3, np.int32)
+    _check(lib().oracle_hex27_node(i, _ptr(abc)), "hex27_node")
+    return tuple(int(v) for v in abc)
+
+
 def quadrature(elem: int):
-    pts = np.zeros((8, 3))
-    wts = np.zeros(8)
+    pts = np.zeros((27, 3))
+    wts = np.zeros(27)
     nq = ctypes.c_int(0)
     _check(lib().oracle_quadrature(elem, ctypes.byref(nq), _ptr(pts), _ptr(wts)), "quadrature")
     d = DIM[elem]

@@ -41,10 +41,11 @@ QUAD4 = 1
 TRI3 = 2
 HEX8 = 3
 TET10 = 4
+HEX27 = 5
 
-ELEM_NAMES = {QUAD4: "quad4", TRI3: "tri3", HEX8: "hex8", TET10: "tet10"}
-ELEM_DIM = {QUAD4: 2, TRI3: 2, HEX8: 3, TET10: 3}
-ELEM_NEN = {QUAD4: 4, TRI3: 3, HEX8: 8, TET10: 10}
+ELEM_NAMES = {QUAD4: "quad4", TRI3: "tri3", HEX8: "hex8", TET10: "tet10", HEX27: "hex27"}
+ELEM_DIM = {QUAD4: 2, TRI3: 2, HEX8: 3, TET10: 3, HEX27: 3}
+ELEM_NEN = {QUAD4: 4, TRI3: 3, HEX8: 8, TET10: 10, HEX27: 27}
 
 
 @dataclasses.dataclass
@@ -105,6 +106,25 @@ def hex_grid(nx: int, ny: int, nz: int, h: float = 1.0) -> Mesh:
         nid(ei, ej, ek + 1), nid(ei + 1, ej, ek + 1), nid(ei + 1, ej + 1, ek + 1), nid(ei, ej + 1, ek + 1),
     ], axis=1)
     return Mesh(HEX8, coords, cells.astype(np.int32))
+
+
+# Q2 hexahedron node order: the 8 corners as for Q1, then the other 19 points
+# (a, b, c) / 2 of the 3 x 3 x 3 reference lattice, a, b, c in {0, 1, 2}, in
+# ascending a + 3 b + 9 c.
+_HEX27_LATTICE = [(0, 0, 0), (2, 0, 0), (2, 2, 0), (0, 2, 0), (0, 0, 2), (2, 0, 2), (2, 2, 2), (0, 2, 2)] + [
+    (a, b, c) for c in range(3) for b in range(3) for a in range(3) if 1 in (a, b, c)]
+
+
+def hex27_grid(nx: int, ny: int, nz: int, h: float = 1.0) -> Mesh:
+    """Structured nx x ny x nz grid of h-cubes as Q2 hexahedra (27 nodes each,
+    on the (2nx+1) x (2ny+1) x (2nz+1) lattice of spacing h/2)."""
+    mx, my, mz = 2 * nx + 1, 2 * ny + 1, 2 * nz + 1
+    i, j, k = np.meshgrid(np.arange(mx), np.arange(my), np.arange(mz), indexing="ij")
+    coords = np.stack([i.ravel() * 0.5 * h, j.ravel() * 0.5 * h, k.ravel() * 0.5 * h], axis=1).astype(np.float64)
+    ei, ej, ek = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    ei, ej, ek = ei.ravel(), ej.ravel(), ek.ravel()
+    cells = np.stack([((2 * ei + a) * my + 2 * ej + b) * mz + 2 * ek + c for a, b, c in _HEX27_LATTICE], axis=1)
+    return Mesh(HEX27, coords, cells.astype(np.int32))
 
 
 def tri_grid(nx: int, ny: int, h: float = 1.0, jitter: float = 0.0,
@@ -336,6 +356,22 @@ def cantilever_hex(nx: int = 120, ny: int = 40, nz: int = 40, seed: int = 1003,
     if skew:
         mesh = skew_mesh(mesh, skew)
     return Problem(f"cantilever_hex_{nx}x{ny}x{nz}" + (f"_{skew}" if skew else ""), mesh, rho, mask, f, u)
+
+
+def cantilever_hex27(nx: int = 60, ny: int = 20, nz: int = 20, h: float = 2.0, jitter: float = 0.15,
+                     seed: int = 1005) -> Problem:
+    """3D cantilever of Q2 hexahedra: nx x ny x nz cubes of side h (the
+    defaults cover the 120 x 40 x 40 box of the Q1 cantilever with the same
+    node lattice), every node off the bounding box moved by U(-jitter, jitter)
+    per coordinate (curved, non-affine elements), rho ~ Beta(2, 2), synthetic u."""
+    rng = np.random.default_rng(seed)
+    mesh = hex27_grid(nx, ny, nz, h)
+    if jitter:
+        mesh = jitter_interior(mesh, jitter, rng)
+    rho = rng.beta(2.0, 2.0, mesh.n_cells)
+    mask, f = clamp_x0_bc(mesh)
+    u = synthetic_u(rng, mask)
+    return Problem(f"cantilever_hex27_{nx}x{ny}x{nz}", mesh, rho, mask, f, u)
 
 
 def box_p2(n: int = 48, seed: int = 1004) -> Problem:

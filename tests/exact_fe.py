@@ -21,8 +21,28 @@ import sympy as sp
 X = sp.symbols("x0:3")
 
 
+def _lagrange_1d(k, t):
+    """Quadratic Lagrange polynomial of node k of {0, 1/2, 1}, by the product
+    formula prod_{m != k} (t - t_m) / (t_k - t_m)."""
+    nodes = [sp.Integer(0), sp.Rational(1, 2), sp.Integer(1)]
+    p = sp.Integer(1)
+    for m in range(3):
+        if m != k:
+            p *= (t - nodes[m]) / (nodes[k] - nodes[m])
+    return sp.expand(p)
+
+
+# Q2 hexahedron: corners as for Q1 (lattice 0/2), then the other lattice
+# points in ascending a + 3b + 9c
+HEX27_LATTICE = [(0, 0, 0), (2, 0, 0), (2, 2, 0), (0, 2, 0), (0, 0, 2), (2, 0, 2), (2, 2, 2), (0, 2, 2)] + [
+    (a, b, c) for c in range(3) for b in range(3) for a in range(3) if a == 1 or b == 1 or c == 1]
+
+
 def _ref_basis(elem):
     x, y, z = X
+    if elem == 5:  # Q2 hex on [0,1]^3
+        return [sp.expand(_lagrange_1d(a, x) * _lagrange_1d(b, y) * _lagrange_1d(c, z))
+                for a, b, c in HEX27_LATTICE], 3, "cube"
     if elem == 1:  # Q1 quad on [0,1]^2, CCW from the origin
         c = [(0, 0), (1, 0), (1, 1), (0, 1)]
         f = lambda b, t: t if b else 1 - t
@@ -75,7 +95,7 @@ def exact_ke0(elem, verts, nu=Fraction(3, 10), plane_strain=False):
     # affine map columns
     if elem == 1:
         cols = [1, 3]
-    elif elem == 3:
+    elif elem in (3, 5):
         cols = [1, 3, 4]
     else:
         cols = list(range(1, dim + 1))
@@ -109,3 +129,23 @@ def exact_ref_moments(elem):
     g = [[sp.diff(ph, X[m]) for m in range(dim)] for ph in phis]
     return [[[[_integrate_ref(sp.expand(g[i][m] * g[j][n]), dim, kind) for n in range(dim)]
               for m in range(dim)] for j in range(nen)] for i in range(nen)]
+
+
+def exact_energy(elem, verts, U, nu=Fraction(3, 10)):
+    """a(u, u) exactly for the field u = sum_i U[i] phi_i of an affine 3D
+    element (E = 1), U rational nodal values [nen][3]: the same affine map as
+    exact_ke0, integrand lambda div(u)^2 + 2 mu eps(u):eps(u)."""
+    phis, dim, kind = _ref_basis(elem)
+    nu = sp.Rational(nu)
+    lam = nu / ((1 + nu) * (1 - 2 * nu))
+    mu = 1 / (2 * (1 + nu))
+    cols = [1, 3, 4] if elem in (3, 5) else list(range(1, dim + 1))
+    x0 = [sp.Rational(v) for v in verts[0]]
+    J = sp.Matrix(dim, dim, lambda a, m: sp.Rational(verts[cols[m]][a]) - x0[a])
+    G = J.inv()
+    uref = [sp.expand(sum(sp.Rational(U[i][a]) * phis[i] for i in range(len(phis)))) for a in range(dim)]
+    grad = [[sp.expand(sum(sp.diff(uref[a], X[m]) * G[m, b] for m in range(dim))) for b in range(dim)]
+            for a in range(dim)]
+    div = sum(grad[a][a] for a in range(dim))
+    ee = sum(((grad[a][b] + grad[b][a]) / 2) ** 2 for a in range(dim) for b in range(dim))
+    return abs(J.det()) * _integrate_ref(sp.expand(lam * div ** 2 + 2 * mu * ee), dim, kind)
