@@ -20,9 +20,17 @@
  *       SOPTX_TRI3   counter-clockwise vertices;
  *       SOPTX_HEX8   bottom face counter-clockwise, then top face;
  *       SOPTX_TET10  4 positively oriented vertices, then the nodes of
- *                    edges 01,02,03,12,13,23.
+ *                    edges 01,02,03,12,13,23;
+ *       SOPTX_HEX27  27-node triquadratic Lagrange hexahedron: the 8 corners
+ *                    as for SOPTX_HEX8, then the other 19 points of the
+ *                    reference lattice {0, 1/2, 1}^3, (a, b, c) / 2 with
+ *                    a, b, c in {0, 1, 2}, in ascending a + 3b + 9c.
  *     Elements must be affine (parallelogram / parallelepiped Q1 cells,
- *     straight-edged P2 cells); others are rejected with SOPTX_E_NONAFFINE.
+ *     straight-edged P2 cells); others are rejected with SOPTX_E_NONAFFINE,
+ *     except by the per-quadrature-point calls (soptx_*_general), which take
+ *     general Q1 cells and SOPTX_HEX27, the latter only there.  SOPTX_HEX27
+ *     is a higher-order variant beyond the paper's examples, which use linear
+ *     elements (Sec. 3.2.2); the paper's platform offers any order (Sec. 1).
  *   - CSR pattern: the set {(dof(e,i), dof(e,j))}; rows ascending, columns
  *     ascending and unique per row; structural zeros are kept.  int32 indices.
  *   - Summation order of every stored K value is fixed by the mesh (the
@@ -68,7 +76,7 @@ extern "C" {
 #define SOPTX_E_OOM (-7)              /* device or host allocation failed */
 #define SOPTX_E_DEVICE (-8)           /* HIP runtime / launch error */
 
-typedef enum { SOPTX_QUAD4 = 1, SOPTX_TRI3 = 2, SOPTX_HEX8 = 3, SOPTX_TET10 = 4 } soptx_elem;
+typedef enum { SOPTX_QUAD4 = 1, SOPTX_TRI3 = 2, SOPTX_HEX8 = 3, SOPTX_TET10 = 4, SOPTX_HEX27 = 5 } soptx_elem;
 
 /* Precision of the element-matrix contraction and of the element energy.
  * K values, the compliance and the cross-element accumulation are FP64 in
@@ -202,12 +210,17 @@ int soptx_spmv(soptx_pattern h, const double *d_K_vals, const double *d_x, doubl
  * handle of a mesh that has non-affine elements the affine-only calls
  * (soptx_assemble, soptx_evaluate and its variants, soptx_assemble_backward)
  * return SOPTX_E_NONAFFINE; pattern queries, soptx_apply_dirichlet,
- * soptx_spmv and soptx_pcg work on any handle. */
+ * soptx_spmv and soptx_pcg work on any handle.  SOPTX_HEX27 meshes (curved
+ * or not, det J > 0 at every Gauss point of the 3 x 3 x 3 rule) are built
+ * only here; on their handles the affine-only calls return
+ * SOPTX_E_UNSUPPORTED_ELEM, and soptx_build_pattern refuses them with that
+ * code. */
 int soptx_build_pattern_general(const soptx_mesh *mesh, soptx_pattern *out, void *stream);
 
 /* SIMP stiffness assembly (Sec. 2.1, Sec. 2.2) with the element matrices
  * integrated by the element's Gauss rule with J evaluated at every quadrature
- * point (Q1 quadrilaterals and hexahedra, affine or not), FP64: each element's
+ * point (Q1 quadrilaterals and hexahedra, affine or not, and Q2 hexahedra),
+ * FP64: each element's
  * blocks E(rho_e) sum_q w_q |det J_q| L(g_i g_j^T), g = J_q^-T grad(phi) the
  * physical gradients, are formed in a workspace (n_cells nen^2 DIM^2 doubles
  * per (device, stream), allocated on first use), then every CSR block sums
@@ -219,7 +232,7 @@ int soptx_assemble_general(soptx_pattern h, const soptx_material *m, const doubl
                            double *d_K_vals, void *stream);
 
 /* Element energies, sensitivities and compliance (Appendix D, Eq. cmpd) with
- * the Jacobian at every Gauss point (Q1, affine or not; handles of
+ * the Jacobian at every Gauss point (Q1, affine or not, and Q2 hexahedra; handles of
  * soptx_build_pattern_general), FP64: s_e = sum_q w_q |det J_q|
  * (lambda tr(eps)^2 + 2 mu eps:eps) = u_e^T K_e^0 u_e, d_dc[e] =
  * -p rho_e^(p-1) (E0 - Emin) s_e (d_dc may be NULL), d_c[0] = sum_e E(rho_e) s_e

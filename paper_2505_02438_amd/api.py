@@ -18,8 +18,8 @@ from ._lib import BF16_FP32ACC, FP32, FP64, REF_QUADRATURE, REF_SYMBOLIC, check,
 __all__ = ["Material", "Pattern", "FP64", "FP32", "BF16_FP32ACC", "REF_SYMBOLIC", "REF_QUADRATURE",
            "reference_tensor", "validate_mesh", "host_plan"]
 
-_DIM = {1: 2, 2: 2, 3: 3, 4: 3}
-_NEN = {1: 4, 2: 3, 3: 8, 4: 10}
+_DIM = {1: 2, 2: 2, 3: 3, 4: 3, 5: 3}
+_NEN = {1: 4, 2: 3, 3: 8, 4: 10, 5: 27}
 
 
 @dataclasses.dataclass

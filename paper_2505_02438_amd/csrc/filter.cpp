@@ -40,12 +40,13 @@ struct soptx_filter_s {
 
 namespace {
 
-// vertex (corner) nodes: Q1 quad 4, P1 triangle 3, Q1 hex 8, P2 tet 4
+// vertex (corner) nodes: Q1 quad 4, P1 triangle 3, Q1 hex 8, P2 tet 4, Q2 hex 8
+// (its nodes 0-7)
 int n_vertex(int elem) {
     switch (elem) {
     case SOPTX_QUAD4: return 4;
     case SOPTX_TRI3: return 3;
-    case SOPTX_HEX8: return 8;
+    case SOPTX_HEX8: case SOPTX_HEX27: return 8;
     case SOPTX_TET10: return 4;
     default: return -1;
     }
@@ -53,7 +54,9 @@ int n_vertex(int elem) {
 
 // Centroids (vertex mean, summed in local order) and measures: |det J| times
 // the reference measure for an affine map, sum_q w_q |det J_q| over the Gauss
-// points (exact for bilinear and trilinear maps) for a general Q1 element.
+// points (exact for bilinear and trilinear maps) for a general Q1 element,
+// and always for a Q2 hexahedron (3 x 3 x 3 points: det J has degree <= 5 in
+// each variable, so the rule is exact for curved cells too).
 void centroids_volumes(const soptx_mesh *m, std::vector<double> &c, std::vector<double> &v) {
     const int dim = m->dim, nen = elem_nen(m->elem), nv = n_vertex(m->elem);
     const int64_t n = m->n_cells;
@@ -64,7 +67,7 @@ void centroids_volumes(const soptx_mesh *m, std::vector<double> &c, std::vector<
     int def[3];
     double ref = 1.0;
     if (m->elem == SOPTX_QUAD4) { def[0] = 1; def[1] = 3; }
-    else if (m->elem == SOPTX_HEX8) { def[0] = 1; def[1] = 3; def[2] = 4; }
+    else if (m->elem == SOPTX_HEX8 || m->elem == SOPTX_HEX27) { def[0] = 1; def[1] = 3; def[2] = 4; }
     else { for (int a = 0; a < dim; a++) def[a] = a + 1; ref = dim == 2 ? 0.5 : 1.0 / 6.0; }
     for (int64_t e = 0; e < n; e++) {
         const int32_t *cell = m->cells + e * nen;
@@ -83,12 +86,12 @@ void centroids_volumes(const soptx_mesh *m, std::vector<double> &c, std::vector<
             det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
                   J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
         v[(size_t)e] = std::fabs(det) * ref;
-        if (m->elem != SOPTX_QUAD4 && m->elem != SOPTX_HEX8) continue;
+        if (m->elem != SOPTX_QUAD4 && m->elem != SOPTX_HEX8 && m->elem != SOPTX_HEX27) continue;
         // a Q1 cell whose map is not affine: integrate |det J| at the Gauss points
         double scale = 0.0;
         for (int a = 0; a < dim; a++)
             for (int b = 0; b < dim; b++) scale = std::max(scale, std::fabs(J[a][b]));
-        bool affine = true;
+        bool affine = m->elem != SOPTX_HEX27;
         for (int i = 0; i < nv && affine; i++)
             for (int a = 0; a < dim && affine; a++) {
                 double x = X(0, a);

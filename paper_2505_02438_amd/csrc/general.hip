@@ -291,6 +291,243 @@ __global__ __launch_bounds__(256) void k_energy_general(GenEnergyParams P) {
     }
 }
 
+// Elements with more node pairs than a block has threads (Q2 hexahedra: 729
+// pairs, 27 Gauss points): one element per block.  The block stages the
+// node coordinates, then J_q^-1 and w_q |det J_q| E at the points (a thread
+// per point), then every physical gradient g_k(xi_q) (a thread per (q, k)),
+// all in LDS; each thread forms the 3 x 3 blocks of node pairs tid, tid + 256,
+// ... with the same per-point sums as k_ke_general, and the element's matrix
+// is written out as one contiguous range.
+template <int NEN, int NQ>
+__global__ __launch_bounds__(256) void k_ke_general_wide(GenParams G) {
+    constexpr int DIM = 3, D2 = 9, NP = NEN * NEN;
+    __shared__ double sx[NEN * DIM];       // node coordinates
+    __shared__ double sg[NQ][D2 + 1];      // J_q^-1 (row m: d xi_m / d x), then w_q |det J_q| E
+    __shared__ double sp[NQ * NEN * DIM];  // physical gradients at the points, [q][k][a]
+    __shared__ double so[NP * D2];         // the element matrix
+    const int64_t e = blockIdx.x;
+    const int t = threadIdx.x;
+    for (int x = t; x < NEN * DIM; x += 256) sx[x] = G.coords[(int64_t)G.cells[e * NEN + x / DIM] * DIM + x % DIM];
+    __syncthreads();
+    if (t < NQ) {
+        const int q = t;
+        double J[DIM][DIM];
+#pragma unroll
+        for (int a = 0; a < DIM; a++)
+#pragma unroll
+            for (int m = 0; m < DIM; m++) J[a][m] = 0.0;
+        for (int k = 0; k < NEN; k++)
+#pragma unroll
+            for (int a = 0; a < DIM; a++) {
+                const double x = sx[k * DIM + a];
+#pragma unroll
+                for (int m = 0; m < DIM; m++) J[a][m] += x * G.qgrad[(q * NEN + k) * DIM + m];
+            }
+        const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+        const double c01 = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+        const double c02 = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+        const double c10 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+        const double c11 = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+        const double c12 = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+        const double c20 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+        const double c21 = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+        const double c22 = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        const double det = J[0][0] * c00 + J[0][1] * c10 + J[0][2] * c20;
+        const double id = 1.0 / det;
+        sg[q][0] = c00 * id; sg[q][1] = c01 * id; sg[q][2] = c02 * id;
+        sg[q][3] = c10 * id; sg[q][4] = c11 * id; sg[q][5] = c12 * id;
+        sg[q][6] = c20 * id; sg[q][7] = c21 * id; sg[q][8] = c22 * id;
+        sg[q][D2] = G.qw[q] * fabs(det) * simp_modulus(G.rho[e], G);
+    }
+    __syncthreads();
+    for (int x = t; x < NQ * NEN; x += 256) {
+        const int q = x / NEN, k = x % NEN;
+#pragma unroll
+        for (int a = 0; a < DIM; a++) {
+            double g = 0.0;
+#pragma unroll
+            for (int m = 0; m < DIM; m++) g += G.qgrad[(q * NEN + k) * DIM + m] * sg[q][m * DIM + a];
+            sp[x * DIM + a] = g;
+        }
+    }
+    __syncthreads();
+    for (int pr = t; pr < NP; pr += 256) {
+        const int i = pr / NEN, j = pr % NEN;
+        double blk[DIM][DIM];
+#pragma unroll
+        for (int a = 0; a < DIM; a++)
+#pragma unroll
+            for (int c = 0; c < DIM; c++) blk[a][c] = 0.0;
+        for (int q = 0; q < NQ; q++) {
+            double gi[DIM], gj[DIM];
+#pragma unroll
+            for (int a = 0; a < DIM; a++) {
+                gi[a] = sp[(q * NEN + i) * DIM + a];
+                gj[a] = sp[(q * NEN + j) * DIM + a];
+            }
+            double tr = 0.0;
+#pragma unroll
+            for (int a = 0; a < DIM; a++) tr += gi[a] * gj[a];
+            const double cq = sg[q][D2];
+#pragma unroll
+            for (int a = 0; a < DIM; a++)
+#pragma unroll
+                for (int c = 0; c < DIM; c++)
+                    blk[a][c] += cq * (G.lam * gi[a] * gj[c] + G.mu * gi[c] * gj[a] + (a == c ? G.mu * tr : 0.0));
+        }
+#pragma unroll
+        for (int a = 0; a < DIM; a++)
+#pragma unroll
+            for (int c = 0; c < DIM; c++) so[pr * D2 + a * DIM + c] = blk[a][c];
+    }
+    __syncthreads();
+    double *dst = G.ke + e * NP * D2;
+    for (int x = t; x < NP * D2; x += 256) __builtin_nontemporal_store(so[x], dst + x);
+}
+
+// Element energies of Q2 hexahedra: kEnergyWideElems elements per block, each
+// of the 4 waves takes kEnergyWideElems / 4 of them in turn.  Per element the
+// node coordinates and displacements go to LDS, lane q < NQ forms the
+// point's term w_q |det J_q| (lambda tr(eps)^2 + 2 mu eps:eps) with the same
+// arithmetic as k_energy_general, and lane 0 adds the terms in ascending q.
+// Block partials: the block's element terms E s_e in ascending element
+// order, and f^T u as in k_energy_general.
+template <int NEN, int NQ>
+__global__ __launch_bounds__(256) void k_energy_general_wide(GenEnergyParams P) {
+    constexpr int DIM = 3, EPB = kEnergyWideElems, PER_WAVE = EPB / 4;
+    __shared__ double red[256];
+    __shared__ double cp[EPB];
+    __shared__ double nx[4][NEN][2 * DIM];  // per wave: x then u of each node
+    __shared__ double sv[4][NQ];
+    const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+    for (int it = 0; it < PER_WAVE; it++) {
+        const int el = w * PER_WAVE + it;
+        const int64_t e = (int64_t)blockIdx.x * EPB + el;
+        const bool live = e < P.n_cells;
+        if (live && lane < NEN) {
+            const int64_t nd = P.cells[e * NEN + lane];
+#pragma unroll
+            for (int a = 0; a < DIM; a++) {
+                nx[w][lane][a] = P.coords[nd * DIM + a];
+                nx[w][lane][DIM + a] = P.u[nd * DIM + a];
+            }
+        }
+        __syncthreads();
+        if (live && lane < NQ) {
+            const int q = lane;
+            double J[DIM][DIM], Hr[DIM][DIM];
+#pragma unroll
+            for (int a = 0; a < DIM; a++)
+#pragma unroll
+                for (int m = 0; m < DIM; m++) J[a][m] = Hr[a][m] = 0.0;
+            for (int k = 0; k < NEN; k++)
+#pragma unroll
+                for (int m = 0; m < DIM; m++) {
+                    const double gm = P.qgrad[(q * NEN + k) * DIM + m];
+#pragma unroll
+                    for (int a = 0; a < DIM; a++) {
+                        J[a][m] += nx[w][k][a] * gm;
+                        Hr[a][m] += nx[w][k][DIM + a] * gm;
+                    }
+                }
+            const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+            const double c01 = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+            const double c02 = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+            const double c10 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+            const double c11 = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+            const double c12 = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+            const double c20 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+            const double c21 = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+            const double c22 = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+            const double det = J[0][0] * c00 + J[0][1] * c10 + J[0][2] * c20;
+            const double id = 1.0 / det;
+            const double inv[DIM][DIM] = {{c00 * id, c01 * id, c02 * id},
+                                          {c10 * id, c11 * id, c12 * id},
+                                          {c20 * id, c21 * id, c22 * id}};
+            double H[DIM][DIM];
+#pragma unroll
+            for (int a = 0; a < DIM; a++)
+#pragma unroll
+                for (int b = 0; b < DIM; b++) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int m = 0; m < DIM; m++) t += Hr[a][m] * inv[m][b];
+                    H[a][b] = t;
+                }
+            double tr = 0.0, ee = 0.0;
+#pragma unroll
+            for (int a = 0; a < DIM; a++) {
+                tr += H[a][a];
+#pragma unroll
+                for (int b = 0; b < DIM; b++) {
+                    const double eab = 0.5 * (H[a][b] + H[b][a]);
+                    ee += eab * eab;
+                }
+            }
+            sv[w][q] = P.qw[q] * fabs(det) * (P.lam * tr * tr + 2.0 * P.mu * ee);
+        }
+        __syncthreads();
+        if (lane == 0) {
+            double cpart = 0.0;
+            if (live) {
+                double s = 0.0;
+                for (int q = 0; q < NQ; q++) s += sv[w][q];
+                const double r = P.rho[e];
+                double rp1 = 1.0;  // rho^(p - 1)
+                if (P.ip >= 1) {
+                    for (int k = 0; k < P.ip - 1; k++) rp1 *= r;
+                } else {
+                    rp1 = general_pow(r, P.p - 1.0);
+                }
+                const double E = P.Emin + rp1 * r * (P.E0 - P.Emin);
+                if (P.dc) P.dc[e] = -P.p * rp1 * (P.E0 - P.Emin) * s;
+                cpart = E * s;
+            }
+            cp[el] = cpart;
+        }
+        // the next element's LDS writes come after the next barrier, which
+        // lane 0 reaches only once it has read sv
+    }
+    if (!P.partials) return;
+    double fpart = 0.0;
+    if (P.f)
+        for (int64_t rr = (int64_t)blockIdx.x * 256 + threadIdx.x; rr < P.ndof; rr += (int64_t)gridDim.x * 256)
+            fpart += P.f[rr] * P.u[rr];
+    red[threadIdx.x] = fpart;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double bc = 0.0;
+        for (int k = 0; k < EPB; k++) bc += cp[k];
+        P.partials[blockIdx.x] = bc;
+        P.partials[gridDim.x + blockIdx.x] = P.f ? red[0] : 0.0;
+    }
+}
+
+template <int NEN, int NQ>
+hipError_t launch_energy_wide(const GenEnergyParams &P, hipStream_t st) {
+    if (P.nq != NQ) return hipErrorInvalidValue;
+    const unsigned g = (unsigned)((P.n_cells + kEnergyWideElems - 1) / kEnergyWideElems);
+    hipLaunchKernelGGL((k_energy_general_wide<NEN, NQ>), dim3(g > 0 ? g : 1), dim3(256), 0, st, P);
+    return hipGetLastError();
+}
+
+template <int NEN, int NQ>
+hipError_t launch_wide(const GenParams &G, hipStream_t st) {
+    if (G.nq != NQ) return hipErrorInvalidValue;
+    if (G.n_cells > 0) {
+        hipLaunchKernelGGL((k_ke_general_wide<NEN, NQ>), dim3((unsigned)G.n_cells), dim3(256), 0, st, G);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (G.n_blocks > 0)
+        hipLaunchKernelGGL(k_gather_general<3>, dim3((unsigned)((G.n_blocks + 255) / 256)), dim3(256), 0, st, G);
+    return hipGetLastError();
+}
+
 template <int DIM, int NEN, int NQ>
 hipError_t launch_energy_t(const GenEnergyParams &P, hipStream_t st) {
     if (P.nq != NQ) return hipErrorInvalidValue;
@@ -318,12 +555,14 @@ hipError_t launch_t(const GenParams &G, hipStream_t st) {
 
 hipError_t launch_energy_general(int elem, const GenEnergyParams &P, hipStream_t st) {
     if (elem == SOPTX_HEX8) return launch_energy_t<3, 8, 8>(P, st);
+    if (elem == SOPTX_HEX27) return launch_energy_wide<27, 27>(P, st);
     if (elem == SOPTX_QUAD4) return launch_energy_t<2, 4, 4>(P, st);
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_assemble_general(int elem, const GenParams &G, hipStream_t st) {
     if (elem == SOPTX_HEX8) return launch_t<3, 8, 8>(G, st);
+    if (elem == SOPTX_HEX27) return launch_wide<27, 27>(G, st);
     if (elem == SOPTX_QUAD4) return launch_t<2, 4, 4>(G, st);
     return hipErrorInvalidValue;
 }

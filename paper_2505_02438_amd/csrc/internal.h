@@ -15,7 +15,7 @@ constexpr int kGroupElems = 160;   // distinct elements per group (staged in LDS
 constexpr int kMaxAdjacent = 32;   // elements around one node (slot table entries per node)
 constexpr int kStageBytes = 62208; // LDS for one group's row blocks (32 Q1-hex nodes x 243 values);
                                    // the assembly kernel holds two
-constexpr int kMaxNen = 10;
+constexpr int kMaxNen = 27;
 // fields per group in grp_info, and the flag bits of its last field
 constexpr int kGrpInfo = 6;
 constexpr int kGrpDiag = 1;  // every element of the group has a diagonal J^-1 (axis-aligned)
@@ -27,7 +27,7 @@ constexpr int kWideInts = 32;  // ints per wide work item: P, Q, T, 0 x 5, p[8],
 inline int elem_dim(int elem) {
     switch (elem) {
     case SOPTX_QUAD4: case SOPTX_TRI3: return 2;
-    case SOPTX_HEX8: case SOPTX_TET10: return 3;
+    case SOPTX_HEX8: case SOPTX_TET10: case SOPTX_HEX27: return 3;
     default: return -1;
     }
 }
@@ -37,11 +37,13 @@ inline int elem_nen(int elem) {
     case SOPTX_TRI3: return 3;
     case SOPTX_HEX8: return 8;
     case SOPTX_TET10: return 10;
+    case SOPTX_HEX27: return 27;
     default: return -1;
     }
 }
 
 int corner_bit(int elem, int i, int a);
+int lattice_index(int i, int a);
 void quadrature_rule(int elem, std::vector<double> &pts, std::vector<double> &wts);
 int reference_tensor(int elem, int method, double *M);
 int reference_qp_grads(int elem, std::vector<double> &wts, std::vector<double> &grads);

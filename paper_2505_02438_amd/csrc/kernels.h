@@ -120,6 +120,9 @@ struct GenParams {
     int64_t n_blocks;
 };
 hipError_t launch_assemble_general(int elem, const GenParams &G, hipStream_t st);
+// elements per block (and per c partial) of the Q2 hexahedron's energy kernel;
+// the other elements take 256
+constexpr int kEnergyWideElems = 16;
 // element energies with per-quadrature-point geometry: dc and block partials
 // of c and f^T u (as EnergyParams), FP64
 struct GenEnergyParams {

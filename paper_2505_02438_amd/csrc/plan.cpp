@@ -53,6 +53,40 @@ double inv_small(int dim, const double *J, double *G) {
     return d;
 }
 
+// ---- contribution table of the per-quadrature-point assembly: block b of
+// node n's neighbour q gets (e, i, j) for every element e holding both
+// nodes, in ascending e (the order of a sequential element loop)
+int general_table(const soptx_mesh *mesh, HostPlan &hp) {
+    const int dim = hp.dim, nen = hp.nen;
+    const int64_t NN = hp.n_nodes, NC = hp.n_cells;
+    const int32_t *cells = mesh->cells;
+    const int d2 = dim * dim;
+    const int64_t nblk = hp.nnz / d2;
+    if (NC * nen * nen >= INT32_MAX || nblk >= INT32_MAX) return SOPTX_E_OVERFLOW;
+    auto blk = [&](int64_t e, int i, int j) {
+        const int64_t I = cells[e * nen + i];
+        return (int64_t)hp.row_ptr[(size_t)(dim * I)] / d2 + hp.pos[((size_t)e * nen + i) * nen + j];
+    };
+    hp.gptr.assign((size_t)nblk + 1, 0);
+    for (int64_t e = 0; e < NC; e++)
+        for (int i = 0; i < nen; i++)
+            for (int j = 0; j < nen; j++) hp.gptr[(size_t)blk(e, i, j) + 1]++;
+    for (int64_t b = 0; b < nblk; b++) hp.gptr[(size_t)b + 1] += hp.gptr[(size_t)b];
+    hp.gent.assign((size_t)NC * nen * nen, 0);
+    std::vector<int32_t> fill(hp.gptr.begin(), hp.gptr.end() - 1);
+    for (int64_t e = 0; e < NC; e++)
+        for (int i = 0; i < nen; i++)
+            for (int j = 0; j < nen; j++)
+                hp.gent[(size_t)fill[(size_t)blk(e, i, j)]++] = (int32_t)((e * nen + i) * nen + j);
+    hp.gnode.assign((size_t)nblk, 0);
+    for (int64_t n = 0; n < NN; n++) {
+        const int64_t b0 = hp.row_ptr[(size_t)(dim * n)] / d2;
+        const int64_t deg = (hp.row_ptr[(size_t)(dim * n + 1)] - hp.row_ptr[(size_t)(dim * n)]) / dim;
+        for (int64_t q = 0; q < deg; q++) hp.gnode[(size_t)(b0 + q)] = (int32_t)n;
+    }
+    return SOPTX_OK;
+}
+
 }  // namespace
 
 int validate_mesh(const soptx_mesh *mesh, bool allow_nonaffine, bool *affine) {
@@ -60,11 +94,13 @@ int validate_mesh(const soptx_mesh *mesh, bool allow_nonaffine, bool *affine) {
     if (!mesh) return SOPTX_E_INVALID_ARG;
     const int dim = elem_dim(mesh->elem), nen = elem_nen(mesh->elem);
     if (dim < 0) return SOPTX_E_UNSUPPORTED_ELEM;
+    // Q2 hexahedra run only through the per-quadrature-point assembly
+    if (mesh->elem == SOPTX_HEX27 && !allow_nonaffine) return SOPTX_E_UNSUPPORTED_ELEM;
     if (mesh->dim != dim || mesh->n_nodes < 0 || mesh->n_cells < 0) return SOPTX_E_INVALID_ARG;
     if ((mesh->n_nodes > 0 && !mesh->coords) || (mesh->n_cells > 0 && !mesh->cells))
         return SOPTX_E_INVALID_ARG;
     if ((int64_t)dim * mesh->n_nodes >= INT32_MAX) return SOPTX_E_OVERFLOW;
-    if (mesh->n_cells >= INT32_MAX / kMaxNen) return SOPTX_E_OVERFLOW;
+    if (mesh->n_cells >= INT32_MAX / nen) return SOPTX_E_OVERFLOW;
     for (int64_t e = 0; e < mesh->n_cells; e++) {
         const int32_t *c = mesh->cells + e * nen;
         for (int i = 0; i < nen; i++) {
@@ -78,10 +114,10 @@ int validate_mesh(const soptx_mesh *mesh, bool allow_nonaffine, bool *affine) {
     for (int64_t e = 0; e < mesh->n_cells; e++) {
         const int32_t *c = mesh->cells + e * nen;
         auto X = [&](int i, int a) { return mesh->coords[(int64_t)c[i] * dim + a]; };
-        // map-defining nodes: Q1 quad 0,1,3; Q1 hex 0,1,3,4; simplices 0..dim
+        // map-defining nodes: Q1 quad 0,1,3; Q1 and Q2 hex 0,1,3,4; simplices 0..dim
         int def[3];
         if (mesh->elem == SOPTX_QUAD4) { def[0] = 1; def[1] = 3; }
-        else if (mesh->elem == SOPTX_HEX8) { def[0] = 1; def[1] = 3; def[2] = 4; }
+        else if (mesh->elem == SOPTX_HEX8 || mesh->elem == SOPTX_HEX27) { def[0] = 1; def[1] = 3; def[2] = 4; }
         else { for (int m = 0; m < dim; m++) def[m] = m + 1; }
         double J[9], G[9], scale = 0.0;
         for (int a = 0; a < dim; a++)
@@ -90,7 +126,8 @@ int validate_mesh(const soptx_mesh *mesh, bool allow_nonaffine, bool *affine) {
                 scale = std::max(scale, std::fabs(J[a * dim + m]));
             }
         double det = inv_small(dim, J, G);
-        const bool q1 = mesh->elem == SOPTX_QUAD4 || mesh->elem == SOPTX_HEX8;
+        // tensor-product elements may be general (Q1: not affine; Q2: curved)
+        const bool q1 = mesh->elem == SOPTX_QUAD4 || mesh->elem == SOPTX_HEX8 || mesh->elem == SOPTX_HEX27;
         if (!(allow_nonaffine && q1) && (!(det > 0.0) || !std::isfinite(det))) return SOPTX_E_JACOBIAN;
         // every node must sit at the affine image of its reference position
         const double tol = 1e-10 * scale;
@@ -99,6 +136,8 @@ int validate_mesh(const soptx_mesh *mesh, bool allow_nonaffine, bool *affine) {
             double xi[3] = {0, 0, 0};
             if (mesh->elem == SOPTX_QUAD4 || mesh->elem == SOPTX_HEX8) {
                 for (int m = 0; m < dim; m++) xi[m] = corner_bit(mesh->elem, i, m);
+            } else if (mesh->elem == SOPTX_HEX27) {
+                for (int m = 0; m < dim; m++) xi[m] = 0.5 * lattice_index(i, m);
             } else if (mesh->elem == SOPTX_TRI3) {
                 if (i > 0) xi[i - 1] = 1.0;
             } else {  // TET10: vertices then edge midpoints
@@ -117,9 +156,12 @@ int validate_mesh(const soptx_mesh *mesh, bool allow_nonaffine, bool *affine) {
                 if (std::fabs(x - X(i, a)) > tol) is_affine = false;
             }
         }
-        if (is_affine) continue;
+        // a Q2 hexahedron always takes the Gauss-point check (and never the
+        // affine-only calls)
+        if (mesh->elem == SOPTX_HEX27 && affine) *affine = false;
+        if (is_affine && mesh->elem != SOPTX_HEX27) continue;
         if (!(allow_nonaffine && q1)) return SOPTX_E_NONAFFINE;
-        // a general Q1 element: det J > 0 at every quadrature point
+        // a general element: det J > 0 at every quadrature point
         if (affine) *affine = false;
         if (qw.empty() && reference_qp_grads(mesh->elem, qw, qg)) return SOPTX_E_UNSUPPORTED_ELEM;
         for (size_t q = 0; q < qw.size(); q++) {
@@ -154,7 +196,7 @@ int build_host_plan(const soptx_mesh *mesh, HostPlan &hp, bool general) {
             const int32_t *c = cells + e * nen;
             int def[3];
             if (mesh->elem == SOPTX_QUAD4) { def[0] = 1; def[1] = 3; }
-            else if (mesh->elem == SOPTX_HEX8) { def[0] = 1; def[1] = 3; def[2] = 4; }
+            else if (mesh->elem == SOPTX_HEX8 || mesh->elem == SOPTX_HEX27) { def[0] = 1; def[1] = 3; def[2] = 4; }
             else { for (int m = 0; m < dim; m++) def[m] = m + 1; }
             double J[9], G[9];
             for (int a = 0; a < dim; a++)
@@ -248,6 +290,23 @@ int build_host_plan(const soptx_mesh *mesh, HostPlan &hp, bool general) {
                 hp.nb_tdeg[k] = (uint16_t)deg[J];
             }
     });
+
+    if (mesh->elem == SOPTX_HEX27) {
+        // only the per-quadrature-point assembly runs on these elements: the
+        // position table alone, no signatures or groups
+        hp.pos.assign((size_t)NC * nen * nen, 0);
+        parallel_for(NC, [&](int64_t a0, int64_t a1) {
+            for (int64_t e = a0; e < a1; e++)
+                for (int i = 0; i < nen; i++) {
+                    const int64_t I = cells[e * nen + i];
+                    const int32_t *nbn = nb.data() + nb_ptr[I];
+                    for (int j = 0; j < nen; j++)
+                        hp.pos[((size_t)e * nen + i) * nen + j] =
+                            (uint16_t)(std::lower_bound(nbn, nbn + deg[I], cells[e * nen + j]) - nbn);
+                }
+        });
+        return general_table(mesh, hp);
+    }
 
     // ---- signatures and the backward position table
     hp.pos.assign((size_t)NC * nen * nen, 0);
@@ -525,36 +584,7 @@ int build_host_plan(const soptx_mesh *mesh, HostPlan &hp, bool general) {
     if (hp.grp_elems.size() >= (size_t)INT32_MAX || hp.grp_n2l.size() >= (size_t)INT32_MAX)
         return SOPTX_E_OVERFLOW;
 
-    // ---- contribution table of the per-quadrature-point assembly: block b of
-    // node n's neighbour q gets (e, i, j) for every element e holding both
-    // nodes, in ascending e (the order of a sequential element loop)
-    if (general) {
-        const int d2 = dim * dim;
-        const int64_t nblk = hp.nnz / d2;
-        if (NC * nen * nen >= INT32_MAX || nblk >= INT32_MAX) return SOPTX_E_OVERFLOW;
-        auto blk = [&](int64_t e, int i, int j) {
-            const int64_t I = cells[e * nen + i];
-            return (int64_t)hp.row_ptr[(size_t)(dim * I)] / d2 + hp.pos[((size_t)e * nen + i) * nen + j];
-        };
-        hp.gptr.assign((size_t)nblk + 1, 0);
-        for (int64_t e = 0; e < NC; e++)
-            for (int i = 0; i < nen; i++)
-                for (int j = 0; j < nen; j++) hp.gptr[(size_t)blk(e, i, j) + 1]++;
-        for (int64_t b = 0; b < nblk; b++) hp.gptr[(size_t)b + 1] += hp.gptr[(size_t)b];
-        hp.gent.assign((size_t)NC * nen * nen, 0);
-        std::vector<int32_t> fill(hp.gptr.begin(), hp.gptr.end() - 1);
-        for (int64_t e = 0; e < NC; e++)
-            for (int i = 0; i < nen; i++)
-                for (int j = 0; j < nen; j++)
-                    hp.gent[(size_t)fill[(size_t)blk(e, i, j)]++] = (int32_t)((e * nen + i) * nen + j);
-        hp.gnode.assign((size_t)nblk, 0);
-        for (int64_t n = 0; n < NN; n++) {
-            const int64_t b0 = hp.row_ptr[(size_t)(dim * n)] / d2;
-            const int64_t deg = (hp.row_ptr[(size_t)(dim * n + 1)] - hp.row_ptr[(size_t)(dim * n)]) / dim;
-            for (int64_t q = 0; q < deg; q++) hp.gnode[(size_t)(b0 + q)] = (int32_t)n;
-        }
-    }
-    return SOPTX_OK;
+    return general ? general_table(mesh, hp) : SOPTX_OK;
 }
 
 }  // namespace soptx

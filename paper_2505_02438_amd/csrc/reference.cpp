@@ -110,6 +110,19 @@ std::vector<Poly> basis_polys(int elem) {
             }
             ph.push_back(p);
         }
+    } else if (elem == SOPTX_HEX27) {
+        // 1D quadratic Lagrange on {0, 1/2, 1}: (1-t)(1-2t), 4t(1-t), t(2t-1)
+        auto lag = [&](int k, int v) {
+            Poly t = pvar(v);
+            if (k == 0) return pmul(one_minus(v), padd(pconst(1), pscale(t, Rat(-2))));
+            if (k == 1) return pscale(pmul(t, one_minus(v)), Rat(4));
+            return pmul(t, padd(pscale(t, Rat(2)), pconst(-1)));
+        };
+        for (int i = 0; i < 27; i++) {
+            Poly p = pconst(1);
+            for (int a = 0; a < 3; a++) p = pmul(p, lag(lattice_index(i, a), a));
+            ph.push_back(p);
+        }
     } else if (elem == SOPTX_TRI3) {
         ph.push_back(padd(pconst(1), padd(pscale(pvar(0), Rat(-1)), pscale(pvar(1), Rat(-1)))));
         ph.push_back(pvar(0));
@@ -129,7 +142,8 @@ std::vector<Poly> basis_polys(int elem) {
 
 }  // namespace
 
-// corner (0/1) of node i of a Q1 element along axis a
+// corner (0/1) of node i of a Q1 element along axis a (Q2 hexahedra: the
+// same for their corner nodes 0-7)
 int corner_bit(int elem, int i, int a) {
     static const int Q[4][2] = {{0, 0}, {1, 0}, {1, 1}, {0, 1}};
     static const int H[8][3] = {{0, 0, 0}, {1, 0, 0}, {1, 1, 0}, {0, 1, 0},
@@ -137,8 +151,29 @@ int corner_bit(int elem, int i, int a) {
     return elem == SOPTX_QUAD4 ? Q[i][a] : H[i][a];
 }
 
+// lattice index (0, 1, 2: reference coordinate 0, 1/2, 1) of node i of the Q2
+// hexahedron along axis a: corners 0-7 as for Q1, then the other 19 lattice
+// points in ascending a + 3b + 9c
+int lattice_index(int i, int a) {
+    struct Table { int v[27][3]; };
+    static const Table L = [] {  // built once, thread-safe
+        Table t{};
+        for (int k = 0; k < 8; k++)
+            for (int m = 0; m < 3; m++) t.v[k][m] = 2 * corner_bit(SOPTX_HEX8, k, m);
+        int n = 8;
+        for (int z = 0; z < 3; z++)
+            for (int y = 0; y < 3; y++)
+                for (int x = 0; x < 3; x++)
+                    if (x == 1 || y == 1 || z == 1) { t.v[n][0] = x; t.v[n][1] = y; t.v[n][2] = z; n++; }
+        return t;
+    }();
+    return L.v[i][a];
+}
+
 // ----------------------------------------------------------- quadrature rules
-// Gauss 2-point per axis on [0,1] for Q1 (exact to degree 3 per variable);
+// Gauss 2-point per axis on [0,1] for Q1 (exact to degree 3 per variable),
+// 3-point for Q2 hexahedra (1/2 -+ sqrt(3/5)/2 and 1/2, weights 5/18, 8/18,
+// 5/18: exact to degree 5 per variable);
 // centroid rule for P1 (gradients are constant); the symmetric 4-point rule of
 // degree 2 for P2 tetrahedra (barycentric (a,b,b,b), a = (5+3 sqrt5)/20,
 // b = (5-sqrt5)/20, weight 1/24 each).
@@ -160,6 +195,17 @@ void quadrature_rule(int elem, std::vector<double> &pts, std::vector<double> &wt
                     wts.push_back(0.125);
                 }
         break;
+    case SOPTX_HEX27: {
+        const double h[3] = {0.5 - 0.5 * std::sqrt(0.6), 0.5, 0.5 + 0.5 * std::sqrt(0.6)};
+        const double w[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++)
+                for (int c = 0; c < 3; c++) {
+                    pts.push_back(h[a]); pts.push_back(h[b]); pts.push_back(h[c]);
+                    wts.push_back(w[a] * w[b] * w[c]);
+                }
+        break;
+    }
     case SOPTX_TRI3:
         pts.push_back(1.0 / 3.0); pts.push_back(1.0 / 3.0); wts.push_back(0.5);
         break;

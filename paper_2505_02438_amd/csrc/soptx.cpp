@@ -97,6 +97,11 @@ void free_handle(soptx_pattern_s *h) {
     delete h;
 }
 
+// the code an affine-only call returns on a handle with general elements
+int not_affine(const soptx_pattern_s *h) {
+    return h->elem == SOPTX_HEX27 ? SOPTX_E_UNSUPPORTED_ELEM : SOPTX_E_NONAFFINE;
+}
+
 int check_material(const soptx_material *m) {
     if (!m) return SOPTX_E_INVALID_ARG;
     if (!(m->E0 > m->Emin) || !(m->Emin >= 0.0) || !(m->nu > -1.0 && m->nu < 0.5) || !(m->p >= 1.0) ||
@@ -198,6 +203,8 @@ static int build_pattern(const soptx_mesh *mesh, int32_t ref_method, bool genera
             for (int i = 0; i < nen; i++) {
                 if (hp.elem == SOPTX_QUAD4 || hp.elem == SOPTX_HEX8) {
                     for (int m = 0; m < dim; m++) xref[i * dim + m] = corner_bit(hp.elem, i, m);
+                } else if (hp.elem == SOPTX_HEX27) {
+                    for (int m = 0; m < dim; m++) xref[i * dim + m] = 0.5 * lattice_index(i, m);
                 } else if (hp.elem == SOPTX_TRI3) {
                     if (i > 0) xref[i * dim + i - 1] = 1.0;
                 } else {
@@ -278,7 +285,7 @@ int soptx_assemble_general(soptx_pattern h, const soptx_material *m, const doubl
     if (rc) return rc;
     if ((h->n_cells > 0 && !d_rho) || (h->nnz > 0 && !d_K_vals)) return SOPTX_E_INVALID_ARG;
     if (h->nnz == 0) return SOPTX_OK;
-    if (h->elem != SOPTX_QUAD4 && h->elem != SOPTX_HEX8) return SOPTX_E_UNSUPPORTED_ELEM;
+    if (h->elem != SOPTX_QUAD4 && h->elem != SOPTX_HEX8 && h->elem != SOPTX_HEX27) return SOPTX_E_UNSUPPORTED_ELEM;
     DeviceGuard dg(h->device);
     if (!dg.ok) return SOPTX_E_DEVICE;
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -331,7 +338,7 @@ int soptx_pattern_stats_get(soptx_pattern h, soptx_pattern_stats *out) {
 int soptx_assemble(soptx_pattern h, const soptx_material *m, const void *d_rho, const uint8_t *d_dirichlet,
                    double *d_K_vals, int32_t prec, void *stream) {
     if (!h || !valid_prec(prec)) return SOPTX_E_INVALID_ARG;
-    if (!h->affine) return SOPTX_E_NONAFFINE;
+    if (!h->affine) return not_affine(h);
     int rc = check_material(m);
     if (rc) return rc;
     if ((h->n_cells > 0 && !d_rho) || (h->nnz > 0 && !d_K_vals)) return SOPTX_E_INVALID_ARG;
@@ -462,7 +469,7 @@ int soptx_pcg(soptx_pattern h, const double *d_K_vals, const double *d_f, double
 int soptx_evaluate(soptx_pattern h, const soptx_material *m, const void *d_rho, const double *d_u,
                    const double *d_f, void *d_dc, double *d_c, int32_t prec, void *stream) {
     if (!h || !valid_prec(prec)) return SOPTX_E_INVALID_ARG;
-    if (!h->affine) return SOPTX_E_NONAFFINE;
+    if (!h->affine) return not_affine(h);
     int rc = check_material(m);
     if (rc) return rc;
     if (h->n_cells > 0 && (!d_rho || !d_u)) return SOPTX_E_INVALID_ARG;
@@ -498,11 +505,12 @@ int soptx_evaluate_general(soptx_pattern h, const soptx_material *m, const doubl
     if (rc) return rc;
     if (h->n_cells > 0 && (!d_rho || !d_u)) return SOPTX_E_INVALID_ARG;
     if (!d_dc && !d_c) return SOPTX_E_INVALID_ARG;
-    if (h->elem != SOPTX_QUAD4 && h->elem != SOPTX_HEX8) return SOPTX_E_UNSUPPORTED_ELEM;
+    if (h->elem != SOPTX_QUAD4 && h->elem != SOPTX_HEX8 && h->elem != SOPTX_HEX27) return SOPTX_E_UNSUPPORTED_ELEM;
     DeviceGuard dg(h->device);
     if (!dg.ok) return SOPTX_E_DEVICE;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const int nblk = std::max(1, (int)((h->n_cells + 255) / 256));
+    const int per = h->elem == SOPTX_HEX27 ? kEnergyWideElems : 256;  // elements per partial
+    const int nblk = std::max(1, (int)((h->n_cells + per - 1) / per));
     double *ws = nullptr;
     if (d_c) {
         rc = get_workspace(h->device, st, 2 * (size_t)nblk, &ws, 0);
@@ -521,7 +529,7 @@ int soptx_evaluate_general(soptx_pattern h, const soptx_material *m, const doubl
 int soptx_sensitivity(soptx_pattern h, const soptx_material *m, const void *d_rho, const double *d_u,
                       void *d_dc, int32_t prec, void *stream) {
     if (h && h->n_cells > 0 && !d_dc) return SOPTX_E_INVALID_ARG;
-    if (h && !h->affine) return SOPTX_E_NONAFFINE;
+    if (h && !h->affine) return not_affine(h);
     if (h && h->n_cells == 0) return (h && valid_prec(prec) && check_material(m) == 0) ? SOPTX_OK : SOPTX_E_INVALID_ARG;
     return soptx_evaluate(h, m, d_rho, d_u, nullptr, d_dc, nullptr, prec, stream);
 }
@@ -536,7 +544,7 @@ int soptx_assemble_backward(soptx_pattern h, const soptx_material *m, const void
                             const uint8_t *d_dirichlet, const double *d_Kbar, void *d_drho, int32_t prec,
                             void *stream) {
     if (!h || !valid_prec(prec)) return SOPTX_E_INVALID_ARG;
-    if (!h->affine) return SOPTX_E_NONAFFINE;
+    if (!h->affine) return not_affine(h);
     int rc = check_material(m);
     if (rc) return rc;
     if (h->n_cells > 0 && (!d_rho || !d_Kbar || !d_drho)) return SOPTX_E_INVALID_ARG;

@@ -149,12 +149,14 @@ def test_heaviside_beta_continuation():
         api.heaviside_beta(-1)
 
 
-@pytest.mark.parametrize("elem", [I.QUAD4, I.HEX8])
+@pytest.mark.parametrize("elem", [I.QUAD4, I.HEX8, I.HEX27])
 def test_filter_on_general_q1(elem):
-    """Non-affine Q1 cells are accepted; their measures are the Gauss-rule
-    integral of |det J| (the oracle's definition) and tile the box."""
-    m0 = I.quad_grid(9, 7) if elem == I.QUAD4 else I.hex_grid(4, 3, 3)
-    m = I.jitter_interior(m0, 0.3, np.random.default_rng(2))
+    """Non-affine Q1 cells and curved Q2 hexahedra are accepted; their
+    measures are the Gauss-rule integral of |det J| (the oracle's definition)
+    and tile the box; centroids are the means of the corner nodes."""
+    m0 = {I.QUAD4: lambda: I.quad_grid(9, 7), I.HEX8: lambda: I.hex_grid(4, 3, 3),
+          I.HEX27: lambda: I.hex27_grid(4, 3, 3)}[elem]()
+    m = I.jitter_interior(m0, 0.12 if elem == I.HEX27 else 0.3, np.random.default_rng(2))
     hh = api.filter_matrix_host(m.elem, m.coords, m.cells, 1.6)
     v = OF.volumes(elem, m.coords, m.cells)
     np.testing.assert_allclose(hh["vol"], v, rtol=1e-14)

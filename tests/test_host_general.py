@@ -11,14 +11,16 @@ from paper_2505_02438_amd import _lib, api
 from paper_2505_02438_amd import inputs as I
 
 
-@pytest.mark.parametrize("elem", [I.QUAD4, I.HEX8])
+@pytest.mark.parametrize("elem", [I.QUAD4, I.HEX8, I.HEX27])
 def test_contribution_table(elem):
     rng = np.random.default_rng(3)
-    m0 = I.quad_grid(6, 5) if elem == I.QUAD4 else I.hex_grid(4, 3, 3)
-    m = I.jitter_interior(m0, 0.3, rng)
+    m0 = {I.QUAD4: lambda: I.quad_grid(6, 5), I.HEX8: lambda: I.hex_grid(4, 3, 3),
+          I.HEX27: lambda: I.hex27_grid(2, 2, 1)}[elem]()
+    m = I.jitter_interior(m0, 0.12 if elem == I.HEX27 else 0.3, rng)
     with pytest.raises(_lib.SoptxError) as e:
         api.host_plan(m.elem, m.coords, m.cells)
-    assert e.value.code == -5
+    # Q2 hexahedra are refused by the affine-only build even when straight
+    assert e.value.code == (-2 if elem == I.HEX27 else -5)
     hp = api.host_plan(m.elem, m.coords, m.cells, general=True)
     rp, ci = O.pattern(elem, m.n_nodes, m.cells)
     np.testing.assert_array_equal(hp["row_ptr"], rp)
@@ -54,3 +56,30 @@ def test_inverted_cell_rejected():
     with pytest.raises(_lib.SoptxError) as e:
         api.host_plan(I.TET10, x, pr.mesh.cells, general=True)
     assert e.value.code == -5
+
+
+def test_hex27_host_checks():
+    """Q2 hexahedra: the affine-only validation refuses them (straight or
+    not); the general build takes straight and curved cells, refuses a cell
+    whose det J turns negative at a Gauss point; the exact reference tensor
+    equals the 3 x 3 x 3 Gauss rule's (exact for these integrands) to rounding."""
+    m = I.hex27_grid(2, 1, 1)
+    assert api.validate_mesh(m.elem, m.coords, m.cells) == -2
+    hp = api.host_plan(m.elem, m.coords, m.cells, general=True)
+    rp, ci = O.pattern(m.elem, m.n_nodes, m.cells)
+    np.testing.assert_array_equal(hp["row_ptr"], rp)
+    np.testing.assert_array_equal(hp["col_idx"], ci)
+    assert len(ci) == 9 * 17 * 9 * 9
+    # the centre node of element 0 pushed through a face: inverted near that face
+    c = m.coords.copy()
+    centre = m.cells[0, I._HEX27_LATTICE.index((1, 1, 1))]
+    assert np.allclose(c[centre], [0.5, 0.5, 0.5])
+    c[centre] = [0.5, 0.5, 1.4]
+    with pytest.raises(_lib.SoptxError) as e:
+        api.host_plan(m.elem, c, m.cells, general=True)
+    assert e.value.code == -4
+    Ms = api.reference_tensor(I.HEX27, api.REF_SYMBOLIC)
+    Mq = api.reference_tensor(I.HEX27, api.REF_QUADRATURE)
+    assert Ms.shape == (27, 27, 3, 3)
+    assert np.abs(Ms - Mq).max() <= 1e-14 * np.abs(Ms).max()
+    assert np.abs(Ms - np.transpose(Ms, (1, 0, 3, 2))).max() == 0.0
