@@ -3,13 +3,14 @@
 // affine, where the separated form of the fast assembly does not hold).
 //
 // k_ke_general: the blocks of every element's matrix,
-//     Ke[i][j] = E(rho_e) sum_q w_q |det J_q| L(g_i g_j^T),  g_k = J_q^-T grad phi_k(xi_q),
-//     L(A) = lambda A + mu A^T + mu tr(A) I,
-// with one thread per node pair of an element (NEN^2 threads per element: a
-// wave per hexahedron, 16 lanes per quadrilateral).  The first NQ threads of an element
-// form J_q^-1 and w_q |det J_q| E at the quadrature points in LDS; every
-// thread accumulates its DIM x DIM block, and the block's elements are
-// written out as one contiguous range.
+//     Ke[i][j] = E(rho_e) sum_q w_q |det J_q| L(g_i g_j^T) = L(P_ij),
+//     P_ij = sum_q c_q g_i g_j^T,  c_q = w_q |det J_q| E(rho_e),
+//     g_k = J_q^-T grad phi_k(xi_q),  L(A) = lambda A + mu A^T + mu tr(A) I
+// (L is linear, so the per-point sum is taken on P), with one thread per
+// node pair i <= j of an element (36 per hexahedron, 10 per quadrilateral);
+// block (j, i) is the transpose of block (i, j), so Ke is exactly symmetric.
+// The first NQ threads of an element form J_q^-1 and c_q in LDS, and the
+// elements of a block are written out as one contiguous range.
 // k_energy_general: element energies, sensitivities and the compliance
 // partials with the same per-point geometry.
 // k_gather_general: one thread per DIM x DIM block of K adds its element
@@ -42,14 +43,16 @@ __device__ __forceinline__ double simp_modulus(double r, const GenParams &G) {
 
 template <int DIM, int NEN, int NQ>
 __global__ __launch_bounds__(256) void k_ke_general(GenParams G) {
-    constexpr int NP = NEN * NEN;            // threads per element
-    constexpr int EPB = 256 / NP;            // elements per block
+    constexpr int NP = NEN * NEN;            // blocks per element
+    constexpr int NU = NEN * (NEN + 1) / 2;  // threads per element: pairs i <= j
+    constexpr int EPB = 256 / NU;            // elements per block
     constexpr int D2 = DIM * DIM;
+    static_assert(NQ <= NU, "the Jacobians take one thread per point");
     __shared__ double sg[EPB][NQ][D2 + 1];  // J_q^-1 (row m: d xi_m / d x), then w_q |det J_q| E
     __shared__ double sq[NQ * NEN * DIM];   // reference gradients at the quadrature points
     __shared__ double so[EPB * NP * D2];    // the block's element matrices, written out contiguously
     for (int x = threadIdx.x; x < NQ * NEN * DIM; x += 256) sq[x] = G.qgrad[x];
-    const int le = threadIdx.x / NP, pr = threadIdx.x % NP;
+    const int le = threadIdx.x / NU, pr = threadIdx.x % NU;
     const int64_t e = (int64_t)blockIdx.x * EPB + le;
     const bool live = le < EPB && e < G.n_cells;
     __syncthreads();
@@ -100,42 +103,49 @@ __global__ __launch_bounds__(256) void k_ke_general(GenParams G) {
         sg[le][q][D2] = G.qw[q] * fabs(det) * simp_modulus(G.rho[e], G);
     }
     __syncthreads();
-    const int i = pr / NEN, j = pr % NEN;
-    double blk[DIM][DIM];
+    // pair index -> (i, j), i <= j, rows of the upper triangle in order
+    int i = 0, r = pr;
+    while (r >= NEN - i) { r -= NEN - i; i++; }
+    const int j = i + r;
+    double P[DIM][DIM];
 #pragma unroll
     for (int a = 0; a < DIM; a++)
 #pragma unroll
-        for (int c = 0; c < DIM; c++) blk[a][c] = 0.0;
+        for (int c = 0; c < DIM; c++) P[a][c] = 0.0;
+    if (live) {
 #pragma unroll
-    for (int q = 0; q < NQ; q++) {
-        double gi[DIM], gj[DIM];
+        for (int q = 0; q < NQ; q++) {
+            double gi[DIM], gj[DIM];
 #pragma unroll
-        for (int a = 0; a < DIM; a++) {
-            double si = 0.0, sj = 0.0;
+            for (int a = 0; a < DIM; a++) {
+                double si = 0.0, sj = 0.0;
 #pragma unroll
-            for (int m = 0; m < DIM; m++) {
-                const double gm = sg[le][q][m * DIM + a];
-                si += sq[(q * NEN + i) * DIM + m] * gm;
-                sj += sq[(q * NEN + j) * DIM + m] * gm;
+                for (int m = 0; m < DIM; m++) {
+                    const double gm = sg[le][q][m * DIM + a];
+                    si += sq[(q * NEN + i) * DIM + m] * gm;
+                    sj += sq[(q * NEN + j) * DIM + m] * gm;
+                }
+                gi[a] = sg[le][q][D2] * si;
+                gj[a] = sj;
             }
-            gi[a] = si;
-            gj[a] = sj;
+#pragma unroll
+            for (int a = 0; a < DIM; a++)
+#pragma unroll
+                for (int c = 0; c < DIM; c++) P[a][c] += gi[a] * gj[c];
         }
         double tr = 0.0;
 #pragma unroll
-        for (int a = 0; a < DIM; a++) tr += gi[a] * gj[a];
-        const double cq = sg[le][q][D2];
+        for (int a = 0; a < DIM; a++) tr += P[a][a];
+        double *o = so + le * NP * D2;
 #pragma unroll
         for (int a = 0; a < DIM; a++)
 #pragma unroll
-            for (int c = 0; c < DIM; c++)
-                blk[a][c] += cq * (G.lam * gi[a] * gj[c] + G.mu * gi[c] * gj[a] + (a == c ? G.mu * tr : 0.0));
+            for (int c = 0; c < DIM; c++) {
+                const double b = G.lam * P[a][c] + G.mu * P[c][a] + (a == c ? G.mu * tr : 0.0);
+                o[(i * NEN + j) * D2 + a * DIM + c] = b;
+                if (i != j) o[(j * NEN + i) * D2 + c * DIM + a] = b;
+            }
     }
-    double *o = so + (le * NP + pr) * D2;
-#pragma unroll
-    for (int a = 0; a < DIM; a++)
-#pragma unroll
-        for (int c = 0; c < DIM; c++) o[a * DIM + c] = blk[a][c];
     __syncthreads();
     // the block's elements are consecutive: one contiguous range of ke
     const int64_t e0 = (int64_t)blockIdx.x * EPB;
@@ -293,46 +303,49 @@ __global__ __launch_bounds__(256) void k_energy_general(GenEnergyParams P) {
 
 // Elements with more node pairs than a block has threads (Q2 hexahedra: 729
 // pairs, 27 Gauss points): one element per block.  The block stages the
-// node coordinates, then J_q^-1 and w_q |det J_q| E at the points (a thread
-// per point), then every physical gradient g_k(xi_q) (a thread per (q, k)),
-// all in LDS; each thread forms the 3 x 3 blocks of node pairs tid, tid + 256,
-// ... with the same per-point sums as k_ke_general, and the element's matrix
-// is written out as one contiguous range.
+// node coordinates, then J at the points (a thread per entry), J_q^-1 and
+// c_q = w_q |det J_q| E (a thread per point), then every physical gradient
+// g_k(xi_q) (a thread per (q, k)), all in LDS.  A thread per two neighbouring
+// node pairs (i, j), (i, j + 1), i <= j, of the upper triangle (196 threads
+// for a Q2 hexahedron; g_i is read once for both) accumulates
+// P = sum_q c_q g_i g_j^T and forms the block
+//     lambda P + mu P^T + mu tr(P) I
+// (the same sum as k_ke_general's per-point form, regrouped); block (j, i)
+// is its transpose, so the element matrix is exactly symmetric.  The
+// element's matrix is written out as one contiguous range.
 template <int NEN, int NQ>
 __global__ __launch_bounds__(256) void k_ke_general_wide(GenParams G) {
-    constexpr int DIM = 3, D2 = 9, NP = NEN * NEN;
+    constexpr int DIM = 3, D2 = 9, NP = NEN * NEN, NU = NEN * (NEN + 1) / 2;
+    static_assert(NQ * D2 <= 256 && NQ <= 256, "one thread per Jacobian entry");
     __shared__ double sx[NEN * DIM];       // node coordinates
-    __shared__ double sg[NQ][D2 + 1];      // J_q^-1 (row m: d xi_m / d x), then w_q |det J_q| E
+    __shared__ double sJ[NQ * D2];         // J_q, entry (a, m) = d x_a / d xi_m
+    __shared__ double sg[NQ][D2 + 1];      // J_q^-1 (row m: d xi_m / d x), then c_q
     __shared__ double sp[NQ * NEN * DIM];  // physical gradients at the points, [q][k][a]
     __shared__ double so[NP * D2];         // the element matrix
     const int64_t e = blockIdx.x;
     const int t = threadIdx.x;
     for (int x = t; x < NEN * DIM; x += 256) sx[x] = G.coords[(int64_t)G.cells[e * NEN + x / DIM] * DIM + x % DIM];
     __syncthreads();
+    if (t < NQ * D2) {
+        const int q = t / D2, a = (t % D2) / DIM, m = t % DIM;
+        double s = 0.0;
+        for (int k = 0; k < NEN; k++) s += sx[k * DIM + a] * G.qgrad[(q * NEN + k) * DIM + m];
+        sJ[t] = s;
+    }
+    __syncthreads();
     if (t < NQ) {
         const int q = t;
-        double J[DIM][DIM];
-#pragma unroll
-        for (int a = 0; a < DIM; a++)
-#pragma unroll
-            for (int m = 0; m < DIM; m++) J[a][m] = 0.0;
-        for (int k = 0; k < NEN; k++)
-#pragma unroll
-            for (int a = 0; a < DIM; a++) {
-                const double x = sx[k * DIM + a];
-#pragma unroll
-                for (int m = 0; m < DIM; m++) J[a][m] += x * G.qgrad[(q * NEN + k) * DIM + m];
-            }
-        const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
-        const double c01 = J[0][2] * J[2][1] - J[0][1] * J[2][2];
-        const double c02 = J[0][1] * J[1][2] - J[0][2] * J[1][1];
-        const double c10 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
-        const double c11 = J[0][0] * J[2][2] - J[0][2] * J[2][0];
-        const double c12 = J[0][2] * J[1][0] - J[0][0] * J[1][2];
-        const double c20 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-        const double c21 = J[0][1] * J[2][0] - J[0][0] * J[2][1];
-        const double c22 = J[0][0] * J[1][1] - J[0][1] * J[1][0];
-        const double det = J[0][0] * c00 + J[0][1] * c10 + J[0][2] * c20;
+        const double *J = sJ + q * D2;  // J[a * 3 + m]
+        const double c00 = J[4] * J[8] - J[5] * J[7];
+        const double c01 = J[2] * J[7] - J[1] * J[8];
+        const double c02 = J[1] * J[5] - J[2] * J[4];
+        const double c10 = J[5] * J[6] - J[3] * J[8];
+        const double c11 = J[0] * J[8] - J[2] * J[6];
+        const double c12 = J[2] * J[3] - J[0] * J[5];
+        const double c20 = J[3] * J[7] - J[4] * J[6];
+        const double c21 = J[1] * J[6] - J[0] * J[7];
+        const double c22 = J[0] * J[4] - J[1] * J[3];
+        const double det = J[0] * c00 + J[1] * c10 + J[2] * c20;
         const double id = 1.0 / det;
         sg[q][0] = c00 * id; sg[q][1] = c01 * id; sg[q][2] = c02 * id;
         sg[q][3] = c10 * id; sg[q][4] = c11 * id; sg[q][5] = c12 * id;
@@ -351,34 +364,52 @@ __global__ __launch_bounds__(256) void k_ke_general_wide(GenParams G) {
         }
     }
     __syncthreads();
-    for (int pr = t; pr < NP; pr += 256) {
-        const int i = pr / NEN, j = pr % NEN;
-        double blk[DIM][DIM];
+    int ns = 0;  // strips of two neighbouring pairs (i, j), (i, j + 1) in the upper triangle
+    for (int r = 0; r < NEN; r++) ns += (NEN - r + 1) / 2;
+    for (int pu = t; pu < ns; pu += 256) {
+        int i = 0, r = pu;
+        while (r >= (NEN - i + 1) / 2) { r -= (NEN - i + 1) / 2; i++; }
+        const int j0 = i + 2 * r;
+        const bool two = j0 + 1 < NEN;
+        const int j1 = two ? j0 + 1 : j0;
+        double P0[DIM][DIM], P1[DIM][DIM];
 #pragma unroll
         for (int a = 0; a < DIM; a++)
 #pragma unroll
-            for (int c = 0; c < DIM; c++) blk[a][c] = 0.0;
+            for (int c = 0; c < DIM; c++) P0[a][c] = P1[a][c] = 0.0;
+#pragma unroll 3
         for (int q = 0; q < NQ; q++) {
-            double gi[DIM], gj[DIM];
+            const double cq = sg[q][D2];
+            double wi[DIM], g0[DIM], g1[DIM];
 #pragma unroll
             for (int a = 0; a < DIM; a++) {
-                gi[a] = sp[(q * NEN + i) * DIM + a];
-                gj[a] = sp[(q * NEN + j) * DIM + a];
+                wi[a] = cq * sp[(q * NEN + i) * DIM + a];
+                g0[a] = sp[(q * NEN + j0) * DIM + a];
+                g1[a] = sp[(q * NEN + j1) * DIM + a];
             }
-            double tr = 0.0;
-#pragma unroll
-            for (int a = 0; a < DIM; a++) tr += gi[a] * gj[a];
-            const double cq = sg[q][D2];
 #pragma unroll
             for (int a = 0; a < DIM; a++)
 #pragma unroll
-                for (int c = 0; c < DIM; c++)
-                    blk[a][c] += cq * (G.lam * gi[a] * gj[c] + G.mu * gi[c] * gj[a] + (a == c ? G.mu * tr : 0.0));
+                for (int c = 0; c < DIM; c++) {
+                    P0[a][c] += wi[a] * g0[c];
+                    P1[a][c] += wi[a] * g1[c];
+                }
         }
 #pragma unroll
-        for (int a = 0; a < DIM; a++)
+        for (int h = 0; h < 2; h++) {
+            if (h == 1 && !two) break;
+            const int j = h ? j1 : j0;
+            double (*P)[DIM] = h ? P1 : P0;
+            const double mtr = G.mu * (P[0][0] + P[1][1] + P[2][2]);
 #pragma unroll
-            for (int c = 0; c < DIM; c++) so[pr * D2 + a * DIM + c] = blk[a][c];
+            for (int a = 0; a < DIM; a++)
+#pragma unroll
+                for (int c = 0; c < DIM; c++) {
+                    const double b = G.lam * P[a][c] + G.mu * P[c][a] + (a == c ? mtr : 0.0);
+                    so[(i * NEN + j) * D2 + a * DIM + c] = b;
+                    if (i != j) so[(j * NEN + i) * D2 + c * DIM + a] = b;
+                }
+        }
     }
     __syncthreads();
     double *dst = G.ke + e * NP * D2;
@@ -538,7 +569,7 @@ hipError_t launch_energy_t(const GenEnergyParams &P, hipStream_t st) {
 
 template <int DIM, int NEN, int NQ>
 hipError_t launch_t(const GenParams &G, hipStream_t st) {
-    constexpr int EPB = 256 / (NEN * NEN);
+    constexpr int EPB = 256 / (NEN * (NEN + 1) / 2);
     if (G.nq != NQ) return hipErrorInvalidValue;
     if (G.n_cells > 0) {
         hipLaunchKernelGGL((k_ke_general<DIM, NEN, NQ>), dim3((unsigned)((G.n_cells + EPB - 1) / EPB)), dim3(256), 0,
