@@ -169,3 +169,30 @@ def test_hex27_optimisation_iterations_match_oracle():
         print(f"iteration {it}: c {res.compliance[it]:.10f} / {co:.10f}")
         assert abs(res.compliance[it] - co) <= 1e-8 * co
     assert float(np.max(np.abs(host(res.rho) - rho))) <= 1e-6
+
+
+def test_hex27_degenerate_meshes():
+    """No cells and no nodes; nodes but no cells (c = [0, f^T u]); one element
+    beside an isolated node (its rows empty, the rest as the oracle)."""
+    mat = api.Material()
+    pat = api.Pattern(H27, np.zeros((0, 3)), np.zeros((0, 27), dtype=np.int32), general=True)
+    assert pat.nnz == 0 and pat.ndof == 0
+    z = torch.zeros(0, dtype=torch.float64, device="cuda:0")
+    pat.assemble_general(mat, z, out=torch.zeros(0, dtype=torch.float64, device="cuda:0"))
+    _, c = pat.evaluate_general(mat, z, z, f=z)
+    assert np.array_equal(host(c), [0.0, 0.0])
+    x = np.random.default_rng(75).standard_normal((5, 3))
+    pat = api.Pattern(H27, x, np.zeros((0, 27), dtype=np.int32), general=True)
+    assert pat.nnz == 0 and pat.ndof == 15
+    u, f = np.arange(15.0), np.linspace(-1, 1, 15)
+    _, c = pat.evaluate_general(mat, z, dev(u), f=dev(f))
+    assert host(c)[0] == 0.0 and abs(host(c)[1] - f @ u) <= 1e-13 * np.abs(f) @ np.abs(u)
+    m = I.hex27_grid(1, 1, 1)
+    coords = np.vstack([m.coords, [[5.0, 5.0, 5.0]]])
+    pat = api.Pattern(H27, coords, m.cells, general=True)
+    rp, ci = O.pattern(H27, coords.shape[0], m.cells)
+    drp, dci = pat.pattern()
+    assert np.array_equal(drp, rp) and np.array_equal(dci, ci) and rp[-1] == rp[-4]
+    rho = np.array([0.4])
+    K = host(pat.assemble_general(mat, dev(rho)))
+    assert _row_scaled(rp, K, O.assemble(H27, coords, m.cells, rho, rp, ci)) <= 1e-12

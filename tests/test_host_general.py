@@ -83,3 +83,10 @@ def test_hex27_host_checks():
     assert Ms.shape == (27, 27, 3, 3)
     assert np.abs(Ms - Mq).max() <= 1e-14 * np.abs(Ms).max()
     assert np.abs(Ms - np.transpose(Ms, (1, 0, 3, 2))).max() == 0.0
+    # the library's basis and rule against the oracle's (same node order)
+    pts, wts = O.quadrature(I.HEX27)
+    Mo = np.zeros((27, 27, 3, 3))
+    for xq, wq in zip(pts, wts):
+        _, g = O.ref_basis(I.HEX27, xq)
+        Mo += wq * np.einsum("im,jn->ijmn", g, g)
+    assert np.abs(Ms - Mo).max() <= 1e-14 * np.abs(Mo).max()
