@@ -68,7 +68,7 @@ extern "C" {
 
 #define SOPTX_OK 0
 #define SOPTX_E_INVALID_ARG (-1)      /* null pointer, bad size or enum */
-#define SOPTX_E_UNSUPPORTED_ELEM (-2) /* element type not one of soptx_elem */
+#define SOPTX_E_UNSUPPORTED_ELEM (-2) /* element type not one of soptx_elem, or not taken by this call */
 #define SOPTX_E_BAD_MESH (-3)         /* node index out of range, node repeated in a cell */
 #define SOPTX_E_JACOBIAN (-4)         /* element with det J <= 0 (inverted or degenerate) */
 #define SOPTX_E_NONAFFINE (-5)        /* element map is not affine */
