@@ -196,3 +196,23 @@ def test_hex27_degenerate_meshes():
     rho = np.array([0.4])
     K = host(pat.assemble_general(mat, dev(rho)))
     assert _row_scaled(rp, K, O.assemble(H27, coords, m.cells, rho, rp, ci)) <= 1e-12
+
+
+def test_hex27_filter_stencil_and_oracle():
+    """A straight Q2 grid: centroids (corner means) on a regular lattice, so
+    the filter takes its stencil form; stencil and CSR forms bitwise equal,
+    and the sensitivity filter bitwise equal to the oracle's."""
+    from oracle import filters as OF
+    m = I.hex27_grid(9, 5, 4)
+    fs = api.Filter.from_mesh(m, 1.5)
+    fc = api.Filter(m.elem, m.coords, m.cells, 1.5, csr_only=True)
+    assert fs.stencil_size == 19 and fc.stencil_size == 0
+    rng = np.random.default_rng(76)
+    rho = rng.uniform(0.0, 1.0, m.n_cells)
+    dc = -rng.exponential(1.0, m.n_cells)
+    a, b = fs.sensitivity(dev(rho), dev(dc)), fc.sensitivity(dev(rho), dev(dc))
+    assert torch.equal(a, b)
+    H = OF.filter_matrix(OF.centroids(H27, m.coords, m.cells), 1.5)
+    assert np.array_equal(host(a), OF.sensitivity_filter(H, rho, dc))
+    v = OF.volumes(H27, m.coords, m.cells)
+    np.testing.assert_allclose(host(fs.density(dev(rho))), OF.density_filter(H, v, rho), rtol=1e-14, atol=0)
