@@ -216,3 +216,25 @@ def test_hex27_filter_stencil_and_oracle():
     assert np.array_equal(host(a), OF.sensitivity_filter(H, rho, dc))
     v = OF.volumes(H27, m.coords, m.cells)
     np.testing.assert_allclose(host(fs.density(dev(rho))), OF.density_filter(H, v, rho), rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("elem", [I.HEX8, H27])
+def test_general_noninteger_exponent(elem):
+    """p = 2.5 takes the pow branch of the SIMP law in the element kernels
+    (assembly and energies) of both general element families."""
+    rng = np.random.default_rng(77)
+    m = I.jitter_interior(I.hex_grid(4, 3, 3) if elem == I.HEX8 else I.hex27_grid(3, 2, 2),
+                          0.25 if elem == I.HEX8 else 0.1, rng)
+    pat = api.Pattern.from_mesh(m, general=True)
+    mat = api.Material(E0=2.0, Emin=1e-6, nu=0.25, p=2.5)
+    rho = rng.uniform(0.01, 1.0, m.n_cells)
+    u = rng.standard_normal(m.ndof)
+    rp, ci = O.pattern(elem, m.n_nodes, m.cells)
+    K = host(pat.assemble_general(mat, dev(rho)))
+    Kr = O.assemble(elem, m.coords, m.cells, rho, rp, ci, E0=2.0, Emin=1e-6, p=2.5, nu=0.25)
+    assert _row_scaled(rp, K, Kr) <= 1e-12
+    dc, c = pat.evaluate_general(mat, dev(rho), dev(u))
+    dref = O.sensitivity(elem, m.coords, m.cells, rho, u, E0=2.0, Emin=1e-6, p=2.5, nu=0.25)
+    cref = O.compliance(elem, m.coords, m.cells, rho, u, None, E0=2.0, Emin=1e-6, p=2.5, nu=0.25)
+    np.testing.assert_allclose(host(dc), dref, rtol=1e-12, atol=1e-12 * np.abs(dref).max())
+    assert abs(host(c)[0] - cref[0]) <= 1e-12 * abs(cref[0])
