@@ -310,9 +310,11 @@ __global__ __launch_bounds__(256) void k_energy_general(GenEnergyParams P) {
 // for a Q2 hexahedron; g_i is read once for both) accumulates
 // P = sum_q c_q g_i g_j^T and forms the block
 //     lambda P + mu P^T + mu tr(P) I
-// (the same sum as k_ke_general's per-point form, regrouped); block (j, i)
-// is its transpose, so the element matrix is exactly symmetric.  The
-// element's matrix is written out as one contiguous range.
+// (the same sum as k_ke_general's per-point form, regrouped) into an LDS
+// stage of the upper triangle's blocks (27.2 KB for a Q2 hexahedron, so that
+// three workgroups fit a CU).  The element's full matrix is written out as
+// one contiguous range, block (j, i) read as the transpose of block (i, j):
+// the element matrix is exactly symmetric.
 template <int NEN, int NQ>
 __global__ __launch_bounds__(256) void k_ke_general_wide(GenParams G) {
     constexpr int DIM = 3, D2 = 9, NP = NEN * NEN, NU = NEN * (NEN + 1) / 2;
@@ -321,7 +323,7 @@ __global__ __launch_bounds__(256) void k_ke_general_wide(GenParams G) {
     __shared__ double sJ[NQ * D2];         // J_q, entry (a, m) = d x_a / d xi_m
     __shared__ double sg[NQ][D2 + 1];      // J_q^-1 (row m: d xi_m / d x), then c_q
     __shared__ double sp[NQ * NEN * DIM];  // physical gradients at the points, [q][k][a]
-    __shared__ double so[NP * D2];         // the element matrix
+    __shared__ double so[NU * D2];         // the element matrix's blocks i <= j
     const int64_t e = blockIdx.x;
     const int t = threadIdx.x;
     for (int x = t; x < NEN * DIM; x += 256) sx[x] = G.coords[(int64_t)G.cells[e * NEN + x / DIM] * DIM + x % DIM];
@@ -406,14 +408,18 @@ __global__ __launch_bounds__(256) void k_ke_general_wide(GenParams G) {
 #pragma unroll
                 for (int c = 0; c < DIM; c++) {
                     const double b = G.lam * P[a][c] + G.mu * P[c][a] + (a == c ? mtr : 0.0);
-                    so[(i * NEN + j) * D2 + a * DIM + c] = b;
-                    if (i != j) so[(j * NEN + i) * D2 + c * DIM + a] = b;
+                    so[(i * NEN - i * (i - 1) / 2 + (j - i)) * D2 + a * DIM + c] = b;
                 }
         }
     }
     __syncthreads();
     double *dst = G.ke + e * NP * D2;
-    for (int x = t; x < NP * D2; x += 256) __builtin_nontemporal_store(so[x], dst + x);
+    for (int x = t; x < NP * D2; x += 256) {
+        const int blk = x / D2, u = x % D2, i = blk / NEN, j = blk % NEN, a = u / DIM, c = u % DIM;
+        const double v = i <= j ? so[(i * NEN - i * (i - 1) / 2 + (j - i)) * D2 + a * DIM + c]
+                                : so[(j * NEN - j * (j - 1) / 2 + (i - j)) * D2 + c * DIM + a];
+        __builtin_nontemporal_store(v, dst + x);
+    }
 }
 
 // Element energies of Q2 hexahedra: kEnergyWideElems elements per block, each
