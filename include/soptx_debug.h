@@ -56,6 +56,13 @@ int soptx_debug_filter_matrix(const soptx_mesh *mesh, double rmin, int64_t *n, i
  * grid sizes, slowest axis first (zeros without a stencil). */
 int soptx_debug_filter_stencil(const soptx_mesh *mesh, double rmin, int32_t *S, int64_t *N);
 
+/* Test hook of the host build: the next n chunks of work that the pattern
+ * and plan build hands to its worker threads fail as if an allocation had
+ * failed, so that the build's error path (SOPTX_E_OOM, every thread joined)
+ * can be exercised without exhausting memory.  n = 0 turns it off.
+ * SOPTX_E_INVALID_ARG for n < 0. */
+int soptx_debug_fail_workers(int32_t n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -95,6 +95,7 @@ def lib():
         "soptx_debug_host_plan_array": [_P, ctypes.c_char_p, ctypes.POINTER(_P), ctypes.POINTER(_I64),
                                         ctypes.POINTER(_I32)],
         "soptx_debug_host_plan_scalars": [_P, _P],
+        "soptx_debug_fail_workers": [_I32],
         "soptx_debug_filter_matrix": [ctypes.POINTER(Mesh), ctypes.c_double, ctypes.POINTER(_I64),
                                       ctypes.POINTER(_I64), _P, _P, _P, _P, _P, _P],
         "soptx_oc_update": [_I64, _P, _P, _P, ctypes.c_double, ctypes.POINTER(OcParams), _P,

@@ -95,6 +95,19 @@ def _stream_ptr(stream) -> Optional[int]:
     return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
 
 
+def _on(stream):
+    """Context in which a call allocates its default outputs: the call's own
+    stream, so that the allocation (and a fill such as torch.zeros) is
+    ordered with the library's kernels on that stream."""
+    import contextlib
+    import torch
+    if stream is None:
+        return contextlib.nullcontext()
+    if not isinstance(stream, torch.cuda.Stream):
+        stream = torch.cuda.ExternalStream(int(stream))
+    return torch.cuda.stream(stream)
+
+
 def _dptr(t, name, dtype=None, numel=None):
     import torch
     if t is None:
@@ -174,7 +187,8 @@ class Pattern:
         """K values (FP64, [nnz]) = sum_e E(rho_e) K_e^0 (Eq. cmpd), Dirichlet rows/cols if mask."""
         import torch
         if out is None:
-            out = torch.empty(self.nnz, dtype=torch.float64, device=rho.device)
+            with _on(stream):
+                out = torch.empty(self.nnz, dtype=torch.float64, device=rho.device)
         mc = material._c()
         check(lib().soptx_assemble(self._h, ctypes.byref(mc), _dptr(rho, "rho", self._rho_dtype(prec), self.n_cells),
                                    _dptr(mask, "mask", torch.uint8, self.ndof),
@@ -187,7 +201,8 @@ class Pattern:
         (Q1, affine or not; patterns built with general=True), FP64."""
         import torch
         if out is None:
-            out = torch.empty(self.nnz, dtype=torch.float64, device=rho.device)
+            with _on(stream):
+                out = torch.empty(self.nnz, dtype=torch.float64, device=rho.device)
         mc = material._c()
         check(lib().soptx_assemble_general(self._h, ctypes.byref(mc), _dptr(rho, "rho", torch.float64, self.n_cells),
                                            _dptr(mask, "mask", torch.uint8, self.ndof),
@@ -200,9 +215,11 @@ class Pattern:
         general=True), FP64: dc_e = -E'(rho_e) u_e^T K_e^0 u_e, c = [u^T K u, f^T u]."""
         import torch
         if dc is None:
-            dc = torch.empty(self.n_cells, dtype=torch.float64, device=rho.device)
+            with _on(stream):
+                dc = torch.empty(self.n_cells, dtype=torch.float64, device=rho.device)
         if c is None:
-            c = torch.zeros(2, dtype=torch.float64, device=rho.device)
+            with _on(stream):
+                c = torch.zeros(2, dtype=torch.float64, device=rho.device)
         mc = material._c()
         check(lib().soptx_evaluate_general(self._h, ctypes.byref(mc), _dptr(rho, "rho", torch.float64, self.n_cells),
                                            _dptr(u, "u", torch.float64, self.ndof),
@@ -224,7 +241,8 @@ class Pattern:
         """dc_e = -E'(rho_e) u_e^T K_e^0 u_e (Appendix D)."""
         import torch
         if out is None:
-            out = torch.empty(self.n_cells, dtype=self._rho_dtype(prec), device=rho.device)
+            with _on(stream):
+                out = torch.empty(self.n_cells, dtype=self._rho_dtype(prec), device=rho.device)
         mc = material._c()
         check(lib().soptx_sensitivity(self._h, ctypes.byref(mc),
                                       _dptr(rho, "rho", self._rho_dtype(prec), self.n_cells),
@@ -237,7 +255,8 @@ class Pattern:
         """[u^T K u, f^T u] as a device FP64 tensor of 2 (Eq. cmpd)."""
         import torch
         if out is None:
-            out = torch.zeros(2, dtype=torch.float64, device=rho.device)
+            with _on(stream):
+                out = torch.zeros(2, dtype=torch.float64, device=rho.device)
         mc = material._c()
         check(lib().soptx_compliance(self._h, ctypes.byref(mc),
                                      _dptr(rho, "rho", self._rho_dtype(prec), self.n_cells),
@@ -251,9 +270,11 @@ class Pattern:
         """Fused sensitivity + compliance; returns (dc, c)."""
         import torch
         if dc is None:
-            dc = torch.empty(self.n_cells, dtype=self._rho_dtype(prec), device=rho.device)
+            with _on(stream):
+                dc = torch.empty(self.n_cells, dtype=self._rho_dtype(prec), device=rho.device)
         if c is None:
-            c = torch.zeros(2, dtype=torch.float64, device=rho.device)
+            with _on(stream):
+                c = torch.zeros(2, dtype=torch.float64, device=rho.device)
         mc = material._c()
         check(lib().soptx_evaluate(self._h, ctypes.byref(mc),
                                    _dptr(rho, "rho", self._rho_dtype(prec), self.n_cells),
@@ -266,7 +287,8 @@ class Pattern:
         """y = K x on the pattern (FP64)."""
         import torch
         if out is None:
-            out = torch.empty(self.ndof, dtype=torch.float64, device=x.device)
+            with _on(stream):
+                out = torch.empty(self.ndof, dtype=torch.float64, device=x.device)
         check(lib().soptx_spmv(self._h, _dptr(K, "K", torch.float64, self.nnz), _dptr(x, "x", torch.float64, self.ndof),
                                _dptr(out, "y", torch.float64, self.ndof), _stream_ptr(stream)), "soptx_spmv")
         return out
@@ -278,7 +300,8 @@ class Pattern:
         Returns (u, iterations, ||r_k|| / ||f||)."""
         import torch
         if u is None:
-            u = torch.zeros(self.ndof, dtype=torch.float64, device=f.device)
+            with _on(stream):
+                u = torch.zeros(self.ndof, dtype=torch.float64, device=f.device)
         it = ctypes.c_int32()
         rel = ctypes.c_double()
         check(lib().soptx_pcg(self._h, _dptr(K, "K", torch.float64, self.nnz), _dptr(f, "f", torch.float64, self.ndof),
@@ -290,7 +313,8 @@ class Pattern:
         """drho_e = E'(rho_e) <Kbar, K_e^0> over the element's slots (reverse of assemble)."""
         import torch
         if out is None:
-            out = torch.empty(self.n_cells, dtype=self._rho_dtype(prec), device=rho.device)
+            with _on(stream):
+                out = torch.empty(self.n_cells, dtype=self._rho_dtype(prec), device=rho.device)
         mc = material._c()
         check(lib().soptx_assemble_backward(self._h, ctypes.byref(mc),
                                             _dptr(rho, "rho", self._rho_dtype(prec), self.n_cells),
@@ -386,7 +410,8 @@ class Filter:
         """dc~_i = sum_j H_ij rho_j dc_j / (max(1e-3, rho_i) sum_j H_ij)."""
         import torch
         if out is None:
-            out = torch.empty(self.n, dtype=torch.float64, device=rho.device)
+            with _on(stream):
+                out = torch.empty(self.n, dtype=torch.float64, device=rho.device)
         check(lib().soptx_filter_sensitivity(self._h, _dptr(rho, "rho", torch.float64, self.n),
                                              _dptr(dc, "dc", torch.float64, self.n),
                                              _dptr(out, "dc_out", torch.float64, self.n), _stream_ptr(stream)),
@@ -399,9 +424,11 @@ class Filter:
         (rho~, rho_bar) with beta."""
         import torch
         if rho_tilde is None:
-            rho_tilde = torch.empty(self.n, dtype=torch.float64, device=rho.device)
+            with _on(stream):
+                rho_tilde = torch.empty(self.n, dtype=torch.float64, device=rho.device)
         if beta is not None and rho_bar is None:
-            rho_bar = torch.empty(self.n, dtype=torch.float64, device=rho.device)
+            with _on(stream):
+                rho_bar = torch.empty(self.n, dtype=torch.float64, device=rho.device)
         check(lib().soptx_filter_density(self._h, _dptr(rho, "rho", torch.float64, self.n),
                                          float(beta if beta is not None else 0.0),
                                          _dptr(rho_tilde, "rho_tilde", torch.float64, self.n),
@@ -416,7 +443,8 @@ class Filter:
         if (rho_tilde is None) != (beta is None):
             raise ValueError("rho_tilde and beta go together")
         if out is None:
-            out = torch.empty(self.n, dtype=torch.float64, device=grad.device)
+            with _on(stream):
+                out = torch.empty(self.n, dtype=torch.float64, device=grad.device)
         check(lib().soptx_filter_density_backward(
             self._h, _dptr(rho_tilde, "rho_tilde", torch.float64, self.n), float(beta if beta is not None else 0.0),
             _dptr(grad, "grad", torch.float64, self.n), _dptr(out, "grad_rho", torch.float64, self.n),
@@ -445,7 +473,8 @@ def oc_update(rho, dc, dv, vol_target: float, move: float = 0.2, eta: float = 0.
     import torch
     n = int(rho.numel())
     if out is None:
-        out = torch.empty(n, dtype=torch.float64, device=rho.device)
+        with _on(stream):
+            out = torch.empty(n, dtype=torch.float64, device=rho.device)
     prm = _lib.OcParams(float(move), float(eta), float(lmax), float(tol), int(max_steps))
     res = _lib.OcResult()
     check(lib().soptx_oc_update(n, _dptr(rho, "rho", torch.float64, n), _dptr(dc, "dc", torch.float64, n),

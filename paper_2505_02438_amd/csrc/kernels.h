@@ -9,7 +9,6 @@ namespace soptx {
 
 constexpr int kF64 = SOPTX_FP64;
 constexpr int kF32 = SOPTX_FP32;
-constexpr int kBF16 = SOPTX_BF16_FP32ACC;
 
 struct AsmParams {
     const int32_t *grp_info;    // [G][kGrpInfo]: sig, n_nodes, elem_off, n_elem, n2l_off, flags
@@ -27,7 +26,6 @@ struct AsmParams {
     const void *rho;
     const double *M;
     const float *M32;
-    const float *Mbf;
     double *K;
     int64_t n_cells;
     int64_t n_groups;

@@ -54,13 +54,6 @@ __device__ __forceinline__ void store_out(void *out, int64_t e, double v) {
     else static_cast<float *>(out)[e] = (float)v;
 }
 
-// round-to-nearest-even to bfloat16, kept in a float
-__device__ __forceinline__ float bf16_round(float x) {
-    uint32_t u = __float_as_uint(x);
-    uint32_t r = ((u >> 16) & 1u) + 0x7fffu;
-    return __uint_as_float((u + r) & 0xffff0000u);
-}
-
 template <int PREC> struct CT { using T = float; };
 template <> struct CT<kF64> { using T = double; };
 
@@ -81,23 +74,6 @@ __device__ __forceinline__ T ldc(const T *base, int64_t idx) {
 // acc += G'^T M_ij G' in the precision of the form (FP64 accumulation)
 template <int DIM, int PREC, typename T>
 __device__ __forceinline__ void accumulate(const T (&G)[DIM][DIM], const T (&M)[DIM * DIM], double (&acc)[DIM][DIM]) {
-    if (PREC == kBF16) {
-        // bf16 inputs, fp32 accumulation: A[a][b] = sum_mn M[m][n] W[m,a][n,b]
-        // with both GEMM operands rounded to bf16, W = G'[m][a] G'[n][b]
-#pragma unroll
-        for (int a = 0; a < DIM; a++)
-#pragma unroll
-            for (int b = 0; b < DIM; b++) {
-                float s = 0.0f;
-#pragma unroll
-                for (int m = 0; m < DIM; m++)
-#pragma unroll
-                    for (int n = 0; n < DIM; n++)
-                        s += (float)M[m * DIM + n] * bf16_round((float)G[m][a] * (float)G[n][b]);
-                acc[a][b] += (double)s;
-            }
-        return;
-    }
     T Tm[DIM][DIM];
 #pragma unroll
     for (int m = 0; m < DIM; m++)
@@ -128,16 +104,15 @@ __device__ __forceinline__ void accumulate(const T (&G)[DIM][DIM], const T (&M)[
     }
 }
 
-// G'_aa G'_cc in the form's precision (bf16-rounded in the bf16 form)
+// G'_aa G'_cc in the form's precision
 template <int PREC, typename T>
 __device__ __forceinline__ T diag_product(T da, T dc) {
     if (PREC == kF64) return da * dc;
-    if (PREC == kF32) return (T)((float)da * (float)dc);
-    return (T)bf16_round((float)da * (float)dc);
+    return (T)((float)da * (float)dc);
 }
 
 // acc += G'^T M_ij G' for diagonal G': entry (a, b) is G'_aa G'_bb M_ij[a][b];
-// dd holds the products G'_aa G'_bb (bf16-rounded in the bf16 form)
+// dd holds the products G'_aa G'_bb
 template <int DIM, int PREC, typename T>
 __device__ __forceinline__ void accumulate_diag(const T (&dd)[DIM][DIM], const T (&M)[DIM * DIM],
                                                 double (&acc)[DIM][DIM]) {
@@ -222,8 +197,7 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
 
     for (int x = tid; x < NEN * NEN * D2; x += kAsmThreads) {
         if (PREC == kF64) sM[x] = (T)P.M[x];
-        else if (PREC == kF32) sM[x] = (T)P.M32[x];
-        else sM[x] = (T)P.Mbf[x];
+        else sM[x] = (T)P.M32[x];
     }
 
     // ---- load role: two sets of kLoadWaves / 2 waves; set x puts the groups
@@ -1157,8 +1131,7 @@ hipError_t launch_assemble(int elem, int prec, const AsmParams &P, int64_t ngrou
 #define SOPTX_ASM(E, D, N)                                                    \
     case E:                                                                   \
         if (prec == kF64) return launch_assemble_t<D, N, kF64>(P, ngroups, st); \
-        if (prec == kF32) return launch_assemble_t<D, N, kF32>(P, ngroups, st); \
-        return launch_assemble_t<D, N, kBF16>(P, ngroups, st);
+        return launch_assemble_t<D, N, kF32>(P, ngroups, st);
     switch (elem) {
         SOPTX_ASM(SOPTX_QUAD4, 2, 4)
         SOPTX_ASM(SOPTX_TRI3, 2, 3)
@@ -1180,7 +1153,7 @@ static hipError_t launch_energy_t(const EnergyParams &P, hipStream_t st) {
 }
 
 hipError_t launch_energy(int elem, int prec, const EnergyParams &P, hipStream_t st) {
-    const int pr = prec == kF64 ? kF64 : kF32;  // bf16 form evaluates energies in FP32
+    const int pr = prec == kF64 ? kF64 : kF32;
 #define SOPTX_EN(E, D, N, Q)                                               \
     case E:                                                                \
         if (pr == kF64) return launch_energy_t<D, N, Q, kF64>(P, st);      \

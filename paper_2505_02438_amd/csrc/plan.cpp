@@ -2,14 +2,17 @@
 // pattern and the assembly plan (Sec. 3.2.2: invariant components are built
 // once and reused across optimisation iterations).
 #include <algorithm>
+#include <atomic>
 #include <array>
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <new>
 #include <thread>
 #include <unordered_map>
 #include <unordered_set>
 
+#include "../../include/soptx_debug.h"
 #include "internal.h"
 
 namespace soptx {
@@ -23,18 +26,49 @@ int hw_threads() {
     return (int)n;
 }
 
+// Test hook: the next n worker chunks of parallel_for throw std::bad_alloc
+// (soptx_debug_fail_workers), so that the failure path runs without
+// exhausting memory.
+std::atomic<int> g_fail_chunks{0};
+
+// f(a, b) over chunks of [0, n) on up to hw_threads() threads.  An exception
+// in a chunk is caught where it is thrown and reported by the return value
+// (false); a thread that cannot be created leaves its chunk to the calling
+// thread.  Every thread is joined before the return.
 template <class F>
-void parallel_for(int64_t n, F &&f) {
-    int T = hw_threads();
-    if (n < 4096 || T <= 1) { f(0, n); return; }
-    std::vector<std::thread> th;
-    int64_t chunk = (n + T - 1) / T;
-    for (int t = 0; t < T; t++) {
-        int64_t a = t * chunk, b = std::min(n, a + chunk);
-        if (a >= b) break;
-        th.emplace_back([&f, a, b] { f(a, b); });
+bool parallel_for(int64_t n, F &&f) {
+    std::atomic<bool> failed{false};
+    auto run = [&](int64_t a, int64_t b) {
+        try {
+            if (g_fail_chunks.load() > 0 && g_fail_chunks.fetch_sub(1) > 0) throw std::bad_alloc();
+            f(a, b);
+        } catch (...) {
+            failed = true;
+        }
+    };
+    const int T = hw_threads();
+    if (n < 4096 || T <= 1) {
+        run(0, n);
+        return !failed;
     }
+    std::vector<std::thread> th;
+    try {
+        th.reserve((size_t)T);
+    } catch (...) {
+    }
+    const int64_t chunk = (n + T - 1) / T;
+    for (int t = 1; t < T; t++) {
+        const int64_t a = t * chunk, b = std::min(n, a + chunk);
+        if (a >= b) break;
+        try {
+            th.emplace_back(run, a, b);
+        } catch (...) {
+            run(a, b);  // no thread available: the calling thread does the chunk
+        }
+    }
+    run(0, std::min(n, chunk));
     for (auto &x : th) x.join();
+    return !failed;
 }
 
 // det and inverse of a dim x dim row-major matrix J[a][m] = d x_a / d xi_m;
@@ -191,7 +225,7 @@ int build_host_plan(const soptx_mesh *mesh, HostPlan &hp, bool general) {
 
     // ---- geometry (a1): G = J^-1 and det J per element, SoA
     hp.geo.assign((size_t)(dim * dim + 1) * NC, 0.0);
-    parallel_for(NC, [&](int64_t a0, int64_t a1) {
+    if (!parallel_for(NC, [&](int64_t a0, int64_t a1) {
         for (int64_t e = a0; e < a1; e++) {
             const int32_t *c = cells + e * nen;
             int def[3];
@@ -206,7 +240,8 @@ int build_host_plan(const soptx_mesh *mesh, HostPlan &hp, bool general) {
             for (int k = 0; k < dim * dim; k++) hp.geo[(size_t)k * NC + e] = G[k];
             hp.geo[(size_t)dim * dim * NC + e] = det;
         }
-    });
+    }))
+        return SOPTX_E_OOM;
 
     // ---- node -> (element, local index), elements ascending (counting sort)
     std::vector<int64_t> n2e_ptr(NN + 1, 0);
@@ -229,7 +264,7 @@ int build_host_plan(const soptx_mesh *mesh, HostPlan &hp, bool general) {
     std::vector<int64_t> deg(NN, 0);
     std::vector<int64_t> nb_ptr(NN + 1, 0);
     // first pass: degrees
-    parallel_for(NN, [&](int64_t a0, int64_t a1) {
+    if (!parallel_for(NN, [&](int64_t a0, int64_t a1) {
         std::vector<int32_t> buf;
         for (int64_t n = a0; n < a1; n++) {
             buf.clear();
@@ -238,7 +273,8 @@ int build_host_plan(const soptx_mesh *mesh, HostPlan &hp, bool general) {
             std::sort(buf.begin(), buf.end());
             deg[n] = std::unique(buf.begin(), buf.end()) - buf.begin();
         }
-    });
+    }))
+        return SOPTX_E_OOM;
     for (int64_t n = 0; n < NN; n++) nb_ptr[n + 1] = nb_ptr[n] + deg[n];
     const int64_t nnz = nb_ptr[NN] * dim * dim;
     if (nnz >= INT32_MAX) return SOPTX_E_OVERFLOW;
@@ -247,7 +283,7 @@ int build_host_plan(const soptx_mesh *mesh, HostPlan &hp, bool general) {
     hp.nnz = nnz;
     std::vector<int32_t> &nb = hp.nb;
     nb.assign(nb_ptr[NN], 0);
-    parallel_for(NN, [&](int64_t a0, int64_t a1) {
+    if (!parallel_for(NN, [&](int64_t a0, int64_t a1) {
         std::vector<int32_t> buf;
         for (int64_t n = a0; n < a1; n++) {
             buf.clear();
@@ -257,7 +293,8 @@ int build_host_plan(const soptx_mesh *mesh, HostPlan &hp, bool general) {
             buf.erase(std::unique(buf.begin(), buf.end()), buf.end());
             std::copy(buf.begin(), buf.end(), nb.begin() + nb_ptr[n]);
         }
-    });
+    }))
+        return SOPTX_E_OOM;
 
     // ---- CSR: rows dim*n+a hold dim*J+b for J in nb(n) ascending, b ascending
     hp.row_ptr.assign(hp.ndof + 1, 0);
@@ -265,14 +302,15 @@ int build_host_plan(const soptx_mesh *mesh, HostPlan &hp, bool general) {
         for (int a = 0; a < dim; a++)
             hp.row_ptr[dim * n + a + 1] = (int32_t)(dim * dim * nb_ptr[n] + (a + 1) * dim * deg[n]);
     hp.col_idx.resize(nnz);
-    parallel_for(NN, [&](int64_t a0, int64_t a1) {
+    if (!parallel_for(NN, [&](int64_t a0, int64_t a1) {
         for (int64_t n = a0; n < a1; n++)
             for (int a = 0; a < dim; a++) {
                 int64_t o = hp.row_ptr[dim * n + a];
                 for (int64_t k = nb_ptr[n]; k < nb_ptr[n + 1]; k++)
                     for (int b = 0; b < dim; b++) hp.col_idx[o++] = (int32_t)(dim * nb[k] + b);
             }
-    });
+    }))
+        return SOPTX_E_OOM;
 
     // ---- transposed slots: for J = nb(n)[q], the CSR slot of (row dim J,
     // column dim n) (n sits in nb(J): the neighbour relation is symmetric) and
@@ -280,7 +318,7 @@ int build_host_plan(const soptx_mesh *mesh, HostPlan &hp, bool general) {
     // fixed dof through them
     hp.nb_tslot.assign(nb_ptr[NN], 0);
     hp.nb_tdeg.assign(nb_ptr[NN], 0);
-    parallel_for(NN, [&](int64_t a0, int64_t a1) {
+    if (!parallel_for(NN, [&](int64_t a0, int64_t a1) {
         for (int64_t n = a0; n < a1; n++)
             for (int64_t k = nb_ptr[n]; k < nb_ptr[n + 1]; k++) {
                 const int32_t J = nb[k];
@@ -289,13 +327,14 @@ int build_host_plan(const soptx_mesh *mesh, HostPlan &hp, bool general) {
                 hp.nb_tslot[k] = (int32_t)(dim * dim * nb_ptr[J] + dim * t);
                 hp.nb_tdeg[k] = (uint16_t)deg[J];
             }
-    });
+    }))
+        return SOPTX_E_OOM;
 
     if (mesh->elem == SOPTX_HEX27) {
         // only the per-quadrature-point assembly runs on these elements: the
         // position table alone, no signatures or groups
         hp.pos.assign((size_t)NC * nen * nen, 0);
-        parallel_for(NC, [&](int64_t a0, int64_t a1) {
+        if (!parallel_for(NC, [&](int64_t a0, int64_t a1) {
             for (int64_t e = a0; e < a1; e++)
                 for (int i = 0; i < nen; i++) {
                     const int64_t I = cells[e * nen + i];
@@ -304,7 +343,8 @@ int build_host_plan(const soptx_mesh *mesh, HostPlan &hp, bool general) {
                         hp.pos[((size_t)e * nen + i) * nen + j] =
                             (uint16_t)(std::lower_bound(nbn, nbn + deg[I], cells[e * nen + j]) - nbn);
                 }
-        });
+        }))
+            return SOPTX_E_OOM;
         return general_table(mesh, hp);
     }
 
@@ -318,7 +358,7 @@ int build_host_plan(const soptx_mesh *mesh, HostPlan &hp, bool general) {
         int64_t c1 = std::min(NN, c0 + CH);
         std::vector<std::vector<int32_t>> sv(c1 - c0);
         std::vector<uint64_t> hv(c1 - c0);
-        parallel_for(c1 - c0, [&](int64_t a0, int64_t a1) {
+        if (!parallel_for(c1 - c0, [&](int64_t a0, int64_t a1) {
             std::vector<std::array<int32_t, 4>> t;  // p, k, i, j
             for (int64_t x = a0; x < a1; x++) {
                 int64_t n = c0 + x;
@@ -352,7 +392,8 @@ int build_host_plan(const soptx_mesh *mesh, HostPlan &hp, bool general) {
                 for (int32_t v : s) { h ^= (uint32_t)v; h *= 1099511628211ull; }
                 hv[x] = h;
             }
-        });
+        }))
+            return SOPTX_E_OOM;
         for (int64_t x = 0; x < c1 - c0; x++) {
             auto &cand = sig_by_hash[hv[x]];
             int32_t id = -1;
@@ -588,3 +629,9 @@ int build_host_plan(const soptx_mesh *mesh, HostPlan &hp, bool general) {
 }
 
 }  // namespace soptx
+
+extern "C" int soptx_debug_fail_workers(int32_t n) {
+    if (n < 0) return SOPTX_E_INVALID_ARG;
+    soptx::g_fail_chunks.store(n);
+    return SOPTX_OK;
+}

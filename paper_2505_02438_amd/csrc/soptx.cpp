@@ -69,7 +69,7 @@ struct soptx_pattern_s {
     int32_t *nb_tslot = nullptr;
     int32_t *nb = nullptr;
     double *M = nullptr;
-    float *M32 = nullptr, *Mbf = nullptr;
+    float *M32 = nullptr;
     double *qw = nullptr, *qgrad = nullptr, *cgrad = nullptr, *xref = nullptr;
     // per-quadrature-point assembly (handles built by soptx_build_pattern_general)
     bool affine = true, general = false;
@@ -123,7 +123,9 @@ int int_exponent(double p) {
     return -1;
 }
 
-bool valid_prec(int32_t prec) { return prec == SOPTX_FP64 || prec == SOPTX_FP32 || prec == SOPTX_BF16_FP32ACC; }
+// SOPTX_BF16_FP32ACC is refused: bf16-rounded inputs miss the FP32 form's
+// bound on K by two to three orders of magnitude
+bool valid_prec(int32_t prec) { return prec == SOPTX_FP64 || prec == SOPTX_FP32; }
 
 }  // namespace
 
@@ -183,14 +185,7 @@ static int build_pattern(const soptx_mesh *mesh, int32_t ref_method, bool genera
         std::vector<double> M((size_t)nen * nen * dim * dim);
         rc = reference_tensor(hp.elem, ref_method, M.data());
         if (rc) { free_handle(h); return rc; }
-        std::vector<float> M32(M.size()), Mbf(M.size());
-        for (size_t k = 0; k < M.size(); k++) {
-            M32[k] = (float)M[k];
-            uint32_t u;
-            std::memcpy(&u, &M32[k], 4);
-            u = (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u;  // round to nearest even bf16
-            std::memcpy(&Mbf[k], &u, 4);
-        }
+        std::vector<float> M32(M.begin(), M.end());
         std::vector<double> qw, qg;
         rc = reference_qp_grads(hp.elem, qw, qg);
         if (rc) { free_handle(h); return rc; }
@@ -239,7 +234,7 @@ static int build_pattern(const soptx_mesh *mesh, int32_t ref_method, bool genera
         h->stats.plan_bytes = h->stats.device_bytes - base_bytes;
         if ((rc = upload(h, hp.pos, &h->pos, st)) || (rc = upload(h, hp.nb_tslot, &h->nb_tslot, st)) ||
             (rc = upload(h, hp.nb, &h->nb, st)) || (rc = upload(h, hp.nb_tdeg, &h->nb_tdeg, st)) || (rc = upload(h, M, &h->M, st)) ||
-            (rc = upload(h, M32, &h->M32, st)) || (rc = upload(h, Mbf, &h->Mbf, st)) ||
+            (rc = upload(h, M32, &h->M32, st)) ||
             (rc = upload(h, qw, &h->qw, st)) || (rc = upload(h, qg, &h->qgrad, st)) ||
             (rc = upload(h, qg32, &h->qgrad32, st)) || (rc = upload(h, cg, &h->cgrad, st)) ||
             (rc = upload(h, xref, &h->xref, st))) {
@@ -351,7 +346,7 @@ int soptx_assemble(soptx_pattern h, const soptx_material *m, const void *d_rho, 
     P.sig_info = h->sig_info; P.sig_pos_ptr = h->sig_pos_ptr; P.sig_contrib = h->sig_contrib;
     P.sig_pairs = h->sig_pairs; P.sig_witems = h->sig_witems; P.sig_witem_ptr = h->sig_witem_ptr;
     P.geo = h->geo; P.rho = d_rho;
-    P.M = h->M; P.M32 = h->M32; P.Mbf = h->Mbf; P.K = d_K_vals;
+    P.M = h->M; P.M32 = h->M32; P.K = d_K_vals;
     P.n_cells = h->n_cells; P.E0 = m->E0; P.Emin = m->Emin; P.p = m->p; P.ip = int_exponent(m->p);
     lame(h, m, &P.lam, &P.mu);
     P.kmax = h->kmax; P.stage = h->stage;

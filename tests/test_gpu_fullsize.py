@@ -3,9 +3,9 @@
 
 * MBB 60x20 Q1: everything against the oracle, u from the oracle's solve;
 * cantilever 600x200 P1 tris, 3D cantilever 120x40x40 Q1 hexes, box 48^3 P2
-  tets: pattern (closed form / oracle), rows of seeded sample nodes against
+  tets: pattern (closed form and the oracle's, bit-exact), rows of seeded sample nodes against
   the oracle's assembly of the elements around them (every contribution to
-  those rows), FP32 and BF16 forms, sensitivities of seeded sample elements,
+  those rows), the FP32 form, sensitivities of seeded sample elements,
   compliance, rigid-body modes, the linear patch test, Dirichlet rows and
   columns.
 """
@@ -107,13 +107,13 @@ def test_pattern_full(name):
     # node-pair structure: a node's dim rows have the same columns, interleaved dofs
     lens = np.diff(rp).reshape(-1, m.dim)
     assert np.all(lens == lens[:, :1]) and np.all(lens % m.dim == 0)
-    if name in ("tri", "hex"):
-        orp, oci = O.pattern(m.elem, m.n_nodes, m.cells)
-        assert np.array_equal(rp, orp) and np.array_equal(ci, oci)
+    # bit-exact against the oracle's pattern at full size, P2 included
+    orp, oci = O.pattern(m.elem, m.n_nodes, m.cells)
+    assert np.array_equal(rp, orp) and np.array_equal(ci, oci)
 
 
 @pytest.mark.parametrize("name", ["tri", "hex", "p2"])
-def test_sampled_rows_fp64_fp32_bf16(name):
+def test_sampled_rows_fp64_fp32(name):
     pr, pat, rp, ci = _setup(name)
     m = pr.mesh
     rng = np.random.default_rng(77)
@@ -126,11 +126,8 @@ def test_sampled_rows_fp64_fp32_bf16(name):
     rho_r = pr.rho.astype(np.float32).astype(np.float64)
     srp2, sci2, sK2 = _sample_rows_oracle(pr, nodes, rho_r)
     e32 = _compare_rows(m, nodes, rp, ci, K32, srp2, sci2, sK2)
-    K16 = host(pat.assemble(MAT, rho32, prec=api.BF16_FP32ACC))
-    e16 = _compare_rows(m, nodes, rp, ci, K16, srp2, sci2, sK2)
-    print(f"{name}: sampled rows FP64 {e64:.2e}  FP32 {e32:.2e}  BF16-in/FP32-acc {e16:.2e}")
+    print(f"{name}: sampled rows FP64 {e64:.2e}  FP32 {e32:.2e}")
     assert e64 <= 1e-12 and e32 <= 1e-5
-    assert np.isfinite(K16).all() and e16 < 5e-2
 
 
 @pytest.mark.parametrize("name", ["tri", "hex", "p2"])

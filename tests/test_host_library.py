@@ -392,3 +392,62 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     msg = json.loads(r.stdout.strip().splitlines()[-1])
     assert "one GPU" in msg["error"] and msg["n_gpus"] == 2
+
+
+def _raw_host_plan(m):
+    """Status of the host build (pattern + plan) of a mesh through the raw ABI."""
+    L = _lib.lib()
+    mesh, keep = api._mesh_struct(m.elem, m.coords, m.cells)
+    h = ctypes.c_void_p()
+    rc = L.soptx_debug_host_plan_ex(ctypes.byref(mesh), 0, ctypes.byref(h))
+    if rc == 0:
+        L.soptx_debug_host_plan_free(h)
+    else:
+        assert h.value is None
+    return rc
+
+
+def test_plan_build_worker_failure_returns_oom():
+    """A worker chunk that fails (forced through the test hook) makes the build
+    return SOPTX_E_OOM with every thread joined; the next build succeeds."""
+    L = _lib.lib()
+    big = I.hex_grid(20, 20, 20)     # above the size where the build uses threads
+    small = I.quad_grid(4, 3)        # built on the calling thread
+    try:
+        for m in (big, small):
+            for n in (1, 3):
+                assert L.soptx_debug_fail_workers(n) == 0
+                assert _raw_host_plan(m) == -7
+                assert L.soptx_debug_fail_workers(0) == 0
+                assert _raw_host_plan(m) == 0
+        assert L.soptx_debug_fail_workers(-1) == -1
+    finally:
+        L.soptx_debug_fail_workers(0)
+
+
+def test_overflow_paths_before_allocation():
+    """Sizes beyond the int32 index range are refused with SOPTX_E_OVERFLOW by
+    the checks that run before anything is read or allocated."""
+    L = _lib.lib()
+    dummy_x = np.zeros(3)
+    dummy_c = np.zeros(8, dtype=np.int32)
+    # dof count 3 * 2^30 >= 2^31 - 1
+    mesh = _lib.Mesh(I.HEX8, 3, 1 << 30, dummy_x.ctypes.data, 1, dummy_c.ctypes.data)
+    assert L.soptx_validate_mesh(ctypes.byref(mesh)) == -6
+    # n_cells * nen >= 2^31 - 1
+    mesh = _lib.Mesh(I.HEX8, 3, 8, dummy_x.ctypes.data, (2**31 - 1) // 8, dummy_c.ctypes.data)
+    assert L.soptx_validate_mesh(ctypes.byref(mesh)) == -6
+    out = ctypes.c_void_p()
+    assert L.soptx_debug_host_plan_ex(ctypes.byref(mesh), 0, ctypes.byref(out)) == -6
+
+
+def test_adjacency_cap_overflow():
+    """A node with more adjacent elements than the assembly plan's slot table
+    holds (32) is refused with SOPTX_E_OVERFLOW; 32 are accepted."""
+    for n, expect in ((32, 0), (33, -6)):
+        ang = 2 * np.pi * np.arange(n) / n
+        coords = np.vstack([[0.0, 0.0], np.stack([np.cos(ang), np.sin(ang)], axis=1)])
+        cells = np.array([[0, 1 + k, 1 + (k + 1) % n] for k in range(n)], dtype=np.int32)
+        m = I.Mesh(I.TRI3, coords, cells)
+        assert api.validate_mesh(m.elem, m.coords, m.cells) == 0
+        assert _raw_host_plan(m) == expect, n
