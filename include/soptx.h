@@ -75,6 +75,7 @@ extern "C" {
 #define SOPTX_E_OVERFLOW (-6)         /* nnz, dof count or a plan index exceeds its int32 range */
 #define SOPTX_E_OOM (-7)              /* device or host allocation failed */
 #define SOPTX_E_DEVICE (-8)           /* HIP runtime / launch error */
+#define SOPTX_E_SCRATCH (-9)          /* input exceeds the fixed scratch of an allocation-free call */
 
 typedef enum { SOPTX_QUAD4 = 1, SOPTX_TRI3 = 2, SOPTX_HEX8 = 3, SOPTX_TET10 = 4, SOPTX_HEX27 = 5 } soptx_elem;
 
@@ -182,6 +183,24 @@ int soptx_compliance(soptx_pattern h, const soptx_material *m, const void *d_rho
 int soptx_evaluate(soptx_pattern h, const soptx_material *m, const void *d_rho,
                    const double *d_u, const double *d_f, void *d_dc, double *d_c, int32_t prec,
                    void *stream);
+
+/* soptx_evaluate for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, kernels and results (bitwise) as soptx_evaluate, but the
+ * block partials of the compliance live in a fixed device array of the
+ * library (2 x 8192 doubles = 128 KiB per device, held from the library's
+ * load until the process ends) instead of a workspace allocated on first
+ * use: the call allocates nothing (no hipMalloc, no allocating library
+ * routine).  Limit: with d_c != NULL, n_cells <= 8192 * 256 = 2,097,152;
+ * larger meshes return SOPTX_E_SCRATCH before any device work (d_c == NULL
+ * has no limit).  Every call on a device shares that device's array, which
+ * keeps the last call's partials; each call overwrites every partial it
+ * reads, so nothing needs clearing.  Calls that overlap on one device (on
+ * different streams, or from different threads) race on the array and must
+ * be serialized by the caller. */
+int soptx_evaluate_noalloc(soptx_pattern h, const soptx_material *m, const void *d_rho,
+                           const double *d_u, const double *d_f, void *d_dc, double *d_c,
+                           int32_t prec, void *stream);
 
 /* Reverse of soptx_assemble: for L = <Kbar, K(rho)>,
  * d_drho[e] = E'(rho_e) sum_ij Kbar[slot(e,i,j)] K_e^0[i,j],

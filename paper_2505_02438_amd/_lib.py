@@ -16,7 +16,7 @@ SOPTX_OK = 0
 STATUS = {
     0: "SOPTX_OK", -1: "SOPTX_E_INVALID_ARG", -2: "SOPTX_E_UNSUPPORTED_ELEM", -3: "SOPTX_E_BAD_MESH",
     -4: "SOPTX_E_JACOBIAN", -5: "SOPTX_E_NONAFFINE", -6: "SOPTX_E_OVERFLOW", -7: "SOPTX_E_OOM",
-    -8: "SOPTX_E_DEVICE",
+    -8: "SOPTX_E_DEVICE", -9: "SOPTX_E_SCRATCH",
 }
 
 FP64, FP32, BF16_FP32ACC = 0, 1, 2
@@ -84,6 +84,7 @@ def lib():
         "soptx_sensitivity": [_P, ctypes.POINTER(Material), _P, _P, _P, _I32, _P],
         "soptx_compliance": [_P, ctypes.POINTER(Material), _P, _P, _P, _P, _I32, _P],
         "soptx_evaluate": [_P, ctypes.POINTER(Material), _P, _P, _P, _P, _P, _I32, _P],
+        "soptx_evaluate_noalloc": [_P, ctypes.POINTER(Material), _P, _P, _P, _P, _P, _I32, _P],
         "soptx_assemble_backward": [_P, ctypes.POINTER(Material), _P, _P, _P, _P, _I32, _P],
         "soptx_spmv": [_P, _P, _P, _P, _P],
         "soptx_pcg": [_P, _P, _P, _P, ctypes.c_double, _I32, ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_double),

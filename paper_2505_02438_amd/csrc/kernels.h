@@ -79,6 +79,11 @@ hipError_t launch_dirichlet(int dim, const int32_t *row_ptr, const int32_t *nb_t
                             const uint8_t *mask, double *K, int64_t ndof, hipStream_t st);
 hipError_t launch_energy(int elem, int prec, const EnergyParams &P, hipStream_t st);
 hipError_t launch_finalize(const double *partials, int n, int with_f, double *c, hipStream_t st);
+// the allocation-free evaluate: its block partials live in a fixed device
+// array of 2 x kNoAllocBlocks doubles (256 elements per block); the address
+// of the current device's copy (device must be current)
+constexpr int kNoAllocBlocks = 8192;
+hipError_t noalloc_scratch(int device, double **out);
 
 // solve (node-block Jacobi preconditioned CG); nb = neighbour lists, K's block structure
 int64_t spmv_blocks(int dim, int64_t n_nodes);

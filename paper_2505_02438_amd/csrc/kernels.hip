@@ -1209,4 +1209,34 @@ hipError_t launch_backward(int elem, int prec, const BwdParams &P, hipStream_t s
 #undef SOPTX_BW
 }
 
+// ------------------------------------------------ allocation-free evaluate
+//
+// Fixed device scratch of soptx_evaluate_noalloc: the block partials of c and
+// of f^T u, 2 x kNoAllocBlocks doubles (128 KiB).  Every device that loads the
+// library holds its own copy until the process ends.  In host code `scratch`
+// names a host-side stand-in, not a device address: the device address comes
+// from hipGetSymbolAddress, once per device with that device current, and
+// only that address is passed to kernels.
+static __device__ __align__(256) double scratch[2 * kNoAllocBlocks];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, double *> g_scratch_ptr;  // device -> address of its scratch
+}  // namespace
+
+hipError_t noalloc_scratch(int device, double **out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    if (it != g_scratch_ptr.end()) {
+        *out = it->second;
+        return hipSuccess;
+    }
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) return e != hipSuccess ? e : hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = static_cast<double *>(p);
+    *out = static_cast<double *>(p);
+    return hipSuccess;
+}
+
 }  // namespace soptx

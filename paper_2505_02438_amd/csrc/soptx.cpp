@@ -142,6 +142,7 @@ const char *soptx_status_string(int s) {
     case SOPTX_E_OVERFLOW: return "size exceeds the int32 index range";
     case SOPTX_E_OOM: return "out of memory";
     case SOPTX_E_DEVICE: return "HIP device or launch error";
+    case SOPTX_E_SCRATCH: return "input exceeds the fixed scratch of an allocation-free call";
     default: return "unknown status";
     }
 }
@@ -461,23 +462,31 @@ int soptx_pcg(soptx_pattern h, const double *d_K_vals, const double *d_f, double
     return SOPTX_OK;
 }
 
-int soptx_evaluate(soptx_pattern h, const soptx_material *m, const void *d_rho, const double *d_u,
-                   const double *d_f, void *d_dc, double *d_c, int32_t prec, void *stream) {
+// soptx_evaluate and its allocation-free variant: the same kernels; the block
+// partials of c go to the per-stream workspace or to the fixed scratch
+static int evaluate_impl(soptx_pattern h, const soptx_material *m, const void *d_rho, const double *d_u,
+                         const double *d_f, void *d_dc, double *d_c, int32_t prec, void *stream, bool noalloc) {
     if (!h || !valid_prec(prec)) return SOPTX_E_INVALID_ARG;
     if (!h->affine) return not_affine(h);
     int rc = check_material(m);
     if (rc) return rc;
     if (h->n_cells > 0 && (!d_rho || !d_u)) return SOPTX_E_INVALID_ARG;
     if (!d_dc && !d_c) return SOPTX_E_INVALID_ARG;
+    const int64_t nblk64 = std::max<int64_t>(1, (h->n_cells + 255) / 256);
+    if (noalloc && d_c && nblk64 > kNoAllocBlocks) return SOPTX_E_SCRATCH;
+    const int nblk = (int)nblk64;
     DeviceGuard dg(h->device);
     if (!dg.ok) return SOPTX_E_DEVICE;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const int nblk = std::max(1, (int)((h->n_cells + 255) / 256));
     double *ws = nullptr;
     if (d_c) {
         // block partials of c, then of f^T u
-        rc = get_workspace(h->device, st, 2 * (size_t)nblk, &ws, 0);
-        if (rc) return rc;
+        if (noalloc) {
+            if (noalloc_scratch(h->device, &ws) != hipSuccess) return SOPTX_E_DEVICE;
+        } else {
+            rc = get_workspace(h->device, st, 2 * (size_t)nblk, &ws, 0);
+            if (rc) return rc;
+        }
     }
     EnergyParams P{};
     P.cells = h->cells; P.geo = h->geo; P.rho = d_rho; P.u = d_u;
@@ -491,6 +500,16 @@ int soptx_evaluate(soptx_pattern h, const soptx_material *m, const void *d_rho, 
     if (launch_energy(h->elem, prec, P, st) != hipSuccess) return SOPTX_E_DEVICE;
     if (d_c && launch_finalize(ws, nblk, d_f ? 1 : 0, d_c, st) != hipSuccess) return SOPTX_E_DEVICE;
     return SOPTX_OK;
+}
+
+int soptx_evaluate(soptx_pattern h, const soptx_material *m, const void *d_rho, const double *d_u,
+                   const double *d_f, void *d_dc, double *d_c, int32_t prec, void *stream) {
+    return evaluate_impl(h, m, d_rho, d_u, d_f, d_dc, d_c, prec, stream, false);
+}
+
+int soptx_evaluate_noalloc(soptx_pattern h, const soptx_material *m, const void *d_rho, const double *d_u,
+                           const double *d_f, void *d_dc, double *d_c, int32_t prec, void *stream) {
+    return evaluate_impl(h, m, d_rho, d_u, d_f, d_dc, d_c, prec, stream, true);
 }
 
 int soptx_evaluate_general(soptx_pattern h, const soptx_material *m, const double *d_rho, const double *d_u,

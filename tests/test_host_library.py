@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_strings():
     L = _lib.lib()
-    for code in range(0, -9, -1):
+    for code in range(0, -10, -1):
         assert L.soptx_status_string(code)
     assert L.soptx_status_string(-99) == b"unknown status"
 
