@@ -278,6 +278,43 @@ int soptx_evaluate_general(soptx_pattern h, const soptx_material *m, const doubl
 int soptx_pcg(soptx_pattern h, const double *d_K_vals, const double *d_f, double *d_u, double rtol,
               int32_t max_iter, int32_t *h_iters, double *h_relres, void *stream);
 
+/* Dirichlet boundary conditions bound once to a pattern (zero prescribed
+ * values, Appendices A-C; the supports do not change during an optimisation,
+ * Sec. 2.2).  h_mask: host [ndof] uint8, nonzero = fixed dof, read during the
+ * call.  The handle holds, for the pattern's assembly plan, which stored
+ * entries lie in a fixed row or column, so that soptx_step writes K with the
+ * boundary conditions applied and no pass of its own: every fixed dof r gets
+ * K[r,:] = 0, K[:,r] = 0, K[r,r] = 1, the same values as soptx_assemble with
+ * that mask.  It is immutable and tied to h (destroy it before h); it
+ * blocks until its device copies are made.  SOPTX_E_NONAFFINE /
+ * SOPTX_E_UNSUPPORTED_ELEM on handles the affine calls refuse. */
+typedef struct soptx_dirichlet_s *soptx_dirichlet;
+int soptx_build_dirichlet(soptx_pattern h, const uint8_t *h_mask, soptx_dirichlet *out, void *stream);
+
+/* Number of fixed dofs, and of plan groups whose blocks the mask touches
+ * (either output may be NULL). */
+int soptx_dirichlet_info(soptx_dirichlet bc, int64_t *n_fixed, int64_t *n_groups);
+
+/* Release a Dirichlet handle (NULL is allowed). */
+void soptx_destroy_dirichlet(soptx_dirichlet bc);
+
+/* The whole per-iteration step of the paper's assembly and sensitivity path
+ * (Sec. 2.1 SIMP, Sec. 2.2 Eq. cmpc/cmpd, Appendix D): d_K_vals =
+ * soptx_assemble(rho) with the Dirichlet rows and columns of bc applied
+ * while the assembly stages its blocks (bc NULL: none; no separate pass);
+ * and, when d_u is given, the element energies s_e = u_e^T K_e^0 u_e of
+ * soptx_evaluate: d_dc[e] = -E'(rho_e) s_e (d_dc may be NULL), d_c[0] =
+ * sum_e E(rho_e) s_e and d_c[1] = f^T u (0 when d_f is NULL) (d_c may be
+ * NULL).  d_u may be NULL only when d_dc and d_c are.  K is the same, value
+ * for value, as soptx_assemble + the mask's Dirichlet step, and d_dc, d_c
+ * are those of soptx_evaluate (the same kernels), in both precision forms.
+ * d_rho: [n_cells]; d_u, d_f: [ndof] double; d_K_vals: [nnz]; d_dc:
+ * [n_cells]; d_c: 2 doubles.  Asynchronous on stream; the compliance's
+ * partials live in a per-(device, stream) workspace allocated on first use. */
+int soptx_step(soptx_pattern h, soptx_dirichlet bc, const soptx_material *m, const void *d_rho,
+               const double *d_u, const double *d_f, double *d_K_vals, void *d_dc, double *d_c,
+               int32_t prec, void *stream);
+
 /* Release every device and host resource of h (NULL is allowed). */
 void soptx_destroy_pattern(soptx_pattern h);
 

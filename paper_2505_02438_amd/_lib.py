@@ -85,6 +85,9 @@ def lib():
         "soptx_compliance": [_P, ctypes.POINTER(Material), _P, _P, _P, _P, _I32, _P],
         "soptx_evaluate": [_P, ctypes.POINTER(Material), _P, _P, _P, _P, _P, _I32, _P],
         "soptx_evaluate_noalloc": [_P, ctypes.POINTER(Material), _P, _P, _P, _P, _P, _I32, _P],
+        "soptx_build_dirichlet": [_P, _P, ctypes.POINTER(_P), _P],
+        "soptx_dirichlet_info": [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64)],
+        "soptx_step": [_P, _P, ctypes.POINTER(Material), _P, _P, _P, _P, _P, _P, _I32, _P],
         "soptx_assemble_backward": [_P, ctypes.POINTER(Material), _P, _P, _P, _P, _I32, _P],
         "soptx_spmv": [_P, _P, _P, _P, _P],
         "soptx_pcg": [_P, _P, _P, _P, ctypes.c_double, _I32, ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_double),
@@ -117,6 +120,8 @@ def lib():
         fn.restype = _I
     L.soptx_destroy_pattern.argtypes = [_P]
     L.soptx_destroy_pattern.restype = None
+    L.soptx_destroy_dirichlet.argtypes = [_P]
+    L.soptx_destroy_dirichlet.restype = None
     L.soptx_destroy_filter.argtypes = [_P]
     L.soptx_destroy_filter.restype = None
     L.soptx_debug_host_plan_free.argtypes = [_P]

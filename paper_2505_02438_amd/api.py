@@ -15,7 +15,7 @@ import numpy as np
 from . import _lib
 from ._lib import BF16_FP32ACC, FP32, FP64, REF_QUADRATURE, REF_SYMBOLIC, check, lib
 
-__all__ = ["Material", "Pattern", "FP64", "FP32", "BF16_FP32ACC", "REF_SYMBOLIC", "REF_QUADRATURE",
+__all__ = ["Material", "Pattern", "Dirichlet", "FP64", "FP32", "BF16_FP32ACC", "REF_SYMBOLIC", "REF_QUADRATURE",
            "reference_tensor", "validate_mesh", "host_plan"]
 
 _DIM = {1: 2, 2: 2, 3: 3, 4: 3, 5: 3}
@@ -283,6 +283,28 @@ class Pattern:
                                    _dptr(c, "c", torch.float64, 2), prec, _stream_ptr(stream)), "soptx_evaluate")
         return dc, c
 
+    def step(self, material: Material, rho, u=None, f=None, bc: Optional["Dirichlet"] = None, K=None, dc=None,
+             c=None, prec: int = FP64, stream=None, want_dc: bool = True, want_c: bool = True):
+        """The whole step in one pass (soptx_step): K (FP64, with the Dirichlet
+        rows and columns of bc) and, when u is given, dc and c = [u^T K u, f^T u].
+        Returns (K, dc, c) (dc, c None without u or when not wanted)."""
+        import torch
+        with _on(stream):
+            if K is None:
+                K = torch.empty(self.nnz, dtype=torch.float64, device=rho.device)
+            if u is not None and dc is None and want_dc:
+                dc = torch.empty(self.n_cells, dtype=self._rho_dtype(prec), device=rho.device)
+            if u is not None and c is None and want_c:
+                c = torch.empty(2, dtype=torch.float64, device=rho.device)
+        mc = material._c()
+        check(lib().soptx_step(self._h, None if bc is None else bc._h, ctypes.byref(mc),
+                               _dptr(rho, "rho", self._rho_dtype(prec), self.n_cells),
+                               _dptr(u, "u", torch.float64, self.ndof), _dptr(f, "f", torch.float64, self.ndof),
+                               _dptr(K, "K", torch.float64, self.nnz),
+                               _dptr(dc, "dc", self._rho_dtype(prec), self.n_cells),
+                               _dptr(c, "c", torch.float64, 2), prec, _stream_ptr(stream)), "soptx_step")
+        return K, dc, c
+
     def spmv(self, K, x, out=None, stream=None):
         """y = K x on the pattern (FP64)."""
         import torch
@@ -323,6 +345,36 @@ class Pattern:
                                             _dptr(out, "drho", self._rho_dtype(prec), self.n_cells), prec,
                                             _stream_ptr(stream)), "soptx_assemble_backward")
         return out
+
+
+class Dirichlet:
+    """Dirichlet rows and columns bound once to a pattern (soptx_build_dirichlet):
+    mask is a host array of ndof uint8, nonzero = fixed dof.  Used by
+    Pattern.step; close it (or let it be collected) before the pattern."""
+
+    def __init__(self, pattern: Pattern, mask, stream=None):
+        mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        if mask.shape != (pattern.ndof,):
+            raise ValueError(f"mask must have {pattern.ndof} entries")
+        h = ctypes.c_void_p()
+        check(lib().soptx_build_dirichlet(pattern._h, mask.ctypes.data, ctypes.byref(h), _stream_ptr(stream)),
+              "soptx_build_dirichlet")
+        self._h = h
+        self._pattern = pattern   # keeps the pattern alive while the table exists
+        nf, ng = ctypes.c_int64(), ctypes.c_int64()
+        check(lib().soptx_dirichlet_info(h, ctypes.byref(nf), ctypes.byref(ng)), "soptx_dirichlet_info")
+        self.n_fixed, self.n_groups = nf.value, ng.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().soptx_destroy_dirichlet(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def filter_stencil_host(elem: int, coords, cells, rmin: float):

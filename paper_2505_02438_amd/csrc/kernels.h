@@ -35,6 +35,9 @@ struct AsmParams {
     double lam, mu;  // Lame constants at unit modulus (plane-stress lambda* in 2D)
     int kmax;
     int64_t stage;   // doubles of LDS stage needed by the largest group
+    // the fused step (soptx_step) only; null in soptx_assemble
+    const int32_t *bc_off;         // [G] offset of the group's Dirichlet bits, -1: none (null: no table)
+    const uint8_t *bc_bits;        // per group [n_nodes][deg] bits of dirichlet_entry
 };
 
 struct EnergyParams {
@@ -74,11 +77,13 @@ struct BwdParams {
     double lam, mu;
 };
 
-hipError_t launch_assemble(int elem, int prec, const AsmParams &P, int64_t ngroups, hipStream_t st);
+// fuse: the whole step (Dirichlet table, energies, dc, compliance partials)
+hipError_t launch_assemble(int elem, int prec, const AsmParams &P, int64_t ngroups, hipStream_t st, bool fuse = false);
 hipError_t launch_dirichlet(int dim, const int32_t *row_ptr, const int32_t *nb_tslot, const uint16_t *nb_tdeg,
                             const uint8_t *mask, double *K, int64_t ndof, hipStream_t st);
 hipError_t launch_energy(int elem, int prec, const EnergyParams &P, hipStream_t st);
 hipError_t launch_finalize(const double *partials, int n, int with_f, double *c, hipStream_t st);
+
 // the allocation-free evaluate: its block partials live in a fixed device
 // array of 2 x kNoAllocBlocks doubles (256 elements per block); the address
 // of the current device's copy (device must be current)

@@ -134,8 +134,12 @@ static size_t assemble_lds_bytes(int dim, int nen, int prec, int64_t stage, int 
 // Persistent, warp-specialised assembly.  One workgroup of 16 waves per CU
 // walks the node groups g0 = blockIdx.x, g0 + gridDim.x, ...  The groups are
 // in node order, so at any time the whole chip writes one contiguous stretch
-// of K (slicing the groups per XCD instead, to share element loads in an
-// XCD's L2, spreads the writes over eight distant stretches and is slower).
+// of K (a window of gridDim.x consecutive groups).  Workgroups are dealt to
+// the 8 XCDs round robin; workgroup b takes slot (b mod 8) gridDim.x/8 + b/8
+// of each window, so every XCD walks a contiguous run of the window and
+// neighbouring groups find their shared element data in that XCD's L2
+// (slicing the whole group range per XCD instead spreads the writes over
+// eight distant stretches and is slower).
 // In step s:
 //   - compute waves (0..7) assemble group s into LDS stage s&1: each takes a
 //     pair of neighbour positions of the group's signature from a ticket
@@ -155,12 +159,27 @@ static size_t assemble_lds_bytes(int dim, int nen, int prec, int64_t stage, int 
 // wide work item, each phase's contributions in that order, then the phases
 // by a butterfly), then L(A) = lam A + mu A^T + mu tr(A) I; fixed by the
 // mesh, independent of waves and streams.
+//
+// FUSE (soptx_step): the compute waves also apply a bound Dirichlet table
+// while they stage a block (a fixed row or column: 0, the diagonal entry of a
+// fixed dof: 1), so the stored K already carries the boundary conditions and
+// no pass of its own follows.
+
+// Dirichlet bits of one stored block (node n, neighbour J): bit a (a < DIM):
+// row dof DIM n + a is fixed; bit 3 + c: column dof DIM J + c is fixed; bit 6:
+// J == n.  An entry in a fixed row or column is 0, the diagonal entry of a
+// fixed dof 1 (zero prescribed values).
+__device__ __forceinline__ double dirichlet_entry(int bits, int a, int c, double v) {
+    if (((bits >> a) | (bits >> (3 + c))) & 1) return (a == c && (bits & 64)) ? 1.0 : 0.0;
+    return v;
+}
+
 constexpr int kAsmThreads = 1024;
 constexpr int kCompWaves = 8, kStoreWaves = 4, kLoadWaves = 4;
 static_assert(kCompWaves + kStoreWaves + kLoadWaves == kAsmThreads / 64, "wave roles");
 static_assert(2 * kGroupNodes == 64, "two positions per wavefront");
 
-template <int DIM, int NEN, int PREC>
+template <int DIM, int NEN, int PREC, bool FUSE>
 __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
     using T = typename CT<PREC>::T;
     using R = typename std::conditional<PREC == kF64, double, float>::type;  // rho as stored
@@ -179,10 +198,11 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
     uint16_t *sn2l = reinterpret_cast<uint16_t *>(srows + 3 * NG * 2);      // [2][kmax][NG]
     __shared__ int ticket[2];
     // group headers, one per row-offset buffer: nn, deg, posoff, blk, flags,
-    // first wide work item, number of wide work items.
+    // first wide work item, number of wide work items, offset of the group's
+    // Dirichlet bits (-1: none).
     // Written by the load waves with the group's other data, so that the
     // compute and store waves start a step without a chain of scalar loads
-    __shared__ int shdr[3][7];
+    __shared__ int shdr[3][8];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -190,7 +210,7 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
     const int64_t NC = P.n_cells;
     const int ngr = P.n_groups;
     const int stride = gridDim.x;
-    const int g0 = blockIdx.x;
+    const int g0 = stride % 8 == 0 ? (int)(blockIdx.x % 8) * (stride / 8) + (int)(blockIdx.x / 8) : (int)blockIdx.x;
     if (g0 >= ngr) return;
     const int nsteps = (ngr - 1 - g0) / stride + 2;  // groups of this workgroup, plus the last store step
     const int n2l_stride = P.kmax * NG;
@@ -287,6 +307,7 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
             const int wi0 = ldc(P.sig_witem_ptr, sg);
             shdr[rb][5] = wi0;
             shdr[rb][6] = ldc(P.sig_witem_ptr, sg + 1) - wi0;
+            shdr[rb][7] = (FUSE && P.bc_off) ? P.bc_off[gg] : -1;
         }
     };
 
@@ -302,6 +323,7 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
         const int flags = wave_uniform(shdr[rb][4]);
         const int wi0 = wave_uniform(shdr[rb][5]);
         const int nwi = wave_uniform(shdr[rb][6]);
+        const int bcoff = FUSE ? wave_uniform(shdr[rb][7]) : -1;
         const bool diag = flags & kGrpDiag;
         const int lgN = 5 - ((flags >> kGrpWideShift) & 3);  // N = 8 or 16
         const int N = 1 << lgN;
@@ -330,6 +352,8 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
                     cnt = ldc(rec, 24 + k);
                 }
             const bool mine = pp < np && node < nn;
+            // Dirichlet bits of the lane's block, fetched now and used at the end
+            const int bcb = (FUSE && bcoff >= 0 && mine && q == 0) ? P.bc_bits[bcoff + node * deg + p] : 0;
             double acc[DIM][DIM];
 #pragma unroll
             for (int a = 0; a < DIM; a++)
@@ -387,6 +411,7 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
                     for (int c = 0; c < DIM; c++) {
                         double o = P.lam * acc[a][c] + P.mu * acc[c][a];
                         if (a == c) o += P.mu * tr;
+                        if (FUSE && bcoff >= 0) o = dirichlet_entry(bcb, a, c, o);
                         st[a * rl + DIM * p + c] = o;
                     }
             }
@@ -404,6 +429,7 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
         const int deg = wave_uniform(shdr[rb][1]);
         const int posoff = wave_uniform(shdr[rb][2]);
         const int blk = wave_uniform(shdr[rb][3]);
+        const int bcoff = FUSE ? wave_uniform(shdr[rb][7]) : -1;
         const bool diag = flags & kGrpDiag;
         const int rl = DIM * deg;
         const bool hi = lane >= NG;
@@ -435,6 +461,9 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
                 nhi = ldc(P.sig_pos_ptr, posoff + pb + 1) - hi0;
             }
             const int mycnt = hi ? nhi : nlo;
+            // Dirichlet bits of the lane's block, fetched now and used at the end
+            const int pme = hi ? pb : pa;
+            const int bcb = (FUSE && bcoff >= 0 && node < nn && pme >= 0) ? P.bc_bits[bcoff + node * deg + pme] : 0;
             double acc[DIM][DIM];
 #pragma unroll
             for (int a = 0; a < DIM; a++)
@@ -499,6 +528,7 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
                     for (int c = 0; c < DIM; c++) {
                         double o = P.lam * acc[a][c] + P.mu * acc[c][a];
                         if (a == c) o += P.mu * tr;
+                        if (FUSE && bcoff >= 0) o = dirichlet_entry(bcb, a, c, o);
                         st[a * rl + DIM * p + c] = o;
                     }
             }
@@ -690,11 +720,6 @@ __global__ __launch_bounds__(256) void k_dirichlet(const int32_t *__restrict__ r
 // s_e = u_e^T K_e^0 u_e evaluated as the strain energy sum_q w_q |det J|
 // (lambda tr(eps)^2 + 2 mu eps:eps) at the reference quadrature points (exact
 // for affine elements; the same quadratic form as u_e^T K_e^0 u_e).
-// Writes dc_e = -E'(rho_e) s_e and a fixed-order block partial of
-// sum_e E(rho_e) s_e.  In the reduced-precision forms the element's rigid
-// motion (translation of node 0 and the rotation of the centroid gradient) is
-// removed in FP64 first; it is in the null space of K_e^0, so s_e is unchanged
-// in exact arithmetic while the FP32 part sees only the deforming part.
 // Q1 elements, FP64: the reference gradient of u at the 2^d Gauss points of
 // [0,1]^d by tensor-product factorisation.  The derivative along one axis does
 // not depend on that axis' coordinate: it is the (bi)linear interpolation, in
@@ -805,6 +830,12 @@ __device__ __forceinline__ double q1_quad_energy(const double (&u)[4][2], const 
     return 0.25 * sum;
 }
 
+// Element energies on their own, one thread per element: dc_e =
+// -E'(rho_e) s_e and a fixed-order block partial of sum_e E(rho_e) s_e.  In the
+// FP32 form the element's rigid motion (translation of node 0 and the rotation
+// of the centroid gradient) is removed in FP64 first; it is in the null space
+// of K_e^0, so s_e is unchanged in exact arithmetic while the FP32 part sees
+// only the deforming part.
 template <int DIM, int NEN, int NQ, int PREC>
 __global__ __launch_bounds__(256) void k_energy(EnergyParams P) {
     __shared__ double red[256];
@@ -1089,12 +1120,12 @@ __global__ __launch_bounds__(256) void k_backward(BwdParams P) {
 
 // ---------------------------------------------------------------- launchers
 
-template <int DIM, int NEN, int PREC>
+template <int DIM, int NEN, int PREC, bool FUSE>
 static hipError_t launch_assemble_t(const AsmParams &P, int64_t ngroups, hipStream_t st) {
     if (ngroups <= 0) return hipSuccess;
     const size_t lds = assemble_lds_bytes(DIM, NEN, PREC, P.stage, P.kmax);
     if (lds + 64 > 160 * 1024) return hipErrorInvalidValue;  // dynamic + static LDS
-    const void *fn = reinterpret_cast<const void *>(&k_assemble<DIM, NEN, PREC>);
+    const void *fn = reinterpret_cast<const void *>(&k_assemble<DIM, NEN, PREC, FUSE>);
     // the dynamic LDS limit only grows (per device, to the largest size
     // requested so far); the occupancy query runs once per device and size
     static std::mutex mu;
@@ -1123,15 +1154,19 @@ static hipError_t launch_assemble_t(const AsmParams &P, int64_t ngroups, hipStre
     }
     const int ncu = P.n_cu > 0 ? P.n_cu : 256;
     const int64_t grid = std::min<int64_t>(ngroups, (int64_t)per_cu * ncu);
-    hipLaunchKernelGGL((k_assemble<DIM, NEN, PREC>), dim3((unsigned)grid), dim3(kAsmThreads), lds, st, P);
+    hipLaunchKernelGGL((k_assemble<DIM, NEN, PREC, FUSE>), dim3((unsigned)grid), dim3(kAsmThreads), lds, st, P);
     return hipGetLastError();
 }
 
-hipError_t launch_assemble(int elem, int prec, const AsmParams &P, int64_t ngroups, hipStream_t st) {
-#define SOPTX_ASM(E, D, N)                                                    \
-    case E:                                                                   \
-        if (prec == kF64) return launch_assemble_t<D, N, kF64>(P, ngroups, st); \
-        return launch_assemble_t<D, N, kF32>(P, ngroups, st);
+hipError_t launch_assemble(int elem, int prec, const AsmParams &P, int64_t ngroups, hipStream_t st, bool fuse) {
+#define SOPTX_ASM(E, D, N)                                                                     \
+    case E:                                                                                    \
+        if (fuse) {                                                                            \
+            if (prec == kF64) return launch_assemble_t<D, N, kF64, true>(P, ngroups, st);      \
+            return launch_assemble_t<D, N, kF32, true>(P, ngroups, st);                        \
+        }                                                                                      \
+        if (prec == kF64) return launch_assemble_t<D, N, kF64, false>(P, ngroups, st);         \
+        return launch_assemble_t<D, N, kF32, false>(P, ngroups, st);
     switch (elem) {
         SOPTX_ASM(SOPTX_QUAD4, 2, 4)
         SOPTX_ASM(SOPTX_TRI3, 2, 3)

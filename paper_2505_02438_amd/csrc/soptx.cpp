@@ -84,6 +84,19 @@ struct soptx_host_plan_s {
     HostPlan hp;
 };
 
+// A Dirichlet mask bound to a pattern: for every group of the plan whose
+// blocks hold a fixed row or column, the offset of its bits (one byte per
+// (node, neighbour position), see dirichlet_entry), -1 for the others.
+struct soptx_dirichlet_s {
+    soptx_pattern h = nullptr;
+    int device = 0;
+    int64_t n_fixed = 0, n_groups = 0;
+    int32_t *off = nullptr;
+    uint8_t *bits = nullptr;
+    std::vector<void *> allocs;
+    int64_t device_bytes = 0;
+};
+
 namespace {
 
 template <class T>
@@ -572,6 +585,125 @@ int soptx_assemble_backward(soptx_pattern h, const soptx_material *m, const void
     lame(h, m, &P.lam, &P.mu);
     if (launch_backward(h->elem, prec, P, static_cast<hipStream_t>(stream)) != hipSuccess) return SOPTX_E_DEVICE;
     return SOPTX_OK;
+}
+
+int soptx_build_dirichlet(soptx_pattern h, const uint8_t *h_mask, soptx_dirichlet *out, void *stream) {
+    if (!out) return SOPTX_E_INVALID_ARG;
+    *out = nullptr;
+    if (!h || (h->ndof > 0 && !h_mask)) return SOPTX_E_INVALID_ARG;
+    if (!h->affine) return not_affine(h);
+    DeviceGuard dg(h->device);
+    if (!dg.ok) return SOPTX_E_DEVICE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    soptx_dirichlet_s *bc = new (std::nothrow) soptx_dirichlet_s();
+    if (!bc) return SOPTX_E_OOM;
+    bc->h = h;
+    bc->device = h->device;
+    auto fail = [&](int code) {
+        for (void *p : bc->allocs) (void)hipFree(p);
+        delete bc;
+        return code;
+    };
+    try {
+        const int dim = h->dim, d2 = dim * dim;
+        const int64_t G = h->ngroups;
+        for (int64_t r = 0; r < h->ndof; r++) bc->n_fixed += h_mask[r] ? 1 : 0;
+        // the plan's group tables and the neighbour lists, back from the device
+        std::vector<int32_t> gi((size_t)G * kGrpInfo), si((size_t)h->nsig * 4), gn((size_t)G * kGroupNodes),
+            rp((size_t)h->ndof + 1), nb((size_t)(h->nnz / d2));
+        auto down = [&](std::vector<int32_t> &v, const int32_t *d) {
+            return v.empty() || hipMemcpy(v.data(), d, v.size() * sizeof(int32_t), hipMemcpyDeviceToHost) == hipSuccess;
+        };
+        if (!down(gi, h->grp_info) || !down(si, h->sig_info) || !down(gn, h->grp_nodes) || !down(rp, h->row_ptr) ||
+            !down(nb, h->nb))
+            return fail(SOPTX_E_DEVICE);
+        std::vector<int32_t> off((size_t)G, -1);
+        std::vector<uint8_t> bits;
+        if (bc->n_fixed > 0) {
+            for (int64_t g = 0; g < G; g++) {
+                const int nn = gi[(size_t)(kGrpInfo * g + 1)];
+                const int deg = si[(size_t)(4 * gi[(size_t)(kGrpInfo * g)] + 1)];
+                std::vector<uint8_t> gb((size_t)nn * deg, 0);
+                bool any = false;
+                for (int l = 0; l < nn; l++) {
+                    const int64_t n = gn[(size_t)(g * kGroupNodes + l)];
+                    int row = 0;
+                    for (int a = 0; a < dim; a++) row |= h_mask[dim * n + a] ? 1 << a : 0;
+                    const int64_t b0 = rp[(size_t)(dim * n)] / d2;
+                    for (int p = 0; p < deg; p++) {
+                        const int64_t J = nb[(size_t)(b0 + p)];
+                        int col = 0;
+                        for (int c = 0; c < dim; c++) col |= h_mask[dim * J + c] ? 1 << (3 + c) : 0;
+                        const int v = row | col | (J == n ? 64 : 0);
+                        any = any || (row | col) != 0;
+                        gb[(size_t)l * deg + p] = (uint8_t)v;
+                    }
+                }
+                if (any) {
+                    if (bits.size() + gb.size() >= (size_t)INT32_MAX) return fail(SOPTX_E_OVERFLOW);
+                    off[(size_t)g] = (int32_t)bits.size();
+                    bits.insert(bits.end(), gb.begin(), gb.end());
+                    bc->n_groups++;
+                }
+            }
+        }
+        int rc;
+        if ((rc = upload_vector(bc->allocs, off, &bc->off, st, &bc->device_bytes)) ||
+            (rc = upload_vector(bc->allocs, bits, &bc->bits, st, &bc->device_bytes)))
+            return fail(rc);
+        if (hipStreamSynchronize(st) != hipSuccess) return fail(SOPTX_E_DEVICE);
+    } catch (const std::bad_alloc &) {
+        return fail(SOPTX_E_OOM);
+    }
+    *out = bc;
+    return SOPTX_OK;
+}
+
+int soptx_dirichlet_info(soptx_dirichlet bc, int64_t *n_fixed, int64_t *n_groups) {
+    if (!bc) return SOPTX_E_INVALID_ARG;
+    if (n_fixed) *n_fixed = bc->n_fixed;
+    if (n_groups) *n_groups = bc->n_groups;
+    return SOPTX_OK;
+}
+
+void soptx_destroy_dirichlet(soptx_dirichlet bc) {
+    if (!bc) return;
+    DeviceGuard dg(bc->device);
+    for (void *p : bc->allocs) (void)hipFree(p);
+    delete bc;
+}
+
+int soptx_step(soptx_pattern h, soptx_dirichlet bc, const soptx_material *m, const void *d_rho, const double *d_u,
+               const double *d_f, double *d_K_vals, void *d_dc, double *d_c, int32_t prec, void *stream) {
+    if (!h || !valid_prec(prec)) return SOPTX_E_INVALID_ARG;
+    if (!h->affine) return not_affine(h);
+    int rc = check_material(m);
+    if (rc) return rc;
+    if (bc && bc->h != h) return SOPTX_E_INVALID_ARG;
+    if ((h->n_cells > 0 && !d_rho) || (h->nnz > 0 && !d_K_vals)) return SOPTX_E_INVALID_ARG;
+    if (h->n_cells > 0 && (d_dc || d_c) && !d_u) return SOPTX_E_INVALID_ARG;
+    DeviceGuard dg(h->device);
+    if (!dg.ok) return SOPTX_E_DEVICE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // assembly with the Dirichlet table applied while the blocks are staged
+    if (h->ngroups > 0) {
+        AsmParams P{};
+        P.grp_info = h->grp_info; P.grp_nodes = h->grp_nodes; P.grp_elems = h->grp_elems; P.grp_n2l = h->grp_n2l;
+        P.grp_rows = h->grp_rows; P.n_groups = h->ngroups; P.n_cu = h->n_cu;
+        P.sig_info = h->sig_info; P.sig_pos_ptr = h->sig_pos_ptr; P.sig_contrib = h->sig_contrib;
+        P.sig_pairs = h->sig_pairs; P.sig_witems = h->sig_witems; P.sig_witem_ptr = h->sig_witem_ptr;
+        P.geo = h->geo; P.rho = d_rho;
+        P.M = h->M; P.M32 = h->M32; P.K = d_K_vals;
+        P.n_cells = h->n_cells; P.E0 = m->E0; P.Emin = m->Emin; P.p = m->p; P.ip = int_exponent(m->p);
+        lame(h, m, &P.lam, &P.mu);
+        P.kmax = h->kmax; P.stage = h->stage;
+        P.bc_off = (bc && bc->n_groups > 0) ? bc->off : nullptr;
+        P.bc_bits = bc ? bc->bits : nullptr;
+        if (launch_assemble(h->elem, prec, P, h->ngroups, st, true) != hipSuccess) return SOPTX_E_DEVICE;
+    }
+    if (!d_dc && !d_c) return SOPTX_OK;
+    // element energies, dc and c: the kernels of soptx_evaluate
+    return evaluate_impl(h, m, d_rho, d_u, d_f, d_dc, d_c, prec, stream, false);
 }
 
 void soptx_destroy_pattern(soptx_pattern h) {
