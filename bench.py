@@ -4,17 +4,21 @@
 Workload: the 3D cantilever of 120 x 40 x 40 unit Q1 hexahedra (192,000
 elements, 610,203 dofs, 47,568,609 stored K entries), rho ~ Beta(2, 2), p = 3,
 E0 = 1, Emin = 1e-9, nu = 0.3, x = 0 face clamped, synthetic u ~ N(0, 1)
-(zero on fixed dofs).  One step = soptx_assemble (FP64 CSR values) +
-soptx_apply_dirichlet (the clamped face) + soptx_evaluate (dc and c), all
-inputs resident in HBM, three rotating output buffers so that writes do not
-hit in the 256 MB MALL.  The assembly kernel is timed on its own with HIP
-events on the bench stream (its roofline).  A second timed region replays the
-same step as a captured HIP graph (graph_value, graph_ms_per_step).  Prints
-one JSON line.
+(zero on fixed dofs).  One step = soptx_step (FP64 CSR values with the
+clamped face's rows and columns, from a Dirichlet table bound once) +
+soptx_evaluate (dc and c), all inputs resident in HBM, three rotating output
+buffers so that writes do not hit in the 256 MB MALL.  HIP events on the
+bench stream time the assembly (its roofline) and the evaluation of every
+step.  A second timed region replays the same step as a captured HIP graph
+(graph_value, graph_ms_per_step).  Then: the FP32 form of the same step, the
+labelled rows (the same cantilever sheared, so every J^-1 is full; P1
+triangles 600x200; P2 tetrahedra 48^3 in both forms), the solve, filter, OC
+and loop measurements, serving, and the CPU oracle on a bounded sample.
+Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps 50] [--warmup 5]
 
---workload runs the same step on one of the other configurations (P1
+--workload runs the headline step on one of the other configurations (P1
 triangles 600x200, P2 tetrahedra 48^3, Q1 hexahedra 96^3) instead.
 """
 from __future__ import annotations
@@ -27,6 +31,8 @@ import platform
 import statistics
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -54,39 +60,27 @@ WORKLOADS = {
     "p2box48": ("3D box 48^3 cubes x 6 jittered Kuhn P2 tetrahedra (663,552 elements, 2,738,019 dofs, "
                 "231,797,385 K entries), rho~U(0.001,1), p=3, nu=0.3, x=0 face clamped, u~N(0,1)",
                 lambda I: I.box_p2()),
+    "hex120x40x40_sheared": ("the 120x40x40 cantilever mapped by x -> A x, A = [[1, .3, .1], [-.2, 1, .25], "
+                             "[.15, -.1, 1]]: every element affine with a full J^-1 (the general affine "
+                             "contraction), rho, u and supports as the headline", lambda I: I.cantilever_hex(skew="global")),
     "hex96": ("3D cube 96^3 unit Q1 hexahedra (884,736 elements, 2,738,019 dofs, 217,238,121 K entries; the "
               "largest serving request), rho~Beta(2,2), p=3, nu=0.3, x=0 face clamped, u~N(0,1)",
               lambda I: I.cantilever_hex(96, 96, 96)),
 }
-STEP = "; step = assemble (FP64 CSR) + Dirichlet rows/columns + sensitivity + compliance"
+STEP = "; step = assemble (FP64 CSR) with the Dirichlet rows/columns + sensitivity + compliance"
 
 
 def algorithmic_bytes(n_nodes, n_cells, nnz, dim, nen, ndof):
     """Minimum bytes each call must move (FP64 form).
 
-    assemble: write K values (nnz*8); read rho (NC*8), coordinates
-    (n_nodes*dim*8) and cells (NC*nen*4).
+    assemble with Dirichlet: write K values (nnz*8); read rho (NC*8),
+    coordinates (n_nodes*dim*8), cells (NC*nen*4) and the fixed-dof mask
+    (ndof bytes).
     evaluate: read rho, u (ndof*8), coordinates, cells; write dc (NC*8).
     """
-    asm = nnz * 8 + n_cells * 8 + n_nodes * dim * 8 + n_cells * nen * 4
+    asm = nnz * 8 + n_cells * 8 + n_nodes * dim * 8 + n_cells * nen * 4 + ndof
     ev = n_cells * 8 + ndof * 8 + n_nodes * dim * 8 + n_cells * nen * 4 + n_cells * 8
     return asm, ev
-
-
-def cpu_baseline(pr, rp, ci, min_seconds=10.0):
-    """The CPU oracle as it stands (single thread) on the whole workload,
-    repeated until min_seconds have passed; elements/s of the median pass."""
-    from oracle import oracle as O
-    m = pr.mesh
-    times = []
-    t_all = time.perf_counter()
-    while not times or time.perf_counter() - t_all < min_seconds:
-        t0 = time.perf_counter()
-        O.assemble(m.elem, m.coords, m.cells, pr.rho, rp, ci, mask=pr.mask)
-        O.sensitivity(m.elem, m.coords, m.cells, pr.rho, pr.u)
-        O.compliance(m.elem, m.coords, m.cells, pr.rho, pr.u)
-        times.append(time.perf_counter() - t0)
-    return m.n_cells / statistics.median(times), times
 
 
 def solve_run(pat, m, K, f, stream, rtol, reps=20):
@@ -389,17 +383,227 @@ def serving_run(count, slots=4, budget=32 << 30):
             "poisson_elements_per_s": st_p["elements_per_s"]}
 
 
+class StepState:
+    """Device inputs of one workload, its Dirichlet table bound once, and
+    `nbuf` rotating outputs (so that successive steps do not write K into
+    lines the 256 MB MALL still holds)."""
+
+    def __init__(self, pr, pat, prec, stream, nbuf=3):
+        import torch
+        from paper_2505_02438_amd import api
+        dev = torch.device("cuda:0")
+        self.pat, self.prec, self.nbuf = pat, prec, nbuf
+        self.mat = api.Material(E0=pr.E0, Emin=pr.Emin, nu=pr.nu, p=pr.p)
+        rdt = torch.float64 if prec == api.FP64 else torch.float32
+        with torch.cuda.stream(stream):
+            self.rho = torch.from_numpy(pr.rho).to(dev).to(rdt)
+            self.u = torch.from_numpy(pr.u).to(dev)
+            self.Ks = [torch.empty(pat.nnz, dtype=torch.float64, device=dev) for _ in range(nbuf)]
+            self.dcs = [torch.empty(pat.n_cells, dtype=rdt, device=dev) for _ in range(nbuf)]
+            self.cs = [torch.zeros(2, dtype=torch.float64, device=dev) for _ in range(nbuf)]
+        self.bc = api.Dirichlet(pat, pr.mask, stream=stream)
+        torch.cuda.synchronize()
+
+    def step(self, i, stream, ev=None):
+        """One step: K with the Dirichlet rows and columns (soptx_step, the
+        bound table), then dc and c (soptx_evaluate); events around each."""
+        b = i % self.nbuf
+        if ev is not None:
+            ev[0].record(stream)
+        self.pat.step(self.mat, self.rho, bc=self.bc, K=self.Ks[b], prec=self.prec, stream=stream)
+        if ev is not None:
+            ev[1].record(stream)
+        self.pat.evaluate(self.mat, self.rho, self.u, dc=self.dcs[b], c=self.cs[b], prec=self.prec, stream=stream)
+        if ev is not None:
+            ev[2].record(stream)
+
+
+def spin_up(st, stream, seconds):
+    """Untimed steps for `seconds` of wall time, so that the timed steps run at
+    the clocks a busy GPU holds (after the seconds of host-only work of the
+    pattern build the GPU idles at lower clocks, and a few warm-up steps of
+    0.1 ms do not bring them back)."""
+    import torch
+    t0 = time.perf_counter()
+    i = 0
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(20):
+            st.step(i, stream)
+            i += 1
+        torch.cuda.synchronize()
+    return i
+
+
+def pct(xs):
+    xs = sorted(xs)
+    n = len(xs)
+    return {"p10": xs[n // 10], "p50": xs[n // 2], "p90": xs[min(n - 1, (9 * n) // 10)]}
+
+
+def timed_steps(st, stream, steps, warmup):
+    """warmup untimed steps, then `steps` steps timed by the wall clock
+    (synchronised on both sides) with HIP events on the bench stream around
+    the assembly and the evaluation of each step."""
+    import torch
+    for i in range(warmup):
+        st.step(i, stream)
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        st.step(i, stream, events[i])
+    torch.cuda.synchronize()
+    total_s = time.perf_counter() - t0
+    asm_ms = [e[0].elapsed_time(e[1]) for e in events]
+    ev_ms = [e[1].elapsed_time(e[2]) for e in events]
+    return total_s, asm_ms, ev_ms
+
+
+def row_scaled_err(rows, K, Kref):
+    """max over stored entries of |K - Kref| / max |Kref| of the entry's row (on the GPU)."""
+    import torch
+    rmax = torch.zeros(int(rows.max()) + 1, dtype=torch.float64, device=K.device)
+    rmax.scatter_reduce_(0, rows, Kref.abs(), "amax")
+    return float(((K - Kref).abs() / rmax[rows].clamp_min(1e-300)).max())
+
+
+def labelled_run(name, desc, pr, stream, steps, warmup, precs, extra=None):
+    """The headline step (assembly with Dirichlet, then dc and c) on another
+    mesh: HIP events per stage, the assembly kernel against its algorithmic
+    bytes, in each precision form of precs (FP32 also gives its error against
+    the FP64 result of the same inputs)."""
+    import torch
+    from paper_2505_02438_amd import api
+    m = pr.mesh
+    t0 = time.perf_counter()
+    pat = api.Pattern.from_mesh(m)
+    build_s = time.perf_counter() - t0
+    stats = pat.stats()
+    asm_bytes, ev_bytes = algorithmic_bytes(m.n_nodes, m.n_cells, pat.nnz, m.dim, m.nen, m.ndof)
+    out = {"workload": desc, "elements": m.n_cells, "ndof": pat.ndof, "nnz": pat.nnz,
+           "pattern_build_s": build_s, "groups": stats["n_groups"], "signatures": stats["n_signatures"]}
+    if extra:
+        out.update(extra)
+    states = {}
+    for prec in precs:
+        st = states[prec] = StepState(pr, pat, prec, stream)
+        spin_up(st, stream, 0.2)
+        total_s, asm_ms, ev_ms = timed_steps(st, stream, steps, warmup)
+        a = statistics.mean(asm_ms) / 1e3
+        key = "fp64" if prec == api.FP64 else "fp32"
+        out[key] = {"elements_per_s": m.n_cells * steps / total_s, "ms_per_step": total_s / steps * 1e3,
+                    "assemble_avg_ms": a * 1e3, "evaluate_avg_ms": statistics.mean(ev_ms),
+                    "assemble_achieved_GBs": asm_bytes / a / 1e9,
+                    "assemble_frac": asm_bytes / a / 1e9 / HBM_PEAK_GBS,
+                    "step_frac": (asm_bytes + ev_bytes) / (total_s / steps) / 1e9 / HBM_PEAK_GBS}
+        if prec != api.FP64 and api.FP64 in states:
+            out[key].update(precision_error(pat, states[api.FP64], st))
+    for st in states.values():
+        st.bc.close()
+    out["jacobian_path"] = jacobian_path(stats)
+    out["assemble_algorithmic_bytes"] = asm_bytes
+    out["evaluate_algorithmic_bytes"] = ev_bytes
+    return out
+
+
+def precision_error(pat, ref, st):
+    """The FP32 form against the FP64 form of the same step (the last outputs
+    of each): K row-scaled, dc scaled by max |dc|, c relative."""
+    import torch
+    rp, _ = pat.pattern()
+    rows = torch.repeat_interleave(torch.arange(pat.ndof, device="cuda"),
+                                   torch.from_numpy(np.diff(rp).astype(np.int64)).cuda())
+    torch.cuda.synchronize()
+    # every buffer holds the same step's result (the inputs do not change)
+    k_err = row_scaled_err(rows, st.Ks[0], ref.Ks[0])
+    dc64, dc32 = ref.dcs[0], st.dcs[0].double()
+    dc_err = float((dc32 - dc64).abs().max() / dc64.abs().max())
+    c_err = float((st.cs[0][0] - ref.cs[0][0]).abs() / ref.cs[0][0].abs())
+    return {"K_row_scaled_err_vs_fp64": k_err, "dc_err_vs_fp64": dc_err, "c_rel_err_vs_fp64": c_err}
+
+
+def jacobian_path(stats):
+    """Which contraction the assembly ran: groups of axis-aligned elements
+    (diagonal J^-1) use the shorter one, the others the general affine one."""
+    d, g = stats["n_groups_diag"], stats["n_groups"]
+    kind = "axis-aligned (diagonal J^-1)" if d == g else "general affine (full J^-1)" if d == 0 else "mixed"
+    return {"kind": kind, "groups_diagonal": d, "groups": g}
+
+
+def cpu_info():
+    """The host CPU as /proc/cpuinfo names it, its current clock and the
+    cores this process may use."""
+    model, mhz = platform.processor() or platform.machine(), None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                k, _, v = line.partition(":")
+                k = k.strip()
+                if k == "model name" and model in ("", "x86_64", platform.machine()):
+                    model = v.strip()
+                elif k == "cpu MHz" and mhz is None:
+                    mhz = float(v)
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"model": model, "mhz": mhz, "nproc": usable, "cpu_count": os.cpu_count()}
+
+
+def cpu_baseline_run(passes=5):
+    """The CPU oracle on a bounded sample of the headline workload: the same
+    cantilever cut to 120 x 40 x 8 elements (38,400 of the 192,000; rho and u
+    drawn the same way), one pass = oracle assemble (FP64, full pattern,
+    Dirichlet) + sensitivity + compliance; median of `passes` passes, serial
+    and as the row-block OpenMP variant (bitwise the serial result)."""
+    from oracle import oracle as O
+    from paper_2505_02438_amd import inputs as I
+    pr = I.cantilever_hex(120, 40, 8)
+    m = pr.mesh
+    rp, ci = O.pattern(m.elem, m.n_nodes, m.cells)
+    res = {}
+    for mt in (False, True):
+        ts = []
+        for _ in range(passes):
+            t0 = time.perf_counter()
+            O.assemble(m.elem, m.coords, m.cells, pr.rho, rp, ci, mask=pr.mask, mt=mt)
+            O.sensitivity(m.elem, m.coords, m.cells, pr.rho, pr.u, mt=mt)
+            O.compliance(m.elem, m.coords, m.cells, pr.rho, pr.u, mt=mt)
+            ts.append(time.perf_counter() - t0)
+        res[mt] = (m.n_cells / statistics.median(ts), ts)
+    threads = O.threads()
+    hw = cpu_info()
+    v1, t1 = res[False]
+    vt, tt = res[True]
+    return {
+        "value": v1, "unit": "elements/s", "cores": 1, "kind": "oracle",
+        "sample": f"120x40x8 slab of the same cantilever ({m.n_cells} elements, Q1 hex, rho~Beta(2,2), "
+                  f"x=0 clamped); one pass = oracle assemble (FP64, full pattern, Dirichlet) + sensitivity + "
+                  f"compliance; median of {passes} passes ({statistics.median(t1):.2f} s), single thread",
+        "cpu": hw,
+        "row_block_openmp": {"value": vt, "unit": "elements/s", "cores": threads, "kind": "oracle (OpenMP rows)",
+                             "median_pass_s": statistics.median(tt), "passes": passes,
+                             "speedup_vs_serial": vt / v1},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0,
-                    help="minimum CPU time of the oracle baseline (whole passes over the workload)")
+    ap.add_argument("--cpu-passes", type=int, default=5, help="oracle passes of the CPU baseline (median)")
+    ap.add_argument("--spin-up", type=float, default=0.3,
+                    help="seconds of untimed steps before the warm-up steps (GPU clocks ramp-up)")
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the second timed region (the same step replayed as a captured HIP graph)")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="hex120x40x40")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 form of the headline step")
+    ap.add_argument("--no-labelled", action="store_true",
+                    help="skip the labelled rows (sheared hexahedra, the other workloads)")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="skip the SpMV / preconditioned CG measurement")
     ap.add_argument("--solve-rtol", type=float, default=1e-9)
@@ -438,71 +642,39 @@ def main():
     pat = api.Pattern.from_mesh(m)
     build_s = time.perf_counter() - t0
     stats = pat.stats()
-    mat = api.Material(E0=pr.E0, Emin=pr.Emin, nu=pr.nu, p=pr.p)
 
     stream = torch.cuda.Stream()
-    with torch.cuda.stream(stream):
-        rho = torch.from_numpy(pr.rho).to(dev)
-        u = torch.from_numpy(pr.u).to(dev)
-        mask = torch.from_numpy(pr.mask).to(dev)
-        nbuf = 3
-        Ks = [torch.empty(pat.nnz, dtype=torch.float64, device=dev) for _ in range(nbuf)]
-        dcs = [torch.empty(pat.n_cells, dtype=torch.float64, device=dev) for _ in range(nbuf)]
-        cs = [torch.zeros(2, dtype=torch.float64, device=dev) for _ in range(nbuf)]
-    torch.cuda.synchronize()
-
-    def step(i, ev=None):
-        b = i % nbuf
-        if ev is not None:
-            ev[0].record(stream)
-        pat.assemble(mat, rho, None, out=Ks[b], stream=stream)
-        if ev is not None:
-            ev[1].record(stream)
-        pat.apply_dirichlet(mask, Ks[b], stream=stream)
-        if ev is not None:
-            ev[2].record(stream)
-        pat.evaluate(mat, rho, u, dc=dcs[b], c=cs[b], stream=stream)
-        if ev is not None:
-            ev[3].record(stream)
-
-    for i in range(args.warmup):
-        step(i)
-    torch.cuda.synchronize()
+    st = StepState(pr, pat, api.FP64, stream)
+    mat, rho = st.mat, st.rho
 
     graphs = None
     if not args.no_graph:
         # one captured step per output buffer (HIP graph replay; the kernels
-        # and their order are those of step()), timed after the eager region
+        # and their order are those of the eager step), timed after the eager region
+        st.step(0, stream)
+        torch.cuda.synchronize()
         graphs = []
-        for b in range(nbuf):
+        for b in range(st.nbuf):
             g = torch.cuda.CUDAGraph()
             with torch.cuda.graph(g, stream=stream):
-                step(b)
+                st.step(b, stream)
             graphs.append(g)
         torch.cuda.synchronize()
 
-    events = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(i, events[i])
-    torch.cuda.synchronize()
-    total_s = time.perf_counter() - t0
+    spun = spin_up(st, stream, args.spin_up)
+    total_s, asm_ms, ev_ms = timed_steps(st, stream, args.steps, args.warmup)
     graph_s = None
     if graphs is not None:
         with torch.cuda.stream(stream):
             for i in range(args.warmup):
-                graphs[i % nbuf].replay()
+                graphs[i % st.nbuf].replay()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         with torch.cuda.stream(stream):
             for i in range(args.steps):
-                graphs[i % nbuf].replay()
+                graphs[i % st.nbuf].replay()
         torch.cuda.synchronize()
         graph_s = time.perf_counter() - t0
-    asm_ms = [e[0].elapsed_time(e[1]) for e in events]
-    bc_ms = [e[1].elapsed_time(e[2]) for e in events]
-    ev_ms = [e[2].elapsed_time(e[3]) for e in events]
 
     if args.copy_probe:
         # known traffic for the counter calibration: a 1 GiB fill (writes
@@ -514,6 +686,7 @@ def main():
             for _ in range(3):
                 torch.mul(x, 2.0, out=y)
         torch.cuda.synchronize()
+        del x, y
 
     # the box's own streaming rates, for the roofline: a 1 GiB fill (writes)
     # and a 1 GiB copy (reads + writes), HIP events on the bench stream, median
@@ -569,7 +742,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_assemble<%d,%d,fp64>" % (m.dim, m.nen),
+            "kernel": "k_assemble<%d,%d,fp64> with the bound Dirichlet table" % (m.dim, m.nen),
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -581,9 +754,13 @@ def main():
             "measured_copy_GBs": copy_gbs,
             "frac_of_measured_fill": achieved / fill_gbs,
         },
-        "stage_ms": {"assemble": statistics.mean(asm_ms), "dirichlet": statistics.mean(bc_ms),
-                     "evaluate": statistics.mean(ev_ms)},
+        "step_frac": (asm_bytes + ev_bytes) / (total_s / args.steps) / 1e9 / HBM_PEAK_GBS,
+        "stage_ms": {"assemble_dirichlet": statistics.mean(asm_ms), "evaluate": statistics.mean(ev_ms)},
+        "stage_ms_pct": {"assemble_dirichlet": pct(asm_ms), "evaluate": pct(ev_ms)},
         "launch": "eager (value, stage_ms and roofline from this timed region)",
+        "spin_up": {"seconds": args.spin_up, "steps": spun,
+                    "note": "untimed steps before the warm-up steps, so that the GPU clocks have ramped"},
+        "jacobian_path": jacobian_path(stats),
         "graph_value": None if graph_s is None else n * args.steps / graph_s,
         "graph_ms_per_step": None if graph_s is None else graph_s / args.steps * 1e3,
         "evaluate_algorithmic_bytes": ev_bytes,
@@ -591,13 +768,35 @@ def main():
         "plan": {"groups": stats["n_groups"], "signatures": stats["n_signatures"],
                  "plan_bytes": stats["plan_bytes"]},
     }
+    if not args.no_fp32:
+        st32 = StepState(pr, pat, api.FP32, stream)
+        spin_up(st32, stream, 0.2)
+        t32, a32, e32 = timed_steps(st32, stream, args.steps, args.warmup)
+        out["fp32"] = {"value": n * args.steps / t32, "ms_per_step": t32 / args.steps * 1e3,
+                       "stage_ms": {"assemble_dirichlet": statistics.mean(a32), "evaluate": statistics.mean(e32)},
+                       "value_ratio_vs_fp64": (n * args.steps / t32) / out["value"]}
+        out["fp32"].update(precision_error(pat, st, st32))
+        st32.bc.close()
+        del st32
     if not args.no_solve:
         f = torch.from_numpy(pr.f).to(dev)
-        out["solve"] = solve_run(pat, m, Ks[0], f, stream, args.solve_rtol)
+        out["solve"] = solve_run(pat, m, st.Ks[0], f, stream, args.solve_rtol)
     if not args.no_filter:
-        out["filter"] = filter_run(pat, m, mat, rho, Ks[0], stream)
+        out["filter"] = filter_run(pat, m, mat, rho, st.Ks[0], stream)
     if not args.no_oc:
-        out["oc"] = oc_run(pat, pat.n_cells, dcs[0], stream)
+        out["oc"] = oc_run(pat, pat.n_cells, st.dcs[0], stream)
+    st.bc.close()
+    del st
+    torch.cuda.empty_cache()
+    if not args.no_labelled:
+        rows = {}
+        for wl in ("hex120x40x40_sheared", "tri600x200", "p2box48"):
+            if wl != args.workload:
+                d, mk = WORKLOADS[wl]
+                rows[wl] = labelled_run(wl, d, mk(I), stream, min(args.steps, 20), 3,
+                                        (api.FP64, api.FP32) if wl == "p2box48" else (api.FP64,))
+                torch.cuda.empty_cache()
+        out["labelled"] = rows
     if args.to_iters > 0:
         out["optimisation_loop"] = to_loop_run(args.to_iters, stream)
     if not args.no_general:
@@ -608,17 +807,9 @@ def main():
         out["paper_runs"] = paper_runs()
     if not args.no_serving:
         out["serving"] = serving_run(args.serve_requests)
+        out["serving"]["burst_vs_plain"] = out["serving"]["burst_elements_per_s"] / out["value"]
     if not args.no_cpu_baseline:
-        from oracle import oracle as O
-        rp, ci = O.pattern(m.elem, m.n_nodes, m.cells)
-        v, times = cpu_baseline(pr, rp, ci, args.cpu_seconds)
-        out["cpu_baseline"] = {
-            "value": v, "unit": "elements/s", "cores": 1, "kind": "oracle",
-            "sample": f"the whole workload ({n} elements), {len(times)} passes of oracle assemble (FP64, "
-                      f"full pattern, Dirichlet) + sensitivity + compliance, median pass "
-                      f"{statistics.median(times):.2f} s, single thread on "
-                      f"{platform.processor() or platform.machine()} ({os.cpu_count()} cpus visible)",
-        }
+        out["cpu_baseline"] = cpu_baseline_run(args.cpu_passes)
     print(json.dumps(out))
 
 

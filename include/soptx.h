@@ -123,6 +123,8 @@ typedef struct {
     int64_t n_contributions; /* sum over elements of nen^2 block contributions */
     int64_t plan_bytes;      /* device bytes of the assembly plan (beyond the CSR pattern) */
     int64_t device_bytes;    /* all device bytes held by the handle */
+    int64_t n_groups_diag;   /* groups whose elements all have a diagonal J^-1 (axis-aligned boxes),
+                                assembled with the shorter contraction of such elements */
 } soptx_pattern_stats;
 
 /* Build the CSR pattern, the per-element geometry (J^-1, det J) and the

@@ -650,3 +650,151 @@ int oracle_solve_banded(int64_t n, const int64_t *row_ptr, const int32_t *col_id
 #undef LB
     return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * Multi-threaded variants (OpenMP), used only as the second row of the
+ * benchmark's CPU baseline.  They do the arithmetic of oracle_assemble,
+ * oracle_element_energy, oracle_sensitivity and oracle_compliance in the
+ * same per-value order, so each result is bitwise the serial one:
+ *  - assembly: thread t owns a contiguous block of rows holding about 1/T of
+ *    the stored entries and walks every element in ascending id, adding only
+ *    into its own rows, so every stored value still sums its elements in
+ *    ascending id (an element whose nodes fall in two blocks has K_e^0
+ *    computed by both threads);
+ *  - energies: elements split over threads (s_e is one element's own sum);
+ *  - compliance: energies in parallel, then the serial ascending sum.
+ * ---------------------------------------------------------------------- */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+int oracle_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* smallest row r in [0, n] with row_ptr[r] >= s */
+static int64_t first_row_at(const int64_t *row_ptr, int64_t n, int64_t s) {
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (row_ptr[mid] >= s) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+int oracle_assemble_mt(int elem, int64_t n_nodes, const double *coords, int64_t n_cells,
+                       const int32_t *cells, const double *rho, double E0, double Emin, double p,
+                       double nu, int plane_strain, const uint8_t *mask, const int64_t *row_ptr,
+                       const int32_t *col_idx, double *K) {
+    int dim = elem_dim(elem), nen = elem_nen(elem), bad = 0;
+    int64_t ndof, nnz;
+    if (dim < 0) return -1;
+    ndof = dim * n_nodes;
+    nnz = row_ptr[ndof];
+#pragma omp parallel reduction(| : bad)
+    {
+        int nt = 1, t = 0, ldof = dim * nen, i, j, a;
+        int64_t e, r, k, r0, r1;
+        double xe[3 * MAXNEN], Ke[MAXLDOF * MAXLDOF];
+#ifdef _OPENMP
+        nt = omp_get_num_threads();
+        t = omp_get_thread_num();
+#endif
+        r0 = first_row_at(row_ptr, ndof, nnz * t / nt);
+        r1 = t == nt - 1 ? ndof : first_row_at(row_ptr, ndof, nnz * (t + 1) / nt);
+        if (r1 > r0) memset(K + row_ptr[r0], 0, sizeof(double) * (size_t)(row_ptr[r1] - row_ptr[r0]));
+        for (e = 0; e < n_cells && !bad; e++) {
+            const int32_t *cell = cells + e * nen;
+            int touch = 0;
+            double Ee;
+            for (i = 0; i < nen; i++)
+                for (a = 0; a < dim; a++) {
+                    int64_t gr = (int64_t)dim * cell[i] + a;
+                    if (gr >= r0 && gr < r1) touch = 1;
+                }
+            if (!touch) continue;
+            Ee = simp_E(rho[e], E0, Emin, p);
+            gather_coords(dim, nen, coords, cell, xe);
+            oracle_element_ke0(elem, xe, nu, plane_strain, Ke);
+            for (i = 0; i < ldof; i++) {
+                int64_t gr = (int64_t)dim * cell[i / dim] + i % dim;
+                if (gr < r0 || gr >= r1) continue;
+                for (j = 0; j < ldof; j++) {
+                    int32_t gc = (int32_t)(dim * cell[j / dim] + j % dim);
+                    int64_t s = find_slot(row_ptr, col_idx, gr, gc);
+                    if (s < 0) { bad = 1; break; }
+                    K[s] += Ee * Ke[ldof * i + j];
+                }
+            }
+        }
+        if (mask && !bad) {
+            for (r = r0; r < r1; r++)
+                for (k = row_ptr[r]; k < row_ptr[r + 1]; k++) {
+                    int32_t c = col_idx[k];
+                    if (mask[r] || mask[c]) K[k] = (r == c) ? 1.0 : 0.0;
+                }
+        }
+    }
+    return bad ? -2 : 0;
+}
+
+int oracle_element_energy_mt(int elem, int64_t n_nodes, const double *coords, int64_t n_cells,
+                             const int32_t *cells, double nu, int plane_strain, const double *u,
+                             double *s) {
+    int dim = elem_dim(elem), nen = elem_nen(elem);
+    int64_t e;
+    if (dim < 0) return -1;
+    (void)n_nodes;
+#pragma omp parallel for schedule(static)
+    for (e = 0; e < n_cells; e++) {
+        int ldof = dim * nen, i, j;
+        const int32_t *cell = cells + e * nen;
+        double xe[3 * MAXNEN], Ke[MAXLDOF * MAXLDOF], ue[MAXLDOF], acc = 0.0;
+        gather_coords(dim, nen, coords, cell, xe);
+        oracle_element_ke0(elem, xe, nu, plane_strain, Ke);
+        for (i = 0; i < ldof; i++) ue[i] = u[(int64_t)dim * cell[i / dim] + i % dim];
+        for (i = 0; i < ldof; i++) {
+            double row = 0.0;
+            for (j = 0; j < ldof; j++) row += Ke[ldof * i + j] * ue[j];
+            acc += ue[i] * row;
+        }
+        s[e] = acc;
+    }
+    return 0;
+}
+
+int oracle_sensitivity_mt(int elem, int64_t n_nodes, const double *coords, int64_t n_cells,
+                          const int32_t *cells, const double *rho, double E0, double Emin, double p,
+                          double nu, int plane_strain, const double *u, double *dc) {
+    int64_t e;
+    int rc = oracle_element_energy_mt(elem, n_nodes, coords, n_cells, cells, nu, plane_strain, u, dc);
+    if (rc) return rc;
+#pragma omp parallel for schedule(static)
+    for (e = 0; e < n_cells; e++) dc[e] = -simp_dE(rho[e], E0, Emin, p) * dc[e];
+    return 0;
+}
+
+int oracle_compliance_mt(int elem, int64_t n_nodes, const double *coords, int64_t n_cells,
+                         const int32_t *cells, const double *rho, double E0, double Emin, double p,
+                         double nu, int plane_strain, const double *u, const double *f, double *c) {
+    int dim = elem_dim(elem);
+    int64_t e, r;
+    double acc = 0.0, *s;
+    if (dim < 0) return -1;
+    s = (double *)malloc(sizeof(double) * (size_t)(n_cells > 0 ? n_cells : 1));
+    if (!s) return -3;
+    oracle_element_energy_mt(elem, n_nodes, coords, n_cells, cells, nu, plane_strain, u, s);
+    for (e = 0; e < n_cells; e++) acc += simp_E(rho[e], E0, Emin, p) * s[e];
+    free(s);
+    c[0] = acc;
+    if (f) {
+        double fu = 0.0;
+        for (r = 0; r < dim * n_nodes; r++) fu += f[r] * u[r];
+        c[1] = fu;
+    }
+    return 0;
+}

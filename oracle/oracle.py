@@ -29,10 +29,12 @@ _D = ctypes.c_double
 
 
 def build(force: bool = True) -> str:
-    """Compile oracle.c into liboracle.so with gcc (plain -O2, no fast-math)."""
+    """Compile oracle.c into liboracle.so with gcc (plain -O2, no fast-math;
+    OpenMP for the multi-threaded baseline variants only)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC,
+                               "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -60,10 +62,16 @@ def lib():
         L.oracle_quadrature.argtypes = [_I32, _P, _P, _P]
         L.oracle_D.argtypes = [_I32, _I32, _D, _D, _P]
         L.oracle_hex27_node.argtypes = [_I32, _P]
+        L.oracle_assemble_mt.argtypes = L.oracle_assemble.argtypes
+        L.oracle_element_energy_mt.argtypes = L.oracle_element_energy.argtypes
+        L.oracle_sensitivity_mt.argtypes = L.oracle_sensitivity.argtypes
+        L.oracle_compliance_mt.argtypes = L.oracle_compliance.argtypes
+        L.oracle_threads.argtypes = []
         for name in ("oracle_pattern_from_pairs", "oracle_assemble", "oracle_element_energy",
                      "oracle_sensitivity", "oracle_compliance", "oracle_assemble_backward",
                      "oracle_spmv", "oracle_solve_banded", "oracle_ref_basis", "oracle_quadrature",
-                     "oracle_D", "oracle_hex27_node"):
+                     "oracle_D", "oracle_hex27_node", "oracle_assemble_mt", "oracle_element_energy_mt",
+                     "oracle_sensitivity_mt", "oracle_compliance_mt", "oracle_threads"):
             getattr(L, name).restype = _I32
         _lib = L
     return _lib
@@ -152,43 +160,45 @@ def pattern(elem: int, n_nodes: int, cells):
 # ------------------------------------------------------------- global ops
 
 def assemble(elem, coords, cells, rho, row_ptr, col_idx, E0=1.0, Emin=1e-9, p=3.0, nu=0.3,
-             plane_strain=0, mask=None):
+             plane_strain=0, mask=None, mt=False):
     coords, cells, rho = _c(coords, np.float64), _c(cells, np.int32), _c(rho, np.float64)
     row_ptr, col_idx = _c(row_ptr, np.int64), _c(col_idx, np.int32)
     mask = None if mask is None else _c(mask, np.uint8)
     K = np.zeros(col_idx.shape[0])
-    _check(lib().oracle_assemble(elem, coords.shape[0], _ptr(coords), cells.shape[0], _ptr(cells),
-                                 _ptr(rho), E0, Emin, p, nu, plane_strain, _ptr(mask), _ptr(row_ptr),
-                                 _ptr(col_idx), _ptr(K)), "assemble")
+    fn = lib().oracle_assemble_mt if mt else lib().oracle_assemble
+    _check(fn(elem, coords.shape[0], _ptr(coords), cells.shape[0], _ptr(cells), _ptr(rho), E0, Emin, p, nu,
+              plane_strain, _ptr(mask), _ptr(row_ptr), _ptr(col_idx), _ptr(K)), "assemble")
     return K
 
 
-def element_energy(elem, coords, cells, u, nu=0.3, plane_strain=0):
+def element_energy(elem, coords, cells, u, nu=0.3, plane_strain=0, mt=False):
     coords, cells, u = _c(coords, np.float64), _c(cells, np.int32), _c(u, np.float64)
     s = np.zeros(cells.shape[0])
-    _check(lib().oracle_element_energy(elem, coords.shape[0], _ptr(coords), cells.shape[0], _ptr(cells),
-                                       nu, plane_strain, _ptr(u), _ptr(s)), "element_energy")
+    fn = lib().oracle_element_energy_mt if mt else lib().oracle_element_energy
+    _check(fn(elem, coords.shape[0], _ptr(coords), cells.shape[0], _ptr(cells), nu, plane_strain, _ptr(u),
+              _ptr(s)), "element_energy")
     return s
 
 
-def sensitivity(elem, coords, cells, rho, u, E0=1.0, Emin=1e-9, p=3.0, nu=0.3, plane_strain=0):
+def sensitivity(elem, coords, cells, rho, u, E0=1.0, Emin=1e-9, p=3.0, nu=0.3, plane_strain=0, mt=False):
     coords, cells = _c(coords, np.float64), _c(cells, np.int32)
     rho, u = _c(rho, np.float64), _c(u, np.float64)
     dc = np.zeros(cells.shape[0])
-    _check(lib().oracle_sensitivity(elem, coords.shape[0], _ptr(coords), cells.shape[0], _ptr(cells),
-                                    _ptr(rho), E0, Emin, p, nu, plane_strain, _ptr(u), _ptr(dc)),
-           "sensitivity")
+    fn = lib().oracle_sensitivity_mt if mt else lib().oracle_sensitivity
+    _check(fn(elem, coords.shape[0], _ptr(coords), cells.shape[0], _ptr(cells), _ptr(rho), E0, Emin, p, nu,
+              plane_strain, _ptr(u), _ptr(dc)), "sensitivity")
     return dc
 
 
-def compliance(elem, coords, cells, rho, u, f=None, E0=1.0, Emin=1e-9, p=3.0, nu=0.3, plane_strain=0):
+def compliance(elem, coords, cells, rho, u, f=None, E0=1.0, Emin=1e-9, p=3.0, nu=0.3, plane_strain=0,
+               mt=False):
     coords, cells = _c(coords, np.float64), _c(cells, np.int32)
     rho, u = _c(rho, np.float64), _c(u, np.float64)
     f = None if f is None else _c(f, np.float64)
     c = np.zeros(2)
-    _check(lib().oracle_compliance(elem, coords.shape[0], _ptr(coords), cells.shape[0], _ptr(cells),
-                                   _ptr(rho), E0, Emin, p, nu, plane_strain, _ptr(u), _ptr(f), _ptr(c)),
-           "compliance")
+    fn = lib().oracle_compliance_mt if mt else lib().oracle_compliance
+    _check(fn(elem, coords.shape[0], _ptr(coords), cells.shape[0], _ptr(cells), _ptr(rho), E0, Emin, p, nu,
+              plane_strain, _ptr(u), _ptr(f), _ptr(c)), "compliance")
     return c
 
 
@@ -202,6 +212,11 @@ def assemble_backward(elem, coords, cells, rho, row_ptr, col_idx, Kbar, E0=1.0, 
                                           _ptr(row_ptr), _ptr(col_idx), _ptr(Kbar), _ptr(drho)),
            "assemble_backward")
     return drho
+
+
+def threads() -> int:
+    """Threads the multi-threaded variants (mt=True) use: OpenMP's maximum."""
+    return int(lib().oracle_threads())
 
 
 def spmv(row_ptr, col_idx, K, x):

@@ -42,7 +42,8 @@ class Material(ctypes.Structure):
 
 class PatternStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("ndof", "nnz", "n_cells", "n_nodes", "n_groups", "n_signatures",
-                                               "n_contributions", "plan_bytes", "device_bytes")]
+                                               "n_contributions", "plan_bytes", "device_bytes",
+                                               "n_groups_diag")]
 
 
 class OcParams(ctypes.Structure):

@@ -266,6 +266,8 @@ static int build_pattern(const soptx_mesh *mesh, int32_t ref_method, bool genera
         const int64_t ncontrib = hp.n_cells * (int64_t)nen * nen;
         h->stats.ndof = hp.ndof; h->stats.nnz = hp.nnz; h->stats.n_cells = hp.n_cells; h->stats.n_nodes = hp.n_nodes;
         h->stats.n_groups = h->ngroups; h->stats.n_signatures = h->nsig; h->stats.n_contributions = ncontrib;
+        for (int64_t g = 0; g < h->ngroups; g++)
+            h->stats.n_groups_diag += (hp.grp_info[g * kGrpInfo + kGrpInfo - 1] & kGrpDiag) ? 1 : 0;
     } catch (const std::bad_alloc &) {
         free_handle(h);
         return SOPTX_E_OOM;
