@@ -365,22 +365,27 @@ def paper_runs():
 def serving_run(count, slots=4, budget=32 << 30):
     """Serving form: seeded requests (2D Q1 n^2, n in 32..512; 3D Q1 n^3,
     n in 16..96; p in {3, 4}), first as a burst (saturated elements/s), then
-    with Poisson arrivals at 0.7 x that rate (p50/p99 latency)."""
+    with Poisson arrivals at 0.7 x that rate (p50/p99 latency).  Inputs are
+    resident in HBM when the run starts, as in the plain step; the burst is
+    also run with every request's inputs copied from pinned host memory at
+    launch (PCIe included)."""
     from paper_2505_02438_amd import serving as S
-    ex = S.GpuExecutor(slots)
-    burst = S.make_requests(count)
-    ex.prepare(burst)
-    ex.t0 = time.perf_counter()
-    st_b = S.latency_stats(S.Scheduler(ex, slots, budget).run(burst))
+
+    def run(reqs, pcie=False):
+        ex = S.GpuExecutor(slots, pcie=pcie)
+        ex.prepare(reqs)
+        ex.t0 = time.perf_counter()
+        return S.latency_stats(S.Scheduler(ex, slots, budget).run(reqs))
+
+    st_b = run(S.make_requests(count))
     lam = 0.7 * st_b["elements_per_s"]
-    arr = S.make_requests(count, rate_elems_per_s=lam)
-    ex.prepare(arr)
-    ex.t0 = time.perf_counter()
-    st_p = S.latency_stats(S.Scheduler(ex, slots, budget).run(arr))
+    st_p = run(S.make_requests(count, rate_elems_per_s=lam))
+    st_x = run(S.make_requests(count), pcie=True)
     return {"requests": count, "slots": slots, "hbm_budget_bytes": budget,
             "burst_elements_per_s": st_b["elements_per_s"], "burst_makespan_s": st_b["makespan_s"],
             "poisson_lambda_elements_per_s": lam, "p50_ms": st_p["p50_ms"], "p99_ms": st_p["p99_ms"],
-            "poisson_elements_per_s": st_p["elements_per_s"]}
+            "poisson_elements_per_s": st_p["elements_per_s"],
+            "burst_pcie_elements_per_s": st_x["elements_per_s"], "burst_pcie_makespan_s": st_x["makespan_s"]}
 
 
 class StepState:

@@ -11,7 +11,13 @@ with its own densities, penalisation p and displacement field.  The loop
 * runs each admitted request on its own stream, so requests that arrive
   while others are on the GPU overlap with them on the device;
 * retires requests whose completion event has fired, freeing their slot and
-  memory, and records latency = completion - arrival.
+  memory, and records latency = completion - arrival; when no waiting request
+  can be admitted it blocks on the oldest request's completion event instead
+  of polling.
+
+Each request is one soptx_step call (assembly with the mesh's Dirichlet
+table bound once, dc and c) into outputs allocated before the run: one K
+buffer per stream slot, and dc and c per request.
 
 Every kernel sums in a fixed order and no request shares an output with
 another, so a request's result is bitwise the same alone and in any mix.
@@ -57,6 +63,7 @@ class Result:
     finish: float
     dc: object = None     # device tensor [n_cells]
     c: object = None      # device tensor [2]: u^T K u, f^T u (0 here)
+    K: object = None      # device tensor [nnz] (the executor's keep_K), else None
 
     @property
     def latency(self) -> float:
@@ -79,7 +86,8 @@ class Scheduler:
 
     executor.launch(req, slot) -> handle   (asynchronous; slot in [0, slots))
     executor.done(handle) -> bool
-    executor.finish(handle) -> (dc, c)     (called once done)
+    executor.wait(handle)                  (blocks until done)
+    executor.finish(handle) -> (dc, c) or (dc, c, K)   (called once done)
     executor.now() -> seconds
     """
 
@@ -111,8 +119,9 @@ class Scheduler:
             # retire
             for rid in [k for k, v in inflight.items() if self.ex.done(v[1])]:
                 req, h, slot, t0 = inflight.pop(rid)
-                dc, c = self.ex.finish(h)
-                results.append(Result(rid, req.n_cells, req.arrival, t0, self.ex.now(), dc, c))
+                out = self.ex.finish(h)
+                results.append(Result(rid, req.n_cells, req.arrival, t0, self.ex.now(), out[0], out[1],
+                                      out[2] if len(out) > 2 else None))
                 self.in_use -= self.footprint(req)
                 self.free_slots.append(slot)
             # admit in arrival order (no overtaking: the head waits for room)
@@ -124,6 +133,10 @@ class Scheduler:
                 inflight[req.rid] = (req, self.ex.launch(req, slot), slot, self.ex.now())
             if not inflight and not waiting and i < len(pending):
                 self.ex.wait_until(pending[i].arrival)
+            elif inflight and waiting and (i >= len(pending) or pending[i].arrival > self.ex.now()):
+                # the head of the queue waits for a slot or for memory: block
+                # on the oldest request in flight
+                self.ex.wait(min(inflight.values(), key=lambda v: v[3])[1])
             elif poll_sleep > 0:
                 time.sleep(poll_sleep)
         return sorted(results, key=lambda r: r.rid)
@@ -157,9 +170,17 @@ def make_requests(count: int, rate_elems_per_s: Optional[float] = None, first_ri
 
 
 class GpuExecutor:
-    """Runs requests through the library on a pool of streams."""
+    """Runs requests through the library on a pool of streams.
 
-    def __init__(self, slots: int, device: int = 0):
+    prepare() builds the resident meshes (pattern, plan and the bound
+    Dirichlet table of each distinct mesh), puts every request's inputs in
+    HBM (or, with pcie=True, in pinned host memory, copied to the slot's
+    device buffers at launch), and allocates the outputs: one K buffer per
+    slot (the largest request's size) and dc and c per request.  A launch then
+    allocates nothing and makes one library call.  keep_K gives every request
+    a K of its own, returned in its Result (for tests)."""
+
+    def __init__(self, slots: int, device: int = 0, pcie: bool = False, keep_K: bool = False):
         import torch
 
         from . import api
@@ -168,7 +189,10 @@ class GpuExecutor:
         self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(slots)]  # default priority
         self.meshes: Dict[Tuple[str, int], tuple] = {}
         self.t0 = time.perf_counter()
-        self.inputs_cache: Dict[int, tuple] = {}
+        self.pcie, self.keep_K = pcie, keep_K
+        self.staged: Dict[int, tuple] = {}
+        self.outputs: Dict[int, tuple] = {}
+        self.slot_bufs: List[Optional[tuple]] = [None] * slots
 
     def now(self) -> float:
         return time.perf_counter() - self.t0
@@ -179,14 +203,14 @@ class GpuExecutor:
             time.sleep(d)
 
     def resident(self, key):
-        """(pattern, device mask, mesh, host mask), built once per distinct mesh."""
+        """(pattern, Dirichlet table, mesh, host mask), built once per distinct mesh."""
         if key not in self.meshes:
             from . import inputs as I
             kind, n = key
             mesh = I.quad_grid(n, n) if kind == "quad" else I.hex_grid(n, n, n)
             mask, _ = I.mbb_bc(mesh) if kind == "quad" else I.clamp_x0_bc(mesh)
             pat = self.api.Pattern.from_mesh(mesh)
-            self.meshes[key] = (pat, self.torch.from_numpy(mask).to(self.dev), mesh, mask)
+            self.meshes[key] = (pat, self.api.Dirichlet(pat, mask), mesh, mask)
         return self.meshes[key]
 
     def request_inputs(self, req: Request):
@@ -197,47 +221,65 @@ class GpuExecutor:
         return rng.uniform(0.001, 1.0, mesh.n_cells), I.synthetic_u(rng, mask)
 
     def prepare(self, requests: List[Request]):
-        """Build the resident meshes, and stage each request's host inputs in
-        pinned memory (where a server receives them), ahead of the timed run."""
+        """Resident meshes, staged inputs and preallocated outputs, ahead of the timed run."""
+        torch = self.torch
+        nnz_max = cells_max = dof_max = 0
         for r in requests:
+            pat = self.resident(r.mesh_key)[0]
+            nnz_max, cells_max, dof_max = max(nnz_max, pat.nnz), max(cells_max, pat.n_cells), max(dof_max, pat.ndof)
             rho, u = self.request_inputs(r)
-            self.inputs_cache[r.rid] = (self.torch.from_numpy(rho).pin_memory(),
-                                        self.torch.from_numpy(u).pin_memory())
+            if self.pcie:
+                self.staged[r.rid] = (torch.from_numpy(rho).pin_memory(), torch.from_numpy(u).pin_memory())
+            else:
+                self.staged[r.rid] = (torch.from_numpy(rho).to(self.dev), torch.from_numpy(u).to(self.dev))
+            self.outputs[r.rid] = (torch.empty(pat.n_cells, dtype=torch.float64, device=self.dev),
+                                   torch.empty(2, dtype=torch.float64, device=self.dev),
+                                   torch.empty(pat.nnz, dtype=torch.float64, device=self.dev) if self.keep_K else None)
+        for k in range(len(self.streams)):
+            cur = self.slot_bufs[k]
+            if cur is None or cur[0].numel() < nnz_max or cur[1].numel() < cells_max or cur[2].numel() < dof_max:
+                self.slot_bufs[k] = (torch.empty(nnz_max, dtype=torch.float64, device=self.dev),
+                                     torch.empty(cells_max, dtype=torch.float64, device=self.dev),
+                                     torch.empty(dof_max, dtype=torch.float64, device=self.dev))
+        torch.cuda.synchronize(self.dev)
 
     def launch(self, req: Request, slot: int):
         torch = self.torch
         st = self.streams[slot]
-        pat, mask_d = self.resident(req.mesh_key)[:2]
-        staged = self.inputs_cache.pop(req.rid, None)
-        if staged is None:
-            staged = tuple(torch.from_numpy(x) for x in self.request_inputs(req))
-        rho_h, u_h = staged
+        pat, bc = self.resident(req.mesh_key)[:2]
+        if req.rid not in self.staged:
+            self.prepare([req])
+        rho_h, u_h = rho, u = self.staged.pop(req.rid)
+        dc, c, Kown = self.outputs.pop(req.rid)
+        Kslot, rho_slot, u_slot = self.slot_bufs[slot]
+        if self.pcie:
+            # asynchronous copies from pinned memory into the slot's buffers
+            rho = self._h2d(rho_h, rho_slot, st)
+            u = self._h2d(u_h, u_slot, st)
+        K = Kown if Kown is not None else Kslot[: pat.nnz]
         mat = self.api.Material(E0=1.0, Emin=1e-9, nu=0.3, p=req.p)
-        with torch.cuda.stream(st):
-            rho = rho_h.to(self.dev, non_blocking=True)  # asynchronous from pinned memory
-            u = u_h.to(self.dev, non_blocking=True)
-            K = torch.empty(pat.nnz, dtype=torch.float64, device=self.dev)
-            dc = torch.empty(pat.n_cells, dtype=torch.float64, device=self.dev)
-            c = torch.zeros(2, dtype=torch.float64, device=self.dev)
-        pat.assemble(mat, rho, None, out=K, stream=st)
-        pat.apply_dirichlet(mask_d, K, stream=st)
-        pat.evaluate(mat, rho, u, dc=dc, c=c, stream=st)
+        pat.step(mat, rho, u, bc=bc, K=K, dc=dc, c=c, stream=st)
         ev = torch.cuda.Event()
         ev.record(st)
-        return (ev, K, dc, c, rho, u, st, rho_h, u_h)  # host buffers live until the copies are done
+        return (ev, dc, c, Kown, rho, u, rho_h, u_h)  # inputs (and pinned sources) live until the work is done
+
+    def _h2d(self, src, buf, st):
+        with self.torch.cuda.stream(st):
+            return buf[: src.numel()].copy_(src, non_blocking=True)
 
     def done(self, h) -> bool:
         return h[0].query()
 
+    def wait(self, h):
+        h[0].synchronize()
+
     def finish(self, h):
-        # the request's work is complete (its event fired): K, rho and u are
-        # released with the handle; dc and c go to the result
-        return h[2], h[3]
+        return h[1], h[2], h[3]
 
 
-def serve(requests: List[Request], slots: int = 4, hbm_budget: int = 32 << 30, executor=None):
+def serve(requests: List[Request], slots: int = 4, hbm_budget: int = 32 << 30, executor=None, keep_K: bool = False):
     """Run requests through a Scheduler on the GPU; returns (results, stats)."""
-    ex = executor or GpuExecutor(slots)
+    ex = executor or GpuExecutor(slots, keep_K=keep_K)
     ex.prepare(requests)
     ex.t0 = time.perf_counter()
     sched = Scheduler(ex, slots, hbm_budget)

@@ -7,9 +7,11 @@ The device bisection takes the sequential loop's decisions on its own vol
 sums (fixed order), the oracle on correctly rounded sums; with the same
 decisions the multiplier and the number of steps are bitwise equal, and with
 eta = 0.5 or 1 (square root or nothing: correctly rounded operations only)
-so are the updated densities and the change.  A decision could differ only if
-vol at a midpoint fell within rounding of V*; the tests' seeds do not do that
-(they would fail, not pass silently)."""
+so are the updated densities and the change.  A decision may differ only
+where vol at a midpoint lies within the rounding error of the device's sum
+of V*: every test replays the device's path (rebuilt from its multiplier and
+step count) and checks each decision against the oracle's correctly rounded
+vol with that error bound, and one test puts V* exactly on such a tie."""
 import numpy as np
 import pytest
 
@@ -35,6 +37,38 @@ def _inputs(n, seed):
     return rho, dc, dv
 
 
+def _check_decisions(rho, dc, dv, target, info, move, eta, tol, lmax=1e9, max_steps=200):
+    """Replay the device's bisection path, recovered from its final multiplier
+    and step count, and check every decision: vol(mid) > V* must send l1 to
+    mid and vol(mid) < V* l2, with vol the oracle's correctly rounded sum,
+    unless |vol(mid) - V*| is within the error bound of the device's
+    fixed-order sum of n products (n u sum_e dv_e rho_new_e, u = 2^-53).
+    Returns the number of decisions that fell within that bound."""
+    lam_g, steps_g = info["lambda"], info["steps"]
+    l1, l2 = 0.0, float(lmax)
+    n, ties = len(rho), 0
+    for k in range(steps_g):
+        assert l2 - l1 > tol * (l1 + l2) and k < max_steps, "device ran more steps than the loop allows"
+        mid = 0.5 * (l1 + l2)
+        vol = OC.volume(dv, OC.oc_candidate(rho, dc, dv, mid, move, eta))
+        bound = n * 2.0 ** -53 * vol
+        if k == steps_g - 1:
+            assert mid == lam_g, "the device's multiplier is not on its own path"
+            break
+        went_up = lam_g > mid               # the device set l1 = mid (it saw vol > V*)
+        if abs(vol - target) > bound:
+            assert went_up == (vol > target), f"step {k}: vol {vol!r} V* {target!r} decided the other way"
+        else:
+            ties += 1
+        if went_up:
+            l1 = mid
+        else:
+            l2 = mid
+    else:
+        assert steps_g == 0
+    return ties
+
+
 @pytest.mark.parametrize("n,eta,tol,move", [(5000, 0.5, 1e-3, 0.2), (5000, 1.0, 1e-3, 0.2), (5000, 0.5, 1e-12, 0.05),
                                             (777, 0.5, 1e-6, 1.0), (1, 0.5, 1e-3, 0.2), (256 * 1024 + 77, 0.5, 1e-4, 0.2)])
 def test_oc_update_matches_oracle_bitwise(n, eta, tol, move):
@@ -43,10 +77,42 @@ def test_oc_update_matches_oracle_bitwise(n, eta, tol, move):
     rn, lam, vol, steps, change = OC.oc_update(rho, dc, dv, target, move=move, eta=eta, tol=tol)
     got, info = api.oc_update(dev(rho), dev(dc), dev(dv), target, move=move, eta=eta, tol=tol)
     print(f"n={n} eta={eta} tol={tol}: steps {info['steps']} / {steps}, lambda {info['lambda']!r} / {lam!r}")
-    assert info["steps"] == steps and info["lambda"] == lam
-    assert np.array_equal(host(got), rn)
-    assert info["change"] == change
-    assert abs(info["volume"] - vol) <= 1e-13 * abs(vol)
+    ties = _check_decisions(rho, dc, dv, target, info, move, eta, tol)
+    if ties == 0:
+        # no decision within rounding: the paths, hence every result, agree
+        assert info["steps"] == steps and info["lambda"] == lam
+        assert np.array_equal(host(got), rn)
+        assert info["change"] == change
+        assert abs(info["volume"] - vol) <= 1e-13 * abs(vol)
+    # whatever the path: the densities are the update at the device's multiplier
+    assert np.array_equal(host(got), OC.oc_candidate(rho, dc, dv, info["lambda"], move, eta))
+
+
+@pytest.mark.parametrize("tie_step", [3, 9, 17])
+def test_oc_decisions_valid_at_a_tie(tie_step):
+    """V* set exactly to the oracle's vol at the midpoint of one bisection
+    step: there the oracle takes l2 = mid, and the device, whose sum may lie
+    an ulp or so either side, may take either branch.  Every decision must be
+    valid (above), and the densities are the update at the device's
+    multiplier."""
+    rho, dc, dv = _inputs(20000, 77 + tie_step)
+    move, eta, tol = 0.2, 0.5, 1e-9
+    l1, l2 = 0.0, 1e9
+    target0 = 0.4 * dv.sum()
+    for _ in range(tie_step):
+        mid = 0.5 * (l1 + l2)
+        v = OC.volume(dv, OC.oc_candidate(rho, dc, dv, mid, move, eta))
+        if v > target0:
+            l1 = mid
+        else:
+            l2 = mid
+    mid = 0.5 * (l1 + l2)
+    target = OC.volume(dv, OC.oc_candidate(rho, dc, dv, mid, move, eta))   # a tie at step tie_step
+    got, info = api.oc_update(dev(rho), dev(dc), dev(dv), target, move=move, eta=eta, tol=tol)
+    ties = _check_decisions(rho, dc, dv, target, info, move, eta, tol)
+    print(f"tie at step {tie_step}: device steps {info['steps']}, decisions within rounding {ties}")
+    assert ties >= 1
+    assert np.array_equal(host(got), OC.oc_candidate(rho, dc, dv, info["lambda"], move, eta))
 
 
 def test_oc_update_general_eta():

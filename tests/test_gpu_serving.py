@@ -21,17 +21,44 @@ def _small_mix(count=14):
 
 
 def test_alone_equals_mix_bitwise():
+    """K (with the Dirichlet rows), dc and c of every request, alone and in a
+    mix on four streams: the assembly kernels of different requests run at
+    the same time there."""
     reqs = _small_mix()
     assert len({r.mesh_key for r in reqs}) >= 4
     alone = {}
     for r in reqs:
-        res, _ = S.serve([S.Request(r.rid, r.kind, r.n, r.p)], slots=1)
-        alone[r.rid] = (host(res[0].dc), host(res[0].c))
-    mix, st = S.serve([S.Request(r.rid, r.kind, r.n, r.p) for r in reqs], slots=4)
+        res, _ = S.serve([S.Request(r.rid, r.kind, r.n, r.p)], slots=1, keep_K=True)
+        alone[r.rid] = (host(res[0].dc), host(res[0].c), host(res[0].K))
+    mix, st = S.serve([S.Request(r.rid, r.kind, r.n, r.p) for r in reqs], slots=4, keep_K=True)
     print(st)
     for m in mix:
-        a_dc, a_c = alone[m.rid]
+        a_dc, a_c, a_K = alone[m.rid]
         assert np.array_equal(host(m.dc), a_dc) and np.array_equal(host(m.c), a_c), m.rid
+        assert np.array_equal(host(m.K), a_K), m.rid
+
+
+def test_served_K_matches_oracle_and_pcie_path():
+    """The served K of small requests against the oracle's (Dirichlet rows
+    and columns included), and the path that copies the inputs from pinned
+    host memory at launch gives the same results as resident inputs."""
+    reqs = [r for r in S.make_requests(300) if (r.kind, r.n) in (("quad", 32), ("hex", 16))][:4]
+    res, _ = S.serve(reqs, slots=2, keep_K=True)
+    ex = S.GpuExecutor(2, pcie=True)
+    ex.prepare(reqs)
+    res2 = S.Scheduler(ex, 2, 32 << 30).run(reqs)
+    for r, out, out2 in zip(reqs, res, res2):
+        mesh, mask = ex.resident(r.mesh_key)[2:]
+        rho, u = ex.request_inputs(r)
+        rp, ci = O.pattern(mesh.elem, mesh.n_nodes, mesh.cells)
+        Kr = O.assemble(mesh.elem, mesh.coords, mesh.cells, rho, rp, ci, p=r.p, mask=mask)
+        rows = np.repeat(np.arange(mesh.ndof), np.diff(rp))
+        rmax = np.zeros(mesh.ndof)
+        np.maximum.at(rmax, rows, np.abs(Kr))
+        err = np.max(np.abs(host(out.K) - Kr) / rmax[rows])
+        print(r.kind, r.n, f"K row-scaled err {err:.2e}")
+        assert err <= 1e-12
+        assert np.array_equal(host(out.dc), host(out2.dc)) and np.array_equal(host(out.c), host(out2.c))
 
 
 def test_served_results_match_oracle():

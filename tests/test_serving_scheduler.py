@@ -33,6 +33,9 @@ class FakeExecutor:
     def done(self, h):
         return self.t >= self.running[h][1]
 
+    def wait(self, h):
+        self.t = max(self.t, self.running[h][1])
+
     def finish(self, h):
         self.running.pop(h)
         self.log.append(("finish", h, self.t))
