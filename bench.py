@@ -63,6 +63,9 @@ WORKLOADS = {
     "hex120x40x40_sheared": ("the 120x40x40 cantilever mapped by x -> A x, A = [[1, .3, .1], [-.2, 1, .25], "
                              "[.15, -.1, 1]]: every element affine with a full J^-1 (the general affine "
                              "contraction), rho, u and supports as the headline", lambda I: I.cantilever_hex(skew="global")),
+    "hex120x40x40_renumbered": ("the headline cantilever with its nodes and elements renumbered by a seeded "
+                                "permutation (seed 17): the plan takes its canonical order",
+                                lambda I: I.renumber(I.cantilever_hex(), 17)),
     "hex96": ("3D cube 96^3 unit Q1 hexahedra (884,736 elements, 2,738,019 dofs, 217,238,121 K entries; the "
               "largest serving request), rho~Beta(2,2), p=3, nu=0.3, x=0 face clamped, u~N(0,1)",
               lambda I: I.cantilever_hex(96, 96, 96)),
@@ -486,7 +489,8 @@ def labelled_run(name, desc, pr, stream, steps, warmup, precs, extra=None):
     stats = pat.stats()
     asm_bytes, ev_bytes = algorithmic_bytes(m.n_nodes, m.n_cells, pat.nnz, m.dim, m.nen, m.ndof)
     out = {"workload": desc, "elements": m.n_cells, "ndof": pat.ndof, "nnz": pat.nnz,
-           "pattern_build_s": build_s, "groups": stats["n_groups"], "signatures": stats["n_signatures"]}
+           "pattern_build_s": build_s, "groups": stats["n_groups"], "signatures": stats["n_signatures"],
+           "groups_with_rank_table": stats["n_groups_ranked"]}
     if extra:
         out.update(extra)
     states = {}
@@ -795,7 +799,7 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_labelled:
         rows = {}
-        for wl in ("hex120x40x40_sheared", "tri600x200", "p2box48"):
+        for wl in ("hex120x40x40_sheared", "hex120x40x40_renumbered", "tri600x200", "p2box48"):
             if wl != args.workload:
                 d, mk = WORKLOADS[wl]
                 rows[wl] = labelled_run(wl, d, mk(I), stream, min(args.steps, 20), 3,

@@ -125,6 +125,8 @@ typedef struct {
     int64_t device_bytes;    /* all device bytes held by the handle */
     int64_t n_groups_diag;   /* groups whose elements all have a diagonal J^-1 (axis-aligned boxes),
                                 assembled with the shorter contraction of such elements */
+    int64_t n_groups_ranked; /* groups that carry a rank table: the plan took the canonical order of
+                                nodes and elements (the given numbering fragmented it) */
 } soptx_pattern_stats;
 
 /* Build the CSR pattern, the per-element geometry (J^-1, det J) and the

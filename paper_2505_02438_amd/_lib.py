@@ -43,7 +43,7 @@ class Material(ctypes.Structure):
 class PatternStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("ndof", "nnz", "n_cells", "n_nodes", "n_groups", "n_signatures",
                                                "n_contributions", "plan_bytes", "device_bytes",
-                                               "n_groups_diag")]
+                                               "n_groups_diag", "n_groups_ranked")]
 
 
 class OcParams(ctypes.Structure):

@@ -66,9 +66,10 @@ def host_plan(elem: int, coords, cells, general: bool = False) -> dict:
     check(L.soptx_debug_host_plan_ex(ctypes.byref(m), 1 if general else 0, ctypes.byref(h)), "soptx_debug_host_plan")
     try:
         out = {}
-        dt = {4: np.int32, 2: np.uint16, 8: np.float64}
+        dt = {4: np.int32, 2: np.uint16, 1: np.uint8, 8: np.float64}
         for name in ("row_ptr", "col_idx", "geo", "sig_info", "sig_pos_ptr", "sig_contrib", "sig_pairs", "sig_witems", "sig_witem_ptr",
-                     "grp_info", "grp_nodes", "grp_elems", "grp_n2l", "grp_rows", "pos", "nb_tslot", "nb_tdeg",
+                     "grp_info", "grp_nodes", "grp_elems", "grp_n2l", "grp_rows", "grp_rank_off", "grp_rank", "elem_by_rank", "pos", "nb_tslot",
+                     "nb_tdeg",
                      "gptr", "gent", "gnode"):
             ptr, cnt, eb = ctypes.c_void_p(), ctypes.c_int64(), ctypes.c_int32()
             check(L.soptx_debug_host_plan_array(h, name.encode(), ctypes.byref(ptr), ctypes.byref(cnt),

@@ -12,7 +12,9 @@ namespace soptx {
 
 // Scratch of at least n doubles for work on (device, stream); `use` keeps
 // independent buffers apart: 0 = reduction partials of the energy kernel,
-// 1 = CG vectors, 2 = filter chain rule, 3 = OC bisection state and partials.  Work on one stream is ordered, so
+// 1 = CG vectors, 2 = filter chain rule, 3 = OC bisection state and partials,
+// 4 = element matrices of the per-quadrature-point assembly, 5 = densities in
+// the rank order of a canonical-order plan.  Work on one stream is ordered, so
 // one buffer per (device, stream, use) is race-free.  Held until the process
 // ends; grown (after a synchronisation of the stream) when a call needs more.
 int get_workspace(int device, hipStream_t st, size_t n, double **out, int use);

@@ -80,6 +80,17 @@ struct HostPlan {
     std::vector<int32_t> grp_elems;  // concatenated element ids, grp_info elem_off .. next
     std::vector<uint16_t> grp_n2l;   // per group K*kGroupNodes (k-major): slot of element k of lane's node
     std::vector<int32_t> grp_rows;   // [ngroups][kGroupNodes][2]: first CSR slot of the node's rows, row length
+    // canonical order only (canonical = true): per group the offset of its
+    // rank table in grp_rank, or -1 where every neighbour position is its CSR
+    // position; a rank table holds, [position][kGroupNodes], the CSR position
+    // of each canonical neighbour position of each node of the group
+    bool canonical = false;
+    std::vector<int32_t> grp_rank_off;  // [ngroups]
+    std::vector<uint8_t> grp_rank;
+    // canonical order only: grp_elems holds element ranks; elem_by_rank [n_cells]
+    // maps a rank to its element, geo_rank is geo with its columns in rank order
+    std::vector<int32_t> elem_by_rank;
+    std::vector<double> geo_rank;
     // backward: position of cells[e][j] in the neighbour list of cells[e][i]
     std::vector<uint16_t> pos;       // [n_cells][nen][nen]
     // per node n and neighbour J = nb(n)[q] (offset row_ptr[dim n] / dim^2 + q):

@@ -199,10 +199,10 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
     __shared__ int ticket[2];
     // group headers, one per row-offset buffer: nn, deg, posoff, blk, flags,
     // first wide work item, number of wide work items, offset of the group's
-    // Dirichlet bits (-1: none).
+    // Dirichlet bits (-1: none), offset of its rank table (-1: none).
     // Written by the load waves with the group's other data, so that the
     // compute and store waves start a step without a chain of scalar loads
-    __shared__ int shdr[3][8];
+    __shared__ int shdr[3][9];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -308,6 +308,7 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
             shdr[rb][5] = wi0;
             shdr[rb][6] = ldc(P.sig_witem_ptr, sg + 1) - wi0;
             shdr[rb][7] = (FUSE && P.bc_off) ? P.bc_off[gg] : -1;
+            shdr[rb][8] = P.grp_rank_off ? P.grp_rank_off[gg] : -1;
         }
     };
 
@@ -324,6 +325,7 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
         const int wi0 = wave_uniform(shdr[rb][5]);
         const int nwi = wave_uniform(shdr[rb][6]);
         const int bcoff = FUSE ? wave_uniform(shdr[rb][7]) : -1;
+        const int rkoff = wave_uniform(shdr[rb][8]);
         const bool diag = flags & kGrpDiag;
         const int lgN = 5 - ((flags >> kGrpWideShift) & 3);  // N = 8 or 16
         const int N = 1 << lgN;
@@ -352,8 +354,10 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
                     cnt = ldc(rec, 24 + k);
                 }
             const bool mine = pp < np && node < nn;
-            // Dirichlet bits of the lane's block, fetched now and used at the end
+            // Dirichlet bits of the lane's block and its CSR position (a
+            // canonical-order plan's rank table), fetched now and used at the end
             const int bcb = (FUSE && bcoff >= 0 && mine && q == 0) ? P.bc_bits[bcoff + node * deg + p] : 0;
+            const int pcsr = (rkoff >= 0 && mine && q == 0) ? (int)P.grp_rank[rkoff + p * NG + node] : p;
             double acc[DIM][DIM];
 #pragma unroll
             for (int a = 0; a < DIM; a++)
@@ -412,7 +416,7 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
                         double o = P.lam * acc[a][c] + P.mu * acc[c][a];
                         if (a == c) o += P.mu * tr;
                         if (FUSE && bcoff >= 0) o = dirichlet_entry(bcb, a, c, o);
-                        st[a * rl + DIM * p + c] = o;
+                        st[a * rl + DIM * pcsr + c] = o;
                     }
             }
         }
@@ -430,6 +434,7 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
         const int posoff = wave_uniform(shdr[rb][2]);
         const int blk = wave_uniform(shdr[rb][3]);
         const int bcoff = FUSE ? wave_uniform(shdr[rb][7]) : -1;
+        const int rkoff = wave_uniform(shdr[rb][8]);
         const bool diag = flags & kGrpDiag;
         const int rl = DIM * deg;
         const bool hi = lane >= NG;
@@ -464,6 +469,8 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
             // Dirichlet bits of the lane's block, fetched now and used at the end
             const int pme = hi ? pb : pa;
             const int bcb = (FUSE && bcoff >= 0 && node < nn && pme >= 0) ? P.bc_bits[bcoff + node * deg + pme] : 0;
+            // the block's CSR position (a canonical-order plan's rank table)
+            const int pcsr = (rkoff >= 0 && node < nn && pme >= 0) ? (int)P.grp_rank[rkoff + pme * NG + node] : pme;
             double acc[DIM][DIM];
 #pragma unroll
             for (int a = 0; a < DIM; a++)
@@ -529,7 +536,7 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
                         double o = P.lam * acc[a][c] + P.mu * acc[c][a];
                         if (a == c) o += P.mu * tr;
                         if (FUSE && bcoff >= 0) o = dirichlet_entry(bcb, a, c, o);
-                        st[a * rl + DIM * p + c] = o;
+                        st[a * rl + DIM * pcsr + c] = o;
                     }
             }
         }
@@ -1118,6 +1125,18 @@ __global__ __launch_bounds__(256) void k_backward(BwdParams P) {
     store_out<PREC>(P.drho, e, dE * det * acc);
 }
 
+// ------------------------------------------------ densities in rank order
+//
+// dst[r] = src[idx[r]] (element data of a canonical-order plan: the
+// assembly then reads the densities of a group's elements from neighbouring
+// addresses).  T: double or float.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather(const T *__restrict__ src, const int32_t *__restrict__ idx,
+                                                T *__restrict__ dst, int64_t n) {
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r < n) dst[r] = src[idx[r]];
+}
+
 // ---------------------------------------------------------------- launchers
 
 template <int DIM, int NEN, int PREC, bool FUSE>
@@ -1272,6 +1291,18 @@ hipError_t noalloc_scratch(int device, double **out) {
     g_scratch_ptr[device] = static_cast<double *>(p);
     *out = static_cast<double *>(p);
     return hipSuccess;
+}
+
+hipError_t launch_gather(int elem_bytes, const void *src, const int32_t *idx, void *dst, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((n + 255) / 256));
+    if (elem_bytes == 8)
+        hipLaunchKernelGGL(k_gather<double>, grid, dim3(256), 0, st, static_cast<const double *>(src), idx,
+                           static_cast<double *>(dst), n);
+    else
+        hipLaunchKernelGGL(k_gather<float>, grid, dim3(256), 0, st, static_cast<const float *>(src), idx,
+                           static_cast<float *>(dst), n);
+    return hipGetLastError();
 }
 
 }  // namespace soptx

@@ -213,6 +213,113 @@ int validate_mesh(const soptx_mesh *mesh, bool allow_nonaffine, bool *affine) {
     return SOPTX_OK;
 }
 
+// Canonical orders of nodes and elements: ranks that depend on the mesh's
+// geometry and connectivity, not on how its nodes and elements are numbered.
+// With h_a the lattice spacing along axis a (the median of |x_a(v) - x_a(w)|
+// over pairs of vertices of one element that lie more than half the median
+// element extent apart along a: unbiased under jitter) and o_a
+// the phase of the vertex lattice along a (the circular mean of the element
+// vertices' x_a modulo h_a, so that jittered lattice points round to their
+// lattice positions):
+//   node n: (q_0, ..., q_{d-1}), q_a = round(2 (x_a - o_a) / h_a) (edge
+//     midpoints of quadratic elements fall on the odd values);
+//   element e: the cell of its vertex centroid, c_a = floor((x_a - o_a) / h_a),
+//     (c_0, ..., c_{d-1}), then the position of each of its vertices in that
+//     cell, round(2 (x_a - o_a - c_a h_a) / h_a) clamped to 0..3, in local
+//     vertex order (the elements of one cell differ there on a structured or
+//     jittered grid);
+// compared lexicographically (x slowest), ties by id.  A mesh numbered along
+// its grid with x slowest gets its own numbering back; node_rank and
+// elem_rank stay empty then.
+static int canonical_orders(const soptx_mesh *mesh, std::vector<int32_t> &node_rank, std::vector<int32_t> &elem_rank) {
+    node_rank.clear();
+    elem_rank.clear();
+    const int dim = elem_dim(mesh->elem), nen = elem_nen(mesh->elem);
+    const int nv = mesh->elem == SOPTX_TRI3 ? 3 : mesh->elem == SOPTX_TET10 ? 4 : nen;
+    const int64_t NN = mesh->n_nodes, NC = mesh->n_cells;
+    if (NN == 0 || NC == 0 || nv > 8) return SOPTX_OK;
+    const double *X = mesh->coords;
+    const int32_t *cells = mesh->cells;
+    double lo[3] = {0, 0, 0}, h[3] = {1, 1, 1};
+    for (int a = 0; a < dim; a++) {
+        std::vector<double> ext((size_t)NC);
+        for (int64_t e = 0; e < NC; e++) {
+            double mn = X[(int64_t)cells[e * nen] * dim + a], mx = mn;
+            for (int v = 1; v < nv; v++) {
+                const double x = X[(int64_t)cells[e * nen + v] * dim + a];
+                mn = std::min(mn, x);
+                mx = std::max(mx, x);
+            }
+            ext[(size_t)e] = mx - mn;
+        }
+        std::nth_element(ext.begin(), ext.begin() + NC / 2, ext.end());
+        const double h0 = ext[(size_t)(NC / 2)];
+        if (!(h0 > 0.0) || !std::isfinite(h0)) return SOPTX_OK;  // no usable spacing: keep the numbering
+        // vertex pairs that span a cell along a, from at most ~2^17 elements
+        std::vector<double> gap;
+        const int64_t stride = std::max<int64_t>(1, NC >> 17);
+        for (int64_t e = 0; e < NC; e += stride)
+            for (int v = 0; v < nv; v++)
+                for (int u = 0; u < v; u++) {
+                    const double d = std::fabs(X[(int64_t)cells[e * nen + v] * dim + a] -
+                                               X[(int64_t)cells[e * nen + u] * dim + a]);
+                    if (d > 0.5 * h0) gap.push_back(d);
+                }
+        if (gap.empty()) return SOPTX_OK;
+        std::nth_element(gap.begin(), gap.begin() + gap.size() / 2, gap.end());
+        h[a] = gap[gap.size() / 2];
+        // lattice phase: circular mean of the vertex coordinates modulo h
+        const double w = 2.0 * M_PI / h[a];
+        double sn = 0.0, cs = 0.0;
+        for (int64_t e = 0; e < NC; e++)
+            for (int v = 0; v < nv; v++) {
+                const double x = X[(int64_t)cells[e * nen + v] * dim + a];
+                sn += std::sin(w * x);
+                cs += std::cos(w * x);
+            }
+        lo[a] = std::atan2(sn, cs) / w;
+    }
+    auto quant = [](double v) -> int64_t {
+        if (!(std::fabs(v) < 4.0e18)) return v > 0 ? INT64_MAX / 2 : -INT64_MAX / 2;
+        return (int64_t)std::floor(v);
+    };
+    // nodes
+    std::vector<std::array<int64_t, 4>> nk((size_t)NN);
+    for (int64_t n = 0; n < NN; n++) {
+        nk[(size_t)n] = {0, 0, 0, n};
+        for (int a = 0; a < dim; a++) nk[(size_t)n][a] = quant(2.0 * (X[n * dim + a] - lo[a]) / h[a] + 0.5);
+    }
+    std::sort(nk.begin(), nk.end());
+    // elements
+    std::vector<std::array<int64_t, 5>> ek((size_t)NC);
+    for (int64_t e = 0; e < NC; e++) {
+        double cen[3] = {0, 0, 0};
+        for (int v = 0; v < nv; v++)
+            for (int a = 0; a < dim; a++) cen[a] += X[(int64_t)cells[e * nen + v] * dim + a] / nv;
+        int64_t c[3] = {0, 0, 0};
+        for (int a = 0; a < dim; a++) c[a] = quant((cen[a] - lo[a]) / h[a]);
+        uint64_t code = 0;
+        for (int v = 0; v < nv; v++)
+            for (int a = 0; a < dim; a++) {
+                const double off = X[(int64_t)cells[e * nen + v] * dim + a] - lo[a] - (double)c[a] * h[a];
+                int64_t r = quant(2.0 * off / h[a] + 0.5);
+                r = std::max<int64_t>(0, std::min<int64_t>(3, r));
+                code = (code << 2) | (uint64_t)r;
+            }
+        ek[(size_t)e] = {c[0], c[1], c[2], (int64_t)code, e};
+    }
+    std::sort(ek.begin(), ek.end());
+    bool ident = true;
+    for (int64_t n = 0; n < NN && ident; n++) ident = nk[(size_t)n][3] == n;
+    for (int64_t e = 0; e < NC && ident; e++) ident = ek[(size_t)e][4] == e;
+    if (ident) return SOPTX_OK;
+    node_rank.assign((size_t)NN, 0);
+    elem_rank.assign((size_t)NC, 0);
+    for (int64_t r = 0; r < NN; r++) node_rank[(size_t)nk[(size_t)r][3]] = (int32_t)r;
+    for (int64_t r = 0; r < NC; r++) elem_rank[(size_t)ek[(size_t)r][4]] = (int32_t)r;
+    return SOPTX_OK;
+}
+
 int build_host_plan(const soptx_mesh *mesh, HostPlan &hp, bool general) {
     int rc = validate_mesh(mesh, general, &hp.affine);
     if (rc) return rc;
@@ -348,65 +455,145 @@ int build_host_plan(const soptx_mesh *mesh, HostPlan &hp, bool general) {
         return general_table(mesh, hp);
     }
 
-    // ---- signatures and the backward position table
+    // ---- backward position table: position of cells[e][j] in the CSR
+    // neighbour list of cells[e][i]
     hp.pos.assign((size_t)NC * nen * nen, 0);
+    if (!parallel_for(NC, [&](int64_t a0, int64_t a1) {
+        for (int64_t e = a0; e < a1; e++)
+            for (int i = 0; i < nen; i++) {
+                const int64_t I = cells[e * nen + i];
+                const int32_t *nbn = nb.data() + nb_ptr[I];
+                for (int j = 0; j < nen; j++)
+                    hp.pos[((size_t)e * nen + i) * nen + j] =
+                        (uint16_t)(std::lower_bound(nbn, nbn + deg[I], cells[e * nen + j]) - nbn);
+            }
+    }))
+        return SOPTX_E_OOM;
+
+    // ---- signatures.  In the given numbering a node's adjacent elements are
+    // taken in ascending id and its neighbours in CSR order; in the canonical
+    // order (canonical_orders) both follow ranks that do not depend on the
+    // numbering, and nb_perm maps a canonical neighbour position to the CSR
+    // one.  The canonical order is tried when the given numbering fragments
+    // the plan (more than 64 signatures, fewer than 32 nodes per signature)
+    // and kept when it at least halves the number of signatures.
+    std::vector<int32_t> node_rank, elem_rank;
+    bool canon = false;
+    std::vector<uint8_t> nb_perm;  // [nb_ptr[NN]]: CSR position of canonical position pc of node n
     std::vector<int32_t> node_sig(NN, -1);
-    std::unordered_map<uint64_t, std::vector<int32_t>> sig_by_hash;
     std::vector<std::vector<int32_t>> sigs;  // canonical vectors
-    const int64_t CH = 1 << 16;
-    for (int64_t c0 = 0; c0 < NN; c0 += CH) {
-        int64_t c1 = std::min(NN, c0 + CH);
-        std::vector<std::vector<int32_t>> sv(c1 - c0);
-        std::vector<uint64_t> hv(c1 - c0);
-        if (!parallel_for(c1 - c0, [&](int64_t a0, int64_t a1) {
-            std::vector<std::array<int32_t, 4>> t;  // p, k, i, j
-            for (int64_t x = a0; x < a1; x++) {
-                int64_t n = c0 + x;
-                const int32_t *nbn = nb.data() + nb_ptr[n];
-                const int64_t dg = deg[n];
-                const int K = (int)(n2e_ptr[n + 1] - n2e_ptr[n]);
-                t.clear();
-                for (int k = 0; k < K; k++) {
-                    int64_t e = n2e_e[n2e_ptr[n] + k];
-                    int i = n2e_i[n2e_ptr[n] + k];
-                    for (int j = 0; j < nen; j++) {
-                        int32_t J = cells[e * nen + j];
-                        int p = (int)(std::lower_bound(nbn, nbn + dg, J) - nbn);
-                        t.push_back({p, k, i, j});
-                        hp.pos[((size_t)e * nen + i) * nen + j] = (uint16_t)p;
+    auto signatures = [&](bool use_canon, std::vector<int32_t> &nsig_of, std::vector<std::vector<int32_t>> &sv_all) {
+        std::unordered_map<uint64_t, std::vector<int32_t>> sig_by_hash;
+        sv_all.clear();
+        const int64_t CH = 1 << 16;
+        for (int64_t c0 = 0; c0 < NN; c0 += CH) {
+            int64_t c1 = std::min(NN, c0 + CH);
+            std::vector<std::vector<int32_t>> sv(c1 - c0);
+            std::vector<uint64_t> hv(c1 - c0);
+            if (!parallel_for(c1 - c0, [&](int64_t a0, int64_t a1) {
+                std::vector<std::array<int32_t, 4>> t;  // position, k, i, j
+                std::vector<std::array<int64_t, 2>> ord;
+                std::vector<int32_t> pc_of;
+                for (int64_t x = a0; x < a1; x++) {
+                    int64_t n = c0 + x;
+                    const int32_t *nbn = nb.data() + nb_ptr[n];
+                    const int64_t dg = deg[n];
+                    const int K = (int)(n2e_ptr[n + 1] - n2e_ptr[n]);
+                    if (use_canon) {
+                        // canonical position of each CSR neighbour
+                        ord.resize(dg);
+                        for (int64_t q = 0; q < dg; q++) ord[q] = {node_rank[nbn[q]], q};
+                        std::sort(ord.begin(), ord.end());
+                        if ((int64_t)pc_of.size() < dg) pc_of.resize(dg);
+                        for (int64_t r = 0; r < dg; r++) {
+                            pc_of[ord[r][1]] = (int32_t)r;
+                            nb_perm[nb_ptr[n] + r] = (uint8_t)ord[r][1];
+                        }
                     }
+                    t.clear();
+                    for (int k = 0; k < K; k++) {
+                        int64_t e = n2e_e[n2e_ptr[n] + k];
+                        int i = n2e_i[n2e_ptr[n] + k];
+                        for (int j = 0; j < nen; j++) {
+                            int32_t J = cells[e * nen + j];
+                            int p = (int)(std::lower_bound(nbn, nbn + dg, J) - nbn);
+                            t.push_back({use_canon ? pc_of[p] : p, k, i, j});
+                        }
+                    }
+                    std::sort(t.begin(), t.end());
+                    std::vector<int32_t> &sg = sv[x];
+                    sg.clear();
+                    sg.push_back(K);
+                    sg.push_back((int32_t)dg);
+                    size_t q = 0;
+                    for (int p = 0; p < dg; p++) {
+                        size_t q0 = q;
+                        while (q < t.size() && t[q][0] == p) q++;
+                        sg.push_back((int32_t)(q - q0));
+                        for (size_t r = q0; r < q; r++) sg.push_back((t[r][1] << 16) | (t[r][2] << 8) | t[r][3]);
+                    }
+                    uint64_t h = 1469598103934665603ull;
+                    for (int32_t v : sg) { h ^= (uint32_t)v; h *= 1099511628211ull; }
+                    hv[x] = h;
                 }
-                std::sort(t.begin(), t.end());
-                std::vector<int32_t> &s = sv[x];
-                s.clear();
-                s.push_back(K);
-                s.push_back((int32_t)dg);
-                size_t q = 0;
-                for (int p = 0; p < dg; p++) {
-                    size_t q0 = q;
-                    while (q < t.size() && t[q][0] == p) q++;
-                    s.push_back((int32_t)(q - q0));
-                    for (size_t r = q0; r < q; r++) s.push_back((t[r][1] << 16) | (t[r][2] << 8) | t[r][3]);
+            }))
+                return false;
+            for (int64_t x = 0; x < c1 - c0; x++) {
+                auto &cand = sig_by_hash[hv[x]];
+                int32_t id = -1;
+                for (int32_t c : cand)
+                    if (sv_all[c] == sv[x]) { id = c; break; }
+                if (id < 0) {
+                    id = (int32_t)sv_all.size();
+                    sv_all.push_back(std::move(sv[x]));
+                    cand.push_back(id);
                 }
-                uint64_t h = 1469598103934665603ull;
-                for (int32_t v : s) { h ^= (uint32_t)v; h *= 1099511628211ull; }
-                hv[x] = h;
+                nsig_of[c0 + x] = id;
+            }
+        }
+        return true;
+    };
+    if (!signatures(false, node_sig, sigs)) return SOPTX_E_OOM;
+    if (sigs.size() > 64 && (int64_t)sigs.size() * 32 > NN) {
+        if ((rc = canonical_orders(mesh, node_rank, elem_rank))) return rc;
+        canon = !node_rank.empty();
+        for (int64_t n = 0; canon && n < NN; n++)
+            if (deg[n] > 255) canon = false;  // canonical positions are stored in bytes
+    }
+    if (canon) {
+        // the adjacent elements of every node in ascending rank
+        std::vector<int32_t> e2(n2e_e);
+        std::vector<uint8_t> i2(n2e_i);
+        if (!parallel_for(NN, [&](int64_t a0, int64_t a1) {
+            std::vector<std::array<int64_t, 3>> v;
+            for (int64_t n = a0; n < a1; n++) {
+                v.clear();
+                for (int64_t s = n2e_ptr[n]; s < n2e_ptr[n + 1]; s++) v.push_back({elem_rank[e2[s]], e2[s], i2[s]});
+                std::sort(v.begin(), v.end());
+                for (size_t r = 0; r < v.size(); r++) {
+                    e2[n2e_ptr[n] + r] = (int32_t)v[r][1];
+                    i2[n2e_ptr[n] + r] = (uint8_t)v[r][2];
+                }
             }
         }))
             return SOPTX_E_OOM;
-        for (int64_t x = 0; x < c1 - c0; x++) {
-            auto &cand = sig_by_hash[hv[x]];
-            int32_t id = -1;
-            for (int32_t c : cand)
-                if (sigs[c] == sv[x]) { id = c; break; }
-            if (id < 0) {
-                id = (int32_t)sigs.size();
-                sigs.push_back(sv[x]);
-                cand.push_back(id);
-            }
-            node_sig[c0 + x] = id;
+        std::swap(e2, n2e_e);
+        std::swap(i2, n2e_i);
+        nb_perm.assign(nb_ptr[NN], 0);
+        std::vector<int32_t> node_sig2(NN, -1);
+        std::vector<std::vector<int32_t>> sigs2;
+        if (!signatures(true, node_sig2, sigs2)) return SOPTX_E_OOM;
+        if (2 * sigs2.size() <= sigs.size()) {
+            node_sig.swap(node_sig2);
+            sigs.swap(sigs2);
+        } else {
+            canon = false;
+            std::swap(e2, n2e_e);
+            std::swap(i2, n2e_i);
+            nb_perm.clear();
         }
     }
+    hp.canonical = canon;
 
     // ---- signature tables
     const int64_t nsig = (int64_t)sigs.size();
@@ -484,6 +671,7 @@ int build_host_plan(const soptx_mesh *mesh, HostPlan &hp, bool general) {
     struct Open { std::vector<int32_t> nodes; std::vector<int32_t> elems; std::unordered_set<int32_t> in; };
     std::vector<Open> open(nsig);
     hp.grp_info.clear(); hp.grp_nodes.clear(); hp.grp_elems.clear(); hp.grp_n2l.clear(); hp.grp_rows.clear();
+    hp.grp_rank_off.clear(); hp.grp_rank.clear();
     hp.stage_max = 0;
     struct Closed { int32_t sig; std::vector<int32_t> nodes, elems; };
     std::vector<Closed> closed;
@@ -498,11 +686,32 @@ int build_host_plan(const soptx_mesh *mesh, HostPlan &hp, bool general) {
     auto emit = [&](Closed &o) {
         const int64_t s = o.sig;
         const int K = hp.sig_info[s * 4 + 0];
+        const int dg = hp.sig_info[s * 4 + 1];
         const int blk = hp.sig_info[s * 4 + 3];
         hp.stage_max = std::max<int64_t>(hp.stage_max, (int64_t)o.nodes.size() * blk);
-        // elements sorted by id: for a fixed k, neighbouring lanes then read
-        // neighbouring LDS slots on structured meshes
-        std::sort(o.elems.begin(), o.elems.end());
+        // elements sorted by id (by rank in the canonical order): for a fixed
+        // k, neighbouring lanes then read neighbouring LDS slots on structured
+        // meshes
+        if (canon)
+            std::sort(o.elems.begin(), o.elems.end(), [&](int32_t x, int32_t y) { return elem_rank[x] < elem_rank[y]; });
+        else
+            std::sort(o.elems.begin(), o.elems.end());
+        // canonical order: the CSR position of each canonical neighbour
+        // position, [position][lane], unless it is the position itself for
+        // every node of the group
+        int32_t roff = -1;
+        if (canon) {
+            bool ident = true;
+            for (const int32_t n : o.nodes)
+                for (int p = 0; p < dg && ident; p++) ident = nb_perm[nb_ptr[n] + p] == p;
+            if (!ident) {
+                roff = (int32_t)hp.grp_rank.size();
+                for (int p = 0; p < dg; p++)
+                    for (int l = 0; l < kGroupNodes; l++)
+                        hp.grp_rank.push_back(l < (int)o.nodes.size() ? nb_perm[nb_ptr[o.nodes[l]] + p] : (uint8_t)p);
+            }
+        }
+        if (canon) hp.grp_rank_off.push_back(roff);
         hp.grp_info.push_back((int32_t)s);
         hp.grp_info.push_back((int32_t)o.nodes.size());
         hp.grp_info.push_back((int32_t)hp.grp_elems.size());
@@ -517,12 +726,19 @@ int build_host_plan(const soptx_mesh *mesh, HostPlan &hp, bool general) {
                     if (m != a && hp.geo[(size_t)(m * dim + a) * NC + e] != 0.0) { diag = false; break; }
         hp.grp_info.push_back(diag ? kGrpDiag : 0);
         for (int l = 0; l < kGroupNodes; l++) hp.grp_nodes.push_back(l < (int)o.nodes.size() ? o.nodes[l] : -1);
-        for (int32_t e : o.elems) hp.grp_elems.push_back(e);
+        // canonical order: the elements by rank (the assembly reads their data
+        // from arrays in rank order, geo_rank and the densities gathered so)
+        for (int32_t e : o.elems) hp.grp_elems.push_back(canon ? elem_rank[e] : e);
         for (int k = 0; k < K; k++)
             for (int l = 0; l < kGroupNodes; l++) {
                 const int ln = l < (int)o.nodes.size() ? l : 0;
                 const int32_t e = n2e_e[n2e_ptr[o.nodes[ln]] + k];
-                const int slot = (int)(std::lower_bound(o.elems.begin(), o.elems.end(), e) - o.elems.begin());
+                const int slot = (int)((canon ? std::lower_bound(o.elems.begin(), o.elems.end(), e,
+                                                                 [&](int32_t x, int32_t y) {
+                                                                     return elem_rank[x] < elem_rank[y];
+                                                                 })
+                                              : std::lower_bound(o.elems.begin(), o.elems.end(), e)) -
+                                        o.elems.begin());
                 hp.grp_n2l.push_back((uint16_t)slot);
             }
         for (int l = 0; l < kGroupNodes; l++) {
@@ -536,7 +752,14 @@ int build_host_plan(const soptx_mesh *mesh, HostPlan &hp, bool general) {
             }
         }
     };
-    for (int64_t n = 0; n < NN; n++) {
+    // nodes in ascending id, or in ascending rank in the canonical order
+    std::vector<int32_t> by_rank;
+    if (canon) {
+        by_rank.assign((size_t)NN, 0);
+        for (int64_t n = 0; n < NN; n++) by_rank[(size_t)node_rank[n]] = (int32_t)n;
+    }
+    for (int64_t r = 0; r < NN; r++) {
+        const int64_t n = canon ? by_rank[(size_t)r] : r;
         const int32_t s = node_sig[n];
         if (hp.sig_info[s * 4 + 1] == 0) continue;  // isolated node: empty rows
         Open &o = open[s];
@@ -556,7 +779,11 @@ int build_host_plan(const soptx_mesh *mesh, HostPlan &hp, bool general) {
     // workgroups take consecutive groups at the same time, so the device
     // writes one contiguous window of K at a time and neighbouring groups
     // share element data in cache
-    std::sort(closed.begin(), closed.end(), [](const Closed &x, const Closed &y) { return x.nodes[0] < y.nodes[0]; });
+    if (canon)
+        std::sort(closed.begin(), closed.end(),
+                  [&](const Closed &x, const Closed &y) { return node_rank[x.nodes[0]] < node_rank[y.nodes[0]]; });
+    else
+        std::sort(closed.begin(), closed.end(), [](const Closed &x, const Closed &y) { return x.nodes[0] < y.nodes[0]; });
     // ---- wide work items.  A signature whose groups hold at most N = 8 or 16
     // nodes would leave most lanes of a half-wave idle.  Its work items
     // instead cover P positions, each dealt round robin over Q phases
@@ -622,7 +849,19 @@ int build_host_plan(const soptx_mesh *mesh, HostPlan &hp, bool general) {
     }
     hp.ne_max = 0;
     for (int64_t g = 0; g < hp.n_groups(); g++) hp.ne_max = std::max(hp.ne_max, hp.grp_info[kGrpInfo * g + 3]);
-    if (hp.grp_elems.size() >= (size_t)INT32_MAX || hp.grp_n2l.size() >= (size_t)INT32_MAX)
+    if (canon) {
+        // element data in rank order: the groups' elements are then as close
+        // together in memory as on a mesh numbered along its grid
+        hp.elem_by_rank.assign((size_t)NC, 0);
+        for (int64_t e = 0; e < NC; e++) hp.elem_by_rank[(size_t)elem_rank[e]] = (int32_t)e;
+        const int ng = dim * dim + 1;
+        hp.geo_rank.assign(hp.geo.size(), 0.0);
+        for (int c = 0; c < ng; c++)
+            for (int64_t r = 0; r < NC; r++)
+                hp.geo_rank[(size_t)c * NC + r] = hp.geo[(size_t)c * NC + hp.elem_by_rank[(size_t)r]];
+    }
+    if (hp.grp_elems.size() >= (size_t)INT32_MAX || hp.grp_n2l.size() >= (size_t)INT32_MAX ||
+        hp.grp_rank.size() >= (size_t)INT32_MAX)
         return SOPTX_E_OVERFLOW;
 
     return general ? general_table(mesh, hp) : SOPTX_OK;

@@ -62,6 +62,11 @@ struct soptx_pattern_s {
     int32_t *grp_info = nullptr, *grp_nodes = nullptr, *grp_elems = nullptr;
     uint16_t *grp_n2l = nullptr;
     int32_t *grp_rows = nullptr;
+    int32_t *grp_rank_off = nullptr;  // canonical-order plans only
+    uint8_t *grp_rank = nullptr;
+    int64_t n_rank_bytes = 0;
+    int32_t *elem_by_rank = nullptr;  // canonical-order plans only: rank -> element
+    double *geo_rank = nullptr;       // geo with its columns in rank order
     int n_cu = 0;
     int32_t *sig_info = nullptr, *sig_pos_ptr = nullptr, *sig_contrib = nullptr, *sig_pairs = nullptr;
     int32_t *sig_witems = nullptr, *sig_witem_ptr = nullptr;
@@ -240,12 +245,17 @@ static int build_pattern(const soptx_mesh *mesh, int32_t ref_method, bool genera
         if ((rc = upload(h, hp.grp_info, &h->grp_info, st)) || (rc = upload(h, hp.grp_nodes, &h->grp_nodes, st)) ||
             (rc = upload(h, hp.grp_elems, &h->grp_elems, st)) || (rc = upload(h, hp.grp_n2l, &h->grp_n2l, st)) ||
             (rc = upload(h, hp.grp_rows, &h->grp_rows, st)) ||
+            (hp.canonical && (rc = upload(h, hp.grp_rank_off, &h->grp_rank_off, st))) ||
+            (hp.canonical && (rc = upload(h, hp.grp_rank, &h->grp_rank, st))) ||
+            (hp.canonical && (rc = upload(h, hp.elem_by_rank, &h->elem_by_rank, st))) ||
+            (hp.canonical && (rc = upload(h, hp.geo_rank, &h->geo_rank, st))) ||
             (rc = upload(h, hp.sig_info, &h->sig_info, st)) || (rc = upload(h, hp.sig_pos_ptr, &h->sig_pos_ptr, st)) ||
             (rc = upload(h, hp.sig_contrib, &h->sig_contrib, st)) || (rc = upload(h, hp.sig_pairs, &h->sig_pairs, st)) ||
             (rc = upload(h, hp.sig_witems, &h->sig_witems, st)) || (rc = upload(h, hp.sig_witem_ptr, &h->sig_witem_ptr, st))) {
             free_handle(h); return rc;
         }
         h->stats.plan_bytes = h->stats.device_bytes - base_bytes;
+        h->n_rank_bytes = (int64_t)hp.grp_rank.size();
         if ((rc = upload(h, hp.pos, &h->pos, st)) || (rc = upload(h, hp.nb_tslot, &h->nb_tslot, st)) ||
             (rc = upload(h, hp.nb, &h->nb, st)) || (rc = upload(h, hp.nb_tdeg, &h->nb_tdeg, st)) || (rc = upload(h, M, &h->M, st)) ||
             (rc = upload(h, M32, &h->M32, st)) ||
@@ -268,6 +278,7 @@ static int build_pattern(const soptx_mesh *mesh, int32_t ref_method, bool genera
         h->stats.n_groups = h->ngroups; h->stats.n_signatures = h->nsig; h->stats.n_contributions = ncontrib;
         for (int64_t g = 0; g < h->ngroups; g++)
             h->stats.n_groups_diag += (hp.grp_info[g * kGrpInfo + kGrpInfo - 1] & kGrpDiag) ? 1 : 0;
+        for (int32_t ro : hp.grp_rank_off) h->stats.n_groups_ranked += ro >= 0 ? 1 : 0;
     } catch (const std::bad_alloc &) {
         free_handle(h);
         return SOPTX_E_OOM;
@@ -346,6 +357,35 @@ int soptx_pattern_stats_get(soptx_pattern h, soptx_pattern_stats *out) {
     return SOPTX_OK;
 }
 
+// Parameters of the assembly kernel.  A canonical-order plan reads its
+// element data in rank order: geo_rank, and the densities gathered into rank
+// order first (a workspace of the stream, so calls on other streams keep
+// theirs).
+static int asm_params(soptx_pattern h, const soptx_material *m, const void *d_rho, double *d_K_vals, int32_t prec,
+                      hipStream_t st, AsmParams &P) {
+    P.grp_info = h->grp_info; P.grp_nodes = h->grp_nodes; P.grp_elems = h->grp_elems; P.grp_n2l = h->grp_n2l;
+    P.grp_rows = h->grp_rows; P.n_groups = h->ngroups; P.n_cu = h->n_cu;
+    P.grp_rank_off = h->grp_rank_off; P.grp_rank = h->grp_rank;
+    P.sig_info = h->sig_info; P.sig_pos_ptr = h->sig_pos_ptr; P.sig_contrib = h->sig_contrib;
+    P.sig_pairs = h->sig_pairs; P.sig_witems = h->sig_witems; P.sig_witem_ptr = h->sig_witem_ptr;
+    P.geo = h->geo; P.rho = d_rho;
+    if (h->elem_by_rank) {
+        double *ws = nullptr;
+        const size_t bytes = (size_t)h->n_cells * (prec == SOPTX_FP64 ? 8 : 4);
+        int rc = get_workspace(h->device, st, (bytes + 7) / 8, &ws, 5);
+        if (rc) return rc;
+        if (launch_gather(prec == SOPTX_FP64 ? 8 : 4, d_rho, h->elem_by_rank, ws, h->n_cells, st) != hipSuccess)
+            return SOPTX_E_DEVICE;
+        P.geo = h->geo_rank;
+        P.rho = ws;
+    }
+    P.M = h->M; P.M32 = h->M32; P.K = d_K_vals;
+    P.n_cells = h->n_cells; P.E0 = m->E0; P.Emin = m->Emin; P.p = m->p; P.ip = int_exponent(m->p);
+    lame(h, m, &P.lam, &P.mu);
+    P.kmax = h->kmax; P.stage = h->stage;
+    return SOPTX_OK;
+}
+
 int soptx_assemble(soptx_pattern h, const soptx_material *m, const void *d_rho, const uint8_t *d_dirichlet,
                    double *d_K_vals, int32_t prec, void *stream) {
     if (!h || !valid_prec(prec)) return SOPTX_E_INVALID_ARG;
@@ -356,17 +396,9 @@ int soptx_assemble(soptx_pattern h, const soptx_material *m, const void *d_rho, 
     if (h->nnz == 0) return SOPTX_OK;
     DeviceGuard dg(h->device);
     if (!dg.ok) return SOPTX_E_DEVICE;
-    AsmParams P{};
-    P.grp_info = h->grp_info; P.grp_nodes = h->grp_nodes; P.grp_elems = h->grp_elems; P.grp_n2l = h->grp_n2l;
-    P.grp_rows = h->grp_rows; P.n_groups = h->ngroups; P.n_cu = h->n_cu;
-    P.sig_info = h->sig_info; P.sig_pos_ptr = h->sig_pos_ptr; P.sig_contrib = h->sig_contrib;
-    P.sig_pairs = h->sig_pairs; P.sig_witems = h->sig_witems; P.sig_witem_ptr = h->sig_witem_ptr;
-    P.geo = h->geo; P.rho = d_rho;
-    P.M = h->M; P.M32 = h->M32; P.K = d_K_vals;
-    P.n_cells = h->n_cells; P.E0 = m->E0; P.Emin = m->Emin; P.p = m->p; P.ip = int_exponent(m->p);
-    lame(h, m, &P.lam, &P.mu);
-    P.kmax = h->kmax; P.stage = h->stage;
     hipStream_t st = static_cast<hipStream_t>(stream);
+    AsmParams P{};
+    if ((rc = asm_params(h, m, d_rho, d_K_vals, prec, st, P))) return rc;
     if (launch_assemble(h->elem, prec, P, h->ngroups, st) != hipSuccess) return SOPTX_E_DEVICE;
     if (d_dirichlet && launch_dirichlet(h->dim, h->row_ptr, h->nb_tslot, h->nb_tdeg, d_dirichlet, d_K_vals, h->ndof, st) != hipSuccess)
         return SOPTX_E_DEVICE;
@@ -619,6 +651,13 @@ int soptx_build_dirichlet(soptx_pattern h, const uint8_t *h_mask, soptx_dirichle
         if (!down(gi, h->grp_info) || !down(si, h->sig_info) || !down(gn, h->grp_nodes) || !down(rp, h->row_ptr) ||
             !down(nb, h->nb))
             return fail(SOPTX_E_DEVICE);
+        // canonical-order plans: the kernel's position p of a node is the CSR
+        // position rank[p][lane] where the group has a rank table
+        std::vector<int32_t> roff(h->grp_rank_off ? (size_t)G : 0);
+        std::vector<uint8_t> rank(h->grp_rank ? (size_t)h->n_rank_bytes : 0);
+        if (!down(roff, h->grp_rank_off) ||
+            (!rank.empty() && hipMemcpy(rank.data(), h->grp_rank, rank.size(), hipMemcpyDeviceToHost) != hipSuccess))
+            return fail(SOPTX_E_DEVICE);
         std::vector<int32_t> off((size_t)G, -1);
         std::vector<uint8_t> bits;
         if (bc->n_fixed > 0) {
@@ -633,7 +672,9 @@ int soptx_build_dirichlet(soptx_pattern h, const uint8_t *h_mask, soptx_dirichle
                     for (int a = 0; a < dim; a++) row |= h_mask[dim * n + a] ? 1 << a : 0;
                     const int64_t b0 = rp[(size_t)(dim * n)] / d2;
                     for (int p = 0; p < deg; p++) {
-                        const int64_t J = nb[(size_t)(b0 + p)];
+                        const int ro = roff.empty() ? -1 : roff[(size_t)g];
+                        const int q = ro < 0 ? p : rank[(size_t)ro + (size_t)p * kGroupNodes + l];
+                        const int64_t J = nb[(size_t)(b0 + q)];
                         int col = 0;
                         for (int c = 0; c < dim; c++) col |= h_mask[dim * J + c] ? 1 << (3 + c) : 0;
                         const int v = row | col | (J == n ? 64 : 0);
@@ -690,15 +731,7 @@ int soptx_step(soptx_pattern h, soptx_dirichlet bc, const soptx_material *m, con
     // assembly with the Dirichlet table applied while the blocks are staged
     if (h->ngroups > 0) {
         AsmParams P{};
-        P.grp_info = h->grp_info; P.grp_nodes = h->grp_nodes; P.grp_elems = h->grp_elems; P.grp_n2l = h->grp_n2l;
-        P.grp_rows = h->grp_rows; P.n_groups = h->ngroups; P.n_cu = h->n_cu;
-        P.sig_info = h->sig_info; P.sig_pos_ptr = h->sig_pos_ptr; P.sig_contrib = h->sig_contrib;
-        P.sig_pairs = h->sig_pairs; P.sig_witems = h->sig_witems; P.sig_witem_ptr = h->sig_witem_ptr;
-        P.geo = h->geo; P.rho = d_rho;
-        P.M = h->M; P.M32 = h->M32; P.K = d_K_vals;
-        P.n_cells = h->n_cells; P.E0 = m->E0; P.Emin = m->Emin; P.p = m->p; P.ip = int_exponent(m->p);
-        lame(h, m, &P.lam, &P.mu);
-        P.kmax = h->kmax; P.stage = h->stage;
+        if ((rc = asm_params(h, m, d_rho, d_K_vals, prec, st, P))) return rc;
         P.bc_off = (bc && bc->n_groups > 0) ? bc->off : nullptr;
         P.bc_bits = bc ? bc->bits : nullptr;
         if (launch_assemble(h->elem, prec, P, h->ngroups, st, true) != hipSuccess) return SOPTX_E_DEVICE;
@@ -749,7 +782,9 @@ int soptx_debug_host_plan_array(soptx_host_plan p, const char *name, const void 
     }
     SOPTX_ARR(row_ptr) SOPTX_ARR(col_idx) SOPTX_ARR(geo) SOPTX_ARR(sig_info) SOPTX_ARR(sig_pos_ptr)
     SOPTX_ARR(sig_contrib) SOPTX_ARR(sig_pairs) SOPTX_ARR(sig_witems) SOPTX_ARR(sig_witem_ptr) SOPTX_ARR(grp_info) SOPTX_ARR(grp_nodes) SOPTX_ARR(grp_elems)
-    SOPTX_ARR(grp_n2l) SOPTX_ARR(grp_rows) SOPTX_ARR(pos) SOPTX_ARR(nb_tslot) SOPTX_ARR(nb_tdeg)
+    SOPTX_ARR(grp_n2l) SOPTX_ARR(grp_rows) SOPTX_ARR(grp_rank_off) SOPTX_ARR(grp_rank) SOPTX_ARR(elem_by_rank)
+    SOPTX_ARR(pos)
+    SOPTX_ARR(nb_tslot) SOPTX_ARR(nb_tdeg)
     SOPTX_ARR(gptr) SOPTX_ARR(gent) SOPTX_ARR(gnode)
 #undef SOPTX_ARR
     return SOPTX_E_INVALID_ARG;

@@ -384,6 +384,29 @@ def box_p2(n: int = 48, seed: int = 1004) -> Problem:
     return Problem(f"box_p2_{n}", mesh, rho, mask, f, u)
 
 
+def renumber(pr: Problem, seed: int) -> Problem:
+    """The same problem with its nodes and elements renumbered by a seeded
+    permutation: node i becomes pn[i], element k of the result is element
+    pe[k] of pr (the nodal arrays and rho follow).  The permutations are
+    returned in the name-independent attributes node_perm and elem_perm."""
+    m0 = pr.mesh
+    rng = np.random.default_rng(seed)
+    pn, pe = rng.permutation(m0.n_nodes), rng.permutation(m0.n_cells)
+    coords = np.empty_like(m0.coords)
+    coords[pn] = m0.coords
+
+    def nodal(v):
+        if v is None:
+            return None
+        w = np.empty_like(v)
+        w.reshape(-1, m0.dim)[pn] = v.reshape(-1, m0.dim)
+        return w
+    out = Problem(pr.name + "_renumbered", Mesh(m0.elem, coords, pn[m0.cells[pe]].astype(np.int32)),
+                  pr.rho[pe], nodal(pr.mask), nodal(pr.f), nodal(pr.u), pr.E0, pr.Emin, pr.nu, pr.p)
+    out.node_perm, out.elem_perm = pn, pe
+    return out
+
+
 def serving_request(rid: int):
     """One serving request: 2D Q1 n^2 (n in 32..512) or 3D Q1 n^3 (n in 16..96), p in {3, 4}."""
     rng = np.random.default_rng(5000 + rid)

@@ -22,7 +22,7 @@
 
 static const char *kArrays[] = {"row_ptr",  "col_idx",       "geo",       "sig_info",  "sig_pos_ptr",
                                 "sig_contrib", "sig_pairs",  "sig_witems", "sig_witem_ptr", "grp_info",
-                                "grp_nodes", "grp_elems",    "grp_n2l",   "grp_rows",  "pos",
+                                "grp_nodes", "grp_elems",    "grp_n2l",   "grp_rows",  "grp_rank_off", "grp_rank", "elem_by_rank", "pos",
                                 "nb_tslot",  "nb_tdeg",      "gptr",      "gent",      "gnode"};
 
 static int nen_of(int elem) {

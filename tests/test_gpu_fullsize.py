@@ -216,3 +216,43 @@ def test_dirichlet_full_hex():
     assert torch.equal(K1[~fixed], K0[~fixed])  # every other entry untouched, bit for bit
     assert bool((K1[fixed & diag] == 1.0).all()) and bool((K1[fixed & ~diag] == 0.0).all())
     assert int(fixed.sum()) > 0
+
+
+def test_renumbered_cantilever_bitwise_through_the_permutation():
+    """The 120x40x40 cantilever with nodes and elements renumbered by a seeded
+    permutation.  The plan takes its canonical order, which here is the
+    generator's own numbering: the same signatures and groups, a rank table
+    per group.  So K with the Dirichlet rows (soptx_step, bound table), read
+    through the permutation, is bit for bit the original mesh's, dc element by
+    element too, and c within the rounding of a sum taken in another order."""
+    pr = I.cantilever_hex()
+    rn = I.renumber(pr, 17)
+    pat0, pat1 = api.Pattern.from_mesh(pr.mesh), api.Pattern.from_mesh(rn.mesh)
+    s0, s1 = pat0.stats(), pat1.stats()
+    assert s1["n_groups_ranked"] == s1["n_groups"] and s0["n_groups_ranked"] == 0
+    assert (s1["n_groups"], s1["n_signatures"]) == (s0["n_groups"], s0["n_signatures"])
+    mat = api.Material(E0=pr.E0, Emin=pr.Emin, nu=pr.nu, p=pr.p)
+    K0, dc0, c0 = pat0.step(mat, dev(pr.rho), dev(pr.u), bc=api.Dirichlet(pat0, pr.mask))
+    K1, dc1, c1 = pat1.step(mat, dev(rn.rho), dev(rn.u), bc=api.Dirichlet(pat1, rn.mask))
+    torch.cuda.synchronize()
+    d, ndof = 3, pat0.ndof
+    pn = torch.from_numpy(rn.node_perm.astype(np.int64)).cuda()
+    def keys(pat, perm=None):
+        rp, ci = pat.pattern()
+        rows = torch.repeat_interleave(torch.arange(ndof, device="cuda"),
+                                       torch.from_numpy(np.diff(rp).astype(np.int64)).cuda())
+        cols = torch.from_numpy(ci.astype(np.int64)).cuda()
+        if perm is not None:
+            rows = d * perm[rows // d] + rows % d
+            cols = d * perm[cols // d] + cols % d
+        return rows * ndof + cols
+    k1 = keys(pat1)
+    assert bool(torch.all(k1[1:] > k1[:-1]))         # CSR order: sorted keys
+    k0 = keys(pat0, pn)                               # original entries in the renumbered numbering
+    idx = torch.searchsorted(k1, k0)
+    assert bool(torch.equal(k1[idx], k0))
+    assert bool(torch.equal(K1[idx], K0)), "K of the renumbered mesh differs through the permutation"
+    pe = torch.from_numpy(rn.elem_perm.astype(np.int64)).cuda()
+    assert bool(torch.equal(dc1, dc0[pe]))
+    c0h, c1h = host(c0), host(c1)
+    assert abs(c1h[0] - c0h[0]) <= 1e-12 * abs(c0h[0])

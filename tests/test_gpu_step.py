@@ -29,13 +29,18 @@ MAT = api.Material()
 TOL = {api.FP64: 1e-12, api.FP32: 1e-5}
 CASES = ([(e, None, None) for e in ELEMS] + [(I.QUAD4, (23, 9), "global"), (I.HEX8, (9, 6, 7), "global"),
          (I.HEX8, (9, 6, 7), "kink"), (I.HEX8, (13, 4, 37), None), (I.TET10, (4, 3, 3), None),
-         (I.TRI3, (31, 12), None)])
+         (I.TRI3, (31, 12), None)] + [(e, d, "renumbered") for e, d in
+                                      ((I.QUAD4, (23, 9)), (I.TRI3, (31, 12)), (I.HEX8, (9, 6, 7)), (I.TET10, (4, 3, 3)))])
 
 
 def _setup(elem, dims, skew, seed=7):
-    pr = I.small_problem(elem, seed=seed, dims=dims, skew=skew)
+    pr = I.small_problem(elem, seed=seed, dims=dims, skew=None if skew == "renumbered" else skew)
+    if skew == "renumbered":
+        pr = I.renumber(pr, seed + 100)
     m = pr.mesh
     pat = api.Pattern(elem, m.coords, m.cells)
+    if skew == "renumbered":
+        assert pat.stats()["n_groups_ranked"] > 0
     rp, ci = O.pattern(elem, m.n_nodes, m.cells)
     return pr, m, pat, rp, ci
 

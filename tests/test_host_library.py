@@ -218,7 +218,14 @@ def walk_plan(hp, mesh, rho, M, E0=1.0, Emin=1e-9, p=3.0, nu=0.3, mask=None):
         else:
             assert hp["sig_witem_ptr"][sig + 1] == hp["sig_witem_ptr"][sig]
         elems = hp["grp_elems"][eoff:eoff + ne]
-        assert ne <= hp["emax"] and np.all(np.diff(elems) > 0)
+        # canonical-order plans: elements listed by rank (ascending), a rank
+        # table per group
+        ro = int(hp["grp_rank_off"][g]) if hp["grp_rank_off"].size else -1
+        canon = hp["grp_rank_off"].size > 0
+        if canon:
+            assert np.all(np.diff(elems) > 0)
+            elems = hp["elem_by_rank"][elems]
+        assert ne <= hp["emax"] and len(np.unique(elems)) == ne and (canon or np.all(np.diff(elems) > 0))
         offdiag = G[elems][:, ~np.eye(D, dtype=bool)]
         assert (flags & 1) == (1 if np.all(offdiag == 0.0) else 0)
         n2l = hp["grp_n2l"][n2loff:n2loff + Kk * NG].reshape(Kk, NG)
@@ -233,13 +240,14 @@ def walk_plan(hp, mesh, rho, M, E0=1.0, Emin=1e-9, p=3.0, nu=0.3, mask=None):
                 c0, c1 = hp["sig_pos_ptr"][posoff + pp], hp["sig_pos_ptr"][posoff + pp + 1]
                 parts = [np.zeros((D, D)), np.zeros((D, D))]
                 last = -1
-                Jcol = ci[base + D * pp] // D
+                pc = int(hp["grp_rank"][ro + pp * NG + lane]) if ro >= 0 else pp  # CSR position
+                Jcol = ci[base + D * pc] // D
                 for t in range(c0, c1):
                     pk = int(hp["sig_contrib"][t])
                     k, i, j = pk >> 16, (pk >> 8) & 255, pk & 255
                     e = elems[n2l[k, lane]]
                     assert cells[e, i] == Inode and cells[e, j] == Jcol
-                    assert e > last  # ascending elements within a stored block
+                    assert canon or e > last  # ascending elements within a stored block
                     last = e
                     seen[e, i, j] += 1
                     half = 1 if pp in split and t - c0 >= split[pp] else 0
@@ -253,7 +261,7 @@ def walk_plan(hp, mesh, rho, M, E0=1.0, Emin=1e-9, p=3.0, nu=0.3, mask=None):
                             if mask[r] or mask[c]:
                                 out[a, b] = 1.0 if r == c else 0.0
                 for a in range(D):
-                    K[base + a * rowlen + D * pp: base + a * rowlen + D * pp + D] = out[a]
+                    K[base + a * rowlen + D * pc: base + a * rowlen + D * pc + D] = out[a]
     assert np.all(seen == 1), "every element-local pair must be assembled exactly once"
     return K
 
@@ -302,6 +310,51 @@ def test_plan_walk_skewed_q1(elem, skew):
     rp, ci = O.pattern(elem, m.n_nodes, m.cells)
     Kref = O.assemble(elem, m.coords, m.cells, pr.rho, rp, ci, mask=pr.mask)
     assert row_scaled_err(rp, K, Kref) <= 1e-13
+
+
+def _renumbered(mesh, seed):
+    rng = np.random.default_rng(seed)
+    pn = rng.permutation(mesh.n_nodes)       # new id of old node i: pn[i]
+    pe = rng.permutation(mesh.n_cells)       # old element of new element k: pe[k]
+    coords = np.empty_like(mesh.coords)
+    coords[pn] = mesh.coords
+    return I.Mesh(mesh.elem, coords, pn[mesh.cells[pe]].astype(np.int32)), pn, pe
+
+
+@pytest.mark.parametrize("elem,dims", [(I.QUAD4, (12, 7)), (I.HEX8, (9, 6, 5)), (I.TRI3, (9, 6)), (I.TET10, (4, 3, 3))])
+def test_plan_survives_renumbering(elem, dims):
+    """Nodes and elements renumbered by a seeded permutation: the plan takes
+    the canonical order, so it has the signatures and group sizes of the
+    lexicographically numbered mesh (a rank table per group maps canonical
+    positions to CSR columns), and its walk still gives the oracle's K."""
+    pr = I.small_problem(elem, seed=6, jitter=False, dims=dims)
+    m0 = pr.mesh
+    hp0 = api.host_plan(elem, m0.coords, m0.cells)
+    m, pn, pe = _renumbered(m0, 91)
+    hp = api.host_plan(elem, m.coords, m.cells)
+    assert hp["grp_rank_off"].size == hp["n_groups"] and np.any(hp["grp_rank_off"] >= 0)
+    assert hp0["grp_rank_off"].size == 0          # numbered along the grid: the given numbering is kept
+    assert hp["n_signatures"] <= hp0["n_signatures"]
+    sizes = lambda h: sorted(h["grp_info"].reshape(-1, 6)[:, 1].tolist())
+    assert sizes(hp) == sizes(hp0)
+    rho = pr.rho[pe]
+    mask = np.empty_like(pr.mask)
+    mask.reshape(-1, m.dim)[pn] = pr.mask.reshape(-1, m.dim)
+    M = api.reference_tensor(elem)
+    rp, ci = O.pattern(elem, m.n_nodes, m.cells)
+    for msk in (None, mask):
+        K = walk_plan(hp, m, rho, M, mask=msk)
+        Kref = O.assemble(elem, m.coords, m.cells, rho, rp, ci, mask=msk)
+        assert not np.isnan(K).any()
+        assert row_scaled_err(rp, K, Kref) <= 1e-13
+
+
+def test_grid_numbered_meshes_keep_their_numbering():
+    """Meshes numbered along the grid (the generators' numberings) have few
+    signatures already: the plan keeps the given order (no rank tables)."""
+    for m in [I.quad_grid(9, 4), I.hex_grid(5, 3, 4), I.skew_mesh(I.hex_grid(4, 3, 3), "global")]:
+        hp = api.host_plan(m.elem, m.coords, m.cells)
+        assert hp["grp_rank_off"].size == 0
 
 
 def test_plan_axis_aligned_flag_set_on_grids():
