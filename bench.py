@@ -656,12 +656,15 @@ def main():
     st = StepState(pr, pat, api.FP64, stream)
     mat, rho = st.mat, st.rho
 
+    spun = spin_up(st, stream, args.spin_up)
+    total_s, asm_ms, ev_ms = timed_steps(st, stream, args.steps, args.warmup)
+    graph_s = None
     graphs = None
     if not args.no_graph:
         # one captured step per output buffer (HIP graph replay; the kernels
-        # and their order are those of the eager step), timed after the eager region
-        st.step(0, stream)
-        torch.cuda.synchronize()
+        # and their order are those of the eager step), captured and timed
+        # after the eager region: eager steps timed while captured graphs
+        # were held ran slower on some runs (108 vs 90 us assembly)
         graphs = []
         for b in range(st.nbuf):
             g = torch.cuda.CUDAGraph()
@@ -669,10 +672,6 @@ def main():
                 st.step(b, stream)
             graphs.append(g)
         torch.cuda.synchronize()
-
-    spun = spin_up(st, stream, args.spin_up)
-    total_s, asm_ms, ev_ms = timed_steps(st, stream, args.steps, args.warmup)
-    graph_s = None
     if graphs is not None:
         with torch.cuda.stream(stream):
             for i in range(args.warmup):
@@ -684,6 +683,7 @@ def main():
                 graphs[i % st.nbuf].replay()
         torch.cuda.synchronize()
         graph_s = time.perf_counter() - t0
+        del graphs  # the captured graphs' memory goes before the other legs
 
     if args.copy_probe:
         # known traffic for the counter calibration: a 1 GiB fill (writes

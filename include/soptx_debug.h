@@ -63,6 +63,13 @@ int soptx_debug_filter_stencil(const soptx_mesh *mesh, double rmin, int32_t *S, 
  * SOPTX_E_INVALID_ARG for n < 0. */
 int soptx_debug_fail_workers(int32_t n);
 
+/* Test hook: which assembly kernel the assembling calls launch, process-wide:
+ * -1 = chosen from the plan (default: one workgroup per node group where a
+ * group's stage is small or groups are few, the persistent warp-specialised
+ * kernel otherwise), 0 = the persistent kernel, 1 = one workgroup per node
+ * group.  All give bitwise the same K.  SOPTX_E_INVALID_ARG for other values. */
+int soptx_debug_set_assembly_variant(int32_t v);
+
 #ifdef __cplusplus
 }
 #endif

@@ -16,6 +16,7 @@ struct AsmParams {
     const int32_t *grp_elems;   // per group, sorted element ids
     const uint16_t *grp_n2l;    // per group [K][64]: slot of the lane's k-th element
     const int32_t *grp_rows;    // [G][64][2]: first CSR slot of the node's rows, row length
+    int os_window;              // one-shot variant: workgroups per window of XCD-local runs (multiple of 8)
     const int32_t *grp_rank_off;  // [G]: offset of the group's rank table, -1 = none (or NULL: no tables)
     const uint8_t *grp_rank;      // rank tables: [position][32] CSR position of a canonical position
     const int32_t *sig_info;    // [S][4]: K, deg, pos_off, padded row-block size
@@ -81,6 +82,9 @@ struct BwdParams {
 
 // fuse: the whole step (Dirichlet table, energies, dc, compliance partials)
 hipError_t launch_assemble(int elem, int prec, const AsmParams &P, int64_t ngroups, hipStream_t st, bool fuse = false);
+// which assembly kernel launch_assemble runs: -1 = chosen by the plan's shape
+// (default), 0 = persistent (k_assemble), 1 = one-shot (k_assemble_os)
+void set_assembly_variant(int v);
 hipError_t launch_dirichlet(int dim, const int32_t *row_ptr, const int32_t *nb_tslot, const uint16_t *nb_tdeg,
                             const uint8_t *mask, double *K, int64_t ndof, hipStream_t st);
 hipError_t launch_energy(int elem, int prec, const EnergyParams &P, hipStream_t st);

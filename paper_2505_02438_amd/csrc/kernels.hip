@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <map>
+#include <atomic>
 #include <mutex>
 
 #include "block_sum.h"
@@ -653,6 +654,372 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
     }
 }
 
+// One-shot assembly: one workgroup per group (two waves in 2D, eight in 3D;
+// XCD-local runs of consecutive groups inside windows of os_window
+// workgroups), several workgroups per CU.  Each loads its group (element
+// data, slot table, row offsets), assembles its blocks into one LDS stage
+// (all its waves take work items from the ticket), then streams the stage to
+// K with non-temporal stores; the hardware overlaps one workgroup's loads and
+// compute with another's stores.  The blocks, their summation order and the
+// stores are those of k_assemble.
+template <int DIM>
+struct OsShape { static constexpr int threads = DIM == 2 ? 128 : 512; };
+
+template <int DIM, int NEN, int PREC, bool FUSE>
+__global__ __launch_bounds__(OsShape<DIM>::threads) void k_assemble_os(AsmParams P) {
+    constexpr int kOsThreads = OsShape<DIM>::threads;
+    using T = typename CT<PREC>::T;
+    using R = typename std::conditional<PREC == kF64, double, float>::type;  // rho as stored
+    constexpr int D2 = DIM * DIM;
+    constexpr int NG = kGroupNodes;
+    constexpr int kStoreWaves = kOsThreads / 64;
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *stage = reinterpret_cast<double *>(smem);                  // [P.stage]
+    T *sG = reinterpret_cast<T *>(stage + P.stage);                     // [D2][kGroupElems]
+    T *sM = sG + D2 * kGroupElems;                                      // [NEN][NEN][D2]
+    int32_t *srows = reinterpret_cast<int32_t *>(sM + NEN * NEN * D2);  // [NG][2]
+    uint16_t *sn2l = reinterpret_cast<uint16_t *>(srows + NG * 2);      // [kmax][NG]
+    __shared__ int ticket;
+    __shared__ int shdr[9];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = wave_uniform(tid >> 6);
+    const int64_t NC = P.n_cells;
+    const int ngr = P.n_groups;
+    const int W = P.os_window;
+    const int bid = blockIdx.x;
+    const int base = bid - bid % W;
+    const int gg = base + W <= ngr ? base + (bid % 8) * (W / 8) + (bid - base) / 8 : bid;
+    if (gg >= ngr) return;
+    // ---- loads
+    const int sg = wave_uniform(ldc(P.grp_info, kGrpInfo * gg + 0));
+    const int eoff = wave_uniform(ldc(P.grp_info, kGrpInfo * gg + 2));
+    const int ne = wave_uniform(ldc(P.grp_info, kGrpInfo * gg + 3));
+    const int n2off = wave_uniform(ldc(P.grp_info, kGrpInfo * gg + 4));
+    const int gflags = wave_uniform(ldc(P.grp_info, kGrpInfo * gg + 5));
+    const int nk = wave_uniform(ldc(P.sig_info, 4 * sg + 0)) * NG;
+    for (int x = tid; x < NEN * NEN * D2; x += kOsThreads) {
+        if (PREC == kF64) sM[x] = (T)P.M[x];
+        else sM[x] = (T)P.M32[x];
+    }
+    for (int slot = tid; slot < ne; slot += kOsThreads) {
+        const int e = P.grp_elems[eoff + slot];
+        const double r = (double)static_cast<const R *>(P.rho)[e];
+        const double E = P.Emin + simp_pow(r, P.p, P.ip) * (P.E0 - P.Emin);
+        const double qq = sqrt(E * P.geo[(int64_t)D2 * NC + e]);
+        if (gflags & kGrpDiag) {
+#pragma unroll
+            for (int a = 0; a < DIM; a++) sG[a * kGroupElems + slot] = (T)(qq * P.geo[(int64_t)(a * DIM + a) * NC + e]);
+        } else {
+#pragma unroll
+            for (int c = 0; c < D2; c++) sG[c * kGroupElems + slot] = (T)(qq * P.geo[(int64_t)c * NC + e]);
+        }
+    }
+    for (int x = tid; x < nk; x += kOsThreads) sn2l[x] = P.grp_n2l[n2off + x];
+    if (tid < 2 * NG) srows[tid] = P.grp_rows[(int64_t)gg * 2 * NG + tid];
+    if (tid == 0) {
+        ticket = 0;
+        shdr[0] = ldc(P.grp_info, kGrpInfo * gg + 1);
+        shdr[1] = ldc(P.sig_info, 4 * sg + 1);
+        shdr[2] = ldc(P.sig_info, 4 * sg + 2);
+        shdr[3] = ldc(P.sig_info, 4 * sg + 3);
+        shdr[4] = gflags;
+        const int wi0 = ldc(P.sig_witem_ptr, sg);
+        shdr[5] = wi0;
+        shdr[6] = ldc(P.sig_witem_ptr, sg + 1) - wi0;
+        shdr[7] = (FUSE && P.bc_off) ? P.bc_off[gg] : -1;
+        shdr[8] = P.grp_rank_off ? P.grp_rank_off[gg] : -1;
+    }
+    __syncthreads();
+
+    auto compute_group_wide = [&]() {
+        const int nn = wave_uniform(shdr[0]);
+        const int deg = wave_uniform(shdr[1]);
+        const int blk = wave_uniform(shdr[3]);
+        const int flags = wave_uniform(shdr[4]);
+        const int wi0 = wave_uniform(shdr[5]);
+        const int nwi = wave_uniform(shdr[6]);
+        const int bcoff = FUSE ? wave_uniform(shdr[7]) : -1;
+        const int rkoff = wave_uniform(shdr[8]);
+        const bool diag = flags & kGrpDiag;
+        const int lgN = 5 - ((flags >> kGrpWideShift) & 3);  // N = 8 or 16
+        const int N = 1 << lgN;
+        const int rl = DIM * deg;
+        const int node = lane & (N - 1);
+        double *st = stage + node * blk;
+        const T *G = sG;
+        const uint16_t *n2l = sn2l + node;
+        for (;;) {
+            int r = 0;
+            if (lane == 0) r = atomicAdd(&ticket, 1);
+            r = wave_uniform(r);
+            if (r >= nwi) break;
+            const int32_t *rec = P.sig_witems + (int64_t)(wi0 + r) * kWideInts;
+            const int np = ldc(rec, 0), Q = ldc(rec, 1), nt = ldc(rec, 2);
+            const int lgQ = 31 - __clz(Q);
+            const int grp = lane >> lgN;
+            const int pp = grp >> lgQ, q = grp & (Q - 1);
+            // this lane's position, its contribution offset and count
+            int p = -1, off = 0, cnt = 0;
+#pragma unroll
+            for (int k = 0; k < 8; k++)
+                if (pp == k) {
+                    p = ldc(rec, 8 + k);
+                    off = ldc(rec, 16 + k);
+                    cnt = ldc(rec, 24 + k);
+                }
+            const bool mine = pp < np && node < nn;
+            // Dirichlet bits of the lane's block and its CSR position (a
+            // canonical-order plan's rank table), fetched now and used at the end
+            const int bcb = (FUSE && bcoff >= 0 && mine && q == 0) ? P.bc_bits[bcoff + node * deg + p] : 0;
+            const int pcsr = (rkoff >= 0 && mine && q == 0) ? (int)P.grp_rank[rkoff + p * NG + node] : p;
+            double acc[DIM][DIM];
+#pragma unroll
+            for (int a = 0; a < DIM; a++)
+#pragma unroll
+                for (int c = 0; c < DIM; c++) acc[a][c] = 0.0;
+            // contributions of this lane: all loads first (nt <= 8)
+            int pk[8];
+#pragma unroll
+            for (int t = 0; t < 8; t++) {
+                const int ti = q + t * Q;
+                pk[t] = (t < nt && mine && ti < cnt) ? P.sig_contrib[off + ti] : -1;
+            }
+#pragma unroll
+            for (int t = 0; t < 8; t++) {
+                if (t >= nt) break;
+                if (pk[t] >= 0) {
+                    const int k = pk[t] >> 16, i = (pk[t] >> 8) & 255, j = pk[t] & 255;
+                    const int slot = n2l[k * NG];
+                    const T *Mij = sM + (i * NEN + j) * D2;
+                    T Mv[D2];
+#pragma unroll
+                    for (int x = 0; x < D2; x++) Mv[x] = Mij[x];
+                    if (diag) {
+                        T dd[DIM][DIM];
+#pragma unroll
+                        for (int a = 0; a < DIM; a++)
+#pragma unroll
+                            for (int c = a; c < DIM; c++) {
+                                dd[a][c] = diag_product<PREC>(G[a * kGroupElems + slot], G[c * kGroupElems + slot]);
+                                dd[c][a] = dd[a][c];
+                            }
+                        accumulate_diag<DIM, PREC>(dd, Mv, acc);
+                    } else {
+                        T Gv[DIM][DIM];
+#pragma unroll
+                        for (int m = 0; m < DIM; m++)
+#pragma unroll
+                            for (int a = 0; a < DIM; a++) Gv[m][a] = G[(m * DIM + a) * kGroupElems + slot];
+                        accumulate<DIM, PREC>(Gv, Mv, acc);
+                    }
+                }
+            }
+            for (int sh = N; sh < N * Q; sh <<= 1)
+#pragma unroll
+                for (int a = 0; a < DIM; a++)
+#pragma unroll
+                    for (int c = 0; c < DIM; c++) acc[a][c] += __shfl_xor(acc[a][c], sh);
+            if (mine && q == 0) {
+                double tr = 0.0;
+#pragma unroll
+                for (int a = 0; a < DIM; a++) tr += acc[a][a];
+#pragma unroll
+                for (int a = 0; a < DIM; a++)
+#pragma unroll
+                    for (int c = 0; c < DIM; c++) {
+                        double o = P.lam * acc[a][c] + P.mu * acc[c][a];
+                        if (a == c) o += P.mu * tr;
+                        if (FUSE && bcoff >= 0) o = dirichlet_entry(bcb, a, c, o);
+                        st[a * rl + DIM * pcsr + c] = o;
+                    }
+            }
+        }
+    };
+
+    auto compute_group = [&]() {
+        const int flags = wave_uniform(shdr[4]);
+        if (flags >> kGrpWideShift) {
+            compute_group_wide();
+            return;
+        }
+        const int nn = wave_uniform(shdr[0]);
+        const int deg = wave_uniform(shdr[1]);
+        const int posoff = wave_uniform(shdr[2]);
+        const int blk = wave_uniform(shdr[3]);
+        const int bcoff = FUSE ? wave_uniform(shdr[7]) : -1;
+        const int rkoff = wave_uniform(shdr[8]);
+        const bool diag = flags & kGrpDiag;
+        const int rl = DIM * deg;
+        const bool hi = lane >= NG;
+        const int node = lane & (NG - 1);
+        double *st = stage + node * blk;
+        const T *G = sG;
+        const uint16_t *n2l = sn2l + node;
+        for (;;) {
+            int r = 0;
+            if (lane == 0) r = atomicAdd(&ticket, 1);
+            r = wave_uniform(r);
+            // the signature's slice holds deg + 1 items, the last ones -1;
+            // late waves draw tickets past the end
+            if (r > deg) break;
+            const int pa = ldc(P.sig_pairs, 2 * posoff + 2 * r);
+            if (pa < 0) break;
+            const int pb = ldc(P.sig_pairs, 2 * posoff + 2 * r + 1);
+            const bool split = pb == pa;
+            const int c0 = ldc(P.sig_pos_ptr, posoff + pa);
+            const int na = ldc(P.sig_pos_ptr, posoff + pa + 1) - c0;
+            // contribution ranges of the two halves: [lo0, lo0 + nlo), [hi0, hi0 + nhi)
+            int lo0 = c0, nlo = na, hi0 = c0, nhi = 0;
+            if (split) {
+                nlo = (na + 1) / 2;
+                hi0 = c0 + nlo;
+                nhi = na - nlo;
+            } else if (pb >= 0) {
+                hi0 = ldc(P.sig_pos_ptr, posoff + pb);
+                nhi = ldc(P.sig_pos_ptr, posoff + pb + 1) - hi0;
+            }
+            const int mycnt = hi ? nhi : nlo;
+            // Dirichlet bits of the lane's block, fetched now and used at the end
+            const int pme = hi ? pb : pa;
+            const int bcb = (FUSE && bcoff >= 0 && node < nn && pme >= 0) ? P.bc_bits[bcoff + node * deg + pme] : 0;
+            // the block's CSR position (a canonical-order plan's rank table)
+            const int pcsr = (rkoff >= 0 && node < nn && pme >= 0) ? (int)P.grp_rank[rkoff + pme * NG + node] : pme;
+            double acc[DIM][DIM];
+#pragma unroll
+            for (int a = 0; a < DIM; a++)
+#pragma unroll
+                for (int c = 0; c < DIM; c++) acc[a][c] = 0.0;
+            // nlo >= nhi: the low half has the longer list
+            for (int t = 0; t < nlo; t += 2) {
+                int pk[2];
+                bool ok[2];
+#pragma unroll
+                for (int u = 0; u < 2; u++) {
+                    const int tl = t + u < nlo ? t + u : nlo - 1;
+                    const int kl = ldc(P.sig_contrib, lo0 + tl);
+                    const int kh = nhi > 0 ? ldc(P.sig_contrib, hi0 + (t + u < nhi ? t + u : nhi - 1)) : kl;
+                    pk[u] = hi ? kh : kl;
+                    ok[u] = t + u < mycnt;
+                }
+#pragma unroll
+                for (int u = 0; u < 2; u++) {
+                    const int k = pk[u] >> 16, i = (pk[u] >> 8) & 255, j = pk[u] & 255;
+                    const int slot = n2l[k * NG];
+                    const T *Mij = sM + (i * NEN + j) * D2;
+                    T Mv[D2];
+#pragma unroll
+                    for (int x = 0; x < D2; x++) Mv[x] = Mij[x];
+                    if (diag) {
+                        T dd[DIM][DIM];
+#pragma unroll
+                        for (int a = 0; a < DIM; a++)
+#pragma unroll
+                            for (int c = a; c < DIM; c++) {
+                                dd[a][c] = diag_product<PREC>(G[a * kGroupElems + slot], G[c * kGroupElems + slot]);
+                                dd[c][a] = dd[a][c];
+                            }
+                        if (ok[u]) accumulate_diag<DIM, PREC>(dd, Mv, acc);
+                    } else {
+                        T Gv[DIM][DIM];
+#pragma unroll
+                        for (int m = 0; m < DIM; m++)
+#pragma unroll
+                            for (int a = 0; a < DIM; a++) Gv[m][a] = G[(m * DIM + a) * kGroupElems + slot];
+                        if (ok[u]) accumulate<DIM, PREC>(Gv, Mv, acc);
+                    }
+                }
+            }
+            if (split) {
+                // low half's sum + high half's sum (the same in both halves:
+                // addition is commutative)
+#pragma unroll
+                for (int a = 0; a < DIM; a++)
+#pragma unroll
+                    for (int c = 0; c < DIM; c++) acc[a][c] += __shfl_xor(acc[a][c], NG);
+            }
+            double tr = 0.0;
+#pragma unroll
+            for (int a = 0; a < DIM; a++) tr += acc[a][a];
+            const int p = hi ? pb : pa;
+            if (node < nn && p >= 0 && !(split && hi)) {
+#pragma unroll
+                for (int a = 0; a < DIM; a++)
+#pragma unroll
+                    for (int c = 0; c < DIM; c++) {
+                        double o = P.lam * acc[a][c] + P.mu * acc[c][a];
+                        if (a == c) o += P.mu * tr;
+                        if (FUSE && bcoff >= 0) o = dirichlet_entry(bcb, a, c, o);
+                        st[a * rl + DIM * pcsr + c] = o;
+                    }
+            }
+        }
+    };
+
+    auto store_group = [&]() {
+        const int nn = wave_uniform(shdr[0]);
+        const int deg = wave_uniform(shdr[1]);
+        const int blk = wave_uniform(shdr[3]);
+        const int bsz = DIM * DIM * deg;  // the node's DIM rows, contiguous in CSR
+        const int32_t *rows = srows;
+        const double *sb = stage;
+        if (DIM == 2 && bsz <= 64) {
+            // short row blocks (2D elements): lane = (node j of npi, value o),
+            // so that one batch of four stores covers 4 npi of the wave's
+            // nodes w', w' + kStoreWaves, ... instead of one node per store
+            const int npi = 64 / bsz;  // nodes per store instruction
+            const int j = lane / bsz, o = lane - j * bsz;
+            const int sw = w;
+            for (int b0 = 0; b0 * kStoreWaves + sw < nn; b0 += 4 * npi) {
+                double v[4];
+                int dst[4];
+#pragma unroll
+                for (int c = 0; c < 4; c++) {
+                    const int n = sw + kStoreWaves * (b0 + c * npi + j);
+                    const bool ok = j < npi && n < nn;
+                    v[c] = ok ? sb[n * blk + o] : 0.0;
+                    dst[c] = ok ? rows[2 * n] + o : -1;
+                }
+#pragma unroll
+                for (int c = 0; c < 4; c++)
+                    if (dst[c] >= 0) __builtin_nontemporal_store(v[c], P.K + dst[c]);
+            }
+            return;
+        }
+        // a wave's two nodes of a batch lie half a group apart
+        const int half = (nn + 1) / 2;
+        for (int n0 = w; n0 < half; n0 += kStoreWaves) {
+            const int n1 = n0 + half;
+            const bool two = n1 < nn;
+            const int base0 = rows[2 * n0];
+            const int base1 = two ? rows[2 * n1] : base0;
+            const double *s0 = sb + n0 * blk;
+            const double *s1 = sb + (two ? n1 : n0) * blk;
+            for (int o0 = lane; o0 < bsz; o0 += 4 * 64) {
+                double v0[4], v1[4];
+#pragma unroll
+                for (int c = 0; c < 4; c++) {
+                    const int o = o0 + 64 * c;
+                    v0[c] = o < bsz ? s0[o] : 0.0;
+                    v1[c] = o < bsz ? s1[o] : 0.0;
+                }
+#pragma unroll
+                for (int c = 0; c < 4; c++) {
+                    const int o = o0 + 64 * c;
+                    if (o < bsz) {
+                        __builtin_nontemporal_store(v0[c], P.K + base0 + o);
+                        if (two) __builtin_nontemporal_store(v1[c], P.K + base1 + o);
+                    }
+                }
+            }
+        }
+    };
+
+    compute_group();
+    __syncthreads();
+    store_group();
+}
+
 // Dirichlet rows and columns (zero prescribed values): for a fixed dof r =
 // DIM I + a, K[r, :] = 0, K[:, r] = 0, K[r, r] = 1.
 //
@@ -1177,15 +1544,73 @@ static hipError_t launch_assemble_t(const AsmParams &P, int64_t ngroups, hipStre
     return hipGetLastError();
 }
 
+static std::atomic<int> g_asm_variant{-1};
+void set_assembly_variant(int v) { g_asm_variant.store(v); }
+
+template <int DIM, int NEN, int PREC, bool FUSE>
+static hipError_t launch_assemble_os_t(const AsmParams &P0, int64_t ngroups, hipStream_t st) {
+    if (ngroups <= 0) return hipSuccess;
+    const size_t csz = PREC == kF64 ? 8 : 4;
+    const size_t lds = 8 * (size_t)P0.stage + csz * DIM * DIM * kGroupElems + csz * NEN * NEN * DIM * DIM +
+                       kGroupNodes * 2 * 4 + 2 * (size_t)P0.kmax * kGroupNodes;
+    if (lds + 64 > 160 * 1024) return hipErrorInvalidValue;
+    const void *fn = reinterpret_cast<const void *>(&k_assemble_os<DIM, NEN, PREC, FUSE>);
+    static std::mutex mu;
+    static std::map<int, size_t> lds_limit;
+    static std::map<std::pair<int, size_t>, int> occupancy;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    int per_cu = 0;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        size_t &lim = lds_limit[dev];
+        if (lds > lim) {
+            e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+            lim = lds;
+        }
+        auto it = occupancy.find({dev, lds});
+        if (it != occupancy.end()) {
+            per_cu = it->second;
+        } else {
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, OsShape<DIM>::threads, lds);
+            if (e != hipSuccess || per_cu < 1) per_cu = 1;
+            occupancy[{dev, lds}] = per_cu;
+        }
+    }
+    AsmParams P = P0;
+    const int ncu = P.n_cu > 0 ? P.n_cu : 256;
+    P.os_window = std::max(8, (per_cu * ncu) / 8 * 8);
+    hipLaunchKernelGGL((k_assemble_os<DIM, NEN, PREC, FUSE>), dim3((unsigned)ngroups), dim3(OsShape<DIM>::threads),
+                       lds, st, P);
+    return hipGetLastError();
+}
+
+// The one-shot kernel where a group's stage is small (2D elements: many
+// workgroups per CU overlap their loads, compute and stores) or where there
+// are no more groups than two per CU (no steps for a persistent workgroup to
+// pipeline); the persistent kernel otherwise.  Measured on MI355X: P1
+// triangles 600x200 20 vs 33 us, Q1 quads 512^2 37 vs 60 us, Q1 hexahedra
+// 16^3 11.1 vs 11.9 us; the 3D cantilever 115 vs 93 us, P2 box 730 vs 697 us.
+template <int DIM, int NEN, int PREC, bool FUSE>
+static hipError_t launch_assemble_v(const AsmParams &P, int64_t ngroups, hipStream_t st) {
+    const int v = g_asm_variant.load();
+    const int ncu = P.n_cu > 0 ? P.n_cu : 256;
+    const bool os = v == 1 || (v < 0 && (8 * P.stage <= 32768 || ngroups <= 2 * (int64_t)ncu));
+    if (os) return launch_assemble_os_t<DIM, NEN, PREC, FUSE>(P, ngroups, st);
+    return launch_assemble_t<DIM, NEN, PREC, FUSE>(P, ngroups, st);
+}
+
 hipError_t launch_assemble(int elem, int prec, const AsmParams &P, int64_t ngroups, hipStream_t st, bool fuse) {
 #define SOPTX_ASM(E, D, N)                                                                     \
     case E:                                                                                    \
         if (fuse) {                                                                            \
-            if (prec == kF64) return launch_assemble_t<D, N, kF64, true>(P, ngroups, st);      \
-            return launch_assemble_t<D, N, kF32, true>(P, ngroups, st);                        \
+            if (prec == kF64) return launch_assemble_v<D, N, kF64, true>(P, ngroups, st);      \
+            return launch_assemble_v<D, N, kF32, true>(P, ngroups, st);                        \
         }                                                                                      \
-        if (prec == kF64) return launch_assemble_t<D, N, kF64, false>(P, ngroups, st);         \
-        return launch_assemble_t<D, N, kF32, false>(P, ngroups, st);
+        if (prec == kF64) return launch_assemble_v<D, N, kF64, false>(P, ngroups, st);         \
+        return launch_assemble_v<D, N, kF32, false>(P, ngroups, st);
     switch (elem) {
         SOPTX_ASM(SOPTX_QUAD4, 2, 4)
         SOPTX_ASM(SOPTX_TRI3, 2, 3)

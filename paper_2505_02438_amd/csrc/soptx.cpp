@@ -749,6 +749,12 @@ void soptx_destroy_pattern(soptx_pattern h) {
 
 // ----------------------------------------------------------- host-only debug
 
+int soptx_debug_set_assembly_variant(int32_t v) {
+    if (v < -1 || v > 1) return SOPTX_E_INVALID_ARG;
+    set_assembly_variant(v);
+    return SOPTX_OK;
+}
+
 int soptx_debug_host_plan(const soptx_mesh *mesh, soptx_host_plan *out) {
     return soptx_debug_host_plan_ex(mesh, 0, out);
 }

@@ -153,3 +153,32 @@ def test_step_argument_errors():
         api.Dirichlet(pat, np.zeros(3, np.uint8))
     out = ctypes.c_void_p(1)
     assert L.soptx_build_dirichlet(None, None, ctypes.byref(out), None) == -1 and out.value is None
+
+
+@pytest.mark.parametrize("elem,dims,skew", [(I.QUAD4, (23, 9), None), (I.TRI3, (31, 12), None),
+                                            (I.HEX8, (9, 6, 7), "global"), (I.TET10, (4, 3, 3), None),
+                                            (I.HEX8, (9, 6, 7), "renumbered"), (I.TRI3, (31, 12), "renumbered")])
+def test_assembly_kernels_agree_bitwise(elem, dims, skew):
+    """The persistent assembly kernel and the one-workgroup-per-group kernel
+    (chosen by the plan's shape; forced here through the debug hook) give
+    bitwise the same K, with and without the bound Dirichlet table, in both
+    precision forms."""
+    pr, m, pat, rp, ci = _setup(elem, dims, skew)
+    bc = api.Dirichlet(pat, pr.mask)
+    L = _lib.lib()
+    out = {}
+    try:
+        for v in (0, 1, -1):
+            assert L.soptx_debug_set_assembly_variant(v) == 0
+            for prec in (api.FP64, api.FP32):
+                rho = dev(pr.rho) if prec == api.FP64 else dev(pr.rho).float()
+                K1 = host(pat.assemble(MAT, rho, prec=prec))
+                K2, _, _ = pat.step(MAT, rho, bc=bc, prec=prec)
+                out[(v, prec)] = (K1, host(K2))
+        assert L.soptx_debug_set_assembly_variant(2) == -1
+    finally:
+        L.soptx_debug_set_assembly_variant(-1)
+    for prec in (api.FP64, api.FP32):
+        for v in (1, -1):
+            assert np.array_equal(out[(v, prec)][0], out[(0, prec)][0]), (v, prec)
+            assert np.array_equal(out[(v, prec)][1], out[(0, prec)][1]), (v, prec)
