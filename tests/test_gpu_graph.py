@@ -48,3 +48,57 @@ def test_graph_replays_equal_eager(elem):
         assert np.array_equal(host(K), ref[0]) and np.array_equal(host(dc), ref[1]), rep
         assert np.array_equal(host(c), ref[2]), rep
         _ = (rho * 2).sum().item()  # eager work between replays
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("elem,renumber", [(I.QUAD4, False), (I.TRI3, False), (I.HEX8, False), (I.TET10, False),
+                                           (I.HEX8, True)])
+def test_graph_replays_of_the_fused_step(elem, renumber, variant):
+    """soptx_step (the bound Dirichlet table; for a renumbered mesh also the
+    density gather into rank order) captured in a HIP graph: every replay,
+    with eager work between replays, gives the eager results bit for bit,
+    with either assembly kernel (forced through the debug hook)."""
+    from paper_2505_02438_amd import _lib
+    L = _lib.lib()
+    assert L.soptx_debug_set_assembly_variant(variant) == 0
+    try:
+        _fused_step_graph(elem, renumber)
+    finally:
+        L.soptx_debug_set_assembly_variant(-1)
+
+
+def _fused_step_graph(elem, renumber):
+    pr = I.small_problem(elem, seed=43, dims=(30, 20) if elem == I.QUAD4 else None)
+    if renumber:
+        pr = I.renumber(pr, 44)
+    m = pr.mesh
+    pat = api.Pattern.from_mesh(m)
+    if renumber:
+        assert pat.stats()["n_groups_ranked"] > 0
+    bc = api.Dirichlet(pat, pr.mask)
+    st = torch.cuda.Stream()
+    rho, u = dev(pr.rho), dev(pr.u)
+    K = torch.empty(pat.nnz, dtype=torch.float64, device="cuda")
+    dc = torch.empty(m.n_cells, dtype=torch.float64, device="cuda")
+    c = torch.zeros(2, dtype=torch.float64, device="cuda")
+
+    def step():
+        pat.step(MAT, rho, u, bc=bc, K=K, dc=dc, c=c, stream=st)
+
+    with torch.cuda.stream(st):
+        step()  # warm-up on the capture stream: workspaces and launch attributes set
+    torch.cuda.synchronize()
+    ref = (host(K).copy(), host(dc).copy(), host(c).copy())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=st):
+        step()
+    for rep in range(4):
+        K.fill_(np.nan)
+        dc.fill_(np.nan)
+        c.fill_(np.nan)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(K), ref[0]) and np.array_equal(host(dc), ref[1]), rep
+        assert np.array_equal(host(c), ref[2]), rep
+        _ = (rho * 2).sum().item()  # eager work between replays
