@@ -132,6 +132,343 @@ static size_t assemble_lds_bytes(int dim, int nen, int prec, int64_t stage, int 
            3 * kGroupNodes * 2 * 4 + 2 * 2 * (size_t)kmax * kGroupNodes;
 }
 
+// Dirichlet bits of one stored block (node n, neighbour J): bit a (a < DIM):
+// row dof DIM n + a is fixed; bit 3 + c: column dof DIM J + c is fixed; bit 6:
+// J == n.  An entry in a fixed row or column is 0, the diagonal entry of a
+// fixed dof 1 (zero prescribed values).
+__device__ __forceinline__ double dirichlet_entry(int bits, int a, int c, double v) {
+    if (((bits >> a) | (bits >> (3 + c))) & 1) return (a == c && (bits & 64)) ? 1.0 : 0.0;
+    return v;
+}
+
+// ---- the roles' work on one group, shared by the persistent kernel
+// (k_assemble) and the one-workgroup-per-group kernel (k_assemble_os).  The
+// group's data in LDS: hdr (nn, deg, posoff, blk, flags, first wide work
+// item, number of wide work items, Dirichlet-bits offset, rank-table offset),
+// stage (its row blocks, blk doubles per node), sG (G' per element slot,
+// [D2][kGroupElems], or the diagonal G'_aa for an axis-aligned group), sM
+// (the reference tensor), sn2l (slot of element k of each node, [K][32]);
+// ticket counts the group's work items.  DIAG: the group is axis-aligned
+// (decided once per group, so the contraction loop has no branch on it).
+
+// ---- compute role, wide work items (groups of at most N = 8 or 16
+// nodes): lane = (pp Q + q) N + node takes position p[pp] of the item and
+// its contributions q, q + Q, ...; the Q phases of a position are then
+// added by a butterfly over the phase bits of the lane index (a fixed
+// order), and phase 0 writes the block
+template <int DIM, int NEN, int PREC, bool FUSE, bool DIAG>
+__device__ __forceinline__ void assemble_wide(const AsmParams &P, const int *hdr, int *ticket, double *stage,
+                                              const typename CT<PREC>::T *sG, const typename CT<PREC>::T *sM,
+                                              const uint16_t *sn2l, int lane) {
+    using T = typename CT<PREC>::T;
+    constexpr int D2 = DIM * DIM;
+    constexpr int NG = kGroupNodes;
+    const int nn = wave_uniform(hdr[0]);
+    const int deg = wave_uniform(hdr[1]);
+    const int blk = wave_uniform(hdr[3]);
+    const int flags = wave_uniform(hdr[4]);
+    const int wi0 = wave_uniform(hdr[5]);
+    const int nwi = wave_uniform(hdr[6]);
+    const int bcoff = FUSE ? wave_uniform(hdr[7]) : -1;
+    const int rkoff = wave_uniform(hdr[8]);
+    const int lgN = 5 - ((flags >> kGrpWideShift) & 3);  // N = 8 or 16
+    const int N = 1 << lgN;
+    const int rl = DIM * deg;
+    const int node = lane & (N - 1);
+    double *st = stage + node * blk;
+    const T *G = sG;
+    const uint16_t *n2l = sn2l + node;
+    for (;;) {
+        int r = 0;
+        if (lane == 0) r = atomicAdd(ticket, 1);
+        r = wave_uniform(r);
+        if (r >= nwi) break;
+        const int32_t *rec = P.sig_witems + (int64_t)(wi0 + r) * kWideInts;
+        const int np = ldc(rec, 0), Q = ldc(rec, 1), nt = ldc(rec, 2);
+        const int lgQ = 31 - __clz(Q);
+        const int grp = lane >> lgN;
+        const int pp = grp >> lgQ, q = grp & (Q - 1);
+        // this lane's position, its contribution offset and count
+        int p = -1, off = 0, cnt = 0;
+#pragma unroll
+        for (int k = 0; k < 8; k++)
+            if (pp == k) {
+                p = ldc(rec, 8 + k);
+                off = ldc(rec, 16 + k);
+                cnt = ldc(rec, 24 + k);
+            }
+        const bool mine = pp < np && node < nn;
+        // Dirichlet bits of the lane's block and its CSR position (a
+        // canonical-order plan's rank table), fetched now and used at the end
+        const int bcb = (FUSE && bcoff >= 0 && mine && q == 0) ? P.bc_bits[bcoff + node * deg + p] : 0;
+        const int pcsr = (rkoff >= 0 && mine && q == 0) ? (int)P.grp_rank[rkoff + p * NG + node] : p;
+        double acc[DIM][DIM];
+#pragma unroll
+        for (int a = 0; a < DIM; a++)
+#pragma unroll
+            for (int c = 0; c < DIM; c++) acc[a][c] = 0.0;
+        // contributions of this lane: all loads first (nt <= 8)
+        int pk[8];
+#pragma unroll
+        for (int t = 0; t < 8; t++) {
+            const int ti = q + t * Q;
+            pk[t] = (t < nt && mine && ti < cnt) ? P.sig_contrib[off + ti] : -1;
+        }
+#pragma unroll
+        for (int t = 0; t < 8; t++) {
+            if (t >= nt) break;
+            if (pk[t] >= 0) {
+                const int k = pk[t] >> 16, i = (pk[t] >> 8) & 255, j = pk[t] & 255;
+                const int slot = n2l[k * NG];
+                const T *Mij = sM + (i * NEN + j) * D2;
+                T Mv[D2];
+#pragma unroll
+                for (int x = 0; x < D2; x++) Mv[x] = Mij[x];
+                if constexpr (DIAG) {
+                    T dd[DIM][DIM];
+#pragma unroll
+                    for (int a = 0; a < DIM; a++)
+#pragma unroll
+                        for (int c = a; c < DIM; c++) {
+                            dd[a][c] = diag_product<PREC>(G[a * kGroupElems + slot], G[c * kGroupElems + slot]);
+                            dd[c][a] = dd[a][c];
+                        }
+                    accumulate_diag<DIM, PREC>(dd, Mv, acc);
+                } else {
+                    T Gv[DIM][DIM];
+#pragma unroll
+                    for (int m = 0; m < DIM; m++)
+#pragma unroll
+                        for (int a = 0; a < DIM; a++) Gv[m][a] = G[(m * DIM + a) * kGroupElems + slot];
+                    accumulate<DIM, PREC>(Gv, Mv, acc);
+                }
+            }
+        }
+        for (int sh = N; sh < N * Q; sh <<= 1)
+#pragma unroll
+            for (int a = 0; a < DIM; a++)
+#pragma unroll
+                for (int c = 0; c < DIM; c++) acc[a][c] += __shfl_xor(acc[a][c], sh);
+        if (mine && q == 0) {
+            double tr = 0.0;
+#pragma unroll
+            for (int a = 0; a < DIM; a++) tr += acc[a][a];
+#pragma unroll
+            for (int a = 0; a < DIM; a++)
+#pragma unroll
+                for (int c = 0; c < DIM; c++) {
+                    double o = P.lam * acc[a][c] + P.mu * acc[c][a];
+                    if (a == c) o += P.mu * tr;
+                    if (FUSE && bcoff >= 0) o = dirichlet_entry(bcb, a, c, o);
+                    st[a * rl + DIM * pcsr + c] = o;
+                }
+        }
+    }
+}
+
+// compute role, work items of position pairs (groups of up to 32 nodes)
+template <int DIM, int NEN, int PREC, bool FUSE, bool DIAG>
+__device__ __forceinline__ void assemble_pairs(const AsmParams &P, const int *hdr, int *ticket, double *stage,
+                                               const typename CT<PREC>::T *sG, const typename CT<PREC>::T *sM,
+                                               const uint16_t *sn2l, int lane) {
+    using T = typename CT<PREC>::T;
+    constexpr int D2 = DIM * DIM;
+    constexpr int NG = kGroupNodes;
+    const int nn = wave_uniform(hdr[0]);
+    const int deg = wave_uniform(hdr[1]);
+    const int posoff = wave_uniform(hdr[2]);
+    const int blk = wave_uniform(hdr[3]);
+    const int bcoff = FUSE ? wave_uniform(hdr[7]) : -1;
+    const int rkoff = wave_uniform(hdr[8]);
+    const int rl = DIM * deg;
+    const bool hi = lane >= NG;
+    const int node = lane & (NG - 1);
+    double *st = stage + node * blk;
+    const T *G = sG;
+    const uint16_t *n2l = sn2l + node;
+    for (;;) {
+        int r = 0;
+        if (lane == 0) r = atomicAdd(ticket, 1);
+        r = wave_uniform(r);
+        // the signature's slice holds deg + 1 items, the last ones -1;
+        // late waves draw tickets past the end
+        if (r > deg) break;
+        const int pa = ldc(P.sig_pairs, 2 * posoff + 2 * r);
+        if (pa < 0) break;
+        const int pb = ldc(P.sig_pairs, 2 * posoff + 2 * r + 1);
+        const bool split = pb == pa;
+        const int c0 = ldc(P.sig_pos_ptr, posoff + pa);
+        const int na = ldc(P.sig_pos_ptr, posoff + pa + 1) - c0;
+        // contribution ranges of the two halves: [lo0, lo0 + nlo), [hi0, hi0 + nhi)
+        int lo0 = c0, nlo = na, hi0 = c0, nhi = 0;
+        if (split) {
+            nlo = (na + 1) / 2;
+            hi0 = c0 + nlo;
+            nhi = na - nlo;
+        } else if (pb >= 0) {
+            hi0 = ldc(P.sig_pos_ptr, posoff + pb);
+            nhi = ldc(P.sig_pos_ptr, posoff + pb + 1) - hi0;
+        }
+        const int mycnt = hi ? nhi : nlo;
+        // Dirichlet bits of the lane's block, fetched now and used at the end
+        const int pme = hi ? pb : pa;
+        const int bcb = (FUSE && bcoff >= 0 && node < nn && pme >= 0) ? P.bc_bits[bcoff + node * deg + pme] : 0;
+        // the block's CSR position (a canonical-order plan's rank table)
+        const int pcsr = (rkoff >= 0 && node < nn && pme >= 0) ? (int)P.grp_rank[rkoff + pme * NG + node] : pme;
+        double acc[DIM][DIM];
+#pragma unroll
+        for (int a = 0; a < DIM; a++)
+#pragma unroll
+            for (int c = 0; c < DIM; c++) acc[a][c] = 0.0;
+        // nlo >= nhi: the low half has the longer list
+        for (int t = 0; t < nlo; t += 2) {
+            int pk[2];
+            bool ok[2];
+#pragma unroll
+            for (int u = 0; u < 2; u++) {
+                const int tl = t + u < nlo ? t + u : nlo - 1;
+                const int kl = ldc(P.sig_contrib, lo0 + tl);
+                const int kh = nhi > 0 ? ldc(P.sig_contrib, hi0 + (t + u < nhi ? t + u : nhi - 1)) : kl;
+                pk[u] = hi ? kh : kl;
+                ok[u] = t + u < mycnt;
+            }
+#pragma unroll
+            for (int u = 0; u < 2; u++) {
+                const int k = pk[u] >> 16, i = (pk[u] >> 8) & 255, j = pk[u] & 255;
+                const int slot = n2l[k * NG];
+                const T *Mij = sM + (i * NEN + j) * D2;
+                T Mv[D2];
+#pragma unroll
+                for (int x = 0; x < D2; x++) Mv[x] = Mij[x];
+                if constexpr (DIAG) {
+                    T dd[DIM][DIM];
+#pragma unroll
+                    for (int a = 0; a < DIM; a++)
+#pragma unroll
+                        for (int c = a; c < DIM; c++) {
+                            dd[a][c] = diag_product<PREC>(G[a * kGroupElems + slot], G[c * kGroupElems + slot]);
+                            dd[c][a] = dd[a][c];
+                        }
+                    if (ok[u]) accumulate_diag<DIM, PREC>(dd, Mv, acc);
+                } else {
+                    T Gv[DIM][DIM];
+#pragma unroll
+                    for (int m = 0; m < DIM; m++)
+#pragma unroll
+                        for (int a = 0; a < DIM; a++) Gv[m][a] = G[(m * DIM + a) * kGroupElems + slot];
+                    if (ok[u]) accumulate<DIM, PREC>(Gv, Mv, acc);
+                }
+            }
+        }
+        if (split) {
+            // low half's sum + high half's sum (the same in both halves:
+            // addition is commutative)
+#pragma unroll
+            for (int a = 0; a < DIM; a++)
+#pragma unroll
+                for (int c = 0; c < DIM; c++) acc[a][c] += __shfl_xor(acc[a][c], NG);
+        }
+        double tr = 0.0;
+#pragma unroll
+        for (int a = 0; a < DIM; a++) tr += acc[a][a];
+        const int p = hi ? pb : pa;
+        if (node < nn && p >= 0 && !(split && hi)) {
+#pragma unroll
+            for (int a = 0; a < DIM; a++)
+#pragma unroll
+                for (int c = 0; c < DIM; c++) {
+                    double o = P.lam * acc[a][c] + P.mu * acc[c][a];
+                    if (a == c) o += P.mu * tr;
+                    if (FUSE && bcoff >= 0) o = dirichlet_entry(bcb, a, c, o);
+                    st[a * rl + DIM * pcsr + c] = o;
+                }
+        }
+    }
+}
+
+// compute role of one group: wide or paired work items; only Q1 elements
+// (quadrilaterals, hexahedra) can form axis-aligned groups
+template <int DIM, int NEN, int PREC, bool FUSE>
+__device__ __forceinline__ void assemble_group(const AsmParams &P, const int *hdr, int *ticket, double *stage,
+                                               const typename CT<PREC>::T *sG, const typename CT<PREC>::T *sM,
+                                               const uint16_t *sn2l, int lane) {
+    constexpr bool kMayDiag = NEN == (1 << DIM);
+    const int flags = wave_uniform(hdr[4]);
+    const bool diag = kMayDiag && (flags & kGrpDiag);
+    if (flags >> kGrpWideShift) {
+        if (diag) assemble_wide<DIM, NEN, PREC, FUSE, kMayDiag>(P, hdr, ticket, stage, sG, sM, sn2l, lane);
+        else assemble_wide<DIM, NEN, PREC, FUSE, false>(P, hdr, ticket, stage, sG, sM, sn2l, lane);
+    } else {
+        if (diag) assemble_pairs<DIM, NEN, PREC, FUSE, kMayDiag>(P, hdr, ticket, stage, sG, sM, sn2l, lane);
+        else assemble_pairs<DIM, NEN, PREC, FUSE, false>(P, hdr, ticket, stage, sG, sM, sn2l, lane);
+    }
+}
+
+// ---- store role: one group's stage sb with its row offsets rows, as store
+// wave sw of KSTORE.  Each store wave takes every KSTORE-th node of the
+// group's first half together with its partner half a group later, four
+// values per lane and node at a time, so that eight LDS reads are in flight
+// per batch.  K is
+// written once and never read back here: the stores are non-temporal, so
+// they stream out instead of taking L2 lines that the element loads use
+template <int DIM, int KSTORE>
+__device__ __forceinline__ void store_rows(const AsmParams &P, const int *hdr, const int32_t *rows, const double *sb,
+                                           int sw, int lane) {
+    const int nn = wave_uniform(hdr[0]);
+    const int deg = wave_uniform(hdr[1]);
+    const int blk = wave_uniform(hdr[3]);
+    const int bsz = DIM * DIM * deg;  // the node's DIM rows, contiguous in CSR
+    if (DIM == 2 && bsz <= 64) {
+        // short row blocks (2D elements): lane = (node j of npi, value o),
+        // so that one batch of four stores covers 4 npi of the wave's
+        // nodes w', w' + KSTORE, ... instead of one node per store
+        const int npi = 64 / bsz;  // nodes per store instruction
+        const int j = lane / bsz, o = lane - j * bsz;
+        for (int b0 = 0; b0 * KSTORE + sw < nn; b0 += 4 * npi) {
+            double v[4];
+            int dst[4];
+#pragma unroll
+            for (int c = 0; c < 4; c++) {
+                const int n = sw + KSTORE * (b0 + c * npi + j);
+                const bool ok = j < npi && n < nn;
+                v[c] = ok ? sb[n * blk + o] : 0.0;
+                dst[c] = ok ? rows[2 * n] + o : -1;
+            }
+#pragma unroll
+            for (int c = 0; c < 4; c++)
+                if (dst[c] >= 0) __builtin_nontemporal_store(v[c], P.K + dst[c]);
+        }
+        return;
+    }
+    // a wave's two nodes of a batch lie half a group apart
+    const int half = (nn + 1) / 2;
+    for (int n0 = sw; n0 < half; n0 += KSTORE) {
+        const int n1 = n0 + half;
+        const bool two = n1 < nn;
+        const int base0 = rows[2 * n0];
+        const int base1 = two ? rows[2 * n1] : base0;
+        const double *s0 = sb + n0 * blk;
+        const double *s1 = sb + (two ? n1 : n0) * blk;
+        for (int o0 = lane; o0 < bsz; o0 += 4 * 64) {
+            double v0[4], v1[4];
+#pragma unroll
+            for (int c = 0; c < 4; c++) {
+                const int o = o0 + 64 * c;
+                v0[c] = o < bsz ? s0[o] : 0.0;
+                v1[c] = o < bsz ? s1[o] : 0.0;
+            }
+#pragma unroll
+            for (int c = 0; c < 4; c++) {
+                const int o = o0 + 64 * c;
+                if (o < bsz) {
+                    __builtin_nontemporal_store(v0[c], P.K + base0 + o);
+                    if (two) __builtin_nontemporal_store(v1[c], P.K + base1 + o);
+                }
+            }
+        }
+    }
+}
+
 // Persistent, warp-specialised assembly.  One workgroup of 16 waves per CU
 // walks the node groups g0 = blockIdx.x, g0 + gridDim.x, ...  The groups are
 // in node order, so at any time the whole chip writes one contiguous stretch
@@ -166,18 +503,16 @@ static size_t assemble_lds_bytes(int dim, int nen, int prec, int64_t stage, int 
 // fixed dof: 1), so the stored K already carries the boundary conditions and
 // no pass of its own follows.
 
-// Dirichlet bits of one stored block (node n, neighbour J): bit a (a < DIM):
-// row dof DIM n + a is fixed; bit 3 + c: column dof DIM J + c is fixed; bit 6:
-// J == n.  An entry in a fixed row or column is 0, the diagonal entry of a
-// fixed dof 1 (zero prescribed values).
-__device__ __forceinline__ double dirichlet_entry(int bits, int a, int c, double v) {
-    if (((bits >> a) | (bits >> (3 + c))) & 1) return (a == c && (bits & 64)) ? 1.0 : 0.0;
-    return v;
-}
-
 constexpr int kAsmThreads = 1024;
-constexpr int kCompWaves = 8, kStoreWaves = 4, kLoadWaves = 4;
-static_assert(kCompWaves + kStoreWaves + kLoadWaves == kAsmThreads / 64, "wave roles");
+constexpr int kLoadWaves = 4;
+// compute and store waves of the persistent kernel (with the 4 load waves, 16
+// in all): P2 tetrahedra, whose steps are paced by the compute waves, take
+// two waves from the store role
+template <int NEN>
+struct Roles {
+    static constexpr int comp = NEN == 10 ? 10 : 8;
+    static constexpr int store = kAsmThreads / 64 - kLoadWaves - comp;
+};
 static_assert(2 * kGroupNodes == 64, "two positions per wavefront");
 
 template <int DIM, int NEN, int PREC, bool FUSE>
@@ -186,6 +521,7 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
     using R = typename std::conditional<PREC == kF64, double, float>::type;  // rho as stored
     constexpr int D2 = DIM * DIM;
     constexpr int NG = kGroupNodes;
+    constexpr int kCompWaves = Roles<NEN>::comp, kStoreWaves = Roles<NEN>::store;
     constexpr int kLoadBase = (kCompWaves + kStoreWaves) * 64;
     constexpr int kSetThreads = kLoadWaves / 2 * 64;  // threads of one load set
     constexpr int NPF = (kMaxAdjacent * NG + kSetThreads - 1) / kSetThreads;  // slot entries per load thread
@@ -313,299 +649,12 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
         }
     };
 
-    // ---- compute role, wide work items (groups of at most N = 8 or 16
-    // nodes): lane = (pp Q + q) N + node takes position p[pp] of the item and
-    // its contributions q, q + Q, ...; the Q phases of a position are then
-    // added by a butterfly over the phase bits of the lane index (a fixed
-    // order), and phase 0 writes the block
-    auto compute_group_wide = [&](int b, int rb) {
-        const int nn = wave_uniform(shdr[rb][0]);
-        const int deg = wave_uniform(shdr[rb][1]);
-        const int blk = wave_uniform(shdr[rb][3]);
-        const int flags = wave_uniform(shdr[rb][4]);
-        const int wi0 = wave_uniform(shdr[rb][5]);
-        const int nwi = wave_uniform(shdr[rb][6]);
-        const int bcoff = FUSE ? wave_uniform(shdr[rb][7]) : -1;
-        const int rkoff = wave_uniform(shdr[rb][8]);
-        const bool diag = flags & kGrpDiag;
-        const int lgN = 5 - ((flags >> kGrpWideShift) & 3);  // N = 8 or 16
-        const int N = 1 << lgN;
-        const int rl = DIM * deg;
-        const int node = lane & (N - 1);
-        double *st = stage + b * P.stage + node * blk;
-        const T *G = sG + b * D2 * kGroupElems;
-        const uint16_t *n2l = sn2l + b * n2l_stride + node;
-        for (;;) {
-            int r = 0;
-            if (lane == 0) r = atomicAdd(&ticket[b], 1);
-            r = wave_uniform(r);
-            if (r >= nwi) break;
-            const int32_t *rec = P.sig_witems + (int64_t)(wi0 + r) * kWideInts;
-            const int np = ldc(rec, 0), Q = ldc(rec, 1), nt = ldc(rec, 2);
-            const int lgQ = 31 - __clz(Q);
-            const int grp = lane >> lgN;
-            const int pp = grp >> lgQ, q = grp & (Q - 1);
-            // this lane's position, its contribution offset and count
-            int p = -1, off = 0, cnt = 0;
-#pragma unroll
-            for (int k = 0; k < 8; k++)
-                if (pp == k) {
-                    p = ldc(rec, 8 + k);
-                    off = ldc(rec, 16 + k);
-                    cnt = ldc(rec, 24 + k);
-                }
-            const bool mine = pp < np && node < nn;
-            // Dirichlet bits of the lane's block and its CSR position (a
-            // canonical-order plan's rank table), fetched now and used at the end
-            const int bcb = (FUSE && bcoff >= 0 && mine && q == 0) ? P.bc_bits[bcoff + node * deg + p] : 0;
-            const int pcsr = (rkoff >= 0 && mine && q == 0) ? (int)P.grp_rank[rkoff + p * NG + node] : p;
-            double acc[DIM][DIM];
-#pragma unroll
-            for (int a = 0; a < DIM; a++)
-#pragma unroll
-                for (int c = 0; c < DIM; c++) acc[a][c] = 0.0;
-            // contributions of this lane: all loads first (nt <= 8)
-            int pk[8];
-#pragma unroll
-            for (int t = 0; t < 8; t++) {
-                const int ti = q + t * Q;
-                pk[t] = (t < nt && mine && ti < cnt) ? P.sig_contrib[off + ti] : -1;
-            }
-#pragma unroll
-            for (int t = 0; t < 8; t++) {
-                if (t >= nt) break;
-                if (pk[t] >= 0) {
-                    const int k = pk[t] >> 16, i = (pk[t] >> 8) & 255, j = pk[t] & 255;
-                    const int slot = n2l[k * NG];
-                    const T *Mij = sM + (i * NEN + j) * D2;
-                    T Mv[D2];
-#pragma unroll
-                    for (int x = 0; x < D2; x++) Mv[x] = Mij[x];
-                    if (diag) {
-                        T dd[DIM][DIM];
-#pragma unroll
-                        for (int a = 0; a < DIM; a++)
-#pragma unroll
-                            for (int c = a; c < DIM; c++) {
-                                dd[a][c] = diag_product<PREC>(G[a * kGroupElems + slot], G[c * kGroupElems + slot]);
-                                dd[c][a] = dd[a][c];
-                            }
-                        accumulate_diag<DIM, PREC>(dd, Mv, acc);
-                    } else {
-                        T Gv[DIM][DIM];
-#pragma unroll
-                        for (int m = 0; m < DIM; m++)
-#pragma unroll
-                            for (int a = 0; a < DIM; a++) Gv[m][a] = G[(m * DIM + a) * kGroupElems + slot];
-                        accumulate<DIM, PREC>(Gv, Mv, acc);
-                    }
-                }
-            }
-            for (int sh = N; sh < N * Q; sh <<= 1)
-#pragma unroll
-                for (int a = 0; a < DIM; a++)
-#pragma unroll
-                    for (int c = 0; c < DIM; c++) acc[a][c] += __shfl_xor(acc[a][c], sh);
-            if (mine && q == 0) {
-                double tr = 0.0;
-#pragma unroll
-                for (int a = 0; a < DIM; a++) tr += acc[a][a];
-#pragma unroll
-                for (int a = 0; a < DIM; a++)
-#pragma unroll
-                    for (int c = 0; c < DIM; c++) {
-                        double o = P.lam * acc[a][c] + P.mu * acc[c][a];
-                        if (a == c) o += P.mu * tr;
-                        if (FUSE && bcoff >= 0) o = dirichlet_entry(bcb, a, c, o);
-                        st[a * rl + DIM * pcsr + c] = o;
-                    }
-            }
-        }
-    };
-
-    // ---- compute role: group gg from buffers b into stage b
     auto compute_group = [&](int b, int rb) {
-        const int flags = wave_uniform(shdr[rb][4]);
-        if (flags >> kGrpWideShift) {
-            compute_group_wide(b, rb);
-            return;
-        }
-        const int nn = wave_uniform(shdr[rb][0]);
-        const int deg = wave_uniform(shdr[rb][1]);
-        const int posoff = wave_uniform(shdr[rb][2]);
-        const int blk = wave_uniform(shdr[rb][3]);
-        const int bcoff = FUSE ? wave_uniform(shdr[rb][7]) : -1;
-        const int rkoff = wave_uniform(shdr[rb][8]);
-        const bool diag = flags & kGrpDiag;
-        const int rl = DIM * deg;
-        const bool hi = lane >= NG;
-        const int node = lane & (NG - 1);
-        double *st = stage + b * P.stage + node * blk;
-        const T *G = sG + b * D2 * kGroupElems;
-        const uint16_t *n2l = sn2l + b * n2l_stride + node;
-        for (;;) {
-            int r = 0;
-            if (lane == 0) r = atomicAdd(&ticket[b], 1);
-            r = wave_uniform(r);
-            // the signature's slice holds deg + 1 items, the last ones -1;
-            // late waves draw tickets past the end
-            if (r > deg) break;
-            const int pa = ldc(P.sig_pairs, 2 * posoff + 2 * r);
-            if (pa < 0) break;
-            const int pb = ldc(P.sig_pairs, 2 * posoff + 2 * r + 1);
-            const bool split = pb == pa;
-            const int c0 = ldc(P.sig_pos_ptr, posoff + pa);
-            const int na = ldc(P.sig_pos_ptr, posoff + pa + 1) - c0;
-            // contribution ranges of the two halves: [lo0, lo0 + nlo), [hi0, hi0 + nhi)
-            int lo0 = c0, nlo = na, hi0 = c0, nhi = 0;
-            if (split) {
-                nlo = (na + 1) / 2;
-                hi0 = c0 + nlo;
-                nhi = na - nlo;
-            } else if (pb >= 0) {
-                hi0 = ldc(P.sig_pos_ptr, posoff + pb);
-                nhi = ldc(P.sig_pos_ptr, posoff + pb + 1) - hi0;
-            }
-            const int mycnt = hi ? nhi : nlo;
-            // Dirichlet bits of the lane's block, fetched now and used at the end
-            const int pme = hi ? pb : pa;
-            const int bcb = (FUSE && bcoff >= 0 && node < nn && pme >= 0) ? P.bc_bits[bcoff + node * deg + pme] : 0;
-            // the block's CSR position (a canonical-order plan's rank table)
-            const int pcsr = (rkoff >= 0 && node < nn && pme >= 0) ? (int)P.grp_rank[rkoff + pme * NG + node] : pme;
-            double acc[DIM][DIM];
-#pragma unroll
-            for (int a = 0; a < DIM; a++)
-#pragma unroll
-                for (int c = 0; c < DIM; c++) acc[a][c] = 0.0;
-            // nlo >= nhi: the low half has the longer list
-            for (int t = 0; t < nlo; t += 2) {
-                int pk[2];
-                bool ok[2];
-#pragma unroll
-                for (int u = 0; u < 2; u++) {
-                    const int tl = t + u < nlo ? t + u : nlo - 1;
-                    const int kl = ldc(P.sig_contrib, lo0 + tl);
-                    const int kh = nhi > 0 ? ldc(P.sig_contrib, hi0 + (t + u < nhi ? t + u : nhi - 1)) : kl;
-                    pk[u] = hi ? kh : kl;
-                    ok[u] = t + u < mycnt;
-                }
-#pragma unroll
-                for (int u = 0; u < 2; u++) {
-                    const int k = pk[u] >> 16, i = (pk[u] >> 8) & 255, j = pk[u] & 255;
-                    const int slot = n2l[k * NG];
-                    const T *Mij = sM + (i * NEN + j) * D2;
-                    T Mv[D2];
-#pragma unroll
-                    for (int x = 0; x < D2; x++) Mv[x] = Mij[x];
-                    if (diag) {
-                        T dd[DIM][DIM];
-#pragma unroll
-                        for (int a = 0; a < DIM; a++)
-#pragma unroll
-                            for (int c = a; c < DIM; c++) {
-                                dd[a][c] = diag_product<PREC>(G[a * kGroupElems + slot], G[c * kGroupElems + slot]);
-                                dd[c][a] = dd[a][c];
-                            }
-                        if (ok[u]) accumulate_diag<DIM, PREC>(dd, Mv, acc);
-                    } else {
-                        T Gv[DIM][DIM];
-#pragma unroll
-                        for (int m = 0; m < DIM; m++)
-#pragma unroll
-                            for (int a = 0; a < DIM; a++) Gv[m][a] = G[(m * DIM + a) * kGroupElems + slot];
-                        if (ok[u]) accumulate<DIM, PREC>(Gv, Mv, acc);
-                    }
-                }
-            }
-            if (split) {
-                // low half's sum + high half's sum (the same in both halves:
-                // addition is commutative)
-#pragma unroll
-                for (int a = 0; a < DIM; a++)
-#pragma unroll
-                    for (int c = 0; c < DIM; c++) acc[a][c] += __shfl_xor(acc[a][c], NG);
-            }
-            double tr = 0.0;
-#pragma unroll
-            for (int a = 0; a < DIM; a++) tr += acc[a][a];
-            const int p = hi ? pb : pa;
-            if (node < nn && p >= 0 && !(split && hi)) {
-#pragma unroll
-                for (int a = 0; a < DIM; a++)
-#pragma unroll
-                    for (int c = 0; c < DIM; c++) {
-                        double o = P.lam * acc[a][c] + P.mu * acc[c][a];
-                        if (a == c) o += P.mu * tr;
-                        if (FUSE && bcoff >= 0) o = dirichlet_entry(bcb, a, c, o);
-                        st[a * rl + DIM * pcsr + c] = o;
-                    }
-            }
-        }
+        assemble_group<DIM, NEN, PREC, FUSE>(P, shdr[rb], &ticket[b], stage + b * P.stage, sG + b * D2 * kGroupElems, sM,
+                                             sn2l + b * n2l_stride, lane);
     };
-
-    // ---- store role: group gg from stage b, row offsets rb.  Each store
-    // wave takes every kStoreWaves-th node of the group's first half together
-    // with its partner half a group later, four values per lane and node at
-    // a time, so that eight LDS reads are in flight per batch.  K is
-    // written once and never read back here: the stores are non-temporal, so
-    // they stream out instead of taking L2 lines that the element loads use
     auto store_group = [&](int b, int rb) {
-        const int nn = wave_uniform(shdr[rb][0]);
-        const int deg = wave_uniform(shdr[rb][1]);
-        const int blk = wave_uniform(shdr[rb][3]);
-        const int bsz = DIM * DIM * deg;  // the node's DIM rows, contiguous in CSR
-        const int32_t *rows = srows + rb * 2 * NG;
-        const double *sb = stage + b * P.stage;
-        if (DIM == 2 && bsz <= 64) {
-            // short row blocks (2D elements): lane = (node j of npi, value o),
-            // so that one batch of four stores covers 4 npi of the wave's
-            // nodes w', w' + kStoreWaves, ... instead of one node per store
-            const int npi = 64 / bsz;  // nodes per store instruction
-            const int j = lane / bsz, o = lane - j * bsz;
-            const int sw = w - kCompWaves;
-            for (int b0 = 0; b0 * kStoreWaves + sw < nn; b0 += 4 * npi) {
-                double v[4];
-                int dst[4];
-#pragma unroll
-                for (int c = 0; c < 4; c++) {
-                    const int n = sw + kStoreWaves * (b0 + c * npi + j);
-                    const bool ok = j < npi && n < nn;
-                    v[c] = ok ? sb[n * blk + o] : 0.0;
-                    dst[c] = ok ? rows[2 * n] + o : -1;
-                }
-#pragma unroll
-                for (int c = 0; c < 4; c++)
-                    if (dst[c] >= 0) __builtin_nontemporal_store(v[c], P.K + dst[c]);
-            }
-            return;
-        }
-        // a wave's two nodes of a batch lie half a group apart
-        const int half = (nn + 1) / 2;
-        for (int n0 = w - kCompWaves; n0 < half; n0 += kStoreWaves) {
-            const int n1 = n0 + half;
-            const bool two = n1 < nn;
-            const int base0 = rows[2 * n0];
-            const int base1 = two ? rows[2 * n1] : base0;
-            const double *s0 = sb + n0 * blk;
-            const double *s1 = sb + (two ? n1 : n0) * blk;
-            for (int o0 = lane; o0 < bsz; o0 += 4 * 64) {
-                double v0[4], v1[4];
-#pragma unroll
-                for (int c = 0; c < 4; c++) {
-                    const int o = o0 + 64 * c;
-                    v0[c] = o < bsz ? s0[o] : 0.0;
-                    v1[c] = o < bsz ? s1[o] : 0.0;
-                }
-#pragma unroll
-                for (int c = 0; c < 4; c++) {
-                    const int o = o0 + 64 * c;
-                    if (o < bsz) {
-                        __builtin_nontemporal_store(v0[c], P.K + base0 + o);
-                        if (two) __builtin_nontemporal_store(v1[c], P.K + base1 + o);
-                    }
-                }
-            }
-        }
+        store_rows<DIM, kStoreWaves>(P, shdr[rb], srows + rb * 2 * NG, stage + b * P.stage, w - kCompWaves, lane);
     };
 
     // Every wave runs nsteps + 1 barriers: one after the prologue, one per
@@ -732,292 +781,9 @@ __global__ __launch_bounds__(OsShape<DIM>::threads) void k_assemble_os(AsmParams
     }
     __syncthreads();
 
-    auto compute_group_wide = [&]() {
-        const int nn = wave_uniform(shdr[0]);
-        const int deg = wave_uniform(shdr[1]);
-        const int blk = wave_uniform(shdr[3]);
-        const int flags = wave_uniform(shdr[4]);
-        const int wi0 = wave_uniform(shdr[5]);
-        const int nwi = wave_uniform(shdr[6]);
-        const int bcoff = FUSE ? wave_uniform(shdr[7]) : -1;
-        const int rkoff = wave_uniform(shdr[8]);
-        const bool diag = flags & kGrpDiag;
-        const int lgN = 5 - ((flags >> kGrpWideShift) & 3);  // N = 8 or 16
-        const int N = 1 << lgN;
-        const int rl = DIM * deg;
-        const int node = lane & (N - 1);
-        double *st = stage + node * blk;
-        const T *G = sG;
-        const uint16_t *n2l = sn2l + node;
-        for (;;) {
-            int r = 0;
-            if (lane == 0) r = atomicAdd(&ticket, 1);
-            r = wave_uniform(r);
-            if (r >= nwi) break;
-            const int32_t *rec = P.sig_witems + (int64_t)(wi0 + r) * kWideInts;
-            const int np = ldc(rec, 0), Q = ldc(rec, 1), nt = ldc(rec, 2);
-            const int lgQ = 31 - __clz(Q);
-            const int grp = lane >> lgN;
-            const int pp = grp >> lgQ, q = grp & (Q - 1);
-            // this lane's position, its contribution offset and count
-            int p = -1, off = 0, cnt = 0;
-#pragma unroll
-            for (int k = 0; k < 8; k++)
-                if (pp == k) {
-                    p = ldc(rec, 8 + k);
-                    off = ldc(rec, 16 + k);
-                    cnt = ldc(rec, 24 + k);
-                }
-            const bool mine = pp < np && node < nn;
-            // Dirichlet bits of the lane's block and its CSR position (a
-            // canonical-order plan's rank table), fetched now and used at the end
-            const int bcb = (FUSE && bcoff >= 0 && mine && q == 0) ? P.bc_bits[bcoff + node * deg + p] : 0;
-            const int pcsr = (rkoff >= 0 && mine && q == 0) ? (int)P.grp_rank[rkoff + p * NG + node] : p;
-            double acc[DIM][DIM];
-#pragma unroll
-            for (int a = 0; a < DIM; a++)
-#pragma unroll
-                for (int c = 0; c < DIM; c++) acc[a][c] = 0.0;
-            // contributions of this lane: all loads first (nt <= 8)
-            int pk[8];
-#pragma unroll
-            for (int t = 0; t < 8; t++) {
-                const int ti = q + t * Q;
-                pk[t] = (t < nt && mine && ti < cnt) ? P.sig_contrib[off + ti] : -1;
-            }
-#pragma unroll
-            for (int t = 0; t < 8; t++) {
-                if (t >= nt) break;
-                if (pk[t] >= 0) {
-                    const int k = pk[t] >> 16, i = (pk[t] >> 8) & 255, j = pk[t] & 255;
-                    const int slot = n2l[k * NG];
-                    const T *Mij = sM + (i * NEN + j) * D2;
-                    T Mv[D2];
-#pragma unroll
-                    for (int x = 0; x < D2; x++) Mv[x] = Mij[x];
-                    if (diag) {
-                        T dd[DIM][DIM];
-#pragma unroll
-                        for (int a = 0; a < DIM; a++)
-#pragma unroll
-                            for (int c = a; c < DIM; c++) {
-                                dd[a][c] = diag_product<PREC>(G[a * kGroupElems + slot], G[c * kGroupElems + slot]);
-                                dd[c][a] = dd[a][c];
-                            }
-                        accumulate_diag<DIM, PREC>(dd, Mv, acc);
-                    } else {
-                        T Gv[DIM][DIM];
-#pragma unroll
-                        for (int m = 0; m < DIM; m++)
-#pragma unroll
-                            for (int a = 0; a < DIM; a++) Gv[m][a] = G[(m * DIM + a) * kGroupElems + slot];
-                        accumulate<DIM, PREC>(Gv, Mv, acc);
-                    }
-                }
-            }
-            for (int sh = N; sh < N * Q; sh <<= 1)
-#pragma unroll
-                for (int a = 0; a < DIM; a++)
-#pragma unroll
-                    for (int c = 0; c < DIM; c++) acc[a][c] += __shfl_xor(acc[a][c], sh);
-            if (mine && q == 0) {
-                double tr = 0.0;
-#pragma unroll
-                for (int a = 0; a < DIM; a++) tr += acc[a][a];
-#pragma unroll
-                for (int a = 0; a < DIM; a++)
-#pragma unroll
-                    for (int c = 0; c < DIM; c++) {
-                        double o = P.lam * acc[a][c] + P.mu * acc[c][a];
-                        if (a == c) o += P.mu * tr;
-                        if (FUSE && bcoff >= 0) o = dirichlet_entry(bcb, a, c, o);
-                        st[a * rl + DIM * pcsr + c] = o;
-                    }
-            }
-        }
-    };
-
-    auto compute_group = [&]() {
-        const int flags = wave_uniform(shdr[4]);
-        if (flags >> kGrpWideShift) {
-            compute_group_wide();
-            return;
-        }
-        const int nn = wave_uniform(shdr[0]);
-        const int deg = wave_uniform(shdr[1]);
-        const int posoff = wave_uniform(shdr[2]);
-        const int blk = wave_uniform(shdr[3]);
-        const int bcoff = FUSE ? wave_uniform(shdr[7]) : -1;
-        const int rkoff = wave_uniform(shdr[8]);
-        const bool diag = flags & kGrpDiag;
-        const int rl = DIM * deg;
-        const bool hi = lane >= NG;
-        const int node = lane & (NG - 1);
-        double *st = stage + node * blk;
-        const T *G = sG;
-        const uint16_t *n2l = sn2l + node;
-        for (;;) {
-            int r = 0;
-            if (lane == 0) r = atomicAdd(&ticket, 1);
-            r = wave_uniform(r);
-            // the signature's slice holds deg + 1 items, the last ones -1;
-            // late waves draw tickets past the end
-            if (r > deg) break;
-            const int pa = ldc(P.sig_pairs, 2 * posoff + 2 * r);
-            if (pa < 0) break;
-            const int pb = ldc(P.sig_pairs, 2 * posoff + 2 * r + 1);
-            const bool split = pb == pa;
-            const int c0 = ldc(P.sig_pos_ptr, posoff + pa);
-            const int na = ldc(P.sig_pos_ptr, posoff + pa + 1) - c0;
-            // contribution ranges of the two halves: [lo0, lo0 + nlo), [hi0, hi0 + nhi)
-            int lo0 = c0, nlo = na, hi0 = c0, nhi = 0;
-            if (split) {
-                nlo = (na + 1) / 2;
-                hi0 = c0 + nlo;
-                nhi = na - nlo;
-            } else if (pb >= 0) {
-                hi0 = ldc(P.sig_pos_ptr, posoff + pb);
-                nhi = ldc(P.sig_pos_ptr, posoff + pb + 1) - hi0;
-            }
-            const int mycnt = hi ? nhi : nlo;
-            // Dirichlet bits of the lane's block, fetched now and used at the end
-            const int pme = hi ? pb : pa;
-            const int bcb = (FUSE && bcoff >= 0 && node < nn && pme >= 0) ? P.bc_bits[bcoff + node * deg + pme] : 0;
-            // the block's CSR position (a canonical-order plan's rank table)
-            const int pcsr = (rkoff >= 0 && node < nn && pme >= 0) ? (int)P.grp_rank[rkoff + pme * NG + node] : pme;
-            double acc[DIM][DIM];
-#pragma unroll
-            for (int a = 0; a < DIM; a++)
-#pragma unroll
-                for (int c = 0; c < DIM; c++) acc[a][c] = 0.0;
-            // nlo >= nhi: the low half has the longer list
-            for (int t = 0; t < nlo; t += 2) {
-                int pk[2];
-                bool ok[2];
-#pragma unroll
-                for (int u = 0; u < 2; u++) {
-                    const int tl = t + u < nlo ? t + u : nlo - 1;
-                    const int kl = ldc(P.sig_contrib, lo0 + tl);
-                    const int kh = nhi > 0 ? ldc(P.sig_contrib, hi0 + (t + u < nhi ? t + u : nhi - 1)) : kl;
-                    pk[u] = hi ? kh : kl;
-                    ok[u] = t + u < mycnt;
-                }
-#pragma unroll
-                for (int u = 0; u < 2; u++) {
-                    const int k = pk[u] >> 16, i = (pk[u] >> 8) & 255, j = pk[u] & 255;
-                    const int slot = n2l[k * NG];
-                    const T *Mij = sM + (i * NEN + j) * D2;
-                    T Mv[D2];
-#pragma unroll
-                    for (int x = 0; x < D2; x++) Mv[x] = Mij[x];
-                    if (diag) {
-                        T dd[DIM][DIM];
-#pragma unroll
-                        for (int a = 0; a < DIM; a++)
-#pragma unroll
-                            for (int c = a; c < DIM; c++) {
-                                dd[a][c] = diag_product<PREC>(G[a * kGroupElems + slot], G[c * kGroupElems + slot]);
-                                dd[c][a] = dd[a][c];
-                            }
-                        if (ok[u]) accumulate_diag<DIM, PREC>(dd, Mv, acc);
-                    } else {
-                        T Gv[DIM][DIM];
-#pragma unroll
-                        for (int m = 0; m < DIM; m++)
-#pragma unroll
-                            for (int a = 0; a < DIM; a++) Gv[m][a] = G[(m * DIM + a) * kGroupElems + slot];
-                        if (ok[u]) accumulate<DIM, PREC>(Gv, Mv, acc);
-                    }
-                }
-            }
-            if (split) {
-                // low half's sum + high half's sum (the same in both halves:
-                // addition is commutative)
-#pragma unroll
-                for (int a = 0; a < DIM; a++)
-#pragma unroll
-                    for (int c = 0; c < DIM; c++) acc[a][c] += __shfl_xor(acc[a][c], NG);
-            }
-            double tr = 0.0;
-#pragma unroll
-            for (int a = 0; a < DIM; a++) tr += acc[a][a];
-            const int p = hi ? pb : pa;
-            if (node < nn && p >= 0 && !(split && hi)) {
-#pragma unroll
-                for (int a = 0; a < DIM; a++)
-#pragma unroll
-                    for (int c = 0; c < DIM; c++) {
-                        double o = P.lam * acc[a][c] + P.mu * acc[c][a];
-                        if (a == c) o += P.mu * tr;
-                        if (FUSE && bcoff >= 0) o = dirichlet_entry(bcb, a, c, o);
-                        st[a * rl + DIM * pcsr + c] = o;
-                    }
-            }
-        }
-    };
-
-    auto store_group = [&]() {
-        const int nn = wave_uniform(shdr[0]);
-        const int deg = wave_uniform(shdr[1]);
-        const int blk = wave_uniform(shdr[3]);
-        const int bsz = DIM * DIM * deg;  // the node's DIM rows, contiguous in CSR
-        const int32_t *rows = srows;
-        const double *sb = stage;
-        if (DIM == 2 && bsz <= 64) {
-            // short row blocks (2D elements): lane = (node j of npi, value o),
-            // so that one batch of four stores covers 4 npi of the wave's
-            // nodes w', w' + kStoreWaves, ... instead of one node per store
-            const int npi = 64 / bsz;  // nodes per store instruction
-            const int j = lane / bsz, o = lane - j * bsz;
-            const int sw = w;
-            for (int b0 = 0; b0 * kStoreWaves + sw < nn; b0 += 4 * npi) {
-                double v[4];
-                int dst[4];
-#pragma unroll
-                for (int c = 0; c < 4; c++) {
-                    const int n = sw + kStoreWaves * (b0 + c * npi + j);
-                    const bool ok = j < npi && n < nn;
-                    v[c] = ok ? sb[n * blk + o] : 0.0;
-                    dst[c] = ok ? rows[2 * n] + o : -1;
-                }
-#pragma unroll
-                for (int c = 0; c < 4; c++)
-                    if (dst[c] >= 0) __builtin_nontemporal_store(v[c], P.K + dst[c]);
-            }
-            return;
-        }
-        // a wave's two nodes of a batch lie half a group apart
-        const int half = (nn + 1) / 2;
-        for (int n0 = w; n0 < half; n0 += kStoreWaves) {
-            const int n1 = n0 + half;
-            const bool two = n1 < nn;
-            const int base0 = rows[2 * n0];
-            const int base1 = two ? rows[2 * n1] : base0;
-            const double *s0 = sb + n0 * blk;
-            const double *s1 = sb + (two ? n1 : n0) * blk;
-            for (int o0 = lane; o0 < bsz; o0 += 4 * 64) {
-                double v0[4], v1[4];
-#pragma unroll
-                for (int c = 0; c < 4; c++) {
-                    const int o = o0 + 64 * c;
-                    v0[c] = o < bsz ? s0[o] : 0.0;
-                    v1[c] = o < bsz ? s1[o] : 0.0;
-                }
-#pragma unroll
-                for (int c = 0; c < 4; c++) {
-                    const int o = o0 + 64 * c;
-                    if (o < bsz) {
-                        __builtin_nontemporal_store(v0[c], P.K + base0 + o);
-                        if (two) __builtin_nontemporal_store(v1[c], P.K + base1 + o);
-                    }
-                }
-            }
-        }
-    };
-
-    compute_group();
+    assemble_group<DIM, NEN, PREC, FUSE>(P, shdr, &ticket, stage, sG, sM, sn2l, lane);
     __syncthreads();
-    store_group();
+    store_rows<DIM, kStoreWaves>(P, shdr, srows, stage, w, lane);
 }
 
 // Dirichlet rows and columns (zero prescribed values): for a fixed dof r =
