@@ -68,6 +68,12 @@ __device__ __forceinline__ T ldc(const T *base, int64_t idx) {
     return ((const __attribute__((address_space(4))) T *)(base))[idx];
 }
 
+// eight consecutive wave-uniform int32 by one scalar load
+typedef int Codes8 __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ Codes8 ld_codes8(const int32_t *p) {
+    return *((const __attribute__((address_space(4))) Codes8 *)(p));
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ assembly
@@ -320,21 +326,24 @@ __device__ __forceinline__ void assemble_pairs(const AsmParams &P, const int *hd
         for (int a = 0; a < DIM; a++)
 #pragma unroll
             for (int c = 0; c < DIM; c++) acc[a][c] = 0.0;
-        // nlo >= nhi: the low half has the longer list
-        for (int t = 0; t < nlo; t += 2) {
-            int pk[2];
-            bool ok[2];
+        // nlo >= nhi: the low half has the longer list.  The codes of a chunk
+        // of 8 contributions of each half are read by scalar loads before the
+        // chunk's LDS reads (scalar loads and LDS reads share one wait
+        // counter: a scalar load waited for between contributions would also
+        // wait for every LDS read in flight).  Both halves read as many
+        // chunks as the longer list needs, past a list's end into the next
+        // codes (the table ends with enough zero codes); such entries are
+        // read but not added.
+        const int32_t *lo_p = P.sig_contrib + lo0;
+        const int32_t *hi_p = P.sig_contrib + (nhi > 0 ? hi0 : lo0);
+        for (int t0 = 0; t0 < nlo; t0 += 8) {
+            const Codes8 cl = ld_codes8(lo_p + t0), ch = ld_codes8(hi_p + t0);
 #pragma unroll
-            for (int u = 0; u < 2; u++) {
-                const int tl = t + u < nlo ? t + u : nlo - 1;
-                const int kl = ldc(P.sig_contrib, lo0 + tl);
-                const int kh = nhi > 0 ? ldc(P.sig_contrib, hi0 + (t + u < nhi ? t + u : nhi - 1)) : kl;
-                pk[u] = hi ? kh : kl;
-                ok[u] = t + u < mycnt;
-            }
-#pragma unroll
-            for (int u = 0; u < 2; u++) {
-                const int k = pk[u] >> 16, i = (pk[u] >> 8) & 255, j = pk[u] & 255;
+            for (int u = 0; u < 8; u++) {
+                if (t0 + u >= nlo) break;
+                const int code = hi && nhi > 0 ? ch[u] : cl[u];
+                const bool oku = t0 + u < mycnt;
+                const int k = code >> 16, i = (code >> 8) & 255, j = code & 255;
                 const int slot = n2l[k * NG];
                 const T *Mij = sM + (i * NEN + j) * D2;
                 T Mv[D2];
@@ -349,14 +358,14 @@ __device__ __forceinline__ void assemble_pairs(const AsmParams &P, const int *hd
                             dd[a][c] = diag_product<PREC>(G[a * kGroupElems + slot], G[c * kGroupElems + slot]);
                             dd[c][a] = dd[a][c];
                         }
-                    if (ok[u]) accumulate_diag<DIM, PREC>(dd, Mv, acc);
+                    if (oku) accumulate_diag<DIM, PREC>(dd, Mv, acc);
                 } else {
                     T Gv[DIM][DIM];
 #pragma unroll
                     for (int m = 0; m < DIM; m++)
 #pragma unroll
                         for (int a = 0; a < DIM; a++) Gv[m][a] = G[(m * DIM + a) * kGroupElems + slot];
-                    if (ok[u]) accumulate<DIM, PREC>(Gv, Mv, acc);
+                    if (oku) accumulate<DIM, PREC>(Gv, Mv, acc);
                 }
             }
         }

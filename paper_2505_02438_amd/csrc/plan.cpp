@@ -658,6 +658,17 @@ int build_host_plan(const soptx_mesh *mesh, HostPlan &hp, bool general) {
             hp.sig_pairs.push_back(-1);
         }
     }
+    // the assembly kernel reads contribution codes in chunks of 8 and reads
+    // the second list of a pair as far as the first (longer) one: reads run
+    // past a list's end by less than the longest list rounded up to 8 (the
+    // codes there are not used).  A tail of that many zero codes keeps them
+    // inside the table.
+    {
+        size_t longest = 0;
+        for (size_t p = 0; p + 1 < hp.sig_pos_ptr.size(); p++)
+            longest = std::max(longest, (size_t)(hp.sig_pos_ptr[p + 1] - hp.sig_pos_ptr[p]));
+        hp.sig_contrib.insert(hp.sig_contrib.end(), std::max<size_t>(8, (longest + 7) / 8 * 8), 0);
+    }
     if (hp.sig_contrib.size() >= (size_t)INT32_MAX) return SOPTX_E_OVERFLOW;
 
     // ---- groups: same-signature nodes in ascending order; at most kGroupNodes nodes,

@@ -191,6 +191,20 @@ def walk_plan(hp, mesh, rho, M, E0=1.0, Emin=1e-9, p=3.0, nu=0.3, mask=None):
                 assert pb < 0 or cnt[pa] >= cnt[pb]  # the low half runs the longer list
                 costs.append(cnt[pa])
         assert sorted(covered) == list(range(deg))  # every position exactly once
+        # the pair path reads codes in chunks of 8, both halves as many chunks
+        # as the low (longer) list needs: every such read stays in the table
+        ncodes = hp["sig_contrib"].size
+        pos = hp["sig_pos_ptr"]
+        for pa, pb in items[:nit]:
+            c0, na = int(pos[posoff + pa]), int(cnt[pa])
+            lo0, nlo, hi0, nhi = c0, na, c0, 0
+            if pb == pa:
+                nlo = (na + 1) // 2
+                hi0, nhi = c0 + nlo, na - nlo
+            elif pb >= 0:
+                hi0, nhi = int(pos[posoff + pb]), int(cnt[pb])
+            span = -(-nlo // 8) * 8
+            assert lo0 + span <= ncodes and (hi0 if nhi > 0 else lo0) + span <= ncodes
         assert np.all(np.diff(costs) <= 0)  # costliest first
         wsh = (flags >> 1) & 3
         if wsh:
