@@ -451,6 +451,45 @@ __device__ __forceinline__ void store_rows(const AsmParams &P, const int *hdr, c
     }
     // a wave's two nodes of a batch lie half a group apart
     const int half = (nn + 1) / 2;
+    if (wave_uniform(hdr[8]) >= 0) {
+        // the group's nodes are scattered over K (a plan in canonical order,
+        // with a rank table): each node's run is issued from the 128 B line
+        // boundary at or below its start (lanes before the start or past the
+        // end store nothing), so that a store instruction covers whole lines
+        // and only a run's first and last lines are written in part.  Runs
+        // of consecutive nodes (below) are issued from their starts instead:
+        // the neighbouring runs complete the lines they share while both are
+        // in the cache, and the shorter code keeps the store waves' issue
+        // rate up
+        for (int n0 = sw; n0 < half; n0 += KSTORE) {
+            const int n1 = n0 + half;
+            const bool two = n1 < nn;
+            const int base0 = wave_uniform(rows[2 * n0]);
+            const int base1 = two ? wave_uniform(rows[2 * n1]) : base0;
+            const int sh0 = base0 & 15, sh1 = base1 & 15;
+            const double *s0 = sb + n0 * blk;
+            const double *s1 = sb + (two ? n1 : n0) * blk;
+            const int span = bsz + (sh0 > sh1 ? sh0 : sh1);
+            for (int c0 = 0; c0 < span; c0 += 4 * 64) {
+                double v0[4], v1[4];
+                bool k0[4], k1[4];
+#pragma unroll
+                for (int c = 0; c < 4; c++) {
+                    const int q0 = c0 + 64 * c + lane - sh0, q1 = c0 + 64 * c + lane - sh1;
+                    k0[c] = q0 >= 0 && q0 < bsz;
+                    k1[c] = two && q1 >= 0 && q1 < bsz;
+                    v0[c] = k0[c] ? s0[q0] : 0.0;
+                    v1[c] = k1[c] ? s1[q1] : 0.0;
+                }
+#pragma unroll
+                for (int c = 0; c < 4; c++) {
+                    if (k0[c]) __builtin_nontemporal_store(v0[c], P.K + base0 + (c0 + 64 * c + lane - sh0));
+                    if (k1[c]) __builtin_nontemporal_store(v1[c], P.K + base1 + (c0 + 64 * c + lane - sh1));
+                }
+            }
+        }
+        return;
+    }
     for (int n0 = sw; n0 < half; n0 += KSTORE) {
         const int n1 = n0 + half;
         const bool two = n1 < nn;
