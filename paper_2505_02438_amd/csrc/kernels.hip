@@ -341,8 +341,10 @@ __device__ __forceinline__ void assemble_pairs(const AsmParams &P, const int *hd
 #pragma unroll
             for (int u = 0; u < 8; u++) {
                 if (t0 + u >= nlo) break;
-                const int code = hi && nhi > 0 ? ch[u] : cl[u];
+                // an entry past the lane's own (shorter) list reads with
+                // code 0, a slot of its own table, and is not added
                 const bool oku = t0 + u < mycnt;
+                const int code = oku ? (hi && nhi > 0 ? ch[u] : cl[u]) : 0;
                 const int k = code >> 16, i = (code >> 8) & 255, j = code & 255;
                 const int slot = n2l[k * NG];
                 const T *Mij = sM + (i * NEN + j) * D2;
@@ -799,18 +801,43 @@ __global__ __launch_bounds__(OsShape<DIM>::threads) void k_assemble_os(AsmParams
         if (PREC == kF64) sM[x] = (T)P.M[x];
         else sM[x] = (T)P.M32[x];
     }
-    for (int slot = tid; slot < ne; slot += kOsThreads) {
-        const int e = P.grp_elems[eoff + slot];
-        const double r = (double)static_cast<const R *>(P.rho)[e];
-        const double E = P.Emin + simp_pow(r, P.p, P.ip) * (P.E0 - P.Emin);
-        const double qq = sqrt(E * P.geo[(int64_t)D2 * NC + e]);
-        if (gflags & kGrpDiag) {
+    // two slots per thread and pass, their loads in flight together (a group
+    // can hold a few more elements than the workgroup has threads)
+    for (int s0 = tid; s0 < ne; s0 += 2 * kOsThreads) {
+        int e[2];
+        double rr[2], gd[2][D2 + 1];
 #pragma unroll
-            for (int a = 0; a < DIM; a++) sG[a * kGroupElems + slot] = (T)(qq * P.geo[(int64_t)(a * DIM + a) * NC + e]);
-        } else {
-#pragma unroll
-            for (int c = 0; c < D2; c++) sG[c * kGroupElems + slot] = (T)(qq * P.geo[(int64_t)c * NC + e]);
+        for (int h = 0; h < 2; h++) {
+            const int slot = s0 + h * kOsThreads;
+            e[h] = slot < ne ? P.grp_elems[eoff + slot] : -1;
         }
+#pragma unroll
+        for (int h = 0; h < 2; h++)
+            if (e[h] >= 0) {
+                rr[h] = (double)static_cast<const R *>(P.rho)[e[h]];
+                gd[h][D2] = P.geo[(int64_t)D2 * NC + e[h]];
+                if (gflags & kGrpDiag) {
+#pragma unroll
+                    for (int a = 0; a < DIM; a++) gd[h][a * DIM + a] = P.geo[(int64_t)(a * DIM + a) * NC + e[h]];
+                } else {
+#pragma unroll
+                    for (int c = 0; c < D2; c++) gd[h][c] = P.geo[(int64_t)c * NC + e[h]];
+                }
+            }
+#pragma unroll
+        for (int h = 0; h < 2; h++)
+            if (e[h] >= 0) {
+                const int slot = s0 + h * kOsThreads;
+                const double E = P.Emin + simp_pow(rr[h], P.p, P.ip) * (P.E0 - P.Emin);
+                const double qq = sqrt(E * gd[h][D2]);
+                if (gflags & kGrpDiag) {
+#pragma unroll
+                    for (int a = 0; a < DIM; a++) sG[a * kGroupElems + slot] = (T)(qq * gd[h][a * DIM + a]);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < D2; c++) sG[c * kGroupElems + slot] = (T)(qq * gd[h][c]);
+                }
+            }
     }
     for (int x = tid; x < nk; x += kOsThreads) sn2l[x] = P.grp_n2l[n2off + x];
     if (tid < 2 * NG) srows[tid] = P.grp_rows[(int64_t)gg * 2 * NG + tid];
