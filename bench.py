@@ -412,9 +412,18 @@ class StepState:
         self.bc = api.Dirichlet(pat, pr.mask, stream=stream)
         torch.cuda.synchronize()
 
+    def fused(self, i, stream):
+        """One step in one call: soptx_step with u, dc and c (the energies,
+        then K with the Dirichlet rows and columns; the assembly kernel adds
+        the partials of c)."""
+        b = i % self.nbuf
+        self.pat.step(self.mat, self.rho, self.u, bc=self.bc, K=self.Ks[b], dc=self.dcs[b], c=self.cs[b],
+                      prec=self.prec, stream=stream)
+
     def step(self, i, stream, ev=None):
-        """One step: K with the Dirichlet rows and columns (soptx_step, the
-        bound table), then dc and c (soptx_evaluate); events around each."""
+        """The same step as two calls, for the stage times: K with the
+        Dirichlet rows and columns (soptx_step, the bound table), then dc and c
+        (soptx_evaluate); events around each."""
         b = i % self.nbuf
         if ev is not None:
             ev[0].record(stream)
@@ -436,7 +445,7 @@ def spin_up(st, stream, seconds):
     i = 0
     while time.perf_counter() - t0 < seconds:
         for _ in range(20):
-            st.step(i, stream)
+            st.fused(i, stream)
             i += 1
         torch.cuda.synchronize()
     return i
@@ -449,19 +458,25 @@ def pct(xs):
 
 
 def timed_steps(st, stream, steps, warmup):
-    """warmup untimed steps, then `steps` steps timed by the wall clock
-    (synchronised on both sides) with HIP events on the bench stream around
-    the assembly and the evaluation of each step."""
+    """warmup untimed steps, then `steps` fused steps (one call each, no
+    events between them) timed by the wall clock, synchronised on both sides.
+    Then the stage-split region: `steps` more steps as two calls with HIP
+    events on the bench stream around the assembly and the evaluation of each
+    (timing events between kernels cost several microseconds per step, so the
+    timed region has none)."""
     import torch
     for i in range(warmup):
-        st.step(i, stream)
-    events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+        st.fused(i, stream)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
-        st.step(i, stream, events[i])
+        st.fused(i, stream)
     torch.cuda.synchronize()
     total_s = time.perf_counter() - t0
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    for i in range(steps):
+        st.step(i, stream, events[i])
+    torch.cuda.synchronize()
     asm_ms = [e[0].elapsed_time(e[1]) for e in events]
     ev_ms = [e[1].elapsed_time(e[2]) for e in events]
     return total_s, asm_ms, ev_ms
@@ -669,7 +684,7 @@ def main():
         for b in range(st.nbuf):
             g = torch.cuda.CUDAGraph()
             with torch.cuda.graph(g, stream=stream):
-                st.step(b, stream)
+                st.fused(b, stream)
             graphs.append(g)
         torch.cuda.synchronize()
     if graphs is not None:
@@ -766,7 +781,10 @@ def main():
         "step_frac": (asm_bytes + ev_bytes) / (total_s / args.steps) / 1e9 / HBM_PEAK_GBS,
         "stage_ms": {"assemble_dirichlet": statistics.mean(asm_ms), "evaluate": statistics.mean(ev_ms)},
         "stage_ms_pct": {"assemble_dirichlet": pct(asm_ms), "evaluate": pct(ev_ms)},
-        "launch": "eager (value, stage_ms and roofline from this timed region)",
+        "launch": ("eager; value and ms_per_step: the timed region, one soptx_step call per step (energies, then "
+                   "the assembly, which adds the partials of c), no events between steps; stage_ms and roofline: "
+                   "the stage-split region right after it, the same steps as two calls (soptx_step for K, "
+                   "soptx_evaluate for dc and c) with HIP events around each"),
         "spin_up": {"seconds": args.spin_up, "steps": spun,
                     "note": "untimed steps before the warm-up steps, so that the GPU clocks have ramped"},
         "jacobian_path": jacobian_path(stats),

@@ -41,6 +41,12 @@ struct AsmParams {
     // the fused step (soptx_step) only; null in soptx_assemble
     const int32_t *bc_off;         // [G] offset of the group's Dirichlet bits, -1: none (null: no table)
     const uint8_t *bc_bits;        // per group [n_nodes][deg] bits of dirichlet_entry
+    // the fused step with compliance: the energy kernel ran first; one wave
+    // of workgroup 0 adds its block partials into fin_c[0..1] (null: none)
+    const double *fin_partials;    // [2][fin_n]
+    int fin_n;
+    int fin_with_f;
+    double *fin_c;
 };
 
 struct EnergyParams {

@@ -68,6 +68,40 @@ __device__ __forceinline__ T ldc(const T *base, int64_t idx) {
     return ((const __attribute__((address_space(4))) T *)(base))[idx];
 }
 
+// c[0] = sum of partials[0:n]; c[1] = sum of partials[n:2n] (f^T u, or 0),
+// by one wave, in the order of a 256-thread block: thread t adds partials t,
+// t + 256, ... in turn, then the 256 sums meet in a tree (t += t + 128, then
+// t + 64, ... down to t + 1).  Lane l holds threads l, l + 64, l + 128 and
+// l + 192; the tree's first two levels are its own, the rest shuffles.
+__device__ __forceinline__ void wave_finalize(const double *partials, int n, int with_f, double *c, int lane) {
+    for (int which = 0; which < 2; which++) {
+        double t[4] = {0.0, 0.0, 0.0, 0.0};
+        if (which == 0 || with_f) {
+            // four rounds of 256 loaded together, then added in order (only
+            // the terms that exist: the sums match the block's bit for bit)
+            const double *src = partials + (int64_t)which * n;
+            for (int k0 = lane; k0 < n; k0 += 4 * 256) {
+                double x[4][4];
+#pragma unroll
+                for (int j = 0; j < 4; j++)
+#pragma unroll
+                    for (int v = 0; v < 4; v++) {
+                        const int k = k0 + 64 * v + 256 * j;
+                        x[j][v] = k < n ? src[k] : 0.0;
+                    }
+#pragma unroll
+                for (int j = 0; j < 4; j++)
+#pragma unroll
+                    for (int v = 0; v < 4; v++)
+                        if (k0 + 64 * v + 256 * j < n) t[v] += x[j][v];
+            }
+        }
+        double x = (t[0] + t[2]) + (t[1] + t[3]);
+        for (int st = 32; st > 0; st >>= 1) x += __shfl_down(x, st);
+        if (lane == 0) c[which] = x;
+    }
+}
+
 // eight consecutive wave-uniform int32 by one scalar load
 typedef int Codes8 __attribute__((ext_vector_type(8)));
 __device__ __forceinline__ Codes8 ld_codes8(const int32_t *p) {
@@ -721,6 +755,10 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
         __syncthreads();
         for (int s = 0; s < nsteps; s++) {
             if (s > 0) store_group((s - 1) & 1, (s - 1) % 3);
+            // step 0 has nothing to store: the first store wave of workgroup
+            // 0 adds the energy kernel's partials of c there
+            else if (P.fin_c && blockIdx.x == 0 && w == kCompWaves)
+                wave_finalize(P.fin_partials, P.fin_n, P.fin_with_f, P.fin_c, lane);
             __syncthreads();
         }
     } else {
@@ -787,6 +825,9 @@ __global__ __launch_bounds__(OsShape<DIM>::threads) void k_assemble_os(AsmParams
     const int ngr = P.n_groups;
     const int W = P.os_window;
     const int bid = blockIdx.x;
+    // the fused step: the first wave of workgroup 0 adds the energy kernel's
+    // partials of c first
+    if (P.fin_c && bid == 0 && w == 0) wave_finalize(P.fin_partials, P.fin_n, P.fin_with_f, P.fin_c, lane);
     const int base = bid - bid % W;
     const int gg = base + W <= ngr ? base + (bid % 8) * (W / 8) + (bid - base) / 8 : bid;
     if (gg >= ngr) return;
@@ -1242,17 +1283,10 @@ __global__ __launch_bounds__(256) void k_energy(EnergyParams P) {
     }
 }
 
-// c[0] = sum of partials[0:n]; c[1] = sum of partials[n:2n] (f^T u, or 0).
-// One block, strided sums then a tree: a fixed order.
-__global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ partials, int n, int with_f, double *c) {
-    __shared__ double red[256];
-    for (int which = 0; which < 2; which++) {
-        double t = 0.0;
-        if (which == 0 || with_f)
-            for (int k = threadIdx.x; k < n; k += 256) t += partials[which * n + k];
-        t = block_sum_256(t, red);
-        if (threadIdx.x == 0) c[which] = t;
-    }
+// c from the energy kernel's block partials: one wave (the fused step runs
+// the same function inside the assembly kernel instead)
+__global__ __launch_bounds__(64) void k_finalize(const double *__restrict__ partials, int n, int with_f, double *c) {
+    wave_finalize(partials, n, with_f, c, threadIdx.x);
 }
 
 // ------------------------------------------------------------------ backward
@@ -1499,7 +1533,7 @@ hipError_t launch_dirichlet(int dim, const int32_t *row_ptr, const int32_t *nb_t
 }
 
 hipError_t launch_finalize(const double *partials, int n, int with_f, double *c, hipStream_t st) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, partials, n, with_f, c);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, partials, n, with_f, c);
     return hipGetLastError();
 }
 

@@ -509,29 +509,23 @@ int soptx_pcg(soptx_pattern h, const double *d_K_vals, const double *d_f, double
     return SOPTX_OK;
 }
 
-// soptx_evaluate and its allocation-free variant: the same kernels; the block
-// partials of c go to the per-stream workspace or to the fixed scratch
-static int evaluate_impl(soptx_pattern h, const soptx_material *m, const void *d_rho, const double *d_u,
-                         const double *d_f, void *d_dc, double *d_c, int32_t prec, void *stream, bool noalloc) {
-    if (!h || !valid_prec(prec)) return SOPTX_E_INVALID_ARG;
-    if (!h->affine) return not_affine(h);
-    int rc = check_material(m);
-    if (rc) return rc;
-    if (h->n_cells > 0 && (!d_rho || !d_u)) return SOPTX_E_INVALID_ARG;
-    if (!d_dc && !d_c) return SOPTX_E_INVALID_ARG;
+// The element-energy kernel of soptx_evaluate and soptx_step: dc, and with
+// d_c the fixed-order block partials of c and f^T u in the per-stream
+// workspace or the fixed scratch (*ws, *nblk of each) for a finalize.
+// Arguments are checked by the callers; the device is current.
+static int launch_energies(soptx_pattern h, const soptx_material *m, const void *d_rho, const double *d_u,
+                           const double *d_f, void *d_dc, double *d_c, int32_t prec, hipStream_t st, bool noalloc,
+                           double **ws_out, int *nblk_out) {
     const int64_t nblk64 = std::max<int64_t>(1, (h->n_cells + 255) / 256);
     if (noalloc && d_c && nblk64 > kNoAllocBlocks) return SOPTX_E_SCRATCH;
     const int nblk = (int)nblk64;
-    DeviceGuard dg(h->device);
-    if (!dg.ok) return SOPTX_E_DEVICE;
-    hipStream_t st = static_cast<hipStream_t>(stream);
     double *ws = nullptr;
     if (d_c) {
         // block partials of c, then of f^T u
         if (noalloc) {
             if (noalloc_scratch(h->device, &ws) != hipSuccess) return SOPTX_E_DEVICE;
         } else {
-            rc = get_workspace(h->device, st, 2 * (size_t)nblk, &ws, 0);
+            const int rc = get_workspace(h->device, st, 2 * (size_t)nblk, &ws, 0);
             if (rc) return rc;
         }
     }
@@ -545,6 +539,28 @@ static int evaluate_impl(soptx_pattern h, const soptx_material *m, const void *d
     P.n_cells = h->n_cells; P.E0 = m->E0; P.Emin = m->Emin; P.p = m->p; P.ip = int_exponent(m->p);
     lame(h, m, &P.lam, &P.mu);
     if (launch_energy(h->elem, prec, P, st) != hipSuccess) return SOPTX_E_DEVICE;
+    *ws_out = ws;
+    *nblk_out = nblk;
+    return SOPTX_OK;
+}
+
+// soptx_evaluate and its allocation-free variant: the same kernels; the block
+// partials of c go to the per-stream workspace or to the fixed scratch
+static int evaluate_impl(soptx_pattern h, const soptx_material *m, const void *d_rho, const double *d_u,
+                         const double *d_f, void *d_dc, double *d_c, int32_t prec, void *stream, bool noalloc) {
+    if (!h || !valid_prec(prec)) return SOPTX_E_INVALID_ARG;
+    if (!h->affine) return not_affine(h);
+    int rc = check_material(m);
+    if (rc) return rc;
+    if (h->n_cells > 0 && (!d_rho || !d_u)) return SOPTX_E_INVALID_ARG;
+    if (!d_dc && !d_c) return SOPTX_E_INVALID_ARG;
+    if (noalloc && d_c && std::max<int64_t>(1, (h->n_cells + 255) / 256) > kNoAllocBlocks) return SOPTX_E_SCRATCH;
+    DeviceGuard dg(h->device);
+    if (!dg.ok) return SOPTX_E_DEVICE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double *ws = nullptr;
+    int nblk = 0;
+    if ((rc = launch_energies(h, m, d_rho, d_u, d_f, d_dc, d_c, prec, st, noalloc, &ws, &nblk))) return rc;
     if (d_c && launch_finalize(ws, nblk, d_f ? 1 : 0, d_c, st) != hipSuccess) return SOPTX_E_DEVICE;
     return SOPTX_OK;
 }
@@ -728,17 +744,31 @@ int soptx_step(soptx_pattern h, soptx_dirichlet bc, const soptx_material *m, con
     DeviceGuard dg(h->device);
     if (!dg.ok) return SOPTX_E_DEVICE;
     hipStream_t st = static_cast<hipStream_t>(stream);
+    // element energies and dc first (the kernel of soptx_evaluate; it does
+    // not read K), so that the assembly kernel can add the partials of c in
+    // the step where its store waves have nothing to store yet: the same
+    // function and order as soptx_evaluate's finalize, one launch fewer
+    double *ws = nullptr;
+    int nblk = 0;
+    if ((d_dc || d_c) && (rc = launch_energies(h, m, d_rho, d_u, d_f, d_dc, d_c, prec, st, false, &ws, &nblk)))
+        return rc;
     // assembly with the Dirichlet table applied while the blocks are staged
     if (h->ngroups > 0) {
         AsmParams P{};
         if ((rc = asm_params(h, m, d_rho, d_K_vals, prec, st, P))) return rc;
         P.bc_off = (bc && bc->n_groups > 0) ? bc->off : nullptr;
         P.bc_bits = bc ? bc->bits : nullptr;
+        if (d_c) {
+            P.fin_partials = ws;
+            P.fin_n = nblk;
+            P.fin_with_f = d_f ? 1 : 0;
+            P.fin_c = d_c;
+        }
         if (launch_assemble(h->elem, prec, P, h->ngroups, st, true) != hipSuccess) return SOPTX_E_DEVICE;
+    } else if (d_c && launch_finalize(ws, nblk, d_f ? 1 : 0, d_c, st) != hipSuccess) {
+        return SOPTX_E_DEVICE;
     }
-    if (!d_dc && !d_c) return SOPTX_OK;
-    // element energies, dc and c: the kernels of soptx_evaluate
-    return evaluate_impl(h, m, d_rho, d_u, d_f, d_dc, d_c, prec, stream, false);
+    return SOPTX_OK;
 }
 
 void soptx_destroy_pattern(soptx_pattern h) {

@@ -162,11 +162,14 @@ def test_assembly_kernels_agree_bitwise(elem, dims, skew):
     """The persistent assembly kernel and the one-workgroup-per-group kernel
     (chosen by the plan's shape; forced here through the debug hook) give
     bitwise the same K, with and without the bound Dirichlet table, in both
-    precision forms."""
+    precision forms.  In the fused step with u the assembly kernel also adds
+    the energy kernel's partials of c: under either kernel, dc and c are
+    bitwise those of soptx_evaluate (k_finalize)."""
     pr, m, pat, rp, ci = _setup(elem, dims, skew)
     bc = api.Dirichlet(pat, pr.mask)
     L = _lib.lib()
-    out = {}
+    u, f = dev(pr.u), dev(pr.f)
+    out, fused = {}, {}
     try:
         for v in (0, 1, -1):
             assert L.soptx_debug_set_assembly_variant(v) == 0
@@ -175,6 +178,9 @@ def test_assembly_kernels_agree_bitwise(elem, dims, skew):
                 K1 = host(pat.assemble(MAT, rho, prec=prec))
                 K2, _, _ = pat.step(MAT, rho, bc=bc, prec=prec)
                 out[(v, prec)] = (K1, host(K2))
+                K3, dc3, c3 = pat.step(MAT, rho, u, f, bc=bc, prec=prec)
+                dce, ce = pat.evaluate(MAT, rho, u, f, prec=prec)
+                fused[(v, prec)] = (host(K3), host(dc3), host(c3), host(dce), host(ce))
         assert L.soptx_debug_set_assembly_variant(2) == -1
     finally:
         L.soptx_debug_set_assembly_variant(-1)
@@ -182,3 +188,8 @@ def test_assembly_kernels_agree_bitwise(elem, dims, skew):
         for v in (1, -1):
             assert np.array_equal(out[(v, prec)][0], out[(0, prec)][0]), (v, prec)
             assert np.array_equal(out[(v, prec)][1], out[(0, prec)][1]), (v, prec)
+        for v in (0, 1, -1):
+            K3, dc3, c3, dce, ce = fused[(v, prec)]
+            assert np.array_equal(K3, out[(0, prec)][1]), (v, prec)
+            assert np.array_equal(dc3, dce) and np.array_equal(c3, ce), (v, prec, c3, ce)
+            assert c3[1] != 0.0
