@@ -676,26 +676,31 @@ def main():
     graph_s = None
     graphs = None
     if not args.no_graph:
-        # one captured step per output buffer (HIP graph replay; the kernels
-        # and their order are those of the eager step), captured and timed
-        # after the eager region: eager steps timed while captured graphs
-        # were held ran slower on some runs (108 vs 90 us assembly)
+        # HIP graph replay of the eager timed region's step (the same kernels
+        # in the same order), captured and timed after the eager region:
+        # eager steps timed while captured graphs were held ran slower on
+        # some runs (108 vs 90 us assembly)
+        # one graph holds one step per output buffer, so a replay runs nbuf
+        # steps and its launch cost is shared among them
         graphs = []
-        for b in range(st.nbuf):
-            g = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(g, stream=stream):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            for b in range(st.nbuf):
                 st.fused(b, stream)
-            graphs.append(g)
+        graphs.append(g)
         torch.cuda.synchronize()
+    graph_steps = 0
     if graphs is not None:
         with torch.cuda.stream(stream):
-            for i in range(args.warmup):
-                graphs[i % st.nbuf].replay()
+            for i in range(max(1, args.warmup // st.nbuf)):
+                graphs[0].replay()
         torch.cuda.synchronize()
+        reps = max(1, -(-args.steps // st.nbuf))
+        graph_steps = reps * st.nbuf
         t0 = time.perf_counter()
         with torch.cuda.stream(stream):
-            for i in range(args.steps):
-                graphs[i % st.nbuf].replay()
+            for i in range(reps):
+                graphs[0].replay()
         torch.cuda.synchronize()
         graph_s = time.perf_counter() - t0
         del graphs  # the captured graphs' memory goes before the other legs
@@ -788,8 +793,9 @@ def main():
         "spin_up": {"seconds": args.spin_up, "steps": spun,
                     "note": "untimed steps before the warm-up steps, so that the GPU clocks have ramped"},
         "jacobian_path": jacobian_path(stats),
-        "graph_value": None if graph_s is None else n * args.steps / graph_s,
-        "graph_ms_per_step": None if graph_s is None else graph_s / args.steps * 1e3,
+        "graph_value": None if graph_s is None else n * graph_steps / graph_s,
+        "graph_ms_per_step": None if graph_s is None else graph_s / graph_steps * 1e3,
+        "graph_steps": graph_steps,
         "evaluate_algorithmic_bytes": ev_bytes,
         "pattern_build_s": build_s,
         "plan": {"groups": stats["n_groups"], "signatures": stats["n_signatures"],
