@@ -63,6 +63,7 @@ struct EnergyParams {
     const double *f;       // [ndof] or null: f^T u as well
     int64_t ndof;
     double *partials;      // [2][grid] block partials of c and f^T u, or null (no compliance)
+    int axis_aligned;      // every element has a diagonal J^-1 (the plan's groups all say so)
     int64_t n_cells;
     double E0, Emin, p;
     int ip;

@@ -536,6 +536,7 @@ static int launch_energies(soptx_pattern h, const soptx_material *m, const void 
     P.f = d_c ? d_f : nullptr;
     P.ndof = h->ndof;
     P.partials = d_c ? ws : nullptr;
+    P.axis_aligned = h->ngroups > 0 && h->stats.n_groups_diag == h->ngroups;
     P.n_cells = h->n_cells; P.E0 = m->E0; P.Emin = m->Emin; P.p = m->p; P.ip = int_exponent(m->p);
     lame(h, m, &P.lam, &P.mu);
     if (launch_energy(h->elem, prec, P, st) != hipSuccess) return SOPTX_E_DEVICE;
