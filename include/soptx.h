@@ -311,10 +311,14 @@ void soptx_destroy_dirichlet(soptx_dirichlet bc);
  * sum_e E(rho_e) s_e and d_c[1] = f^T u (0 when d_f is NULL) (d_c may be
  * NULL).  d_u may be NULL only when d_dc and d_c are.  K is the same, value
  * for value, as soptx_assemble + the mask's Dirichlet step, and d_dc, d_c
- * are those of soptx_evaluate (the same kernels), in both precision forms.
- * d_rho: [n_cells]; d_u, d_f: [ndof] double; d_K_vals: [nnz]; d_dc:
- * [n_cells]; d_c: 2 doubles.  Asynchronous on stream; the compliance's
- * partials live in a per-(device, stream) workspace allocated on first use. */
+ * are bit for bit those of soptx_evaluate, in both precision forms: the
+ * energies run first (the kernel of soptx_evaluate), then the assembly,
+ * which also adds the energy kernel's block partials of c in soptx_evaluate's
+ * order (one launch fewer).  d_rho: [n_cells]; d_u, d_f: [ndof] double;
+ * d_K_vals: [nnz]; d_dc: [n_cells]; d_c: 2 doubles.  Asynchronous on stream;
+ * the compliance's partials live in a per-(device, stream) workspace
+ * allocated on first use, so calls that overlap on one stream's workspace
+ * are ordered by that stream. */
 int soptx_step(soptx_pattern h, soptx_dirichlet bc, const soptx_material *m, const void *d_rho,
                const double *d_u, const double *d_f, double *d_K_vals, void *d_dc, double *d_c,
                int32_t prec, void *stream);
