@@ -193,3 +193,38 @@ def test_assembly_kernels_agree_bitwise(elem, dims, skew):
             assert np.array_equal(K3, out[(0, prec)][1]), (v, prec)
             assert np.array_equal(dc3, dce) and np.array_equal(c3, ce), (v, prec, c3, ce)
             assert c3[1] != 0.0
+
+
+def test_step_degenerate_meshes():
+    """The fused step on meshes without work for the assembly: no cells and no
+    nodes; nodes but no cells (no groups: the compliance partials are summed
+    by their own launch, c = [0, f^T u]); a grid beside an isolated node (the
+    assembly kernel sums them).  dc and c equal soptx_evaluate's bit for bit."""
+    # no cells, no nodes
+    pat = api.Pattern(I.HEX8, np.zeros((0, 3)), np.zeros((0, 8), dtype=np.int32))
+    z = torch.zeros(0, dtype=torch.float64, device="cuda:0")
+    K, dc, c = pat.step(MAT, z, z, z, K=torch.zeros(0, dtype=torch.float64, device="cuda:0"))
+    torch.cuda.synchronize()
+    assert host(c)[0] == 0.0 and host(c)[1] == 0.0 and dc.numel() == 0
+    # nodes but no cells
+    coords = np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [0.0, 2.0, 1.0]])
+    pat = api.Pattern(I.HEX8, coords, np.zeros((0, 8), dtype=np.int32))
+    assert pat.stats()["n_groups"] == 0
+    u = np.linspace(-1.0, 2.0, pat.ndof)
+    f = np.cos(np.arange(pat.ndof, dtype=np.float64))
+    K, dc, c = pat.step(MAT, z, dev(u), dev(f), K=torch.zeros(pat.nnz, dtype=torch.float64, device="cuda:0"))
+    torch.cuda.synchronize()
+    c = host(c)
+    assert c[0] == 0.0 and abs(c[1] - float(np.dot(f, u))) <= 1e-14 * np.sum(np.abs(f * u))
+    # a grid beside an isolated node
+    m = I.quad_grid(5, 3)
+    coords = np.vstack([m.coords, [[10.0, 10.0]]])
+    pat = api.Pattern(I.QUAD4, coords, m.cells)
+    assert pat.stats()["n_groups"] > 0
+    rho = dev(np.linspace(0.1, 1.0, m.n_cells))
+    u = dev(np.sin(np.arange(pat.ndof, dtype=np.float64)))
+    f = dev(np.cos(np.arange(pat.ndof, dtype=np.float64)))
+    _, dc1, c1 = pat.step(MAT, rho, u, f)
+    dc2, c2 = pat.evaluate(MAT, rho, u, f)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(dc1), host(dc2)) and np.array_equal(host(c1), host(c2))
