@@ -848,7 +848,7 @@ def main():
             if wl != args.workload:
                 d, mk = WORKLOADS[wl]
                 rows[wl] = labelled_run(wl, d, mk(I), stream, min(args.steps, 20), 3,
-                                        (api.FP64, api.FP32) if wl == "p2box48" else (api.FP64,))
+                                        (api.FP64, api.FP32) if wl in ("p2box48", "tri600x200") else (api.FP64,))
                 torch.cuda.empty_cache()
         out["labelled"] = rows
     if args.to_iters > 0:
