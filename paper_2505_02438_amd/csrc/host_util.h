@@ -16,7 +16,9 @@ namespace soptx {
 // 4 = element matrices of the per-quadrature-point assembly, 5 = densities in
 // the rank order of a canonical-order plan.  Work on one stream is ordered, so
 // one buffer per (device, stream, use) is race-free.  Held until the process
-// ends; grown (after a synchronisation of the stream) when a call needs more.
+// ends; when a call needs more, a larger buffer replaces it and the old one is
+// kept (not freed), so that a HIP graph captured earlier on the stream, which
+// holds the old address, still replays on valid memory.
 int get_workspace(int device, hipStream_t st, size_t n, double **out, int use);
 
 // Copy a host vector into a new device allocation recorded in `allocs` (freed

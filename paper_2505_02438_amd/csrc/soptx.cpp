@@ -29,6 +29,11 @@ struct Workspace {
 };
 std::mutex g_ws_mu;
 std::map<std::tuple<int, hipStream_t, int>, Workspace> g_ws;
+// Buffers replaced by larger ones.  They are kept, not freed: a HIP graph
+// captured with a call on this stream holds their addresses, and a replay
+// after a larger call must still find valid memory there (it also spares
+// the host a synchronisation before the free)
+std::vector<double *> g_ws_retired;
 }  // namespace
 
 int get_workspace(int device, hipStream_t st, size_t n, double **out, int use) {
@@ -36,8 +41,11 @@ int get_workspace(int device, hipStream_t st, size_t n, double **out, int use) {
     Workspace &w = g_ws[std::make_tuple(device, st, use)];
     if (w.n < n) {
         if (w.buf) {
-            if (hipStreamSynchronize(st) != hipSuccess) return SOPTX_E_DEVICE;
-            (void)hipFree(w.buf);
+            try {
+                g_ws_retired.push_back(w.buf);
+            } catch (...) {
+                return SOPTX_E_OOM;
+            }
             w.buf = nullptr;
             w.n = 0;
         }

@@ -102,3 +102,50 @@ def _fused_step_graph(elem, renumber):
         assert np.array_equal(host(K), ref[0]) and np.array_equal(host(dc), ref[1]), rep
         assert np.array_equal(host(c), ref[2]), rep
         _ = (rho * 2).sum().item()  # eager work between replays
+
+
+def test_graph_replays_after_the_workspace_grew():
+    """A fused step captured on a small renumbered mesh (its graph holds the
+    stream's workspace addresses: the compliance partials and the densities
+    in rank order); then a step on a larger mesh on the same stream, which
+    needs larger workspaces; the earlier graph's replays still give its eager
+    results bit for bit (the replaced workspaces are kept, not freed)."""
+    pr = I.renumber(I.small_problem(I.HEX8, seed=43, dims=(6, 5, 4)), 44)
+    m = pr.mesh
+    pat = api.Pattern.from_mesh(m)
+    assert pat.stats()["n_groups_ranked"] > 0
+    bc = api.Dirichlet(pat, pr.mask)
+    st = torch.cuda.Stream()
+    rho, u, f = dev(pr.rho), dev(pr.u), dev(pr.f)
+    K = torch.empty(pat.nnz, dtype=torch.float64, device="cuda")
+    dc = torch.empty(m.n_cells, dtype=torch.float64, device="cuda")
+    c = torch.zeros(2, dtype=torch.float64, device="cuda")
+
+    def step():
+        pat.step(MAT, rho, u, f, bc=bc, K=K, dc=dc, c=c, stream=st)
+
+    with torch.cuda.stream(st):
+        step()
+    torch.cuda.synchronize()
+    ref = (host(K).copy(), host(dc).copy(), host(c).copy())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=st):
+        step()
+    # a larger renumbered mesh on the same stream: larger workspaces
+    pr2 = I.renumber(I.small_problem(I.HEX8, seed=45, dims=(40, 30, 20)), 46)
+    pat2 = api.Pattern.from_mesh(pr2.mesh)
+    assert pat2.n_cells > 8 * 256 and pat2.stats()["n_groups_ranked"] > 0
+    bc2 = api.Dirichlet(pat2, pr2.mask)
+    K2, dc2, c2 = pat2.step(MAT, dev(pr2.rho), dev(pr2.u), dev(pr2.f), bc=bc2, stream=st)
+    torch.cuda.synchronize()
+    assert np.isfinite(host(c2)).all()
+    for rep in range(3):
+        K.fill_(np.nan)
+        dc.fill_(np.nan)
+        c.fill_(np.nan)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(K), ref[0]) and np.array_equal(host(dc), ref[1]), rep
+        assert np.array_equal(host(c), ref[2]), rep
+        _ = (rho * 2).sum().item()  # eager work between replays
