@@ -763,6 +763,7 @@ def main():
     # dispatch gap before each kernel, stage_ms)
     asm_avg_s = asm_burst_ms / 1e3
     achieved = asm_bytes / asm_avg_s / 1e9
+    step_unique = (pat.nnz * 8 + n * 8 + n * 8 + pat.ndof * 8 + m.n_nodes * m.dim * 8 + n * m.nen * 4 + pat.ndof)
     traffic = None
     if args.workload == "hex120x40x40" and os.path.exists(COUNTERS):
         with open(COUNTERS) as fh:
@@ -804,6 +805,11 @@ def main():
             "frac_of_measured_fill": achieved / fill_gbs,
         },
         "step_frac": (asm_bytes + ev_bytes) / (total_s / args.steps) / 1e9 / HBM_PEAK_GBS,
+        # the step's bytes with the inputs both kernels read (rho, coordinates,
+        # cells) counted once: K and dc written; rho, u, coordinates, cells
+        # and the fixed-dof mask read
+        "step_unique_bytes": step_unique,
+        "step_frac_unique_bytes": step_unique / (total_s / args.steps) / 1e9 / HBM_PEAK_GBS,
         "stage_ms": {"assemble_dirichlet": statistics.mean(asm_ms), "evaluate": statistics.mean(ev_ms)},
         "stage_ms_pct": {"assemble_dirichlet": pct(asm_ms), "evaluate": pct(ev_ms)},
         "launch": ("eager; value and ms_per_step: the timed region, one soptx_step call per step (energies, then "
