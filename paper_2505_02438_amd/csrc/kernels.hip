@@ -982,9 +982,9 @@ __global__ __launch_bounds__(256) void k_dirichlet(const int32_t *__restrict__ r
 // the other coordinates, of the nodal differences along the axis.  Energy
 // lambda tr(eps)^2 + 2 mu eps:eps with eps = sym(grad_xi u G) at each point,
 // equal weights.
-__device__ __forceinline__ double q1_point_energy3(const double (&H)[3][3], const double (&G)[3][3], bool diag,
-                                                   double lam, double mu) {
-    double eps[3][3];
+template <class T>
+__device__ __forceinline__ T q1_point_energy3(const T (&H)[3][3], const T (&G)[3][3], bool diag, T lam, T mu) {
+    T eps[3][3];
     if (diag) {
 #pragma unroll
         for (int a = 0; a < 3; a++)
@@ -996,28 +996,29 @@ __device__ __forceinline__ double q1_point_energy3(const double (&H)[3][3], cons
 #pragma unroll
             for (int b = 0; b < 3; b++) eps[a][b] = H[a][0] * G[0][b] + H[a][1] * G[1][b] + H[a][2] * G[2][b];
     }
-    const double tr = eps[0][0] + eps[1][1] + eps[2][2];
-    const double h01 = 0.5 * (eps[0][1] + eps[1][0]), h02 = 0.5 * (eps[0][2] + eps[2][0]),
-                 h12 = 0.5 * (eps[1][2] + eps[2][1]);
-    const double ee = eps[0][0] * eps[0][0] + eps[1][1] * eps[1][1] + eps[2][2] * eps[2][2] +
-                      2.0 * (h01 * h01 + h02 * h02 + h12 * h12);
-    return lam * tr * tr + 2.0 * mu * ee;
+    const T tr = eps[0][0] + eps[1][1] + eps[2][2];
+    const T h01 = T(0.5) * (eps[0][1] + eps[1][0]), h02 = T(0.5) * (eps[0][2] + eps[2][0]),
+            h12 = T(0.5) * (eps[1][2] + eps[2][1]);
+    const T ee = eps[0][0] * eps[0][0] + eps[1][1] * eps[1][1] + eps[2][2] * eps[2][2] +
+                 T(2.0) * (h01 * h01 + h02 * h02 + h12 * h12);
+    return lam * tr * tr + T(2.0) * mu * ee;
 }
 
 // AXIS: every element of the mesh is an axis-aligned box (diagonal J^-1),
 // known from the plan; the per-element check and the full-G branch are then
-// compiled out (the same arithmetic as the check's diagonal branch)
-template <bool AXIS>
-__device__ __forceinline__ double q1_hex_energy(const double (&u)[8][3], const double (&G)[3][3], double lam,
-                                                double mu) {
+// compiled out (the same arithmetic as the check's diagonal branch).  T is
+// the arithmetic type: double, or float in the FP32 form (on displacements
+// whose rigid motion was removed in FP64)
+template <class T, bool AXIS>
+__device__ __forceinline__ T q1_hex_energy(const T (&u)[8][3], const T (&G)[3][3], T lam, T mu) {
     // local node of corner (x, y, z): bottom face counter-clockwise, then top
     constexpr int N[2][2][2] = {{{0, 4}, {3, 7}}, {{1, 5}, {2, 6}}};
-    const double gp[2] = {0.5 - 0.5 / 1.7320508075688772935, 0.5 + 0.5 / 1.7320508075688772935};
+    const T gp[2] = {T(0.5 - 0.5 / 1.7320508075688772935), T(0.5 + 0.5 / 1.7320508075688772935)};
     const bool diag = AXIS || (G[0][1] == 0.0 && G[0][2] == 0.0 && G[1][0] == 0.0 && G[1][2] == 0.0 &&
                                G[2][0] == 0.0 && G[2][1] == 0.0);
     // d[ax][a][p][q]: nodal differences of u_a along axis ax, at the corners
     // (p, q) of the two other axes (in increasing axis order)
-    double d[3][3][2][2];
+    T d[3][3][2][2];
 #pragma unroll
     for (int a = 0; a < 3; a++)
 #pragma unroll
@@ -1028,28 +1029,28 @@ __device__ __forceinline__ double q1_hex_energy(const double (&u)[8][3], const d
                 d[1][a][p][q] = u[N[p][1][q]][a] - u[N[p][0][q]][a];
                 d[2][a][p][q] = u[N[p][q][1]][a] - u[N[p][q][0]][a];
             }
-    auto lerp2 = [&](const double (&f)[2][2], double s, double t) {
-        const double lo = f[0][0] + s * (f[1][0] - f[0][0]);
-        const double hi = f[0][1] + s * (f[1][1] - f[0][1]);
+    auto lerp2 = [&](const T (&f)[2][2], T s, T t) {
+        const T lo = f[0][0] + s * (f[1][0] - f[0][0]);
+        const T hi = f[0][1] + s * (f[1][1] - f[0][1]);
         return lo + t * (hi - lo);
     };
-    double sum = 0.0;
+    T sum = T(0.0);
 #pragma unroll
     for (int i = 0; i < 2; i++)
 #pragma unroll
         for (int j = 0; j < 2; j++)
 #pragma unroll
             for (int k = 0; k < 2; k++) {
-                double H[3][3];
+                T H[3][3];
 #pragma unroll
                 for (int a = 0; a < 3; a++) {
                     H[a][0] = lerp2(d[0][a], gp[j], gp[k]);
                     H[a][1] = lerp2(d[1][a], gp[i], gp[k]);
                     H[a][2] = lerp2(d[2][a], gp[i], gp[j]);
                 }
-                sum += q1_point_energy3(H, G, diag, lam, mu);
+                sum += q1_point_energy3<T>(H, G, diag, lam, mu);
             }
-    return 0.125 * sum;
+    return T(0.125) * sum;
 }
 
 __device__ __forceinline__ double q1_quad_energy(const double (&u)[4][2], const double (&G)[2][2], double lam,
@@ -1120,7 +1121,7 @@ __global__ __launch_bounds__(256) void k_energy(EnergyParams P) {
         }
         double s = 0.0;
         if constexpr (PREC == kF64 && DIM == 3 && NEN == 8) {
-            s = q1_hex_energy<AXIS>(u, G, P.lam, P.mu);
+            s = q1_hex_energy<double, AXIS>(u, G, P.lam, P.mu);
         } else if constexpr (PREC == kF64 && DIM == 2 && NEN == 4) {
             s = q1_quad_energy(u, G, P.lam, P.mu);
         } else if (PREC == kF64) {
@@ -1225,6 +1226,11 @@ __global__ __launch_bounds__(256) void k_energy(EnergyParams P) {
 #pragma unroll
                 for (int a = 0; a < DIM; a++) Gf[m][a] = (float)G[m][a];
             float sf = 0.0f;
+            if constexpr (DIM == 3 && NEN == 8) {
+                // Q1 hexahedra: the tensor-product form of the FP64 path, in
+                // FP32 (the strains still formed at each Gauss point)
+                sf = q1_hex_energy<float, AXIS>(wf, Gf, (float)P.lam, (float)P.mu);
+            } else {
 #pragma unroll
             for (int q = 0; q < NQ; q++) {
                 const float *dq = P.qgrad32 + q * NEN * DIM;
@@ -1260,6 +1266,7 @@ __global__ __launch_bounds__(256) void k_energy(EnergyParams P) {
                     }
                 }
                 sf += (float)P.qw[q] * ((float)P.lam * tr * tr + 2.0f * (float)P.mu * ee);
+            }
             }
             s = (double)sf;
         }
@@ -1522,10 +1529,10 @@ static hipError_t launch_energy_t(const EnergyParams &P, hipStream_t st) {
     unsigned nb = (unsigned)((P.n_cells + 255) / 256);
     if (nb == 0 && P.partials) nb = 1;  // c (and f^T u) still written
     if (nb == 0) return hipSuccess;
-    // Q1 hexahedra, FP64, all axis-aligned: without the full-G branch the
+    // Q1 hexahedra, all axis-aligned: without the full-G branch the FP64
     // kernel needs 154 VGPRs instead of 188, three waves per SIMD instead of
     // two, and a 120x40x40 mesh's 750 blocks run in one round instead of two
-    if constexpr (DIM == 3 && NEN == 8 && PREC == kF64) {
+    if constexpr (DIM == 3 && NEN == 8) {
         if (P.axis_aligned) {
             hipLaunchKernelGGL((k_energy<DIM, NEN, NQ, PREC, true>), dim3(nb), dim3(256), 0, st, P);
             return hipGetLastError();
