@@ -1278,10 +1278,11 @@ __global__ __launch_bounds__(256) void k_energy(EnergyParams P) {
         cpart = E * s;
     }
     if (!P.partials) return;
-    // compliance: fixed-order block partials of c and f^T u; k_finalize adds
-    // them in index order.  (A last-block-done reduction in this kernel would
-    // need a device-scope release per block, i.e. an L2 write-back on this
-    // chip, which costs more than the extra launch.)
+    // compliance: fixed-order block partials of c and f^T u; wave_finalize
+    // adds them in index order (k_finalize, or the assembly kernel of the
+    // fused step).  (A last-block-done reduction in this kernel would need a
+    // device-scope release per block, i.e. an L2 write-back on this chip,
+    // which costs more than the extra launch.)
     double fpart = 0.0;
     if (P.f)
         for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < P.ndof; r += (int64_t)gridDim.x * 256)
