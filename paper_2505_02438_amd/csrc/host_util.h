@@ -13,8 +13,8 @@ namespace soptx {
 // Scratch of at least n doubles for work on (device, stream); `use` keeps
 // independent buffers apart: 0 = reduction partials of the energy kernel,
 // 1 = CG vectors, 2 = filter chain rule, 3 = OC bisection state and partials,
-// 4 = element matrices of the per-quadrature-point assembly, 5 = densities in
-// the rank order of a canonical-order plan.  Work on one stream is ordered, so
+// 4 = element matrices of the per-quadrature-point assembly.  Work on one
+// stream is ordered, so
 // one buffer per (device, stream, use) is race-free.  Held until the process
 // ends; when a call needs more, a larger buffer replaces it and the old one is
 // kept (not freed), so that a HIP graph captured earlier on the stream, which

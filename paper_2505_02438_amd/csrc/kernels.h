@@ -19,6 +19,7 @@ struct AsmParams {
     int os_window;              // one-shot variant: workgroups per window of XCD-local runs (multiple of 8)
     const int32_t *grp_rank_off;  // [G]: offset of the group's rank table, -1 = none (or NULL: no tables)
     const uint8_t *grp_rank;      // rank tables: [position][32] CSR position of a canonical position
+    const int32_t *elem_by_rank;  // canonical-order plans: rank -> element, rho read through it (else null)
     const int32_t *sig_info;    // [S][4]: K, deg, pos_off, padded row-block size
     const int32_t *sig_pos_ptr;
     const int32_t *sig_contrib;
@@ -102,8 +103,6 @@ hipError_t launch_finalize(const double *partials, int n, int with_f, double *c,
 // of the current device's copy (device must be current)
 constexpr int kNoAllocBlocks = 8192;
 hipError_t noalloc_scratch(int device, double **out);
-// dst[r] = src[idx[r]], r < n, elements of elem_bytes (8: double, 4: float)
-hipError_t launch_gather(int elem_bytes, const void *src, const int32_t *idx, void *dst, int64_t n, hipStream_t st);
 
 // solve (node-block Jacobi preconditioned CG); nb = neighbour lists, K's block structure
 int64_t spmv_blocks(int dim, int64_t n_nodes);

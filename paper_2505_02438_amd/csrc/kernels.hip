@@ -684,7 +684,10 @@ __global__ __launch_bounds__(kAsmThreads, 1) void k_assemble(AsmParams P) {
 #pragma unroll
                     for (int c = 0; c <= D2; c++) q.pd[h][c] = P.geo[(int64_t)c * NC + id.e[h]];
                 }
-                q.prho[h] = static_cast<const R *>(P.rho)[id.e[h]];
+                // a canonical-order plan's slots are ranks: the density is
+                // read through the rank -> element map
+                const int er = P.elem_by_rank ? P.elem_by_rank[id.e[h]] : id.e[h];
+                q.prho[h] = static_cast<const R *>(P.rho)[er];
             }
 #pragma unroll
         for (int r = 0; r < NPF; r++)
@@ -855,7 +858,8 @@ __global__ __launch_bounds__(OsShape<DIM>::threads) void k_assemble_os(AsmParams
 #pragma unroll
         for (int h = 0; h < 2; h++)
             if (e[h] >= 0) {
-                rr[h] = (double)static_cast<const R *>(P.rho)[e[h]];
+                const int eo = P.elem_by_rank ? P.elem_by_rank[e[h]] : e[h];
+                rr[h] = (double)static_cast<const R *>(P.rho)[eo];
                 gd[h][D2] = P.geo[(int64_t)D2 * NC + e[h]];
                 if (gflags & kGrpDiag) {
 #pragma unroll
@@ -1395,18 +1399,6 @@ __global__ __launch_bounds__(256) void k_backward(BwdParams P) {
     store_out<PREC>(P.drho, e, dE * det * acc);
 }
 
-// ------------------------------------------------ densities in rank order
-//
-// dst[r] = src[idx[r]] (element data of a canonical-order plan: the
-// assembly then reads the densities of a group's elements from neighbouring
-// addresses).  T: double or float.
-template <typename T>
-__global__ __launch_bounds__(256) void k_gather(const T *__restrict__ src, const int32_t *__restrict__ idx,
-                                                T *__restrict__ dst, int64_t n) {
-    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (r < n) dst[r] = src[idx[r]];
-}
-
 // ---------------------------------------------------------------- launchers
 
 template <int DIM, int NEN, int PREC, bool FUSE>
@@ -1628,18 +1620,6 @@ hipError_t noalloc_scratch(int device, double **out) {
     g_scratch_ptr[device] = static_cast<double *>(p);
     *out = static_cast<double *>(p);
     return hipSuccess;
-}
-
-hipError_t launch_gather(int elem_bytes, const void *src, const int32_t *idx, void *dst, int64_t n, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    const dim3 grid((unsigned)((n + 255) / 256));
-    if (elem_bytes == 8)
-        hipLaunchKernelGGL(k_gather<double>, grid, dim3(256), 0, st, static_cast<const double *>(src), idx,
-                           static_cast<double *>(dst), n);
-    else
-        hipLaunchKernelGGL(k_gather<float>, grid, dim3(256), 0, st, static_cast<const float *>(src), idx,
-                           static_cast<float *>(dst), n);
-    return hipGetLastError();
 }
 
 }  // namespace soptx

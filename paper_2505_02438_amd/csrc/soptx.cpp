@@ -366,9 +366,8 @@ int soptx_pattern_stats_get(soptx_pattern h, soptx_pattern_stats *out) {
 }
 
 // Parameters of the assembly kernel.  A canonical-order plan reads its
-// element data in rank order: geo_rank, and the densities gathered into rank
-// order first (a workspace of the stream, so calls on other streams keep
-// theirs).
+// geometry in rank order (geo_rank, built with the plan) and the caller's
+// densities through its rank -> element map.
 static int asm_params(soptx_pattern h, const soptx_material *m, const void *d_rho, double *d_K_vals, int32_t prec,
                       hipStream_t st, AsmParams &P) {
     P.grp_info = h->grp_info; P.grp_nodes = h->grp_nodes; P.grp_elems = h->grp_elems; P.grp_n2l = h->grp_n2l;
@@ -378,14 +377,10 @@ static int asm_params(soptx_pattern h, const soptx_material *m, const void *d_rh
     P.sig_pairs = h->sig_pairs; P.sig_witems = h->sig_witems; P.sig_witem_ptr = h->sig_witem_ptr;
     P.geo = h->geo; P.rho = d_rho;
     if (h->elem_by_rank) {
-        double *ws = nullptr;
-        const size_t bytes = (size_t)h->n_cells * (prec == SOPTX_FP64 ? 8 : 4);
-        int rc = get_workspace(h->device, st, (bytes + 7) / 8, &ws, 5);
-        if (rc) return rc;
-        if (launch_gather(prec == SOPTX_FP64 ? 8 : 4, d_rho, h->elem_by_rank, ws, h->n_cells, st) != hipSuccess)
-            return SOPTX_E_DEVICE;
+        // canonical order: the geometry columns in rank order (a copy made
+        // with the plan); the densities read through the rank -> element map
         P.geo = h->geo_rank;
-        P.rho = ws;
+        P.elem_by_rank = h->elem_by_rank;
     }
     P.M = h->M; P.M32 = h->M32; P.K = d_K_vals;
     P.n_cells = h->n_cells; P.E0 = m->E0; P.Emin = m->Emin; P.p = m->p; P.ip = int_exponent(m->p);

@@ -54,8 +54,8 @@ def test_graph_replays_equal_eager(elem):
 @pytest.mark.parametrize("elem,renumber", [(I.QUAD4, False), (I.TRI3, False), (I.HEX8, False), (I.TET10, False),
                                            (I.HEX8, True)])
 def test_graph_replays_of_the_fused_step(elem, renumber, variant):
-    """soptx_step (the bound Dirichlet table; for a renumbered mesh also the
-    density gather into rank order) captured in a HIP graph: every replay,
+    """soptx_step (the bound Dirichlet table; for a renumbered mesh the rank
+    tables and the densities read through the rank map) captured in a HIP graph: every replay,
     with eager work between replays, gives the eager results bit for bit,
     with either assembly kernel (forced through the debug hook)."""
     from paper_2505_02438_amd import _lib
@@ -105,11 +105,11 @@ def _fused_step_graph(elem, renumber):
 
 
 def test_graph_replays_after_the_workspace_grew():
-    """A fused step captured on a small renumbered mesh (its graph holds the
-    stream's workspace addresses: the compliance partials and the densities
-    in rank order); then a step on a larger mesh on the same stream, which
-    needs larger workspaces; the earlier graph's replays still give its eager
-    results bit for bit (the replaced workspaces are kept, not freed)."""
+    """A fused step captured on a small mesh (its graph holds the stream's
+    workspace address of the compliance partials); then a step on a larger
+    mesh on the same stream, which needs a larger workspace; the earlier
+    graph's replays still give its eager results bit for bit (the replaced
+    workspace is kept, not freed)."""
     pr = I.renumber(I.small_problem(I.HEX8, seed=43, dims=(6, 5, 4)), 44)
     m = pr.mesh
     pat = api.Pattern.from_mesh(m)
@@ -131,14 +131,17 @@ def test_graph_replays_after_the_workspace_grew():
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=st):
         step()
-    # a larger renumbered mesh on the same stream: larger workspaces
-    pr2 = I.renumber(I.small_problem(I.HEX8, seed=45, dims=(40, 30, 20)), 46)
-    pat2 = api.Pattern.from_mesh(pr2.mesh)
-    assert pat2.n_cells > 8 * 256 and pat2.stats()["n_groups_ranked"] > 0
-    bc2 = api.Dirichlet(pat2, pr2.mask)
-    K2, dc2, c2 = pat2.step(MAT, dev(pr2.rho), dev(pr2.u), dev(pr2.f), bc=bc2, stream=st)
+    # a larger mesh on the same stream: more than 2048 energy blocks, so the
+    # partials need more than the workspace's first 4096 doubles
+    m2 = I.hex_grid(100, 80, 70)
+    assert (m2.n_cells + 255) // 256 > 2048
+    pat2 = api.Pattern.from_mesh(m2)
+    rng = np.random.default_rng(45)
+    K2, dc2, c2 = pat2.step(MAT, dev(rng.uniform(0.1, 1.0, m2.n_cells)), dev(rng.standard_normal(pat2.ndof)),
+                            dev(rng.standard_normal(pat2.ndof)), stream=st)
     torch.cuda.synchronize()
     assert np.isfinite(host(c2)).all()
+    del K2, dc2, c2, pat2
     for rep in range(3):
         K.fill_(np.nan)
         dc.fill_(np.nan)
