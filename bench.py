@@ -241,9 +241,10 @@ def general_run(stream, reps=20):
     cantilever's 120 x 40 x 40 cells with every interior node moved by
     U(-0.2, 0.2) per coordinate (seed 54), rho of the main workload, FP64,
     Dirichlet rows; HIP events on the bench stream."""
+    import ctypes
     import numpy as np
     import torch
-    from paper_2505_02438_amd import api
+    from paper_2505_02438_amd import _lib, api
     from paper_2505_02438_amd import inputs as I
     pr = I.cantilever_hex()
     m = I.jitter_interior(pr.mesh, 0.2, np.random.default_rng(54))
@@ -254,16 +255,27 @@ def general_run(stream, reps=20):
     rho = torch.from_numpy(pr.rho).cuda()
     mask = torch.from_numpy(pr.mask).cuda()
     K = torch.empty(pat.nnz, dtype=torch.float64, device="cuda")
-    torch.cuda.synchronize()
-    ms = []
-    for r in range(reps + 3):
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        pat.assemble_general(mat, rho, mask, out=K, stream=stream)
-        b.record(stream)
-        torch.cuda.synchronize()
-        ms.append(a.elapsed_time(b))
-    avg = statistics.mean(ms[3:]) / 1e3
+    L = _lib.lib()
+    in_lds = ctypes.c_int32(-1)
+
+    def time_assembly(variant):
+        _lib.check(L.soptx_debug_set_general_variant(variant), "general variant")
+        try:
+            _lib.check(L.soptx_debug_general_path(pat._h, ctypes.byref(in_lds)), "general path")
+            torch.cuda.synchronize()
+            ms = []
+            for r in range(reps + 3):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                pat.assemble_general(mat, rho, mask, out=K, stream=stream)
+                b.record(stream)
+                torch.cuda.synchronize()
+                ms.append(a.elapsed_time(b))
+        finally:
+            L.soptx_debug_set_general_variant(-1)
+        return statistics.mean(ms[3:]) / 1e3, in_lds.value
+    avg_ke, _ = time_assembly(0)
+    avg, form = time_assembly(-1)
     u = torch.from_numpy(pr.u).cuda()
     dc = torch.empty(m.n_cells, dtype=torch.float64, device="cuda")
     c = torch.zeros(2, dtype=torch.float64, device="cuda")
@@ -279,8 +291,11 @@ def general_run(stream, reps=20):
     ev_avg = statistics.mean(ev[3:]) / 1e3
     kbytes = pat.nnz * 8
     return {"mesh": "120x40x40 hexahedra, interior nodes jittered by 0.2", "elements": m.n_cells,
+            "form": "in LDS on the plan's node groups (k_assemble_quad)" if form == 1 else
+                    "element matrices through memory (k_ke_general, k_gather_general)",
             "avg_ms": avg * 1e3, "elements_per_s": m.n_cells / avg, "K_bytes": kbytes,
-            "K_write_GBs": kbytes / avg / 1e9, "evaluate_avg_ms": ev_avg * 1e3,
+            "K_write_GBs": kbytes / avg / 1e9, "element_matrix_form_avg_ms": avg_ke * 1e3,
+            "evaluate_avg_ms": ev_avg * 1e3,
             "step_elements_per_s": m.n_cells / (avg + ev_avg), "pattern_build_s": build_s}
 
 

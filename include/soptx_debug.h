@@ -33,7 +33,10 @@ int soptx_debug_host_plan_ex(const soptx_mesh *mesh, int32_t general, soptx_host
 /* Borrow one array of the plan by name: "row_ptr", "col_idx" (int32 CSR),
  * "geo" (double, [(dim*dim+1)][n_cells]: J^-1 row-major then det J),
  * "sig_info", "sig_pos_ptr", "sig_contrib", "sig_pairs", "sig_witems", "sig_witem_ptr", "grp_info", "grp_nodes",
- * "grp_elems", "grp_rows", "nb_tslot" (int32), "grp_n2l", "pos", "nb_tdeg" (uint16).
+ * "grp_elems", "grp_rows", "nb_tslot" (int32), "grp_n2l", "pos", "nb_tdeg" (uint16); for
+ * general plans "gptr", "gent", "gnode" (int32) and, for Q1 elements, "qgeo"
+ * (double, [NQ][dim][dim][n_cells]: sqrt(w_q |det J_q|) J_q^-1 at Gauss point
+ * q per plan column, the element or, in a canonical-order plan, its rank).
  * The pointer stays valid until soptx_debug_host_plan_free. */
 int soptx_debug_host_plan_array(soptx_host_plan p, const char *name, const void **data, int64_t *count,
                                 int32_t *elem_bytes);
@@ -69,6 +72,22 @@ int soptx_debug_fail_workers(int32_t n);
  * kernel otherwise), 0 = the persistent kernel, 1 = one workgroup per node
  * group.  All give bitwise the same K.  SOPTX_E_INVALID_ARG for other values. */
 int soptx_debug_set_assembly_variant(int32_t v);
+
+/* Test hook: how soptx_assemble_general assembles Q1 elements whose map is
+ * not affine, process-wide: -1 (default) = in LDS, by one workgroup per node
+ * group of the plan with the Jacobian at every Gauss point (no element
+ * matrices in memory), where the plan's largest group fits the kernel's LDS;
+ * 0 = every element matrix written to device memory, then one gather per
+ * block of K.  Both sum each block's contributions in ascending element
+ * order; they differ in rounding only.  Q2 hexahedra always take the second
+ * form.  SOPTX_E_INVALID_ARG for other values. */
+int soptx_debug_set_general_variant(int32_t v);
+
+/* Whether soptx_assemble_general on handle h (built by
+ * soptx_build_pattern_general) runs the in-LDS form under the current
+ * variant: *in_lds = 1, else 0.  SOPTX_E_INVALID_ARG for a null argument or
+ * a handle without the general tables. */
+int soptx_debug_general_path(soptx_pattern h, int32_t *in_lds);
 
 #ifdef __cplusplus
 }

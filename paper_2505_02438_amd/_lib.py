@@ -102,6 +102,8 @@ def lib():
         "soptx_debug_host_plan_scalars": [_P, _P],
         "soptx_debug_fail_workers": [_I32],
         "soptx_debug_set_assembly_variant": [_I32],
+        "soptx_debug_set_general_variant": [_I32],
+        "soptx_debug_general_path": [_P, ctypes.POINTER(_I32)],
         "soptx_debug_filter_matrix": [ctypes.POINTER(Mesh), ctypes.c_double, ctypes.POINTER(_I64),
                                       ctypes.POINTER(_I64), _P, _P, _P, _P, _P, _P],
         "soptx_oc_update": [_I64, _P, _P, _P, ctypes.c_double, ctypes.POINTER(OcParams), _P,

@@ -70,11 +70,11 @@ def host_plan(elem: int, coords, cells, general: bool = False) -> dict:
         for name in ("row_ptr", "col_idx", "geo", "sig_info", "sig_pos_ptr", "sig_contrib", "sig_pairs", "sig_witems", "sig_witem_ptr",
                      "grp_info", "grp_nodes", "grp_elems", "grp_n2l", "grp_rows", "grp_rank_off", "grp_rank", "elem_by_rank", "pos", "nb_tslot",
                      "nb_tdeg",
-                     "gptr", "gent", "gnode"):
+                     "gptr", "gent", "gnode", "qgeo"):
             ptr, cnt, eb = ctypes.c_void_p(), ctypes.c_int64(), ctypes.c_int32()
             check(L.soptx_debug_host_plan_array(h, name.encode(), ctypes.byref(ptr), ctypes.byref(cnt),
                                                 ctypes.byref(eb)), name)
-            dtype = np.float64 if name == "geo" else dt[eb.value]
+            dtype = np.float64 if name in ("geo", "qgeo") else dt[eb.value]
             if cnt.value == 0:
                 out[name] = np.zeros(0, dtype=dtype)
             else:

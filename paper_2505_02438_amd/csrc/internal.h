@@ -110,6 +110,10 @@ struct HostPlan {
     std::vector<int32_t> gptr;   // [nnz / dim^2 + 1]
     std::vector<int32_t> gent;   // [n_cells * nen^2]
     std::vector<int32_t> gnode;  // [nnz / dim^2]
+    // general Q1 elements only: per plan column (the element, or its rank in a
+    // canonical plan) and Gauss point q, sqrt(w_q |det J_q|) J_q^-1,
+    // [NQ][dim][dim][n_cells]
+    std::vector<double> qgeo;
     int64_t n_groups() const { return (int64_t)grp_info.size() / kGrpInfo; }
     int64_t n_sigs() const { return (int64_t)sig_info.size() / 4; }
 };

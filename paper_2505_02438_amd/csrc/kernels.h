@@ -48,6 +48,12 @@ struct AsmParams {
     int fin_n;
     int fin_with_f;
     double *fin_c;
+    // Q1 elements with per-point geometry (k_assemble_quad) only: per plan
+    // column, sqrt(w_q |det J_q|) J_q^-1 at each Gauss point of the 2-point
+    // rule on [0, 1]^DIM ([NQ][DIM][DIM][n_cells], entry (q, m, a) = d xi_m /
+    // d x_a; point q at xi_m = (1 + 1/sqrt(3)) / 2 where bit m of q is set,
+    // else (1 - 1/sqrt(3)) / 2)
+    const double *qgeo;
 };
 
 struct EnergyParams {
@@ -142,6 +148,12 @@ struct GenParams {
     int64_t n_blocks;
 };
 hipError_t launch_assemble_general(int elem, const GenParams &G, hipStream_t st);
+// Q1 elements whose map is not affine, assembled in LDS from per-point
+// geometry (P.qgeo, P.qref) on the plan's node groups, no element matrices in
+// memory; FP64, no Dirichlet rows.  assemble_quad_fits: whether a plan's
+// largest group fits the kernel's LDS (else the element-matrix path runs).
+bool assemble_quad_fits(int elem, int64_t stage, int kmax);
+hipError_t launch_assemble_quad(int elem, const AsmParams &P, int64_t ngroups, hipStream_t st);
 // elements per block (and per c partial) of the Q2 hexahedron's energy kernel;
 // the other elements take 256
 constexpr int kEnergyWideElems = 16;

@@ -181,25 +181,61 @@ __device__ __forceinline__ double dirichlet_entry(int bits, int a, int c, double
     return v;
 }
 
+// Geometry held per element slot of a group in LDS: G' (kGeoFull), its
+// diagonal for an axis-aligned group (kGeoDiag), or for Q1 elements whose map
+// is not affine the scaled physical gradients of the element's nodes at QP
+// Gauss points, GEOM = kGeoPoint + QP (FP64 only)
+constexpr int kGeoFull = 0, kGeoDiag = 1, kGeoPoint = 16;
+// passes of the per-point form over its Gauss points: a pass after the first
+// starts each block from the partial sum in the stage (kPassInit); the last
+// applies L and writes the block (kPassFinal), the others write the raw sum
+constexpr int kPassInit = 1, kPassFinal = 2;
+
+// One contribution of an element slot with per-point geometry, local pair
+// (i, j), added to acc when ok: sum over the QP points q of the pass, in
+// order, of g_i(q) g_j(q)^T, with g_k(q) = sqrt(E w_q |det J_q|) J_q^-T grad
+// phi_k(xi_q) held in Gs ([QP][NEN][DIM][kGroupElems]).  The LDS reads
+// happen whether or not ok.
+template <int DIM, int NEN, int QP>
+__device__ __forceinline__ void contribute_point(const double *Gs, int slot, int i, int j, bool ok,
+                                                 double (&acc)[DIM][DIM]) {
+#pragma unroll
+    for (int q = 0; q < QP; q++) {
+        double gi[DIM], gj[DIM];
+#pragma unroll
+        for (int a = 0; a < DIM; a++) {
+            gi[a] = Gs[((q * NEN + i) * DIM + a) * kGroupElems + slot];
+            gj[a] = Gs[((q * NEN + j) * DIM + a) * kGroupElems + slot];
+        }
+        if (ok) {
+#pragma unroll
+            for (int a = 0; a < DIM; a++)
+#pragma unroll
+                for (int c = 0; c < DIM; c++) acc[a][c] = fma(gi[a], gj[c], acc[a][c]);
+        }
+    }
+}
+
 // ---- the roles' work on one group, shared by the persistent kernel
-// (k_assemble) and the one-workgroup-per-group kernel (k_assemble_os).  The
-// group's data in LDS: hdr (nn, deg, posoff, blk, flags, first wide work
-// item, number of wide work items, Dirichlet-bits offset, rank-table offset),
-// stage (its row blocks, blk doubles per node), sG (G' per element slot,
-// [D2][kGroupElems], or the diagonal G'_aa for an axis-aligned group), sM
-// (the reference tensor), sn2l (slot of element k of each node, [K][32]);
-// ticket counts the group's work items.  DIAG: the group is axis-aligned
-// (decided once per group, so the contraction loop has no branch on it).
+// (k_assemble), the one-workgroup-per-group kernel (k_assemble_os) and the
+// per-point kernel (k_assemble_quad).  The group's data in LDS: hdr (nn,
+// deg, posoff, blk, flags, first wide work item, number of wide work items,
+// Dirichlet-bits offset, rank-table offset), stage (its row blocks, blk
+// doubles per node), sG (the slots' geometry in the layout of GEOM), sM (the
+// reference tensor, or the reference gradients at the Gauss points), sn2l
+// (slot of element k of each node, [K][32]); ticket counts the group's work
+// items.  GEOM is decided once per group, so the contraction loop has no
+// branch on it.
 
 // ---- compute role, wide work items (groups of at most N = 8 or 16
 // nodes): lane = (pp Q + q) N + node takes position p[pp] of the item and
 // its contributions q, q + Q, ...; the Q phases of a position are then
 // added by a butterfly over the phase bits of the lane index (a fixed
 // order), and phase 0 writes the block
-template <int DIM, int NEN, int PREC, bool FUSE, bool DIAG>
+template <int DIM, int NEN, int PREC, bool FUSE, int GEOM>
 __device__ __forceinline__ void assemble_wide(const AsmParams &P, const int *hdr, int *ticket, double *stage,
                                               const typename CT<PREC>::T *sG, const typename CT<PREC>::T *sM,
-                                              const uint16_t *sn2l, int lane) {
+                                              const uint16_t *sn2l, int lane, int pmode = kPassFinal) {
     using T = typename CT<PREC>::T;
     constexpr int D2 = DIM * DIM;
     constexpr int NG = kGroupNodes;
@@ -247,6 +283,14 @@ __device__ __forceinline__ void assemble_wide(const AsmParams &P, const int *hdr
         for (int a = 0; a < DIM; a++)
 #pragma unroll
             for (int c = 0; c < DIM; c++) acc[a][c] = 0.0;
+        if constexpr (GEOM > kGeoPoint) {
+            // a later pass over the Gauss points: the block's partial sum so far
+            if ((pmode & kPassInit) && mine && q == 0)
+#pragma unroll
+                for (int a = 0; a < DIM; a++)
+#pragma unroll
+                    for (int c = 0; c < DIM; c++) acc[a][c] = st[a * rl + DIM * pcsr + c];
+        }
         // contributions of this lane: all loads first (nt <= 8)
         int pk[8];
 #pragma unroll
@@ -260,27 +304,31 @@ __device__ __forceinline__ void assemble_wide(const AsmParams &P, const int *hdr
             if (pk[t] >= 0) {
                 const int k = pk[t] >> 16, i = (pk[t] >> 8) & 255, j = pk[t] & 255;
                 const int slot = n2l[k * NG];
-                const T *Mij = sM + (i * NEN + j) * D2;
-                T Mv[D2];
-#pragma unroll
-                for (int x = 0; x < D2; x++) Mv[x] = Mij[x];
-                if constexpr (DIAG) {
-                    T dd[DIM][DIM];
-#pragma unroll
-                    for (int a = 0; a < DIM; a++)
-#pragma unroll
-                        for (int c = a; c < DIM; c++) {
-                            dd[a][c] = diag_product<PREC>(G[a * kGroupElems + slot], G[c * kGroupElems + slot]);
-                            dd[c][a] = dd[a][c];
-                        }
-                    accumulate_diag<DIM, PREC>(dd, Mv, acc);
+                if constexpr (GEOM > kGeoPoint) {
+                    contribute_point<DIM, NEN, GEOM - kGeoPoint>(G, slot, i, j, true, acc);
                 } else {
-                    T Gv[DIM][DIM];
+                    const T *Mij = sM + (i * NEN + j) * D2;
+                    T Mv[D2];
 #pragma unroll
-                    for (int m = 0; m < DIM; m++)
+                    for (int x = 0; x < D2; x++) Mv[x] = Mij[x];
+                    if constexpr (GEOM == kGeoDiag) {
+                        T dd[DIM][DIM];
 #pragma unroll
-                        for (int a = 0; a < DIM; a++) Gv[m][a] = G[(m * DIM + a) * kGroupElems + slot];
-                    accumulate<DIM, PREC>(Gv, Mv, acc);
+                        for (int a = 0; a < DIM; a++)
+#pragma unroll
+                            for (int c = a; c < DIM; c++) {
+                                dd[a][c] = diag_product<PREC>(G[a * kGroupElems + slot], G[c * kGroupElems + slot]);
+                                dd[c][a] = dd[a][c];
+                            }
+                        accumulate_diag<DIM, PREC>(dd, Mv, acc);
+                    } else {
+                        T Gv[DIM][DIM];
+#pragma unroll
+                        for (int m = 0; m < DIM; m++)
+#pragma unroll
+                            for (int a = 0; a < DIM; a++) Gv[m][a] = G[(m * DIM + a) * kGroupElems + slot];
+                        accumulate<DIM, PREC>(Gv, Mv, acc);
+                    }
                 }
             }
         }
@@ -289,6 +337,16 @@ __device__ __forceinline__ void assemble_wide(const AsmParams &P, const int *hdr
             for (int a = 0; a < DIM; a++)
 #pragma unroll
                 for (int c = 0; c < DIM; c++) acc[a][c] += __shfl_xor(acc[a][c], sh);
+        if constexpr (GEOM > kGeoPoint) {
+            if (!(pmode & kPassFinal)) {
+                if (mine && q == 0)
+#pragma unroll
+                    for (int a = 0; a < DIM; a++)
+#pragma unroll
+                        for (int c = 0; c < DIM; c++) st[a * rl + DIM * pcsr + c] = acc[a][c];
+                continue;
+            }
+        }
         if (mine && q == 0) {
             double tr = 0.0;
 #pragma unroll
@@ -307,10 +365,10 @@ __device__ __forceinline__ void assemble_wide(const AsmParams &P, const int *hdr
 }
 
 // compute role, work items of position pairs (groups of up to 32 nodes)
-template <int DIM, int NEN, int PREC, bool FUSE, bool DIAG>
+template <int DIM, int NEN, int PREC, bool FUSE, int GEOM>
 __device__ __forceinline__ void assemble_pairs(const AsmParams &P, const int *hdr, int *ticket, double *stage,
                                                const typename CT<PREC>::T *sG, const typename CT<PREC>::T *sM,
-                                               const uint16_t *sn2l, int lane) {
+                                               const uint16_t *sn2l, int lane, int pmode = kPassFinal) {
     using T = typename CT<PREC>::T;
     constexpr int D2 = DIM * DIM;
     constexpr int NG = kGroupNodes;
@@ -360,6 +418,15 @@ __device__ __forceinline__ void assemble_pairs(const AsmParams &P, const int *hd
         for (int a = 0; a < DIM; a++)
 #pragma unroll
             for (int c = 0; c < DIM; c++) acc[a][c] = 0.0;
+        if constexpr (GEOM > kGeoPoint) {
+            // a later pass over the Gauss points: the block's partial sum so
+            // far, in the lane that writes the block
+            if ((pmode & kPassInit) && node < nn && pme >= 0 && !(split && hi))
+#pragma unroll
+                for (int a = 0; a < DIM; a++)
+#pragma unroll
+                    for (int c = 0; c < DIM; c++) acc[a][c] = st[a * rl + DIM * pcsr + c];
+        }
         // nlo >= nhi: the low half has the longer list.  The codes of a chunk
         // of 8 contributions of each half are read by scalar loads before the
         // chunk's LDS reads (scalar loads and LDS reads share one wait
@@ -381,27 +448,31 @@ __device__ __forceinline__ void assemble_pairs(const AsmParams &P, const int *hd
                 const int code = oku ? (hi && nhi > 0 ? ch[u] : cl[u]) : 0;
                 const int k = code >> 16, i = (code >> 8) & 255, j = code & 255;
                 const int slot = n2l[k * NG];
-                const T *Mij = sM + (i * NEN + j) * D2;
-                T Mv[D2];
-#pragma unroll
-                for (int x = 0; x < D2; x++) Mv[x] = Mij[x];
-                if constexpr (DIAG) {
-                    T dd[DIM][DIM];
-#pragma unroll
-                    for (int a = 0; a < DIM; a++)
-#pragma unroll
-                        for (int c = a; c < DIM; c++) {
-                            dd[a][c] = diag_product<PREC>(G[a * kGroupElems + slot], G[c * kGroupElems + slot]);
-                            dd[c][a] = dd[a][c];
-                        }
-                    if (oku) accumulate_diag<DIM, PREC>(dd, Mv, acc);
+                if constexpr (GEOM > kGeoPoint) {
+                    contribute_point<DIM, NEN, GEOM - kGeoPoint>(G, slot, i, j, oku, acc);
                 } else {
-                    T Gv[DIM][DIM];
+                    const T *Mij = sM + (i * NEN + j) * D2;
+                    T Mv[D2];
 #pragma unroll
-                    for (int m = 0; m < DIM; m++)
+                    for (int x = 0; x < D2; x++) Mv[x] = Mij[x];
+                    if constexpr (GEOM == kGeoDiag) {
+                        T dd[DIM][DIM];
 #pragma unroll
-                        for (int a = 0; a < DIM; a++) Gv[m][a] = G[(m * DIM + a) * kGroupElems + slot];
-                    if (oku) accumulate<DIM, PREC>(Gv, Mv, acc);
+                        for (int a = 0; a < DIM; a++)
+#pragma unroll
+                            for (int c = a; c < DIM; c++) {
+                                dd[a][c] = diag_product<PREC>(G[a * kGroupElems + slot], G[c * kGroupElems + slot]);
+                                dd[c][a] = dd[a][c];
+                            }
+                        if (oku) accumulate_diag<DIM, PREC>(dd, Mv, acc);
+                    } else {
+                        T Gv[DIM][DIM];
+#pragma unroll
+                        for (int m = 0; m < DIM; m++)
+#pragma unroll
+                            for (int a = 0; a < DIM; a++) Gv[m][a] = G[(m * DIM + a) * kGroupElems + slot];
+                        if (oku) accumulate<DIM, PREC>(Gv, Mv, acc);
+                    }
                 }
             }
         }
@@ -412,6 +483,16 @@ __device__ __forceinline__ void assemble_pairs(const AsmParams &P, const int *hd
             for (int a = 0; a < DIM; a++)
 #pragma unroll
                 for (int c = 0; c < DIM; c++) acc[a][c] += __shfl_xor(acc[a][c], NG);
+        }
+        if constexpr (GEOM > kGeoPoint) {
+            if (!(pmode & kPassFinal)) {
+                if (node < nn && pme >= 0 && !(split && hi))
+#pragma unroll
+                    for (int a = 0; a < DIM; a++)
+#pragma unroll
+                        for (int c = 0; c < DIM; c++) st[a * rl + DIM * pcsr + c] = acc[a][c];
+                continue;
+            }
         }
         double tr = 0.0;
 #pragma unroll
@@ -440,12 +521,13 @@ __device__ __forceinline__ void assemble_group(const AsmParams &P, const int *hd
     constexpr bool kMayDiag = NEN == (1 << DIM);
     const int flags = wave_uniform(hdr[4]);
     const bool diag = kMayDiag && (flags & kGrpDiag);
+    constexpr int kDiag = kMayDiag ? kGeoDiag : kGeoFull;
     if (flags >> kGrpWideShift) {
-        if (diag) assemble_wide<DIM, NEN, PREC, FUSE, kMayDiag>(P, hdr, ticket, stage, sG, sM, sn2l, lane);
-        else assemble_wide<DIM, NEN, PREC, FUSE, false>(P, hdr, ticket, stage, sG, sM, sn2l, lane);
+        if (diag) assemble_wide<DIM, NEN, PREC, FUSE, kDiag>(P, hdr, ticket, stage, sG, sM, sn2l, lane);
+        else assemble_wide<DIM, NEN, PREC, FUSE, kGeoFull>(P, hdr, ticket, stage, sG, sM, sn2l, lane);
     } else {
-        if (diag) assemble_pairs<DIM, NEN, PREC, FUSE, kMayDiag>(P, hdr, ticket, stage, sG, sM, sn2l, lane);
-        else assemble_pairs<DIM, NEN, PREC, FUSE, false>(P, hdr, ticket, stage, sG, sM, sn2l, lane);
+        if (diag) assemble_pairs<DIM, NEN, PREC, FUSE, kDiag>(P, hdr, ticket, stage, sG, sM, sn2l, lane);
+        else assemble_pairs<DIM, NEN, PREC, FUSE, kGeoFull>(P, hdr, ticket, stage, sG, sM, sn2l, lane);
     }
 }
 
@@ -903,6 +985,177 @@ __global__ __launch_bounds__(OsShape<DIM>::threads) void k_assemble_os(AsmParams
 
     assemble_group<DIM, NEN, PREC, FUSE>(P, shdr, &ticket, stage, sG, sM, sn2l, lane);
     __syncthreads();
+    store_rows<DIM, kStoreWaves>(P, shdr, srows, stage, w, lane);
+}
+
+// Gauss points and reference gradients of Q1 elements on [0, 1]^DIM with the
+// 2-point rule per axis: point q has coordinate xi_m = gp if bit m of q is
+// set, else gm (gp, gm = (1 +- 1/sqrt(3)) / 2, weights 1 / 2^DIM); node k
+// sits at corner bits q1_corner(k) (bit m: coordinate m): quadrilateral
+// (0,0) (1,0) (1,1) (0,1), the
+// hexahedron's bottom face in that order then its top face.  d phi_k / d xi_m
+// = s_km prod_{n != m} (xi_n if bit n of k else 1 - xi_n), s_km = +1 if bit m
+// of k else -1; the factor for axis n is gp where the bits of k and q agree
+// on n, gm where they differ.
+__host__ __device__ constexpr int q1_corner(int k) { return k ^ ((k >> 1) & 1); }
+constexpr double kQ1Gp = 0.78867513459481288225457439025098;
+constexpr double kQ1Gm = 0.21132486540518711774542560974902;
+
+// Assembly of Q1 elements whose map is not affine, where the element matrix
+// is K_e^0(i,j) = sum_q w_q |det J_q| L(g_i g_j^T) with g = J_q^-T grad phi
+// at each Gauss point q.  One workgroup per node group of the same plan as
+// k_assemble: the signatures' work items, the element order of the
+// contributions, the stage and the row stores are the same.  An element
+// slot's geometry is, per Gauss point, g_k(q) = sqrt(E(rho)) G'_q^T grad
+// phi_k(xi_q) for its NEN nodes, with G'_q = sqrt(w_q |det J_q|) J_q^-1 read
+// from qgeo (the per-mesh part), so a contribution is sum_q g_i(q) g_j(q)^T.
+// The points are taken QP at a time (LDS holds the gradients of QP points):
+// each pass forms the gradients of its points for every slot, then adds its
+// points' terms of every contribution to the block's sum in the stage; the
+// last pass applies L.  A block's sum: the passes in order; in a pass, the
+// contributions in the plan's order, each over the pass's points in order.
+// No element matrix is written to memory.  FP64; Dirichlet rows and columns
+// are applied by k_dirichlet afterwards.
+template <int DIM>
+struct QuadShape {
+    static constexpr int threads = DIM == 2 ? 256 : 1024;
+    static constexpr int qp = DIM == 2 ? 4 : 3;  // Gauss points per pass
+};
+
+template <int DIM, int NEN>
+__global__ __launch_bounds__(QuadShape<DIM>::threads) void k_assemble_quad(AsmParams P) {
+    constexpr int kThreads = QuadShape<DIM>::threads;
+    constexpr int QP = QuadShape<DIM>::qp;
+    constexpr int D2 = DIM * DIM;
+    constexpr int NQ = 1 << DIM;
+    constexpr int NPASS = (NQ + QP - 1) / QP;
+    constexpr int QLAST = NQ - (NPASS - 1) * QP;  // points of the last pass
+    constexpr int NG = kGroupNodes;
+    constexpr int kStoreWaves = kThreads / 64;
+    static_assert(NEN == NQ, "Q1 elements");
+    static_assert(kGroupElems <= kThreads, "one thread per slot");
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *stage = reinterpret_cast<double *>(smem);               // [P.stage]
+    double *sg = stage + P.stage;                                                         // [QP][NEN][DIM][kGroupElems]
+    int32_t *srows = reinterpret_cast<int32_t *>(sg + QP * NEN * DIM * kGroupElems);     // [NG][2]
+    uint16_t *sn2l = reinterpret_cast<uint16_t *>(srows + NG * 2);  // [kmax][NG]
+    __shared__ int ticket;
+    __shared__ int shdr[9];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = wave_uniform(tid >> 6);
+    const int64_t NC = P.n_cells;
+    const int ngr = P.n_groups;
+    const int W = P.os_window;
+    const int bid = blockIdx.x;
+    const int base = bid - bid % W;
+    const int gg = base + W <= ngr ? base + (bid % 8) * (W / 8) + (bid - base) / 8 : bid;
+    if (gg >= ngr) return;
+    const int sg_ = wave_uniform(ldc(P.grp_info, kGrpInfo * gg + 0));
+    const int eoff = wave_uniform(ldc(P.grp_info, kGrpInfo * gg + 2));
+    const int ne = wave_uniform(ldc(P.grp_info, kGrpInfo * gg + 3));
+    const int n2off = wave_uniform(ldc(P.grp_info, kGrpInfo * gg + 4));
+    const int gflags = wave_uniform(ldc(P.grp_info, kGrpInfo * gg + 5));
+    const int nk = wave_uniform(ldc(P.sig_info, 4 * sg_ + 0)) * NG;
+    for (int x = tid; x < nk; x += kThreads) sn2l[x] = P.grp_n2l[n2off + x];
+    if (tid < 2 * NG) srows[tid] = P.grp_rows[(int64_t)gg * 2 * NG + tid];
+    if (tid == 0) {
+        shdr[0] = ldc(P.grp_info, kGrpInfo * gg + 1);
+        shdr[1] = ldc(P.sig_info, 4 * sg_ + 1);
+        shdr[2] = ldc(P.sig_info, 4 * sg_ + 2);
+        shdr[3] = ldc(P.sig_info, 4 * sg_ + 3);
+        shdr[4] = gflags;
+        const int wi0 = ldc(P.sig_witem_ptr, sg_);
+        shdr[5] = wi0;
+        shdr[6] = ldc(P.sig_witem_ptr, sg_ + 1) - wi0;
+        shdr[7] = -1;
+        shdr[8] = P.grp_rank_off ? P.grp_rank_off[gg] : -1;
+    }
+    // The slots' per-point geometry is read all at once, so that one memory
+    // latency covers every pass: item x = q ne + slot, thread tid takes items
+    // x = NQ ne - 1 - tid - h kThreads (h = 0, 1, ...), from the last point
+    // down.  Item h = 0 stays in registers until its point's pass; items h >
+    // 0 exist where a group has more than kThreads / NQ slots, belong to the
+    // first pass (kThreads >= (NQ - QP) kGroupElems) and are turned into
+    // gradients at once.
+    static_assert(kThreads >= (NQ - QP) * kGroupElems, "items past the first belong to the first pass");
+    constexpr int kItems = (NQ * kGroupElems + kThreads - 1) / kThreads;
+    double G[kItems][D2], se[kItems];
+    int iq[kItems], islot[kItems];
+#pragma unroll
+    for (int h = 0; h < kItems; h++) {
+        const int x = NQ * ne - 1 - tid - h * kThreads;
+        iq[h] = ne > 0 && x >= 0 ? x / ne : NQ;  // NQ: no item
+        islot[h] = iq[h] < NQ ? x - iq[h] * ne : 0;
+        se[h] = 0.0;
+        if (iq[h] < NQ) {
+            const int id = P.grp_elems[eoff + islot[h]];
+            const int eo = P.elem_by_rank ? P.elem_by_rank[id] : id;
+            se[h] = sqrt(P.Emin + simp_pow(static_cast<const double *>(P.rho)[eo], P.p, P.ip) * (P.E0 - P.Emin));
+#pragma unroll
+            for (int c = 0; c < D2; c++) G[h][c] = P.qgeo[(int64_t)(iq[h] * D2 + c) * NC + id];
+        }
+    }
+    // sg[point qq of the pass][node k][a][slot] = g_k[a] = sqrt(E) sum_m
+    // grad phi_k(xi_q)[m] G'_q[m][a]
+    auto gradients = [&](int h, int qq) {
+        const int q = iq[h], slot = islot[h];
+        // the axis factors at point q: f[n][b] for a node with bit n = b
+        double f[DIM][2];
+#pragma unroll
+        for (int n = 0; n < DIM; n++) {
+            const bool up = (q >> n) & 1;
+            f[n][1] = up ? kQ1Gp : kQ1Gm;
+            f[n][0] = up ? kQ1Gm : kQ1Gp;
+        }
+#pragma unroll
+        for (int k = 0; k < NEN; k++) {
+            const int cb = q1_corner(k);
+            double r[DIM];
+#pragma unroll
+            for (int m = 0; m < DIM; m++) {
+                double t = 1.0;
+#pragma unroll
+                for (int n = 0; n < DIM; n++)
+                    if (n != m) t *= f[n][(cb >> n) & 1];
+                r[m] = ((cb >> m) & 1) ? t : -t;
+            }
+#pragma unroll
+            for (int a = 0; a < DIM; a++) {
+                double g = r[0] * G[h][a];
+#pragma unroll
+                for (int m = 1; m < DIM; m++) g = fma(r[m], G[h][m * DIM + a], g);
+                sg[((qq * NEN + k) * DIM + a) * kGroupElems + slot] = se[h] * g;
+            }
+        }
+    };
+#pragma unroll
+    for (int h = 1; h < kItems; h++)
+        if (iq[h] < NQ) gradients(h, iq[h]);
+    for (int pass = 0; pass < NPASS; pass++) {
+        const int nqp = pass < NPASS - 1 ? QP : QLAST;
+        const int qq = iq[0] - pass * QP;
+        if (qq >= 0 && qq < nqp) gradients(0, qq);
+        if (tid == 0) ticket = 0;
+        __syncthreads();
+        const int pmode = (pass > 0 ? kPassInit : 0) | (pass == NPASS - 1 ? kPassFinal : 0);
+        if (pass < NPASS - 1) {
+            if (gflags >> kGrpWideShift)
+                assemble_wide<DIM, NEN, kF64, false, kGeoPoint + QP>(P, shdr, &ticket, stage, sg, nullptr, sn2l, lane,
+                                                                     pmode);
+            else
+                assemble_pairs<DIM, NEN, kF64, false, kGeoPoint + QP>(P, shdr, &ticket, stage, sg, nullptr, sn2l,
+                                                                      lane, pmode);
+        } else {
+            if (gflags >> kGrpWideShift)
+                assemble_wide<DIM, NEN, kF64, false, kGeoPoint + QLAST>(P, shdr, &ticket, stage, sg, nullptr, sn2l,
+                                                                        lane, pmode);
+            else
+                assemble_pairs<DIM, NEN, kF64, false, kGeoPoint + QLAST>(P, shdr, &ticket, stage, sg, nullptr, sn2l,
+                                                                         lane, pmode);
+        }
+        __syncthreads();
+    }
     store_rows<DIM, kStoreWaves>(P, shdr, srows, stage, w, lane);
 }
 
@@ -1515,6 +1768,63 @@ hipError_t launch_assemble(int elem, int prec, const AsmParams &P, int64_t ngrou
         return hipErrorInvalidValue;
     }
 #undef SOPTX_ASM
+}
+
+// LDS of k_assemble_quad for a plan's largest stage and slot table
+static size_t quad_lds(int dim, int nen, int64_t stage, int kmax) {
+    const int qp = dim == 2 ? QuadShape<2>::qp : QuadShape<3>::qp;
+    return 8 * (size_t)stage + 8 * (size_t)qp * nen * dim * kGroupElems + kGroupNodes * 2 * 4 +
+           2 * (size_t)kmax * kGroupNodes;
+}
+
+bool assemble_quad_fits(int elem, int64_t stage, int kmax) {
+    if (elem != SOPTX_QUAD4 && elem != SOPTX_HEX8) return false;
+    const int dim = elem == SOPTX_QUAD4 ? 2 : 3;
+    return quad_lds(dim, 1 << dim, stage, kmax) + 64 <= 160 * 1024;
+}
+
+template <int DIM, int NEN>
+static hipError_t launch_assemble_quad_t(const AsmParams &P0, int64_t ngroups, hipStream_t st) {
+    if (ngroups <= 0) return hipSuccess;
+    const size_t lds = quad_lds(DIM, NEN, P0.stage, P0.kmax);
+    if (lds + 64 > 160 * 1024) return hipErrorInvalidValue;
+    const void *fn = reinterpret_cast<const void *>(&k_assemble_quad<DIM, NEN>);
+    static std::mutex mu;
+    static std::map<int, size_t> lds_limit;
+    static std::map<std::pair<int, size_t>, int> occupancy;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    int per_cu = 0;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        size_t &lim = lds_limit[dev];
+        if (lds > lim) {
+            e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+            lim = lds;
+        }
+        auto it = occupancy.find({dev, lds});
+        if (it != occupancy.end()) {
+            per_cu = it->second;
+        } else {
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, QuadShape<DIM>::threads, lds);
+            if (e != hipSuccess || per_cu < 1) per_cu = 1;
+            occupancy[{dev, lds}] = per_cu;
+        }
+    }
+    AsmParams P = P0;
+    const int ncu = P.n_cu > 0 ? P.n_cu : 256;
+    P.os_window = std::max(8, (per_cu * ncu) / 8 * 8);
+    hipLaunchKernelGGL((k_assemble_quad<DIM, NEN>), dim3((unsigned)ngroups), dim3(QuadShape<DIM>::threads), lds, st, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_assemble_quad(int elem, const AsmParams &P, int64_t ngroups, hipStream_t st) {
+    if (!P.qgeo) return hipErrorInvalidValue;
+    if (elem == SOPTX_QUAD4) return launch_assemble_quad_t<2, 4>(P, ngroups, st);
+    if (elem == SOPTX_HEX8) return launch_assemble_quad_t<3, 8>(P, ngroups, st);
+    return hipErrorInvalidValue;
 }
 
 template <int DIM, int NEN, int NQ, int PREC>

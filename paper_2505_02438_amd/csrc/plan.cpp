@@ -320,6 +320,55 @@ static int canonical_orders(const soptx_mesh *mesh, std::vector<int32_t> &node_r
     return SOPTX_OK;
 }
 
+// ---- per-point geometry of Q1 elements (the row-block assembly of general
+// meshes), with the Gauss points of the 2-point rule per axis on [0, 1]^dim:
+// point q at xi_m = gp where bit m of q is set, else gm, weight 1 / 2^dim.
+// For every plan column (the element, or its rank in a canonical plan) and
+// point q: sqrt(w_q |det J_q|) J_q^-1, J_q = sum_k x_k (grad phi_k(xi_q))^T;
+// entry (q, m, a) = sqrt(w_q |det J_q|) d xi_m / d x_a at
+// hp.qgeo[((q dim + m) dim + a) n_cells + column]
+int quad_geometry(const soptx_mesh *mesh, HostPlan &hp) {
+    const int dim = hp.dim, nen = hp.nen, d2 = dim * dim;
+    const int nq = 1 << dim;
+    if (nen != nq) return SOPTX_E_UNSUPPORTED_ELEM;
+    const int64_t NC = hp.n_cells;
+    const double gp = 0.78867513459481288225457439025098, gm = 0.21132486540518711774542560974902;
+    const double w = 1.0 / nq;
+    // d phi_k / d xi_m at point q: +-prod over the other axes n of gp where
+    // node k's corner and point q agree on n, gm where they differ
+    std::vector<double> rg((size_t)nq * nen * dim);
+    for (int q = 0; q < nq; q++)
+        for (int k = 0; k < nen; k++)
+            for (int m = 0; m < dim; m++) {
+                double t = 1.0;
+                for (int n = 0; n < dim; n++)
+                    if (n != m) t *= corner_bit(mesh->elem, k, n) == ((q >> n) & 1) ? gp : gm;
+                rg[((size_t)q * nen + k) * dim + m] = corner_bit(mesh->elem, k, m) ? t : -t;
+            }
+    hp.qgeo.assign((size_t)nq * d2 * NC, 0.0);
+    if (!parallel_for(NC, [&](int64_t a0, int64_t a1) {
+        for (int64_t col = a0; col < a1; col++) {
+            const int64_t e = hp.canonical ? hp.elem_by_rank[(size_t)col] : col;
+            const int32_t *c = mesh->cells + e * nen;
+            for (int q = 0; q < nq; q++) {
+                double J[9], G[9];
+                for (int a = 0; a < dim; a++)
+                    for (int m = 0; m < dim; m++) {
+                        double t = 0.0;
+                        for (int k = 0; k < nen; k++)
+                            t += mesh->coords[(int64_t)c[k] * dim + a] * rg[((size_t)q * nen + k) * dim + m];
+                        J[a * dim + m] = t;
+                    }
+                const double det = inv_small(dim, J, G);
+                const double s = std::sqrt(w * std::fabs(det));
+                for (int x = 0; x < d2; x++) hp.qgeo[((size_t)q * d2 + x) * NC + col] = s * G[x];
+            }
+        }
+    }))
+        return SOPTX_E_OOM;
+    return SOPTX_OK;
+}
+
 int build_host_plan(const soptx_mesh *mesh, HostPlan &hp, bool general) {
     int rc = validate_mesh(mesh, general, &hp.affine);
     if (rc) return rc;
@@ -875,7 +924,10 @@ int build_host_plan(const soptx_mesh *mesh, HostPlan &hp, bool general) {
         hp.grp_rank.size() >= (size_t)INT32_MAX)
         return SOPTX_E_OVERFLOW;
 
-    return general ? general_table(mesh, hp) : SOPTX_OK;
+    if (!general) return SOPTX_OK;
+    rc = general_table(mesh, hp);
+    if (rc || (mesh->elem != SOPTX_QUAD4 && mesh->elem != SOPTX_HEX8)) return rc;
+    return quad_geometry(mesh, hp);
 }
 
 }  // namespace soptx

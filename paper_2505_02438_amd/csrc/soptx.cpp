@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -88,6 +89,7 @@ struct soptx_pattern_s {
     bool affine = true, general = false;
     double *coords = nullptr;
     int32_t *gptr = nullptr, *gent = nullptr, *gnode = nullptr;
+    double *qgeo = nullptr;  // general Q1: per-point geometry of the row-block kernel
     float *qgrad32 = nullptr;
     soptx_pattern_stats stats{};
     std::vector<void *> allocs;
@@ -275,7 +277,8 @@ static int build_pattern(const soptx_mesh *mesh, int32_t ref_method, bool genera
         if (hp.general) {
             std::vector<double> xy(mesh->coords, mesh->coords + (size_t)mesh->n_nodes * dim);
             if ((rc = upload(h, xy, &h->coords, st)) || (rc = upload(h, hp.gptr, &h->gptr, st)) ||
-                (rc = upload(h, hp.gent, &h->gent, st)) || (rc = upload(h, hp.gnode, &h->gnode, st))) {
+                (rc = upload(h, hp.gent, &h->gent, st)) || (rc = upload(h, hp.gnode, &h->gnode, st)) ||
+                (!hp.qgeo.empty() && (rc = upload(h, hp.qgeo, &h->qgeo, st)))) {
                 free_handle(h);
                 return rc;
             }
@@ -307,6 +310,20 @@ int soptx_build_pattern_general(const soptx_mesh *mesh, soptx_pattern *out, void
     return build_pattern(mesh, SOPTX_REF_SYMBOLIC, true, out, stream);
 }
 
+static int asm_params(soptx_pattern h, const soptx_material *m, const void *d_rho, double *d_K_vals, int32_t prec,
+                      hipStream_t st, AsmParams &P);
+static int assemble_general_ke(soptx_pattern h, const soptx_material *m, const double *d_rho, double *d_K_vals,
+                               hipStream_t st);
+
+// which assembly general handles of Q1 elements run (soptx_debug_set_general_variant)
+static std::atomic<int> g_general_variant{-1};
+
+// the row-block kernel with per-point geometry for this handle (else the
+// element matrices go through memory)
+static bool general_in_lds(soptx_pattern h) {
+    return h->qgeo && g_general_variant.load() != 0 && assemble_quad_fits(h->elem, h->stage, h->kmax);
+}
+
 int soptx_assemble_general(soptx_pattern h, const soptx_material *m, const double *d_rho, const uint8_t *d_dirichlet,
                            double *d_K_vals, void *stream) {
     if (!h) return SOPTX_E_INVALID_ARG;
@@ -319,6 +336,25 @@ int soptx_assemble_general(soptx_pattern h, const soptx_material *m, const doubl
     DeviceGuard dg(h->device);
     if (!dg.ok) return SOPTX_E_DEVICE;
     hipStream_t st = static_cast<hipStream_t>(stream);
+    if (general_in_lds(h)) {
+        AsmParams P{};
+        if ((rc = asm_params(h, m, d_rho, d_K_vals, kF64, st, P))) return rc;
+        P.qgeo = h->qgeo;
+        if (launch_assemble_quad(h->elem, P, h->ngroups, st) != hipSuccess) return SOPTX_E_DEVICE;
+    } else {
+        rc = assemble_general_ke(h, m, d_rho, d_K_vals, st);
+        if (rc) return rc;
+    }
+    if (d_dirichlet && launch_dirichlet(h->dim, h->row_ptr, h->nb_tslot, h->nb_tdeg, d_dirichlet, d_K_vals, h->ndof, st) != hipSuccess)
+        return SOPTX_E_DEVICE;
+    return SOPTX_OK;
+}
+
+// the element-matrix path: every element's matrix to memory, then one
+// gather per block of K in ascending element order
+static int assemble_general_ke(soptx_pattern h, const soptx_material *m, const double *d_rho, double *d_K_vals,
+                               hipStream_t st) {
+    int rc;
     const int nen = h->nen, dim = h->dim;
     double *ke = nullptr;
     rc = get_workspace(h->device, st, (size_t)h->n_cells * nen * nen * dim * dim, &ke, 4);
@@ -332,8 +368,6 @@ int soptx_assemble_general(soptx_pattern h, const soptx_material *m, const doubl
     G.gptr = h->gptr; G.gent = h->gent; G.gnode = h->gnode; G.row_ptr = h->row_ptr; G.K = d_K_vals;
     G.n_blocks = h->nnz / (dim * dim);
     if (launch_assemble_general(h->elem, G, st) != hipSuccess) return SOPTX_E_DEVICE;
-    if (d_dirichlet && launch_dirichlet(h->dim, h->row_ptr, h->nb_tslot, h->nb_tdeg, d_dirichlet, d_K_vals, h->ndof, st) != hipSuccess)
-        return SOPTX_E_DEVICE;
     return SOPTX_OK;
 }
 
@@ -783,6 +817,18 @@ void soptx_destroy_pattern(soptx_pattern h) {
 
 // ----------------------------------------------------------- host-only debug
 
+int soptx_debug_set_general_variant(int32_t v) {
+    if (v < -1 || v > 0) return SOPTX_E_INVALID_ARG;
+    g_general_variant.store(v);
+    return SOPTX_OK;
+}
+
+int soptx_debug_general_path(soptx_pattern h, int32_t *in_lds) {
+    if (!h || !in_lds || !h->general) return SOPTX_E_INVALID_ARG;
+    *in_lds = general_in_lds(h) ? 1 : 0;
+    return SOPTX_OK;
+}
+
 int soptx_debug_set_assembly_variant(int32_t v) {
     if (v < -1 || v > 1) return SOPTX_E_INVALID_ARG;
     set_assembly_variant(v);
@@ -825,7 +871,7 @@ int soptx_debug_host_plan_array(soptx_host_plan p, const char *name, const void 
     SOPTX_ARR(grp_n2l) SOPTX_ARR(grp_rows) SOPTX_ARR(grp_rank_off) SOPTX_ARR(grp_rank) SOPTX_ARR(elem_by_rank)
     SOPTX_ARR(pos)
     SOPTX_ARR(nb_tslot) SOPTX_ARR(nb_tdeg)
-    SOPTX_ARR(gptr) SOPTX_ARR(gent) SOPTX_ARR(gnode)
+    SOPTX_ARR(gptr) SOPTX_ARR(gent) SOPTX_ARR(gnode) SOPTX_ARR(qgeo)
 #undef SOPTX_ARR
     return SOPTX_E_INVALID_ARG;
 }

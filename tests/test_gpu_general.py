@@ -1,10 +1,15 @@
 """Assembly with per-quadrature-point geometry (soptx_assemble_general) on
 the GPU, through the C ABI: general (non-affine) Q1 quadrilaterals and
 hexahedra against the oracle's assembly (row-scaled error, the C12 metric,
-<= 1e-12), with and without Dirichlet rows; on affine meshes against the
-separated-form kernel (two different formulas, same matrix); determinism;
-the affine-only calls refuse a non-affine handle; the full 120x40x40
-hexahedral cantilever with jittered interior nodes against the oracle."""
+<= 1e-12), with and without Dirichlet rows; both forms of the assembly (in
+LDS on the plan's node groups, and through element matrices in memory)
+against the oracle and each other, also on renumbered meshes; on affine
+meshes against the separated-form kernel (two different formulas, same
+matrix); determinism; the affine-only calls refuse a non-affine handle; the
+full 120x40x40 hexahedral cantilever with jittered interior nodes against
+the oracle."""
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -56,6 +61,55 @@ def test_general_matches_oracle(elem, dims):
             rows = np.repeat(np.arange(m.ndof), np.diff(rp))
             sel = np.isin(rows, fixed) | np.isin(ci, fixed)
             assert np.array_equal(K[sel], Kr[sel])
+
+
+def _in_lds(pat):
+    v = ctypes.c_int32(-1)
+    assert _lib.lib().soptx_debug_general_path(pat._h, ctypes.byref(v)) == 0
+    return v.value
+
+
+def _renumbered(m, rng):
+    pn, pe = rng.permutation(m.n_nodes), rng.permutation(m.n_cells)
+    coords = np.empty_like(m.coords)
+    coords[pn] = m.coords
+    return I.Mesh(m.elem, coords, pn[m.cells[pe]].astype(np.int32))
+
+
+@pytest.mark.parametrize("elem,dims,jit,renum", [(I.QUAD4, (9, 7), 0.3, False), (I.QUAD4, (40, 13), 0.3, True),
+                                                 (I.HEX8, (5, 4, 3), 0.3, False), (I.HEX8, (13, 6, 5), 0.3, False),
+                                                 (I.HEX8, (9, 7, 5), 0.2, True), (I.HEX8, (9, 7, 5), 0.3, True)])
+def test_general_forms_match_oracle_and_each_other(elem, dims, jit, renum):
+    """The in-LDS form (one workgroup per node group of the plan, the
+    Jacobian at every Gauss point of each element slot) and the
+    element-matrix form: each against the oracle, and against each other
+    (the same contributions in the same element order, different rounding
+    of the per-point products); renumbered meshes take a canonical-order
+    plan (the quadrilaterals and the hexahedra jittered by 0.2 here), the
+    others a plan in their own numbering."""
+    m, rng = _jittered(elem, dims, jit, 55)
+    if renum:
+        m = _renumbered(m, rng)
+    pat = api.Pattern.from_mesh(m, general=True)
+    rho = rng.uniform(1e-3, 1.0, m.n_cells)
+    mat = api.Material(E0=1.0, Emin=1e-9, nu=0.3, p=3.0)
+    rp, ci = O.pattern(elem, m.n_nodes, m.cells)
+    Kr = O.assemble(elem, m.coords, m.cells, rho, rp, ci)
+    L = _lib.lib()
+    assert L.soptx_debug_set_general_variant(1) == -1
+    out = {}
+    try:
+        for v in (-1, 0):
+            assert L.soptx_debug_set_general_variant(v) == 0
+            out[v] = (host(pat.assemble_general(mat, dev(rho))), _in_lds(pat))
+    finally:
+        L.soptx_debug_set_general_variant(-1)
+    assert out[-1][1] == 1 and out[0][1] == 0
+    e_lds, e_ke = _row_scaled(rp, out[-1][0], Kr), _row_scaled(rp, out[0][0], Kr)
+    e_mut = _row_scaled(rp, out[-1][0], out[0][0])
+    print(f"elem={elem} {dims} jitter {jit} renumbered={renum}: in-LDS {e_lds:.1e}, element matrices {e_ke:.1e}, "
+          f"between {e_mut:.1e}")
+    assert e_lds <= 1e-12 and e_ke <= 1e-12 and e_mut <= 1e-13
 
 
 @pytest.mark.parametrize("case", ["quad_unit", "hex_unit", "quad_sheared", "hex_sheared"])
@@ -110,6 +164,7 @@ def test_general_full_cantilever_hex():
     pr = I.cantilever_hex()
     m = I.jitter_interior(pr.mesh, 0.2, np.random.default_rng(54))
     pat = api.Pattern.from_mesh(m, general=True)
+    assert _in_lds(pat) == 1
     mat = api.Material(E0=pr.E0, Emin=pr.Emin, nu=pr.nu, p=pr.p)
     K = host(pat.assemble_general(mat, dev(pr.rho), dev(pr.mask)))
     rp, ci = O.pattern(m.elem, m.n_nodes, m.cells)

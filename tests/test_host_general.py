@@ -90,3 +90,65 @@ def test_hex27_host_checks():
         _, g = O.ref_basis(I.HEX27, xq)
         Mo += wq * np.einsum("im,jn->ijmn", g, g)
     assert np.abs(Ms - Mo).max() <= 1e-14 * np.abs(Mo).max()
+
+
+def _point_gradient_ke(dim, G):
+    """Element matrix (E = 1, nu = 0.3) from the per-point geometry of one
+    plan column, G[q] = sqrt(w_q |det J_q|) J_q^-1, with the Gauss points and
+    reference gradients the in-LDS assembly uses: the 2-point rule on
+    [0, 1]^dim, point q at (1 +- 1/sqrt(3)) / 2 by the bits of q, node k at
+    corner k ^ ((k >> 1) & 1); block (i, j) = L(sum_q g_i g_j^T),
+    g_k = G^T grad phi_k, L(A) = lam A + mu A^T + mu tr(A) I."""
+    nu = 0.3
+    lam = nu / ((1 + nu) * (1 - 2 * nu)) if dim == 3 else nu / (1 - nu * nu)
+    mu = 1 / (2 * (1 + nu))
+    gp, gm = (1 + 1 / np.sqrt(3)) / 2, (1 - 1 / np.sqrt(3)) / 2
+    nen = 1 << dim
+    ke = np.zeros((dim * nen, dim * nen))
+    for q in range(nen):
+        g = np.zeros((nen, dim))
+        for k in range(nen):
+            cb = k ^ ((k >> 1) & 1)
+            r = np.ones(dim)
+            for m in range(dim):
+                for n in range(dim):
+                    if n != m:
+                        r[m] *= gp if ((cb >> n) & 1) == ((q >> n) & 1) else gm
+                if not (cb >> m) & 1:
+                    r[m] = -r[m]
+            g[k] = G[q].T @ r
+        for i in range(nen):
+            for j in range(nen):
+                P = np.outer(g[i], g[j])
+                ke[dim * i:dim * i + dim, dim * j:dim * j + dim] += lam * P + mu * P.T + mu * np.trace(P) * np.eye(dim)
+    return ke
+
+
+@pytest.mark.parametrize("elem,dims,jit,renum,canonical", [
+    (I.QUAD4, (7, 5), 0.3, False, False), (I.QUAD4, (40, 13), 0.3, True, True), (I.QUAD4, (7, 5), 0.2, True, False),
+    (I.HEX8, (4, 3, 3), 0.3, False, False), (I.HEX8, (4, 3, 3), 0.2, True, True), (I.HEX8, (4, 3, 3), 0.3, True, False)])
+def test_point_geometry_gives_element_matrices(elem, dims, jit, renum, canonical):
+    """The per-point geometry that the in-LDS general assembly reads (qgeo,
+    one column per element, or per element rank in a canonical-order plan),
+    with that assembly's point and gradient convention, gives every
+    element's matrix as the oracle computes it (a different rule
+    parametrisation and code).  Renumbered meshes whose jittered lattice is
+    recognised take a canonical-order plan."""
+    rng = np.random.default_rng(4)
+    m0 = I.quad_grid(*dims) if elem == I.QUAD4 else I.hex_grid(*dims)
+    m = I.jitter_interior(m0, jit, rng)
+    if renum:
+        pn, pe = rng.permutation(m.n_nodes), rng.permutation(m.n_cells)
+        coords = np.empty_like(m.coords)
+        coords[pn] = m.coords
+        m = I.Mesh(m.elem, coords, pn[m.cells[pe]].astype(np.int32))
+    hp = api.host_plan(m.elem, m.coords, m.cells, general=True)
+    d, nc = m.dim, m.n_cells
+    q = hp["qgeo"].reshape(1 << d, d, d, nc)
+    cols = hp["elem_by_rank"] if len(hp["elem_by_rank"]) else np.arange(nc)
+    assert (len(hp["elem_by_rank"]) > 0) == canonical
+    for col in range(nc):
+        e = int(cols[col])
+        ke = _point_gradient_ke(d, q[:, :, :, col])
+        kr = O.element_ke0(elem, m.coords[m.cells[e]])
+        assert np.max(np.abs(ke - kr)) <= 1e-13 * np.max(np.abs(kr)), (col, e)
