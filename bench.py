@@ -275,6 +275,7 @@ def general_run(stream, reps=20):
             L.soptx_debug_set_general_variant(-1)
         return statistics.mean(ms[3:]) / 1e3, in_lds.value
     avg_ke, _ = time_assembly(0)
+    avg_stage, _ = time_assembly(1)
     avg, form = time_assembly(-1)
     u = torch.from_numpy(pr.u).cuda()
     dc = torch.empty(m.n_cells, dtype=torch.float64, device="cuda")
@@ -291,10 +292,12 @@ def general_run(stream, reps=20):
     ev_avg = statistics.mean(ev[3:]) / 1e3
     kbytes = pat.nnz * 8
     return {"mesh": "120x40x40 hexahedra, interior nodes jittered by 0.2", "elements": m.n_cells,
-            "form": "in LDS on the plan's node groups (k_assemble_quad)" if form == 1 else
-                    "element matrices through memory (k_ke_general, k_gather_general)",
+            "form": {1: "in LDS on the plan's node groups, sums in registers (k_assemble_point)",
+                     2: "in LDS on the plan's node groups, sums in an LDS stage (k_assemble_quad)"}.get(
+                         form, "element matrices through memory (k_ke_general, k_gather_general)"),
             "avg_ms": avg * 1e3, "elements_per_s": m.n_cells / avg, "K_bytes": kbytes,
-            "K_write_GBs": kbytes / avg / 1e9, "element_matrix_form_avg_ms": avg_ke * 1e3,
+            "K_write_GBs": kbytes / avg / 1e9, "stage_form_avg_ms": avg_stage * 1e3,
+            "element_matrix_form_avg_ms": avg_ke * 1e3,
             "evaluate_avg_ms": ev_avg * 1e3,
             "step_elements_per_s": m.n_cells / (avg + ev_avg), "pattern_build_s": build_s}
 

@@ -74,20 +74,23 @@ int soptx_debug_fail_workers(int32_t n);
 int soptx_debug_set_assembly_variant(int32_t v);
 
 /* Test hook: how soptx_assemble_general assembles Q1 elements whose map is
- * not affine, process-wide: -1 (default) = in LDS, by one workgroup per node
- * group of the plan with the Jacobian at every Gauss point (no element
- * matrices in memory), where the plan's largest group fits the kernel's LDS;
- * 0 = every element matrix written to device memory, then one gather per
- * block of K.  Both sum each block's contributions in ascending element
- * order; they differ in rounding only.  Q2 hexahedra always take the second
- * form.  SOPTX_E_INVALID_ARG for other values. */
+ * not affine, process-wide.  The forms: (1) in LDS, one workgroup per node
+ * group of the plan with the Jacobian at every Gauss point, the blocks'
+ * sums in registers (plans with few work items per node group); (2) the
+ * same with the sums in an LDS stage; (0) every element matrix written to
+ * device memory, then one gather per block of K.  All sum each block's
+ * contributions in ascending element order and differ in rounding only.
+ * v = -1 (default): form 1 where the plan allows it, else 2 where its
+ * largest group fits LDS, else 0; v = 0: form 0; v = 1: form 2 where it
+ * fits, else 0.  Q2 hexahedra always take form 0.  SOPTX_E_INVALID_ARG for
+ * other values. */
 int soptx_debug_set_general_variant(int32_t v);
 
-/* Whether soptx_assemble_general on handle h (built by
- * soptx_build_pattern_general) runs the in-LDS form under the current
- * variant: *in_lds = 1, else 0.  SOPTX_E_INVALID_ARG for a null argument or
- * a handle without the general tables. */
-int soptx_debug_general_path(soptx_pattern h, int32_t *in_lds);
+/* The form (1, 2 or 0 above) that soptx_assemble_general runs on handle h
+ * (built by soptx_build_pattern_general) under the current variant, in
+ * *form.  SOPTX_E_INVALID_ARG for a null argument or a handle without the
+ * general tables. */
+int soptx_debug_general_path(soptx_pattern h, int32_t *form);
 
 #ifdef __cplusplus
 }

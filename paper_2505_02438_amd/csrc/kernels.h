@@ -154,6 +154,12 @@ hipError_t launch_assemble_general(int elem, const GenParams &G, hipStream_t st)
 // largest group fits the kernel's LDS (else the element-matrix path runs).
 bool assemble_quad_fits(int elem, int64_t stage, int kmax);
 hipError_t launch_assemble_quad(int elem, const AsmParams &P, int64_t ngroups, hipStream_t st);
+// The same blocks with the partial sums in registers (k_assemble_point), for
+// plans whose signatures have at most a fixed number of work items
+// (max_items: the largest over the plan's signatures) and whose stage and
+// gradients fit LDS.
+bool assemble_point_fits(int elem, int64_t stage, int kmax, int max_items);
+hipError_t launch_assemble_point(int elem, const AsmParams &P, int64_t ngroups, hipStream_t st);
 // elements per block (and per c partial) of the Q2 hexahedron's energy kernel;
 // the other elements take 256
 constexpr int kEnergyWideElems = 16;

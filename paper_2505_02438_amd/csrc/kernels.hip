@@ -1159,6 +1159,346 @@ __global__ __launch_bounds__(QuadShape<DIM>::threads) void k_assemble_quad(AsmPa
     store_rows<DIM, kStoreWaves>(P, shdr, srows, stage, w, lane);
 }
 
+// ---- per-point assembly with the partial sums in registers: work item r
+// of a group (pairs, or wide for groups of at most 16 nodes) belongs to one
+// wave for all passes, so a block's sum stays in the lane's registers across
+// the passes and no stage holds partial sums; after the last pass the lane
+// applies L and writes its block to K.  The contributions, their order and
+// the lane layout are those of assemble_pairs / assemble_wide; a split
+// position's two halves, and a wide item's phases, are added at the end.
+
+// Pairs item r (r <= deg): this pass's terms of the lane's contributions
+// into acc; with fin (after the last pass), the halves are added and the
+// lane's block goes to its row block in the stage.
+template <int DIM, int NEN, int QP>
+__device__ __forceinline__ void point_pairs(const AsmParams &P, const int *hdr, int r, const double *Gs,
+                                            const uint16_t *sn2l, int lane, double *stage, bool fin,
+                                            double (&acc)[DIM][DIM]) {
+    constexpr int NG = kGroupNodes;
+    const int nn = wave_uniform(hdr[0]);
+    const int deg = wave_uniform(hdr[1]);
+    const int posoff = wave_uniform(hdr[2]);
+    const int rkoff = wave_uniform(hdr[8]);
+    const int rl = DIM * deg;
+    const bool hi = lane >= NG;
+    const int node = lane & (NG - 1);
+    const uint16_t *n2l = sn2l + node;
+    const int pa = ldc(P.sig_pairs, 2 * posoff + 2 * r);
+    if (pa < 0) return;
+    const int pb = ldc(P.sig_pairs, 2 * posoff + 2 * r + 1);
+    const bool split = pb == pa;
+    const int c0 = ldc(P.sig_pos_ptr, posoff + pa);
+    const int na = ldc(P.sig_pos_ptr, posoff + pa + 1) - c0;
+    int lo0 = c0, nlo = na, hi0 = c0, nhi = 0;
+    if (split) {
+        nlo = (na + 1) / 2;
+        hi0 = c0 + nlo;
+        nhi = na - nlo;
+    } else if (pb >= 0) {
+        hi0 = ldc(P.sig_pos_ptr, posoff + pb);
+        nhi = ldc(P.sig_pos_ptr, posoff + pb + 1) - hi0;
+    }
+    if (!fin) {
+        const int mycnt = hi ? nhi : nlo;
+        const int32_t *lo_p = P.sig_contrib + lo0;
+        const int32_t *hi_p = P.sig_contrib + (nhi > 0 ? hi0 : lo0);
+        for (int t0 = 0; t0 < nlo; t0 += 8) {
+            const Codes8 cl = ld_codes8(lo_p + t0), ch = ld_codes8(hi_p + t0);
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                if (t0 + u >= nlo) break;
+                const bool oku = t0 + u < mycnt;
+                const int code = oku ? (hi && nhi > 0 ? ch[u] : cl[u]) : 0;
+                const int k = code >> 16, i = (code >> 8) & 255, j = code & 255;
+                contribute_point<DIM, NEN, QP>(Gs, n2l[k * NG], i, j, oku, acc);
+            }
+        }
+        return;
+    }
+    if (split) {
+#pragma unroll
+        for (int a = 0; a < DIM; a++)
+#pragma unroll
+            for (int c = 0; c < DIM; c++) acc[a][c] += __shfl_xor(acc[a][c], NG);
+    }
+    const int pme = hi ? pb : pa;
+    if (node < nn && pme >= 0 && !(split && hi)) {
+        const int pcsr = rkoff >= 0 ? (int)P.grp_rank[rkoff + pme * NG + node] : pme;
+        double tr = 0.0;
+#pragma unroll
+        for (int a = 0; a < DIM; a++) tr += acc[a][a];
+        double *dst = stage + node * wave_uniform(hdr[3]) + DIM * pcsr;
+#pragma unroll
+        for (int a = 0; a < DIM; a++)
+#pragma unroll
+            for (int c = 0; c < DIM; c++) {
+                double o = P.lam * acc[a][c] + P.mu * acc[c][a];
+                if (a == c) o += P.mu * tr;
+                dst[a * rl + c] = o;
+            }
+    }
+}
+
+// Wide item r (r < number of wide items): as point_pairs, the phases of a
+// position added by the butterfly at the end
+template <int DIM, int NEN, int QP>
+__device__ __forceinline__ void point_wide(const AsmParams &P, const int *hdr, int r, const double *Gs,
+                                           const uint16_t *sn2l, int lane, double *stage, bool fin,
+                                           double (&acc)[DIM][DIM]) {
+    constexpr int NG = kGroupNodes;
+    const int nn = wave_uniform(hdr[0]);
+    const int deg = wave_uniform(hdr[1]);
+    const int flags = wave_uniform(hdr[4]);
+    const int wi0 = wave_uniform(hdr[5]);
+    const int rkoff = wave_uniform(hdr[8]);
+    const int lgN = 5 - ((flags >> kGrpWideShift) & 3);  // N = 8 or 16
+    const int N = 1 << lgN;
+    const int rl = DIM * deg;
+    const int node = lane & (N - 1);
+    const uint16_t *n2l = sn2l + node;
+    const int32_t *rec = P.sig_witems + (int64_t)(wi0 + r) * kWideInts;
+    const int np = ldc(rec, 0), Q = ldc(rec, 1), nt = ldc(rec, 2);
+    const int lgQ = 31 - __clz(Q);
+    const int grp = lane >> lgN;
+    const int pp = grp >> lgQ, q = grp & (Q - 1);
+    int p = -1, off = 0, cnt = 0;
+#pragma unroll
+    for (int k = 0; k < 8; k++)
+        if (pp == k) {
+            p = ldc(rec, 8 + k);
+            off = ldc(rec, 16 + k);
+            cnt = ldc(rec, 24 + k);
+        }
+    const bool mine = pp < np && node < nn;
+    if (!fin) {
+        int pk[8];
+#pragma unroll
+        for (int t = 0; t < 8; t++) {
+            const int ti = q + t * Q;
+            pk[t] = (t < nt && mine && ti < cnt) ? P.sig_contrib[off + ti] : -1;
+        }
+#pragma unroll
+        for (int t = 0; t < 8; t++) {
+            if (t >= nt) break;
+            if (pk[t] >= 0) {
+                const int k = pk[t] >> 16, i = (pk[t] >> 8) & 255, j = pk[t] & 255;
+                contribute_point<DIM, NEN, QP>(Gs, n2l[k * NG], i, j, true, acc);
+            }
+        }
+        return;
+    }
+    for (int sh = N; sh < N * Q; sh <<= 1)
+#pragma unroll
+        for (int a = 0; a < DIM; a++)
+#pragma unroll
+            for (int c = 0; c < DIM; c++) acc[a][c] += __shfl_xor(acc[a][c], sh);
+    if (mine && q == 0) {
+        const int pcsr = rkoff >= 0 ? (int)P.grp_rank[rkoff + p * NG + node] : p;
+        double tr = 0.0;
+#pragma unroll
+        for (int a = 0; a < DIM; a++) tr += acc[a][a];
+        double *dst = stage + node * wave_uniform(hdr[3]) + DIM * pcsr;
+#pragma unroll
+        for (int a = 0; a < DIM; a++)
+#pragma unroll
+            for (int c = 0; c < DIM; c++) {
+                double o = P.lam * acc[a][c] + P.mu * acc[c][a];
+                if (a == c) o += P.mu * tr;
+                dst[a * rl + c] = o;
+            }
+    }
+}
+
+// Per-point assembly of Q1 elements (see k_assemble_quad) with the blocks'
+// partial sums in registers: wave w owns work items w and w + NW (NW waves)
+// for all passes, which holds for every plan whose signatures have at most
+// 2 NW work items (the host checks; k_assemble_quad takes the others).  LDS
+// holds the gradients of QP points, and after the last pass the finished
+// blocks in a stage over the same bytes, so two workgroups share a CU and
+// one's memory latency overlaps the other's arithmetic.  A block's
+// sum: the passes in order; in a pass, the lane's contributions in the
+// plan's order, each over the pass's points in order; then a split
+// position's halves, or a wide item's phases, as in k_assemble.
+template <int DIM>
+struct PointShape {
+    static constexpr int threads = DIM == 2 ? 256 : 512;
+    static constexpr int qp = DIM == 2 ? 4 : 2;  // Gauss points per pass
+    static constexpr int items = 2 * (threads / 64);  // work items a group may have
+};
+
+template <int DIM, int NEN>
+__global__ __launch_bounds__(PointShape<DIM>::threads) void k_assemble_point(AsmParams P) {
+    constexpr int kThreads = PointShape<DIM>::threads;
+    constexpr int QP = PointShape<DIM>::qp;
+    constexpr int NW = kThreads / 64;
+    constexpr int D2 = DIM * DIM;
+    constexpr int NQ = 1 << DIM;
+    constexpr int NPASS = (NQ + QP - 1) / QP;
+    static_assert(NQ % QP == 0, "equal passes");
+    constexpr int NG = kGroupNodes;
+    static_assert(NEN == NQ, "Q1 elements");
+    static_assert(kGroupElems <= kThreads, "one thread per slot");
+    extern __shared__ __align__(16) unsigned char smem[];
+    // the gradients and, after the last pass, the stage in the same bytes
+    double *sg = reinterpret_cast<double *>(smem);                  // [QP][NEN][DIM][kGroupElems]
+    double *sE = sg + QP * NEN * DIM * kGroupElems;                 // [kGroupElems] sqrt(E(rho))
+    int32_t *sid = reinterpret_cast<int32_t *>(sE + kGroupElems);  // [kGroupElems] column of qgeo
+    double *stage = sg;                                             // [P.stage]
+    const int64_t ubytes = (int64_t)(QP * NEN * DIM + 2) * kGroupElems * 8 > P.stage * 8
+                               ? (int64_t)(QP * NEN * DIM + 2) * kGroupElems * 8
+                               : P.stage * 8;
+    int32_t *srows = reinterpret_cast<int32_t *>(smem + ubytes);    // [NG][2]
+    uint16_t *sn2l = reinterpret_cast<uint16_t *>(srows + NG * 2);  // [kmax][NG]
+    __shared__ int shdr[9];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = wave_uniform(tid >> 6);
+    const int64_t NC = P.n_cells;
+    const int ngr = P.n_groups;
+    const int W = P.os_window;
+    const int bid = blockIdx.x;
+    const int base = bid - bid % W;
+    const int gg = base + W <= ngr ? base + (bid % 8) * (W / 8) + (bid - base) / 8 : bid;
+    if (gg >= ngr) return;
+    const int sgi = wave_uniform(ldc(P.grp_info, kGrpInfo * gg + 0));
+    const int eoff = wave_uniform(ldc(P.grp_info, kGrpInfo * gg + 2));
+    const int ne = wave_uniform(ldc(P.grp_info, kGrpInfo * gg + 3));
+    const int n2off = wave_uniform(ldc(P.grp_info, kGrpInfo * gg + 4));
+    const int gflags = wave_uniform(ldc(P.grp_info, kGrpInfo * gg + 5));
+    const int nk = wave_uniform(ldc(P.sig_info, 4 * sgi + 0)) * NG;
+    for (int x = tid; x < nk; x += kThreads) sn2l[x] = P.grp_n2l[n2off + x];
+    if (tid < 2 * NG) srows[tid] = P.grp_rows[(int64_t)gg * 2 * NG + tid];
+    if (tid == 0) {
+        shdr[0] = ldc(P.grp_info, kGrpInfo * gg + 1);
+        shdr[1] = ldc(P.sig_info, 4 * sgi + 1);
+        shdr[2] = ldc(P.sig_info, 4 * sgi + 2);
+        shdr[3] = ldc(P.sig_info, 4 * sgi + 3);
+        shdr[4] = gflags;
+        const int wi0 = ldc(P.sig_witem_ptr, sgi);
+        shdr[5] = wi0;
+        shdr[6] = ldc(P.sig_witem_ptr, sgi + 1) - wi0;
+        shdr[7] = -1;
+        shdr[8] = P.grp_rank_off ? P.grp_rank_off[gg] : -1;
+    }
+    const bool wide = (gflags >> kGrpWideShift) != 0;
+    double acc[2][DIM][DIM];
+#pragma unroll
+    for (int it = 0; it < 2; it++)
+#pragma unroll
+        for (int a = 0; a < DIM; a++)
+#pragma unroll
+            for (int c = 0; c < DIM; c++) acc[it][a][c] = 0.0;
+    // item (point qq of the pass, slot): the slot's gradients at that point,
+    // sg[qq][k][a][slot] = g_k[a] = sqrt(E) sum_m grad phi_k(xi_q)[m]
+    // G'_q[m][a]
+    auto gradients = [&](const double (&G)[D2], double se, int q, int qq, int slot) {
+        double f[DIM][2];
+#pragma unroll
+        for (int n = 0; n < DIM; n++) {
+            const bool up = (q >> n) & 1;
+            f[n][1] = up ? kQ1Gp : kQ1Gm;
+            f[n][0] = up ? kQ1Gm : kQ1Gp;
+        }
+#pragma unroll
+        for (int k = 0; k < NEN; k++) {
+            const int cb = q1_corner(k);
+            double r[DIM];
+#pragma unroll
+            for (int m = 0; m < DIM; m++) {
+                double t = 1.0;
+#pragma unroll
+                for (int n = 0; n < DIM; n++)
+                    if (n != m) t *= f[n][(cb >> n) & 1];
+                r[m] = ((cb >> m) & 1) ? t : -t;
+            }
+#pragma unroll
+            for (int a = 0; a < DIM; a++) {
+                double g = r[0] * G[a];
+#pragma unroll
+                for (int m = 1; m < DIM; m++) g = fma(r[m], G[m * DIM + a], g);
+                sg[((qq * NEN + k) * DIM + a) * kGroupElems + slot] = se * g;
+            }
+        }
+    };
+    auto modulus_root = [&](int id) {
+        const int eo = P.elem_by_rank ? P.elem_by_rank[id] : id;
+        return sqrt(P.Emin + simp_pow(static_cast<const double *>(P.rho)[eo], P.p, P.ip) * (P.E0 - P.Emin));
+    };
+    // one item per thread and pass (3D): the same slot in every pass, its
+    // column and sqrt(E) kept in registers, and the next pass's G'_q read
+    // while this pass's contributions are added
+    constexpr bool kOneItem = QP * kGroupElems <= kThreads;
+    const bool has = kOneItem && ne > 0 && tid < QP * ne;
+    const int iqq = has ? tid / ne : 0, islot = has ? tid - iqq * ne : 0;
+    int iid = 0;
+    double ise = 0.0, Gc[D2], Gn[D2];
+    if (has) {
+        iid = P.grp_elems[eoff + islot];
+        ise = modulus_root(iid);
+#pragma unroll
+        for (int c = 0; c < D2; c++) Gc[c] = P.qgeo[(int64_t)(iqq * D2 + c) * NC + iid];
+    }
+    for (int pass = 0; pass < NPASS; pass++) {
+        if constexpr (kOneItem) {
+            if (has) {
+                gradients(Gc, ise, pass * QP + iqq, iqq, islot);
+                if (pass + 1 < NPASS)
+#pragma unroll
+                    for (int c = 0; c < D2; c++) Gn[c] = P.qgeo[(int64_t)(((pass + 1) * QP + iqq) * D2 + c) * NC + iid];
+            }
+        } else {
+            // several items per thread (2D: one pass)
+            for (int x = tid; x < QP * ne; x += kThreads) {
+                const int qq = x / ne, slot = x - qq * ne;
+                const int q = pass * QP + qq;
+                int id;
+                double se;
+                if (pass == 0) {
+                    id = P.grp_elems[eoff + slot];
+                    se = modulus_root(id);
+                    if (qq == 0) {
+                        sid[slot] = id;
+                        sE[slot] = se;
+                    }
+                } else {
+                    id = sid[slot];
+                    se = sE[slot];
+                }
+                double G[D2];
+#pragma unroll
+                for (int c = 0; c < D2; c++) G[c] = P.qgeo[(int64_t)(q * D2 + c) * NC + id];
+                gradients(G, se, q, qq, slot);
+            }
+        }
+        __syncthreads();
+        const int nitems = wide ? wave_uniform(shdr[6]) : wave_uniform(shdr[1]) + 1;
+#pragma unroll
+        for (int it = 0; it < 2; it++) {
+            const int r = w + it * NW;
+            if (r >= nitems) break;
+            if (wide) point_wide<DIM, NEN, QP>(P, shdr, r, sg, sn2l, lane, stage, false, acc[it]);
+            else point_pairs<DIM, NEN, QP>(P, shdr, r, sg, sn2l, lane, stage, false, acc[it]);
+        }
+        __syncthreads();
+        if constexpr (kOneItem) {
+#pragma unroll
+            for (int c = 0; c < D2; c++) Gc[c] = Gn[c];
+        }
+    }
+    // the blocks into the stage (over the gradients, read by now), then the
+    // group's rows out as in k_assemble
+    const int nitems = wide ? wave_uniform(shdr[6]) : wave_uniform(shdr[1]) + 1;
+#pragma unroll
+    for (int it = 0; it < 2; it++) {
+        const int r = w + it * NW;
+        if (r >= nitems) break;
+        if (wide) point_wide<DIM, NEN, QP>(P, shdr, r, sg, sn2l, lane, stage, true, acc[it]);
+        else point_pairs<DIM, NEN, QP>(P, shdr, r, sg, sn2l, lane, stage, true, acc[it]);
+    }
+    __syncthreads();
+    store_rows<DIM, NW>(P, shdr, srows, stage, w, lane);
+}
+
 // Dirichlet rows and columns (zero prescribed values): for a fixed dof r =
 // DIM I + a, K[r, :] = 0, K[:, r] = 0, K[r, r] = 1.
 //
@@ -1775,6 +2115,65 @@ static size_t quad_lds(int dim, int nen, int64_t stage, int kmax) {
     const int qp = dim == 2 ? QuadShape<2>::qp : QuadShape<3>::qp;
     return 8 * (size_t)stage + 8 * (size_t)qp * nen * dim * kGroupElems + kGroupNodes * 2 * 4 +
            2 * (size_t)kmax * kGroupNodes;
+}
+
+// LDS of k_assemble_point for a plan's slot table
+static size_t point_lds(int dim, int nen, int64_t stage, int kmax) {
+    const int qp = dim == 2 ? PointShape<2>::qp : PointShape<3>::qp;
+    const size_t grad = 8 * (size_t)(qp * nen * dim + 2) * kGroupElems;  // with sqrt(E) and the columns
+    return std::max(grad, 8 * (size_t)stage) + kGroupNodes * 2 * 4 + 2 * (size_t)kmax * kGroupNodes;
+}
+
+bool assemble_point_fits(int elem, int64_t stage, int kmax, int max_items) {
+    if (elem != SOPTX_QUAD4 && elem != SOPTX_HEX8) return false;
+    const int dim = elem == SOPTX_QUAD4 ? 2 : 3;
+    const int items = dim == 2 ? PointShape<2>::items : PointShape<3>::items;
+    return max_items <= items && point_lds(dim, 1 << dim, stage, kmax) + 64 <= 160 * 1024;
+}
+
+template <int DIM, int NEN>
+static hipError_t launch_assemble_point_t(const AsmParams &P0, int64_t ngroups, hipStream_t st) {
+    if (ngroups <= 0) return hipSuccess;
+    const size_t lds = point_lds(DIM, NEN, P0.stage, P0.kmax);
+    if (lds + 64 > 160 * 1024) return hipErrorInvalidValue;
+    const void *fn = reinterpret_cast<const void *>(&k_assemble_point<DIM, NEN>);
+    static std::mutex mu;
+    static std::map<int, size_t> lds_limit;
+    static std::map<std::pair<int, size_t>, int> occupancy;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    int per_cu = 0;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        size_t &lim = lds_limit[dev];
+        if (lds > lim) {
+            e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+            lim = lds;
+        }
+        auto it = occupancy.find({dev, lds});
+        if (it != occupancy.end()) {
+            per_cu = it->second;
+        } else {
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, PointShape<DIM>::threads, lds);
+            if (e != hipSuccess || per_cu < 1) per_cu = 1;
+            occupancy[{dev, lds}] = per_cu;
+        }
+    }
+    AsmParams P = P0;
+    const int ncu = P.n_cu > 0 ? P.n_cu : 256;
+    P.os_window = std::max(8, (per_cu * ncu) / 8 * 8);
+    hipLaunchKernelGGL((k_assemble_point<DIM, NEN>), dim3((unsigned)ngroups), dim3(PointShape<DIM>::threads), lds, st,
+                       P);
+    return hipGetLastError();
+}
+
+hipError_t launch_assemble_point(int elem, const AsmParams &P, int64_t ngroups, hipStream_t st) {
+    if (!P.qgeo) return hipErrorInvalidValue;
+    if (elem == SOPTX_QUAD4) return launch_assemble_point_t<2, 4>(P, ngroups, st);
+    if (elem == SOPTX_HEX8) return launch_assemble_point_t<3, 8>(P, ngroups, st);
+    return hipErrorInvalidValue;
 }
 
 bool assemble_quad_fits(int elem, int64_t stage, int kmax) {

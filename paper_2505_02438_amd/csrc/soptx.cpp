@@ -89,7 +89,8 @@ struct soptx_pattern_s {
     bool affine = true, general = false;
     double *coords = nullptr;
     int32_t *gptr = nullptr, *gent = nullptr, *gnode = nullptr;
-    double *qgeo = nullptr;  // general Q1: per-point geometry of the row-block kernel
+    double *qgeo = nullptr;  // general Q1: per-point geometry of the row-block kernels
+    int max_items = 0;       // largest number of work items of a signature
     float *qgrad32 = nullptr;
     soptx_pattern_stats stats{};
     std::vector<void *> allocs;
@@ -206,6 +207,12 @@ static int build_pattern(const soptx_mesh *mesh, int32_t ref_method, bool genera
         h->n_nodes = hp.n_nodes; h->n_cells = hp.n_cells; h->ndof = hp.ndof; h->nnz = hp.nnz;
         h->ngroups = hp.n_groups(); h->nsig = hp.n_sigs(); h->emax = hp.ne_max; h->kmax = hp.kmax; h->stage = hp.stage_max;
         h->affine = hp.affine; h->general = hp.general;
+        for (int64_t sg = 0; sg < hp.n_sigs(); sg++) {
+            const int deg = hp.sig_info[4 * sg + 1], posoff = hp.sig_info[4 * sg + 2];
+            int n = 0;
+            while (n <= deg && hp.sig_pairs[2 * (size_t)posoff + 2 * n] >= 0) n++;
+            h->max_items = std::max({h->max_items, n, hp.sig_witem_ptr[sg + 1] - hp.sig_witem_ptr[sg]});
+        }
         if (hipGetDevice(&h->device) != hipSuccess) { free_handle(h); return SOPTX_E_DEVICE; }
         if (hipDeviceGetAttribute(&h->n_cu, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess)
             h->n_cu = 0;
@@ -318,10 +325,15 @@ static int assemble_general_ke(soptx_pattern h, const soptx_material *m, const d
 // which assembly general handles of Q1 elements run (soptx_debug_set_general_variant)
 static std::atomic<int> g_general_variant{-1};
 
-// the row-block kernel with per-point geometry for this handle (else the
-// element matrices go through memory)
-static bool general_in_lds(soptx_pattern h) {
-    return h->qgeo && g_general_variant.load() != 0 && assemble_quad_fits(h->elem, h->stage, h->kmax);
+// the form of soptx_assemble_general on this handle: 1 = in LDS with the
+// blocks' sums in registers (k_assemble_point), 2 = in LDS with the sums in
+// the stage (k_assemble_quad), 0 = element matrices through memory
+static int general_form(soptx_pattern h) {
+    const int v = g_general_variant.load();
+    if (!h->qgeo || v == 0) return 0;
+    if (v != 1 && assemble_point_fits(h->elem, h->stage, h->kmax, h->max_items)) return 1;
+    if (assemble_quad_fits(h->elem, h->stage, h->kmax)) return 2;
+    return 0;
 }
 
 int soptx_assemble_general(soptx_pattern h, const soptx_material *m, const double *d_rho, const uint8_t *d_dirichlet,
@@ -336,11 +348,14 @@ int soptx_assemble_general(soptx_pattern h, const soptx_material *m, const doubl
     DeviceGuard dg(h->device);
     if (!dg.ok) return SOPTX_E_DEVICE;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (general_in_lds(h)) {
+    const int form = general_form(h);
+    if (form) {
         AsmParams P{};
         if ((rc = asm_params(h, m, d_rho, d_K_vals, kF64, st, P))) return rc;
         P.qgeo = h->qgeo;
-        if (launch_assemble_quad(h->elem, P, h->ngroups, st) != hipSuccess) return SOPTX_E_DEVICE;
+        const hipError_t e = form == 1 ? launch_assemble_point(h->elem, P, h->ngroups, st)
+                                       : launch_assemble_quad(h->elem, P, h->ngroups, st);
+        if (e != hipSuccess) return SOPTX_E_DEVICE;
     } else {
         rc = assemble_general_ke(h, m, d_rho, d_K_vals, st);
         if (rc) return rc;
@@ -818,14 +833,14 @@ void soptx_destroy_pattern(soptx_pattern h) {
 // ----------------------------------------------------------- host-only debug
 
 int soptx_debug_set_general_variant(int32_t v) {
-    if (v < -1 || v > 0) return SOPTX_E_INVALID_ARG;
+    if (v < -1 || v > 1) return SOPTX_E_INVALID_ARG;
     g_general_variant.store(v);
     return SOPTX_OK;
 }
 
-int soptx_debug_general_path(soptx_pattern h, int32_t *in_lds) {
-    if (!h || !in_lds || !h->general) return SOPTX_E_INVALID_ARG;
-    *in_lds = general_in_lds(h) ? 1 : 0;
+int soptx_debug_general_path(soptx_pattern h, int32_t *form) {
+    if (!h || !form || !h->general) return SOPTX_E_INVALID_ARG;
+    *form = general_form(h);
     return SOPTX_OK;
 }
 
