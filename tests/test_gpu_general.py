@@ -3,7 +3,9 @@ the GPU, through the C ABI: general (non-affine) Q1 quadrilaterals and
 hexahedra against the oracle's assembly (row-scaled error, the C12 metric,
 <= 1e-12), with and without Dirichlet rows; both forms of the assembly (in
 LDS on the plan's node groups, and through element matrices in memory)
-against the oracle and each other, also on renumbered meshes; on affine
+against the oracle and each other, also on renumbered meshes; a mesh
+with more work items per node group than the register form holds takes the
+stage form; on affine
 meshes against the separated-form kernel (two different formulas, same
 matrix); determinism; the affine-only calls refuse a non-affine handle; the
 full 120x40x40 hexahedral cantilever with jittered interior nodes against
@@ -239,3 +241,42 @@ def test_general_optimisation_iterations_match_oracle():
         print(f"iteration {it}: c {res.compliance[it]:.10f} / {co:.10f}")
         assert abs(res.compliance[it] - co) <= 1e-8 * co
     assert float(np.max(np.abs(host(res.rho) - rho))) <= 1e-6
+
+
+def _quad_star(n, rng):
+    """n kite-shaped quadrilaterals around one centre node (centre, p_k, o_k,
+    p_k+1 counter-clockwise; p on the unit circle, o at radius 2 between),
+    the ring nodes jittered: none is a parallelogram, and the centre has
+    2 n + 1 neighbours."""
+    c = np.zeros((1, 2))
+    t = 2 * np.pi * np.arange(n) / n
+    p = np.stack([np.cos(t), np.sin(t)], 1) * (1 + rng.uniform(-0.05, 0.05, (n, 1)))
+    o = 2 * np.stack([np.cos(t + np.pi / n), np.sin(t + np.pi / n)], 1) * (1 + rng.uniform(-0.05, 0.05, (n, 1)))
+    coords = np.concatenate([c, p, o])
+    cells = np.array([[0, 1 + k, 1 + n + k, 1 + (k + 1) % n] for k in range(n)], dtype=np.int32)
+    return I.Mesh(I.QUAD4, coords, cells)
+
+
+def test_general_many_work_items_take_the_stage_form():
+    """A node with 21 neighbours gives its group more work items than the
+    register form holds (two per wave): the default then runs the stage form,
+    which matches the oracle; the element-matrix form agrees."""
+    rng = np.random.default_rng(56)
+    m = _quad_star(10, rng)
+    pat = api.Pattern.from_mesh(m, general=True)
+    rho = rng.uniform(1e-3, 1.0, m.n_cells)
+    mat = api.Material(E0=1.0, Emin=1e-9, nu=0.3, p=3.0)
+    rp, ci = O.pattern(m.elem, m.n_nodes, m.cells)
+    Kr = O.assemble(m.elem, m.coords, m.cells, rho, rp, ci)
+    assert _in_lds(pat) == 2
+    K = host(pat.assemble_general(mat, dev(rho)))
+    L = _lib.lib()
+    try:
+        assert L.soptx_debug_set_general_variant(0) == 0
+        assert _in_lds(pat) == 0
+        Ke = host(pat.assemble_general(mat, dev(rho)))
+    finally:
+        L.soptx_debug_set_general_variant(-1)
+    e, e_mut = _row_scaled(rp, K, Kr), _row_scaled(rp, K, Ke)
+    print(f"star of 10 quadrilaterals: stage form {e:.1e}, against element matrices {e_mut:.1e}")
+    assert e <= 1e-12 and e_mut <= 1e-13
