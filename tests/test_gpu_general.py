@@ -1,15 +1,15 @@
 """Assembly with per-quadrature-point geometry (soptx_assemble_general) on
 the GPU, through the C ABI: general (non-affine) Q1 quadrilaterals and
 hexahedra against the oracle's assembly (row-scaled error, the C12 metric,
-<= 1e-12), with and without Dirichlet rows; both forms of the assembly (in
-LDS on the plan's node groups, and through element matrices in memory)
-against the oracle and each other, also on renumbered meshes; a mesh
-with more work items per node group than the register form holds takes the
-stage form; on affine
-meshes against the separated-form kernel (two different formulas, same
-matrix); determinism; the affine-only calls refuse a non-affine handle; the
-full 120x40x40 hexahedral cantilever with jittered interior nodes against
-the oracle."""
+<= 1e-12), with and without Dirichlet rows; the three forms of the assembly
+(in LDS on the plan's node groups with the block sums in registers or in an
+LDS stage, and through element matrices in memory) against the oracle and
+each other, also on renumbered meshes; a mesh with more work items per node
+group than the register form holds takes the stage form; on affine meshes
+against the separated-form kernel (two different formulas, same matrix);
+determinism; the affine-only calls refuse a non-affine handle; the full
+120x40x40 hexahedral cantilever with jittered interior nodes against the
+oracle."""
 import ctypes
 
 import numpy as np
