@@ -101,10 +101,16 @@ def test_general_forms_match_oracle_and_each_other(elem, dims, jit, renum):
     L = _lib.lib()
     assert L.soptx_debug_set_general_variant(2) == -1
     out = {}
+    mask = (rng.uniform(size=m.ndof) < 0.1).astype(np.uint8)
+    Krm = O.assemble(elem, m.coords, m.cells, rho, rp, ci, mask=mask)
+    rows = np.repeat(np.arange(m.ndof), np.diff(rp))
+    fixed = np.nonzero(mask)[0]
+    sel = np.isin(rows, fixed) | np.isin(ci, fixed)
     try:
         for v in (-1, 1, 0):
             assert L.soptx_debug_set_general_variant(v) == 0
-            out[v] = (host(pat.assemble_general(mat, dev(rho))), _in_lds(pat))
+            out[v] = (host(pat.assemble_general(mat, dev(rho))), _in_lds(pat),
+                      host(pat.assemble_general(mat, dev(rho), dev(mask))))
     finally:
         L.soptx_debug_set_general_variant(-1)
     # forms: 1 sums in registers, 2 sums in the LDS stage, 0 element matrices
@@ -114,6 +120,12 @@ def test_general_forms_match_oracle_and_each_other(elem, dims, jit, renum):
     print(f"elem={elem} {dims} jitter {jit} renumbered={renum}: in LDS, sums in registers {e[-1]:.1e}, "
           f"in the stage {e[1]:.1e}; element matrices {e[0]:.1e}; between {e_mut:.1e}")
     assert max(e.values()) <= 1e-12 and e_mut <= 1e-13
+    for v in out:
+        # with Dirichlet rows: the fixed rows and columns exactly the oracle's,
+        # the rest as without
+        Km = out[v][2]
+        assert np.array_equal(Km[sel], Krm[sel]), v
+        assert np.array_equal(Km[~sel], out[v][0][~sel]), v
 
 
 @pytest.mark.parametrize("case", ["quad_unit", "hex_unit", "quad_sheared", "hex_sheared"])
