@@ -277,6 +277,18 @@ def general_run(stream, reps=20):
     avg_ke, _ = time_assembly(0)
     avg_stage, _ = time_assembly(1)
     avg, form = time_assembly(-1)
+    # the default form back to back: the fastest of three bursts of `reps`
+    # calls between one pair of events (as the headline's roofline kernel time)
+    bursts = []
+    for rep in range(3):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for r in range(reps):
+            pat.assemble_general(mat, rho, mask, out=K, stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        bursts.append(a.elapsed_time(b) / reps / 1e3)
+    avg_b2b = min(bursts)
     u = torch.from_numpy(pr.u).cuda()
     dc = torch.empty(m.n_cells, dtype=torch.float64, device="cuda")
     c = torch.zeros(2, dtype=torch.float64, device="cuda")
@@ -295,7 +307,10 @@ def general_run(stream, reps=20):
             "form": {1: "in LDS on the plan's node groups, sums in registers (k_assemble_point)",
                      2: "in LDS on the plan's node groups, sums in an LDS stage (k_assemble_quad)"}.get(
                          form, "element matrices through memory (k_ke_general, k_gather_general)"),
-            "avg_ms": avg * 1e3, "elements_per_s": m.n_cells / avg, "K_bytes": kbytes,
+            "avg_ms": avg * 1e3, "avg_ms_back_to_back": avg_b2b * 1e3,
+            "avg_ms_how": "avg_ms: HIP events around each call; avg_ms_back_to_back: the fastest of three "
+                          "bursts of %d calls between one pair of events" % reps,
+            "elements_per_s": m.n_cells / avg, "K_bytes": kbytes,
             "K_write_GBs": kbytes / avg / 1e9, "stage_form_avg_ms": avg_stage * 1e3,
             "element_matrix_form_avg_ms": avg_ke * 1e3,
             "evaluate_avg_ms": ev_avg * 1e3,
