@@ -84,6 +84,26 @@ def test_validation_error_codes():
     assert L.soptx_validate_mesh(None) == -1
 
 
+def test_debug_variant_hooks_check_their_arguments():
+    """The process-wide variant hooks accept only their listed values, and
+    the general-path query refuses a null handle or output, with no device
+    work."""
+    L = _lib.lib()
+    try:
+        for v in (-1, 0, 1):
+            assert L.soptx_debug_set_assembly_variant(v) == 0
+            assert L.soptx_debug_set_general_variant(v) == 0
+        for v in (-2, 2, 7):
+            assert L.soptx_debug_set_assembly_variant(v) == -1
+            assert L.soptx_debug_set_general_variant(v) == -1
+    finally:
+        L.soptx_debug_set_assembly_variant(-1)
+        L.soptx_debug_set_general_variant(-1)
+    form = ctypes.c_int32(5)
+    assert L.soptx_debug_general_path(None, ctypes.byref(form)) == -1
+    assert form.value == 5
+
+
 def test_per_call_argument_errors_without_device():
     """Calls with a NULL handle or bad arguments fail before any device work."""
     L = _lib.lib()
