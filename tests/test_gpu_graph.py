@@ -1,6 +1,7 @@
 """The hot path captured in a HIP graph (assemble, Dirichlet, evaluate on one
-stream): every replay, with the program's own eager work and synchronisations
-in between, gives the eager results bit for bit."""
+stream; the fused step; the general assembly and evaluation of non-affine Q1
+meshes): every replay, with the program's own eager work and
+synchronisations in between, gives the eager results bit for bit."""
 import numpy as np
 import pytest
 
@@ -143,6 +144,47 @@ def test_graph_replays_after_the_workspace_grew():
     assert np.isfinite(host(c2)).all()
     del K2, dc2, c2, pat2
     for rep in range(3):
+        K.fill_(np.nan)
+        dc.fill_(np.nan)
+        c.fill_(np.nan)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(K), ref[0]) and np.array_equal(host(dc), ref[1]), rep
+        assert np.array_equal(host(c), ref[2]), rep
+        _ = (rho * 2).sum().item()  # eager work between replays
+
+
+@pytest.mark.parametrize("elem", [I.QUAD4, I.HEX8])
+def test_graph_replays_of_the_general_assembly(elem):
+    """soptx_assemble_general on a jittered (non-affine) Q1 mesh, in its
+    default form (in LDS on the plan's node groups), then the general
+    evaluation, captured in a HIP graph: every replay, with eager work
+    between replays, gives the eager results bit for bit."""
+    rng = np.random.default_rng(42)
+    m0 = I.quad_grid(30, 20) if elem == I.QUAD4 else I.hex_grid(12, 8, 6)
+    m = I.jitter_interior(m0, 0.25, rng)
+    pat = api.Pattern.from_mesh(m, general=True)
+    st = torch.cuda.Stream()
+    rho = dev(rng.uniform(0.01, 1.0, m.n_cells))
+    u = dev(rng.standard_normal(m.ndof))
+    mask = dev((rng.uniform(size=m.ndof) < 0.1).astype(np.uint8))
+    K = torch.empty(pat.nnz, dtype=torch.float64, device="cuda")
+    dc = torch.empty(m.n_cells, dtype=torch.float64, device="cuda")
+    c = torch.zeros(2, dtype=torch.float64, device="cuda")
+
+    def step():
+        pat.assemble_general(MAT, rho, mask, out=K, stream=st)
+        pat.evaluate_general(MAT, rho, u, dc=dc, c=c, stream=st)
+
+    with torch.cuda.stream(st):
+        step()  # warm-up on the capture stream: workspace and launch attributes set
+    torch.cuda.synchronize()
+    ref = (host(K).copy(), host(dc).copy(), host(c).copy())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=st):
+        step()
+    for rep in range(4):
         K.fill_(np.nan)
         dc.fill_(np.nan)
         c.fill_(np.nan)
