@@ -236,24 +236,37 @@ def to_loop_run(iters, stream, rtol=1e-8):
             "volume_fraction_last": float(rho.sum()) / n}
 
 
-def general_run(stream, reps=20):
-    """Assembly with per-quadrature-point geometry on general hexahedra: the 3D
-    cantilever's 120 x 40 x 40 cells with every interior node moved by
-    U(-0.2, 0.2) per coordinate (seed 54), rho of the main workload, FP64,
-    Dirichlet rows; HIP events on the bench stream."""
+def general_run(stream, reps=20, two_d=False):
+    """Assembly with per-quadrature-point geometry on general Q1 cells: the 3D
+    cantilever's 120 x 40 x 40 hexahedra with every interior node moved by
+    U(-0.2, 0.2) per coordinate (seed 54), rho and u of the main workload; or
+    (two_d) the 2D cantilever's 600 x 200 quadrilaterals jittered the same
+    way (seed 57), rho ~ U(0.001, 1), clamped left edge.  FP64, Dirichlet
+    rows; HIP events on the bench stream."""
     import ctypes
     import numpy as np
     import torch
     from paper_2505_02438_amd import _lib, api
     from paper_2505_02438_amd import inputs as I
-    pr = I.cantilever_hex()
-    m = I.jitter_interior(pr.mesh, 0.2, np.random.default_rng(54))
+    if two_d:
+        rng = np.random.default_rng(57)
+        m = I.jitter_interior(I.quad_grid(600, 200), 0.2, rng)
+        rho_h = rng.uniform(0.001, 1.0, m.n_cells)
+        mask_h, _ = I.cantilever2d_bc(m, load="mid_right")
+        u_h = I.synthetic_u(rng, mask_h)
+        mat = api.Material()
+        mesh_desc = "600x200 quadrilaterals, interior nodes jittered by 0.2"
+    else:
+        pr = I.cantilever_hex()
+        m = I.jitter_interior(pr.mesh, 0.2, np.random.default_rng(54))
+        rho_h, mask_h, u_h = pr.rho, pr.mask, pr.u
+        mat = api.Material(E0=pr.E0, Emin=pr.Emin, nu=pr.nu, p=pr.p)
+        mesh_desc = "120x40x40 hexahedra, interior nodes jittered by 0.2"
     t0 = time.perf_counter()
     pat = api.Pattern.from_mesh(m, general=True)
     build_s = time.perf_counter() - t0
-    mat = api.Material(E0=pr.E0, Emin=pr.Emin, nu=pr.nu, p=pr.p)
-    rho = torch.from_numpy(pr.rho).cuda()
-    mask = torch.from_numpy(pr.mask).cuda()
+    rho = torch.from_numpy(rho_h).cuda()
+    mask = torch.from_numpy(mask_h).cuda()
     K = torch.empty(pat.nnz, dtype=torch.float64, device="cuda")
     L = _lib.lib()
     in_lds = ctypes.c_int32(-1)
@@ -289,7 +302,7 @@ def general_run(stream, reps=20):
         torch.cuda.synchronize()
         bursts.append(a.elapsed_time(b) / reps / 1e3)
     avg_b2b = min(bursts)
-    u = torch.from_numpy(pr.u).cuda()
+    u = torch.from_numpy(u_h).cuda()
     dc = torch.empty(m.n_cells, dtype=torch.float64, device="cuda")
     c = torch.zeros(2, dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
@@ -303,7 +316,7 @@ def general_run(stream, reps=20):
         ev.append(a.elapsed_time(b))
     ev_avg = statistics.mean(ev[3:]) / 1e3
     kbytes = pat.nnz * 8
-    return {"mesh": "120x40x40 hexahedra, interior nodes jittered by 0.2", "elements": m.n_cells,
+    return {"mesh": mesh_desc, "elements": m.n_cells,
             "form": {1: "in LDS on the plan's node groups, sums in registers (k_assemble_point)",
                      2: "in LDS on the plan's node groups, sums in an LDS stage (k_assemble_quad)"}.get(
                          form, "element matrices through memory (k_ke_general, k_gather_general)"),
@@ -907,6 +920,7 @@ def main():
         out["optimisation_loop"] = to_loop_run(args.to_iters, stream)
     if not args.no_general:
         out["general_assembly"] = general_run(stream)
+        out["general_assembly_2d"] = general_run(stream, two_d=True)
     if not args.no_hex27:
         out["hex27_assembly"] = hex27_run(stream)
     if not args.no_paper_runs:
